@@ -1,0 +1,218 @@
+/*
+ * gf2.h -- C ABI of the MI355X (gfx950) RS-SRI-GF2 hot path.
+ *
+ * The library assembles the imaginary-time second-order self-energy
+ * Sigma(tau) and the Galitskii-Migdal correlation energy with the
+ * range-separated stochastic resolution of identity of Dou, Chen,
+ * Takeshita, Baer, Neuhauser and Rabani (arXiv 2005.12338):
+ *
+ *   RI factors        K^Q_ij = sum_A (ij|A) V^{-1/2}_AQ          eq:K_ijQ
+ *   range separation  [K^Q]^L = K^Q where |K| >= eps max|K|    eq:K_L
+ *   stochastic split  R^xi = sum_Q theta_Q K^Q, R^L, R^S = R - R^L (Sec. II)
+ *   self-energy       eq:sigma with v from eq:RS-SRI, as in eq:sigma_2
+ *   energy            eq:corr, with the sign and factor fixed by the MP2 limit
+ *
+ * Conventions
+ *   - Matrices are row-major; dimensions are int64_t.
+ *   - The caller owns every buffer.  Arguments documented as "device" are
+ *     device pointers on the context's device (e.g. from torch); "host"
+ *     arguments are ordinary host memory.  The library owns only the opaque
+ *     context (scratch workspace, tuning table) and split handles.
+ *   - Device work is stream-ordered on the context's stream (gf2_create /
+ *     gf2_set_stream).  Calls that return host values synchronise that
+ *     stream before returning; the others are asynchronous.
+ *   - Every call returns a gf2_status.  On failure gf2_last_error(ctx)
+ *     describes the cause.  No C++ exception crosses this boundary.  A
+ *     context may be used by one host thread at a time.
+ *   - Everything runs in this library's HIP kernels (gfx950); there is no CPU
+ *     fallback for the device work.
+ */
+#ifndef GF2_H
+#define GF2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GF2_OK = 0,
+  GF2_E_ARG = -1,      /* an argument is out of range or inconsistent        */
+  GF2_E_DEVICE = -2,   /* a HIP runtime call failed                          */
+  GF2_E_NOMEM = -3,    /* device or host allocation failed                   */
+  GF2_E_NUMERIC = -4,  /* a non-finite value reached an output               */
+  GF2_E_STATE = -5     /* a handle does not belong to the given data / ctx   */
+} gf2_status;
+
+typedef enum { GF2_F64 = 0, GF2_F32 = 1 } gf2_dtype;
+
+/* Arithmetic of the stochastic-block products (the 24 dense N x N GEMMs per
+ * (tau, pair)).  The deterministic block, traces, accumulation of Sigma and
+ * the energy are always FP64.
+ *   FP64   : FP64 operands, FP64 MFMA.
+ *   FP32   : FP32 operands, FP32 MFMA.
+ *   BF16   : BF16 operands, FP32 accumulation (BF16 MFMA).
+ *   BF16X3 : each operand split hi = bf16(x), lo = bf16(x - hi); products
+ *            hi*hi + hi*lo + lo*hi accumulated in FP32.                     */
+typedef enum {
+  GF2_PREC_FP64 = 0,
+  GF2_PREC_FP32 = 1,
+  GF2_PREC_BF16 = 2,
+  GF2_PREC_BF16X3 = 3
+} gf2_precision;
+
+/* How the stochastic orbitals are drawn (counter-based SplitMix64, see
+ * gf2_rng_word):
+ *   RADEMACHER : theta_Q = +-1 for every Q (the paper's orbitals, Sec. II).
+ *   IMPORTANCE : theta = (1/sqrt k) sum_j e_j u_{Q_j} / sqrt(p_{Q_j}) with
+ *                Q_j drawn from the proposal p and e_j = +-1 (unbiased for
+ *                any p > 0 since E[theta theta^T] = I).                    */
+typedef enum { GF2_SAMPLE_RADEMACHER = 0, GF2_SAMPLE_IMPORTANCE = 1 } gf2_sample_mode;
+
+typedef struct gf2_ctx gf2_ctx;
+typedef struct gf2_split_h gf2_split_h;
+
+/* Synthetic chain: B^Q_ij = amp exp(-a (x_i-x_j)^2) exp(-c (x_Q-(x_i+x_j)/2)^2). */
+typedef struct {
+  int64_t n;          /* number of orbitals N                                */
+  int64_t naux;       /* number of auxiliary functions N_aux                 */
+  const double* x;    /* host [n] orbital centres                           */
+  const double* xq;   /* host [naux] auxiliary centres                      */
+  double amp, a, c;
+} gf2_chain_geom;
+
+typedef struct {
+  int64_t ns;          /* number of stochastic pairs (xi_s, eta_s)          */
+  int64_t s0;          /* index of the first pair (counter offset)          */
+  uint64_t seed;
+  int32_t mode;        /* gf2_sample_mode                                   */
+  int32_t k;           /* draws per vector in IMPORTANCE mode (>= 1)        */
+  const double* p;     /* host [naux] proposal (IMPORTANCE), sums to 1      */
+} gf2_sampling;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t
+ * (NULL = the null stream).  *ctx receives the handle. */
+gf2_status gf2_create(gf2_ctx** ctx, int device, void* hip_stream);
+void gf2_destroy(gf2_ctx* ctx);
+gf2_status gf2_set_stream(gf2_ctx* ctx, void* hip_stream);
+/* Message of the last failure on this context ("" if none); owned by ctx. */
+const char* gf2_last_error(const gf2_ctx* ctx);
+/* Library version string (static storage). */
+const char* gf2_version(void);
+
+/* ------------------------------------------------------------ B (a1) ----
+ * eq:K_ijQ.  Writes B[naux][n][n] (row-major, device, dtype out_dtype).
+ *   ijA == NULL : synthetic chain from *geom (geom->n, geom->naux must equal
+ *                 n, naux); V is ignored (V = I).
+ *   ijA != NULL : device [naux][n][n] three-index integrals (ij|A) in
+ *                 out_dtype; V is host [naux][naux] symmetric positive
+ *                 definite (NULL means V = I, i.e. B = ijA).  V^{-1/2} is
+ *                 formed from V's eigendecomposition in FP64.
+ * Errors: GF2_E_ARG for n, naux <= 0, missing geom in synthetic mode, or a
+ * V that is not positive definite. */
+gf2_status gf2_build_B(gf2_ctx* ctx, int64_t n, int64_t naux, const void* ijA,
+                       const double* V, const gf2_chain_geom* geom,
+                       gf2_dtype out_dtype, void* B);
+
+/* ------------------------------------------------------------ split (a2) --
+ * eq:K_L on K = B: m = max |B| over all elements; K^L keeps elements with
+ * |B| >= eps * m (inclusive) and zeroes the rest.  The handle stores, per Q,
+ * the support S_Q (orbitals with a kept element in their row) and the dense
+ * block K^L[Q][S_Q][S_Q], plus the gather/scatter maps of the union pattern.
+ * B is device [naux][n][n] of dtype `dtype`; it must stay unchanged while the
+ * handle is used (the handle records B's address and checks it).
+ * Outputs (host): *nnzL kept elements, *wmax = max_Q |S_Q|.
+ * Errors: GF2_E_ARG for eps < 0, n or naux <= 0, or a support wider than 32
+ * orbitals (the block kernels' limit). */
+gf2_status gf2_split(gf2_ctx* ctx, const void* B, gf2_dtype dtype, int64_t n,
+                     int64_t naux, double eps, gf2_split_h** out,
+                     int64_t* nnzL, int64_t* wmax);
+void gf2_split_free(gf2_split_h* h);
+/* Copy the split description to host arrays: support widths w[naux],
+ * supports idx[naux][32] (unused slots -1) and blocks blk[naux][32][32]
+ * (FP64, zero padded).  Any pointer may be NULL. */
+gf2_status gf2_split_export(gf2_ctx* ctx, const gf2_split_h* h, int32_t* w,
+                            int32_t* idx, double* blk, double* kmax);
+
+/* ------------------------------------------------------------ tau grid ----
+ * Gauss-Legendre nodes and weights mapped to [0, beta] (host arrays [ntau],
+ * ascending).  The paper leaves the tau grid open; this is the project's. */
+gf2_status gf2_tau_grid(double beta, int64_t ntau, double* tau, double* w);
+
+/* ------------------------------------------------------------ G(tau) (a5) -
+ * Non-interacting finite-temperature Green's function (eq:Gij, eq:G0):
+ * F C = S C eps (C^T S C = I), e~ = eps - mu, f = 1/(1+exp(beta e~)),
+ *   G[t]    = G(tau_t)        = -C diag((1-f) exp(-e~ tau_t)) C^T
+ *   Gbar[t] = G(beta - tau_t) = -C diag(f exp(e~ tau_t)) C^T
+ * F, S host [n][n] (S NULL = identity); tau host [ntau] in (0, beta).
+ * If n_occ > 0, mu is replaced by the mid-gap value (eps[n_occ-1] +
+ * eps[n_occ]) / 2; the value used is returned in *mu_out (host, may be
+ * NULL).  G, Gbar: device [ntau][n][n] FP64.
+ * Errors: GF2_E_ARG for beta <= 0, tau outside (0, beta), n_occ >= n, or an
+ * S that is not positive definite. */
+gf2_status gf2_green_tau(gf2_ctx* ctx, int64_t n, const double* F, const double* S,
+                         double mu, int64_t n_occ, double beta, int64_t ntau,
+                         const double* tau, double* G, double* Gbar, double* mu_out);
+
+/* ------------------------------------------------------------ Sigma (a3-a9)
+ * eq:sigma_2 with N_s independent pairs (theta from stream 0, theta' from
+ * stream 1):
+ *   Sigma(tau) = Sigma[D,D] + (1/N_s) sum_s (Sigma_s + Sigma_s^T)/2,
+ *   Sigma_s    = Sigma[D,S_eta_s] + Sigma[S_xi_s,D] + Sigma[S_xi_s,S_eta_s],
+ * D = sum_Q K^L_Q (x) K^L_Q and S_xi = R^L(x)R^S + R^S(x)R^L + R^S(x)R^S.
+ * Inputs: split handle of B; B device [naux][n][n] (dtype as given to
+ * gf2_split); G, Gbar device [ntau][n][n] FP64 (from gf2_green_tau).
+ * Outputs (device, FP64): Sigma [ntau][n][n]; e_samples [ns][ntau] with
+ * e_s(tau) = Tr(Sigma_s(tau) Gbar(tau)) (the per-pair energy integrand);
+ * e_samples may be NULL.
+ * Errors: GF2_E_ARG (ns < 1, bad mode, k < 1, proposal not positive),
+ * GF2_E_STATE (split handle of another B or context), GF2_E_NUMERIC. */
+gf2_status gf2_sigma_tau(gf2_ctx* ctx, const gf2_split_h* split, const void* B,
+                         const double* G, const double* Gbar, int64_t ntau,
+                         const gf2_sampling* sampling, gf2_precision prec,
+                         double* Sigma, double* e_samples);
+
+/* The two halves of gf2_sigma_tau, for adaptive or batched sampling:
+ * gf2_sigma_det writes Sigma[D,D] (device [ntau][n][n] FP64);
+ * gf2_sigma_stoch ADDS sum_s Sigma_s (unsymmetrised, FP64) into Sigma_sum
+ * (device [ntau][n][n]; zero it before the first batch) and writes
+ * e_samples [ns][ntau] for pairs s0 .. s0+ns-1; gf2_sigma_finalize writes
+ * Sigma = Sigma_det + (Sigma_sum + Sigma_sum^T) / (2 ns_total). */
+gf2_status gf2_sigma_det(gf2_ctx* ctx, const gf2_split_h* split, const double* G,
+                         const double* Gbar, int64_t ntau, double* Sigma_det);
+gf2_status gf2_sigma_stoch(gf2_ctx* ctx, const gf2_split_h* split, const void* B,
+                           const double* G, const double* Gbar, int64_t ntau,
+                           const gf2_sampling* sampling, gf2_precision prec,
+                           double* Sigma_sum, double* e_samples);
+gf2_status gf2_sigma_finalize(gf2_ctx* ctx, int64_t n, int64_t ntau,
+                              const double* Sigma_det, const double* Sigma_sum,
+                              int64_t ns_total, double* Sigma);
+
+/* ------------------------------------------------------------ energy (a10)
+ * E_tot = -(1/2) sum_t w_t Tr(Sigma(tau_t) Gbar(tau_t)) in FP64 (eq:corr;
+ * the -1/2 makes the beta -> infinity limit the closed-shell MP2 energy).
+ * Per-pair energies E_s = E_tot - (1/2) sum_t w_t (e_s(tau_t) - mean_s e);
+ * stderr = std(E_s, ddof=1)/sqrt(ns).  w host [ntau]; Sigma, Gbar device
+ * [ntau][n][n]; e_samples device [ns][ntau] or NULL (then *stderr_tot = 0).
+ * Outputs (host): *E_tot, *E_per_e = E_tot / n_elec, *stderr_tot.
+ * Errors: GF2_E_ARG (n_elec <= 0, ns < 2 with e_samples), GF2_E_NUMERIC. */
+gf2_status gf2_energy(gf2_ctx* ctx, int64_t n, int64_t ntau, const double* w,
+                      const double* Sigma, const double* Gbar,
+                      const double* e_samples, int64_t ns, double n_elec,
+                      double* E_tot, double* E_per_e, double* stderr_tot);
+
+/* ------------------------------------------------------------ RNG ---------
+ * word(seed, stream, s, q) = mix(seed * 0x9E3779B97F4A7C15
+ *                                + ((stream << 62) | (s << 32) | q) + 1),
+ * mix = SplitMix64 finaliser (Steele, Lea, Flood 2014).  Fills out[count]
+ * (host) with the words for q = q0 .. q0+count-1, computed on the device. */
+gf2_status gf2_rng_words(gf2_ctx* ctx, uint64_t seed, uint32_t stream, uint32_t s,
+                         uint32_t q0, int64_t count, uint64_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GF2_H */

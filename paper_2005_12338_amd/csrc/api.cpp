@@ -1,0 +1,857 @@
+// C ABI of libgf2: argument checking, device buffers, and the launch
+// schedule of the RS-SRI-GF2 hot path (see include/gf2.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace {
+
+constexpr double kGM = 0.5;   // E = -1/2 int Tr(Sigma Gbar): the MP2 limit fixes it
+
+// ------------------------------------------------------------ scratch ----
+struct Scratch {
+  std::map<std::string, DevBuf> bufs;
+};
+std::map<const gf2_ctx*, Scratch>& scratch_table() {
+  static std::map<const gf2_ctx*, Scratch> t;
+  return t;
+}
+
+void* ctx_buf(gf2_ctx* ctx, const std::string& tag, size_t bytes, bool zero = false) {
+  auto& s = scratch_table()[ctx];
+  DevBuf& b = s.bufs[tag];
+  if (bytes == 0) bytes = 16;
+  if (b.bytes < bytes) {
+    if (b.p) {
+      GF2_HIP(hipStreamSynchronize(ctx->stream));
+      GF2_HIP(hipFree(b.p));
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+      b.p = nullptr;
+      throw Gf2Error{GF2_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes for " + tag +
+                                      " failed: " + hipGetErrorString(e)};
+    }
+    b.bytes = bytes;
+    zero = true;
+  }
+  if (zero) GF2_HIP(hipMemsetAsync(b.p, 0, bytes, ctx->stream));
+  return b.p;
+}
+
+void free_scratch(const gf2_ctx* ctx) {
+  auto& t = scratch_table();
+  auto it = t.find(ctx);
+  if (it == t.end()) return;
+  for (auto& kv : it->second.bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  t.erase(it);
+}
+
+template <typename T>
+void h2d(gf2_ctx* ctx, T* dst, const T* src, size_t count) {
+  GF2_HIP(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+}
+template <typename T>
+void d2h(gf2_ctx* ctx, T* dst, const T* src, size_t count) {
+  GF2_HIP(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToHost, ctx->stream));
+  GF2_HIP(hipStreamSynchronize(ctx->stream));
+}
+
+template <typename F>
+gf2_status guarded(gf2_ctx* ctx, F&& f) {
+  if (!ctx) return GF2_E_ARG;
+  try {
+    GF2_HIP(hipSetDevice(ctx->device));
+    f();
+    ctx->err.clear();
+    return GF2_OK;
+  } catch (const Gf2Error& e) {
+    ctx->err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "host allocation failed";
+    return GF2_E_NOMEM;
+  } catch (...) {
+    ctx->err = "unexpected internal error";
+    return GF2_E_DEVICE;
+  }
+}
+
+Prec to_prec(gf2_precision p) {
+  switch (p) {
+    case GF2_PREC_FP64: return Prec::F64;
+    case GF2_PREC_FP32: return Prec::F32;
+    case GF2_PREC_BF16: return Prec::BF16;
+    case GF2_PREC_BF16X3: return Prec::BF16X3;
+  }
+  throw Gf2Error{GF2_E_ARG, "unknown precision"};
+}
+size_t st_elem(Prec p) { return p == Prec::F64 ? 8 : p == Prec::F32 ? 4 : 2; }
+int st_planes(Prec p) { return p == Prec::BF16X3 ? 2 : 1; }
+size_t acc_elem(Prec p) { return p == Prec::F64 ? 8 : 4; }
+
+double softplus(double x) { return std::max(x, 0.0) + std::log1p(std::exp(-std::fabs(x))); }
+
+void check_finite(gf2_ctx* ctx, const double* x, int64_t count, const char* what) {
+  auto* bad = (unsigned long long*)ctx_buf(ctx, "nonfinite", sizeof(unsigned long long), true);
+  launch_count_nonfinite(x, count, bad, ctx->stream);
+  unsigned long long h = 0;
+  d2h(ctx, &h, bad, 1);
+  if (h) throw Gf2Error{GF2_E_NUMERIC, std::to_string(h) + " non-finite values in " + what};
+}
+
+OpRef opref(const void* base, int64_t st_tau = 0, int64_t st_s = 0, int64_t st_slot = 0) {
+  OpRef r;
+  r.base = base; r.st_tau = st_tau; r.st_s = st_s; r.st_slot = st_slot;
+  return r;
+}
+OutSpec outspec(void* base, int64_t st_slot, std::initializer_list<float> coef, int layout, int type,
+                int64_t st_tau = 0) {
+  OutSpec o;
+  std::memset(&o, 0, sizeof(o));
+  o.base = base; o.st_tau = st_tau; o.st_s = 0; o.st_slot = st_slot;
+  int i = 0;
+  for (float c : coef) o.coef[i++] = c;
+  o.layout = layout; o.type = type;
+  return o;
+}
+Prob prob0() {
+  Prob p;
+  std::memset(&p, 0, sizeof(p));
+  p.nseg = 1; p.nA = 1; p.nB = 1;
+  return p;
+}
+int tiles_of(const Prob& p, Prec prec, int64_t m, int64_t nc) {
+  const int64_t sm = gemm_tile_m(prec) / p.nA, sn = gemm_tile_n(prec) / p.nB;
+  return (int)(((m + sm - 1) / sm) * ((nc + sn - 1) / sn));
+}
+int tiles_of(const Prob& p, Prec prec, int64_t n) { return tiles_of(p, prec, n, n); }
+
+}  // namespace
+
+// ======================================================================= API
+
+extern "C" {
+
+const char* gf2_version(void) { return "gf2 0.1 (gfx950)"; }
+
+gf2_status gf2_create(gf2_ctx** out, int device, void* stream) {
+  if (!out) return GF2_E_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return GF2_E_DEVICE;
+  if (device < 0 || device >= ndev) return GF2_E_ARG;
+  gf2_ctx* c = new (std::nothrow) gf2_ctx();
+  if (!c) return GF2_E_NOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  *out = c;
+  return GF2_OK;
+}
+
+void gf2_destroy(gf2_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  free_scratch(ctx);
+  delete ctx;
+}
+
+gf2_status gf2_set_stream(gf2_ctx* ctx, void* stream) {
+  if (!ctx) return GF2_E_ARG;
+  ctx->stream = (hipStream_t)stream;
+  return GF2_OK;
+}
+
+const char* gf2_last_error(const gf2_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+gf2_status gf2_rng_words(gf2_ctx* ctx, uint64_t seed, uint32_t stream, uint32_t s, uint32_t q0,
+                         int64_t count, uint64_t* out) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(out && count >= 0 && stream < 4 && s < (1u << 30), GF2_E_ARG, "bad rng arguments");
+    if (count == 0) return;
+    auto* d = (uint64_t*)ctx_buf(ctx, "rng", (size_t)count * 8);
+    launch_rng_words(seed, stream, s, q0, count, d, ctx->stream);
+    GF2_HIP(hipGetLastError());
+    d2h(ctx, out, d, (size_t)count);
+  });
+}
+
+// ------------------------------------------------------------ tau grid ----
+gf2_status gf2_tau_grid(double beta, int64_t ntau, double* tau, double* w) {
+  if (!(beta > 0) || ntau < 1 || !tau || !w) return GF2_E_ARG;
+  std::vector<double> x(ntau), ww(ntau);
+  gauss_legendre(ntau, x.data(), ww.data());
+  for (int64_t i = 0; i < ntau; ++i) {
+    tau[i] = 0.5 * beta * (1.0 + x[i]);
+    w[i] = 0.5 * beta * ww[i];
+  }
+  return GF2_OK;
+}
+
+// ------------------------------------------------------------ B -----------
+gf2_status gf2_build_B(gf2_ctx* ctx, int64_t n, int64_t naux, const void* ijA, const double* V,
+                       const gf2_chain_geom* geom, gf2_dtype out_dtype, void* B) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(n > 0 && naux > 0 && B, GF2_E_ARG, "n, naux must be positive and B non-null");
+    GF2_REQUIRE(out_dtype == GF2_F64 || out_dtype == GF2_F32, GF2_E_ARG, "bad dtype");
+    const bool f64 = out_dtype == GF2_F64;
+    if (!ijA) {
+      GF2_REQUIRE(geom && geom->x && geom->xq, GF2_E_ARG, "synthetic mode needs a geometry");
+      GF2_REQUIRE(geom->n == n && geom->naux == naux, GF2_E_ARG, "geometry size mismatch");
+      auto* dx = (double*)ctx_buf(ctx, "geom_x", (size_t)n * 8);
+      auto* dq = (double*)ctx_buf(ctx, "geom_xq", (size_t)naux * 8);
+      h2d(ctx, dx, geom->x, (size_t)n);
+      h2d(ctx, dq, geom->xq, (size_t)naux);
+      launch_synth_b(n, naux, dx, dq, geom->amp, geom->a, geom->c, B, f64, ctx->stream);
+      GF2_HIP(hipGetLastError());
+      GF2_HIP(hipStreamSynchronize(ctx->stream));
+      return;
+    }
+    const size_t es = f64 ? 8 : 4;
+    if (!V) {
+      GF2_HIP(hipMemcpyAsync(B, ijA, (size_t)naux * n * n * es, hipMemcpyDeviceToDevice, ctx->stream));
+      GF2_HIP(hipStreamSynchronize(ctx->stream));
+      return;
+    }
+    // V^{-1/2} from V's eigendecomposition (FP64, host, O(naux^3) once)
+    std::vector<double> a(V, V + naux * naux), e(naux), u((size_t)(naux * naux));
+    sym_eigen(naux, a.data(), e.data(), u.data());
+    GF2_REQUIRE(e[0] > 0, GF2_E_ARG, "V is not positive definite");
+    const int64_t kp = pad_dim(naux);
+    const int64_t nn = n * n;
+    std::vector<double> w((size_t)(naux * kp), 0.0);    // W[q][A] = V^{-1/2}_{AQ}
+    for (int64_t q = 0; q < naux; ++q)
+      for (int64_t A = 0; A < naux; ++A) {
+        double s = 0.0;
+        for (int64_t k = 0; k < naux; ++k) s += u[A * naux + k] * u[q * naux + k] / std::sqrt(e[k]);
+        w[q * kp + A] = s;
+      }
+    // out^T[ij][q] = sum_A ijA^T[ij][A] W[q][A] on the FP64 MFMA GEMM
+    auto* wd = (double*)ctx_buf(ctx, "bw", w.size() * 8);
+    auto* tin = (double*)ctx_buf(ctx, "bt_in", (size_t)(nn * kp) * 8, true);
+    auto* tout = (double*)ctx_buf(ctx, "bt_out", (size_t)(nn * kp) * 8);
+    h2d(ctx, wd, w.data(), w.size());
+    launch_transpose(ijA, f64, naux, nn, tin, kp, ctx->stream);
+    Prob pb = prob0();
+    pb.a[0] = opref(tin);
+    pb.b[0] = opref(wd);
+    pb.nout = 1;
+    pb.out[0] = outspec(tout, 0, {1.0f}, 0, 0);
+    auto* probs = (Prob*)ctx_buf(ctx, "bprob", sizeof(Prob));
+    h2d(ctx, probs, &pb, 1);
+    Unit uh{0, 0, 0, 0};
+    auto* units = (Unit*)ctx_buf(ctx, "bunit", sizeof(Unit));
+    h2d(ctx, units, &uh, 1);
+    GemmLaunch L{probs, 1, units, 1, nn, naux, kp, kp, 0};
+    launch_gemm(Prec::F64, L, tiles_of(pb, Prec::F64, nn, naux), ctx->stream);
+    launch_untranspose(tout, nn, naux, kp, B, f64, ctx->stream);
+    GF2_HIP(hipGetLastError());
+    GF2_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+// ------------------------------------------------------------ split -------
+gf2_status gf2_split(gf2_ctx* ctx, const void* B, gf2_dtype dtype, int64_t n, int64_t naux, double eps,
+                     gf2_split_h** out, int64_t* nnzL, int64_t* wmax) {
+  gf2_split_h* h = nullptr;
+  gf2_status st = guarded(ctx, [&] {
+    GF2_REQUIRE(out && B && n > 0 && naux > 0 && eps >= 0.0 && std::isfinite(eps), GF2_E_ARG,
+                "bad split arguments");
+    GF2_REQUIRE(n <= 32768 && naux < (1 << 21), GF2_E_ARG, "n or naux too large");
+    const bool f64 = dtype == GF2_F64;
+    const int64_t total = naux * n * n;
+    const int nblk = 1024;
+    auto* part = (double*)ctx_buf(ctx, "split_part", nblk * 8);
+    launch_maxabs(B, f64, total, part, nblk, ctx->stream);
+    GF2_HIP(hipGetLastError());
+    std::vector<double> ph(nblk);
+    d2h(ctx, ph.data(), part, nblk);
+    double kmax = 0.0;
+    for (double v : ph) kmax = std::max(kmax, v);
+    GF2_REQUIRE(std::isfinite(kmax), GF2_E_NUMERIC, "non-finite value in B");
+    const double thr = eps * kmax;
+    auto* flags = (uint8_t*)ctx_buf(ctx, "split_flags", (size_t)(naux * n));
+    auto* cnt = (unsigned long long*)ctx_buf(ctx, "split_cnt", 8, true);
+    launch_rowflags(B, f64, n, naux, thr, flags, cnt, ctx->stream);
+    GF2_HIP(hipGetLastError());
+    std::vector<uint8_t> fh((size_t)(naux * n));
+    unsigned long long nnz = 0;
+    d2h(ctx, fh.data(), flags, fh.size());
+    d2h(ctx, &nnz, cnt, 1);
+
+    h = new gf2_split_h();
+    h->owner = ctx; h->bsrc = B; h->dtype = dtype; h->n = n; h->naux = naux; h->np = pad_dim(n);
+    h->eps = eps; h->kmax = kmax; h->thresh = thr; h->nnz = (int64_t)nnz;
+    std::vector<int32_t> w(naux, 0), idx((size_t)naux * kWMax, -1);
+    int32_t wm = 0;
+    for (int64_t q = 0; q < naux; ++q) {
+      int32_t c = 0;
+      for (int64_t i = 0; i < n; ++i)
+        if (fh[q * n + i]) {
+          GF2_REQUIRE(c < kWMax, GF2_E_ARG,
+                      "support of Q=" + std::to_string(q) + " is wider than 32 orbitals (raise eps)");
+          idx[q * kWMax + c++] = (int32_t)i;
+        }
+      w[q] = c;
+      wm = std::max(wm, c);
+    }
+    h->wmax = wm;
+    // union pattern with its contribution lists (ordered by Q, a, b)
+    std::vector<std::pair<int64_t, int32_t>> contrib;
+    for (int64_t q = 0; q < naux; ++q)
+      for (int a = 0; a < w[q]; ++a)
+        for (int b = 0; b < w[q]; ++b) {
+          int64_t i = idx[q * kWMax + a], j = idx[q * kWMax + b];
+          contrib.push_back({i * h->np + j, (int32_t)(q * 1024 + a * 32 + b)});
+        }
+    std::stable_sort(contrib.begin(), contrib.end(),
+                     [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
+                       return x.first < y.first;
+                     });
+    std::vector<int32_t> pij, poff, pq;
+    for (size_t c = 0; c < contrib.size(); ++c) {
+      if (c == 0 || contrib[c].first != contrib[c - 1].first) {
+        pij.push_back((int32_t)contrib[c].first);
+        poff.push_back((int32_t)c);
+      }
+      pq.push_back(contrib[c].second);
+    }
+    poff.push_back((int32_t)contrib.size());
+    h->npat = (int64_t)pij.size();
+    h->ncontrib = (int64_t)pq.size();
+    // Q lists per row block of the deterministic-block tiles
+    const int td = dblock_tile();
+    const int64_t nbk = (n + td - 1) / td;
+    std::vector<std::vector<int32_t>> lists(nbk);
+    for (int64_t q = 0; q < naux; ++q) {
+      int64_t last = -1;
+      for (int a = 0; a < w[q]; ++a) {
+        int64_t bk = idx[q * kWMax + a] / td;
+        if (bk != last) lists[bk].push_back((int32_t)q);
+        last = bk;
+      }
+    }
+    std::vector<int32_t> toff(nbk + 1, 0), tq;
+    for (int64_t b = 0; b < nbk; ++b) {
+      toff[b] = (int32_t)tq.size();
+      tq.insert(tq.end(), lists[b].begin(), lists[b].end());
+    }
+    toff[nbk] = (int32_t)tq.size();
+
+    auto alloc = [&](void** p, size_t bytes) {
+      if (bytes == 0) bytes = 16;
+      hipError_t e = hipMalloc(p, bytes);
+      if (e != hipSuccess) throw Gf2Error{GF2_E_NOMEM, "split allocation failed"};
+    };
+    alloc((void**)&h->w, naux * 4);
+    alloc((void**)&h->idx, naux * kWMax * 4);
+    alloc((void**)&h->blk, naux * kWMax * kWMax * 8);
+    alloc((void**)&h->blk32, naux * kWMax * kWMax * 4);
+    alloc((void**)&h->pat_ij, pij.size() * 4);
+    alloc((void**)&h->pat_off, poff.size() * 4);
+    alloc((void**)&h->pat_q, pq.size() * 4);
+    alloc((void**)&h->row_off, toff.size() * 4);
+    alloc((void**)&h->row_q, tq.size() * 4);
+    h2d(ctx, h->w, w.data(), w.size());
+    h2d(ctx, h->idx, idx.data(), idx.size());
+    if (!pij.empty()) h2d(ctx, h->pat_ij, pij.data(), pij.size());
+    h2d(ctx, h->pat_off, poff.data(), poff.size());
+    if (!pq.empty()) h2d(ctx, h->pat_q, pq.data(), pq.size());
+    h2d(ctx, h->row_off, toff.data(), toff.size());
+    if (!tq.empty()) h2d(ctx, h->row_q, tq.data(), tq.size());
+    launch_extract_blocks(B, f64, n, naux, thr, h->w, h->idx, h->blk, h->blk32, ctx->stream);
+    GF2_HIP(hipGetLastError());
+    GF2_HIP(hipStreamSynchronize(ctx->stream));
+    *out = h;
+    if (nnzL) *nnzL = h->nnz;
+    if (wmax) *wmax = h->wmax;
+  });
+  if (st != GF2_OK && h) {
+    gf2_split_free(h);
+    if (out) *out = nullptr;
+  }
+  return st;
+}
+
+void gf2_split_free(gf2_split_h* h) {
+  if (!h) return;
+  void* ps[] = {h->w, h->idx, h->blk, h->blk32, h->pat_ij, h->pat_off, h->pat_q, h->row_off, h->row_q};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  delete h;
+}
+
+gf2_status gf2_split_export(gf2_ctx* ctx, const gf2_split_h* h, int32_t* w, int32_t* idx, double* blk,
+                            double* kmax) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(h && h->owner == ctx, GF2_E_STATE, "split handle of another context");
+    if (w) d2h(ctx, w, h->w, (size_t)h->naux);
+    if (idx) d2h(ctx, idx, h->idx, (size_t)h->naux * kWMax);
+    if (blk) d2h(ctx, blk, h->blk, (size_t)h->naux * kWMax * kWMax);
+    if (kmax) *kmax = h->kmax;
+  });
+}
+
+// ------------------------------------------------------------ G(tau) ------
+gf2_status gf2_green_tau(gf2_ctx* ctx, int64_t n, const double* F, const double* S, double mu,
+                         int64_t n_occ, double beta, int64_t ntau, const double* tau, double* G,
+                         double* Gbar, double* mu_out) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(n > 0 && F && tau && G && Gbar && ntau > 0, GF2_E_ARG, "bad green_tau arguments");
+    GF2_REQUIRE(beta > 0 && std::isfinite(beta), GF2_E_ARG, "beta must be positive");
+    GF2_REQUIRE(n_occ < n, GF2_E_ARG, "n_occ must be < n");
+    for (int64_t t = 0; t < ntau; ++t)
+      GF2_REQUIRE(tau[t] > 0 && tau[t] < beta, GF2_E_ARG, "tau outside (0, beta)");
+    std::vector<double> eps(n), c((size_t)(n * n));
+    if (!S) {
+      std::vector<double> a(F, F + n * n);
+      sym_eigen(n, a.data(), eps.data(), c.data());
+    } else {
+      std::vector<double> a(S, S + n * n), se(n), su((size_t)(n * n));
+      sym_eigen(n, a.data(), se.data(), su.data());
+      GF2_REQUIRE(se[0] > 0, GF2_E_ARG, "S is not positive definite");
+      std::vector<double> x((size_t)(n * n)), fx((size_t)(n * n)), xfx((size_t)(n * n)), y((size_t)(n * n));
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+          double s = 0.0;
+          for (int64_t k = 0; k < n; ++k) s += su[i * n + k] * su[j * n + k] / std::sqrt(se[k]);
+          x[i * n + j] = s;
+        }
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+          double s = 0.0;
+          for (int64_t k = 0; k < n; ++k) s += F[i * n + k] * x[k * n + j];
+          fx[i * n + j] = s;
+        }
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+          double s = 0.0;
+          for (int64_t k = 0; k < n; ++k) s += x[i * n + k] * fx[k * n + j];
+          xfx[i * n + j] = s;
+        }
+      sym_eigen(n, xfx.data(), eps.data(), y.data());
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+          double s = 0.0;
+          for (int64_t k = 0; k < n; ++k) s += x[i * n + k] * y[k * n + j];
+          c[i * n + j] = s;
+        }
+    }
+    if (n_occ > 0) mu = 0.5 * (eps[n_occ - 1] + eps[n_occ]);
+    if (mu_out) *mu_out = mu;
+    GF2_REQUIRE(std::isfinite(mu), GF2_E_ARG, "mu is not finite");
+    const int64_t np = pad_dim(n);
+    std::vector<double> lw((size_t)(ntau * n)), lb((size_t)(ntau * n));
+    for (int64_t t = 0; t < ntau; ++t)
+      for (int64_t k = 0; k < n; ++k) {
+        const double et = eps[k] - mu;
+        lw[t * n + k] = -et * tau[t] - softplus(-beta * et);     // ln[(1-f) e^{-e~ tau}]
+        lb[t * n + k] = et * tau[t] - softplus(beta * et);       // ln[f e^{e~ tau}]
+      }
+    std::vector<double> cp((size_t)(np * np), 0.0);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t k = 0; k < n; ++k) cp[i * np + k] = c[i * n + k];
+    auto* dc = (double*)ctx_buf(ctx, "g_c", (size_t)(n * n) * 8);
+    auto* dcp = (double*)ctx_buf(ctx, "g_cp", (size_t)(np * np) * 8);
+    auto* dlw = (double*)ctx_buf(ctx, "g_lw", (size_t)(ntau * n) * 8);
+    auto* da = (double*)ctx_buf(ctx, "g_a", (size_t)(ntau * np * np) * 8);
+    auto* dp = (double*)ctx_buf(ctx, "g_p", (size_t)(ntau * np * np) * 8);
+    h2d(ctx, dc, c.data(), c.size());
+    h2d(ctx, dcp, cp.data(), cp.size());
+    Prob pb = prob0();
+    pb.a[0] = opref(da, np * np);
+    pb.b[0] = opref(dcp);
+    pb.nout = 1;
+    pb.out[0] = outspec(dp, 0, {1.0f}, 0, 0, np * np);
+    auto* probs = (Prob*)ctx_buf(ctx, "g_prob", sizeof(Prob));
+    h2d(ctx, probs, &pb, 1);
+    std::vector<Unit> uh(ntau);
+    for (int64_t t = 0; t < ntau; ++t) uh[t] = Unit{(int32_t)t, 0, 0, 0};
+    auto* units = (Unit*)ctx_buf(ctx, "g_units", (size_t)ntau * sizeof(Unit));
+    h2d(ctx, units, uh.data(), uh.size());
+    GemmLaunch L = chain_launch(probs, 1, units, (int32_t)ntau, n, np, 0);
+    for (int which = 0; which < 2; ++which) {
+      h2d(ctx, dlw, which == 0 ? lw.data() : lb.data(), lw.size());
+      launch_scale_cols(dc, dlw, n, np, ntau, da, ctx->stream);
+      GF2_HIP(hipGetLastError());
+      launch_gemm(Prec::F64, L, tiles_of(pb, Prec::F64, n), ctx->stream);
+      launch_unpad_sym(dp, n, np, ntau, -1.0, which == 0 ? G : Gbar, ctx->stream);
+      GF2_HIP(hipGetLastError());
+    }
+    GF2_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+// ------------------------------------------------------------ Sigma -------
+gf2_status gf2_sigma_det(gf2_ctx* ctx, const gf2_split_h* split, const double* G, const double* Gbar,
+                         int64_t ntau, double* Sigma_det) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(split && split->owner == ctx, GF2_E_STATE, "split handle of another context");
+    GF2_REQUIRE(G && Gbar && Sigma_det && ntau > 0 && ntau <= 65535, GF2_E_ARG, "bad sigma_det arguments");
+    launch_dblock(G, Gbar, split->n, ntau, split->wmax, split->w, split->idx, split->blk, split->row_off,
+                  split->row_q, Sigma_det, ctx->stream);
+    GF2_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+namespace {
+
+struct ChainBufs {
+  int64_t n, np, np2, plane;
+  Prec prec;
+  size_t sbytes, abytes;      // bytes of one storage / accumulator matrix
+  int32_t slots;
+};
+
+void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double* G, const double* Gbar,
+               int64_t ntau, const gf2_sampling* smp, Prec prec, double* Sigma_sum, double* e_samples) {
+  const int64_t n = sp->n, np = sp->np, np2 = np * np, naux = sp->naux;
+  const int64_t ns = smp->ns, s0 = smp->s0;
+  const bool bf64 = sp->dtype == GF2_F64;
+  const int planes = st_planes(prec);
+  const int64_t plane = np2;
+  const size_t sb = (size_t)planes * np2 * st_elem(prec);     // one storage matrix
+  const size_t ab = (size_t)np2 * acc_elem(prec);             // one accumulator matrix
+  const bool accf64 = prec == Prec::F64;
+  hipStream_t st = ctx->stream;
+  // The products run over the zero padding of every np x np matrix, so a
+  // change of layout clears all chain buffers (new allocations are zeroed).
+  const std::string key = std::to_string(n) + ":" + std::to_string(np) + ":" + std::to_string((int)prec);
+  const bool reset = ctx->chain_key != key;
+  ctx->chain_key = key;
+  auto CB = [&](const char* tag, size_t bytes) { return (char*)ctx_buf(ctx, tag, bytes, reset); };
+
+  // ---- G, Gbar in padded storage format and FP64
+  char* gst = CB("c_gst", sb * ntau);
+  char* gbst = CB("c_gbst", sb * ntau);
+  double* gb64 = (double*)CB("c_gb64", (size_t)ntau * np2 * 8);
+  const int64_t mstride = (int64_t)planes * np2;              // elements per storage matrix
+  launch_pad_convert(G, n, np, ntau, prec, gst, plane, mstride, nullptr, st);
+  launch_pad_convert(Gbar, n, np, ntau, prec, gbst, plane, mstride, gb64, st);
+  GF2_HIP(hipGetLastError());
+
+  // ---- stochastic vectors: [0, ns) first vertex (xi), [ns, 2ns) second (eta)
+  const int64_t nvec = 2 * ns;
+  char* xl = CB("c_xl", sb * nvec);
+  char* xs = CB("c_xs", sb * nvec);
+  if (smp->mode == GF2_SAMPLE_RADEMACHER) {
+    auto* theta = (int8_t*)ctx_buf(ctx, "c_theta", (size_t)(nvec * naux));
+    launch_theta(smp->seed, ns, s0, naux, theta, st);
+    launch_rbuild(B, bf64, n, naux, sp->thresh, theta, nvec, prec, xl, xs, np, plane, mstride, st);
+  } else {
+    std::vector<double> cdf(naux);
+    double acc = 0.0;
+    for (int64_t q = 0; q < naux; ++q) {
+      acc += smp->p[q];
+      cdf[q] = acc;
+    }
+    cdf[naux - 1] = 1.0;
+    auto* dcdf = (double*)ctx_buf(ctx, "c_cdf", (size_t)naux * 8);
+    auto* dp = (double*)ctx_buf(ctx, "c_p", (size_t)naux * 8);
+    auto* dq = (int32_t*)ctx_buf(ctx, "c_q", (size_t)(nvec * smp->k) * 4);
+    auto* dw = (double*)ctx_buf(ctx, "c_w", (size_t)(nvec * smp->k) * 8);
+    h2d(ctx, dcdf, cdf.data(), cdf.size());
+    h2d(ctx, dp, smp->p, (size_t)naux);
+    launch_draws(smp->seed, ns, s0, smp->k, dcdf, naux, dp, dq, dw, st);
+    launch_rimportance(B, bf64, n, sp->thresh, dq, dw, smp->k, nvec, prec, xl, xs, np, plane, mstride, st);
+  }
+  GF2_HIP(hipGetLastError());
+
+  // ---- chunking: units (tau, s), s outer so that every Sigma_sum[tau]
+  // receives its pairs in increasing s.
+  int64_t slots = ctx->max_units > 0 ? ctx->max_units : 0;
+  if (slots <= 0) {
+    // keep per-slot scratch near 4 GB and the grid well above 256 CUs
+    const double per_slot = 30.0 * (double)std::max(sb, ab);
+    slots = (int64_t)std::max(1.0, std::min(64.0, 4.0e9 / per_slot));
+  }
+  slots = std::min<int64_t>(slots, ntau * ns);
+  const int64_t sc = std::min<int64_t>(ns, std::max<int64_t>(1, slots / std::min<int64_t>(ntau, slots)));
+  const int64_t tcnt = std::max<int64_t>(1, slots / sc);
+  slots = sc * tcnt;
+
+  // per-slot scratch
+  auto S = [&](const char* tag, size_t bytes) { return (char*)ctx_buf(ctx, tag, bytes * slots, reset); };
+  char *ul_n = S("c_uln", sb), *ul_t = S("c_ult", sb), *us_n = S("c_usn", sb), *us_t = S("c_ust", sb);
+  char *vl_n = S("c_vln", sb), *vs_n = S("c_vsn", sb), *vs_t = S("c_vst", sb), *vsum_t = S("c_vsumt", sb);
+  char* mst = S("c_mst", 4 * sb);
+  char* mct = S("c_mct", 4 * sb);
+  char* wz = S("c_wz", 4 * ab);
+  char* tq = S("c_t", 4 * sb);
+  char* sig = S("c_sig", ab);
+  // pattern-only outputs of JK: zero once, only pattern entries are written
+  char* jk = (char*)ctx_buf(ctx, "c_jk", 4 * sb * slots, true);
+  char *jw_l = jk, *jw_s = jk + sb * slots, *jz_st = jk + 2 * sb * slots, *jz_sum_t = jk + 3 * sb * slots;
+  // (each JK output array is [slot][plane][np][np])
+  const size_t jbytes = (size_t)slots * 4 * naux * kWMax * kWMax * (accf64 ? 8 : 4);
+  char* jblk = (char*)ctx_buf(ctx, "c_jblk", jbytes);
+  const int64_t st_sl = (int64_t)(sb / st_elem(prec));        // elements per storage slot
+  const int64_t ac_sl = (int64_t)np2;
+
+  // ---- problem tables
+  const int64_t vst = planes * np2;                            // one vector
+  const int64_t gstride = planes * np2;                        // one tau of G storage
+  std::vector<Prob> P;
+  // S1: U = X G (dual A), V = G Y (dual B)
+  {
+    Prob p = prob0();
+    p.nA = 2;
+    p.a[0] = opref(xl, 0, vst);
+    p.a[1] = opref(xs, 0, vst);
+    p.b[0] = opref(gst, gstride);
+    p.nout = 4;
+    p.out[0] = outspec(ul_n, st_sl, {1, 0}, 0, 1);
+    p.out[1] = outspec(ul_t, st_sl, {1, 0}, 1, 1);
+    p.out[2] = outspec(us_n, st_sl, {0, 1}, 0, 1);
+    p.out[3] = outspec(us_t, st_sl, {0, 1}, 1, 1);
+    P.push_back(p);
+    Prob q = prob0();
+    q.nB = 2;
+    q.a[0] = opref(gst, gstride);
+    q.b[0] = opref(xl + sb * ns, 0, vst);
+    q.b[1] = opref(xs + sb * ns, 0, vst);
+    q.nout = 4;
+    q.out[0] = outspec(vl_n, st_sl, {1, 0}, 0, 1);
+    q.out[1] = outspec(vs_n, st_sl, {0, 1}, 0, 1);
+    q.out[2] = outspec(vs_t, st_sl, {0, 1}, 1, 1);
+    q.out[3] = outspec(vsum_t, st_sl, {1, 1}, 1, 1);
+    P.push_back(q);
+  }
+  const int s1_off = 0, s1_n = 2;
+  Prob quad = prob0();
+  quad.nA = 2; quad.nB = 2;
+  const int mtiles = tiles_of(quad, prec, n);
+  Prob single = prob0();
+  const int ftiles = tiles_of(single, prec, n);
+  double* mpart = (double*)S("c_mpart", 4 * mtiles * 8);
+  double* epart = (double*)S("c_epart", ftiles * 8);
+  double* coef = (double*)S("c_coef", kMaxAdd * 8);
+  // S2: M quad, W = V Gb (dual A), Z = Gb U (dual B)
+  {
+    Prob p = prob0();
+    p.nA = 2; p.nB = 2;
+    p.a[0] = opref(ul_n, 0, 0, st_sl);
+    p.a[1] = opref(us_n, 0, 0, st_sl);
+    p.b[0] = opref(xl + sb * ns, 0, vst);
+    p.b[1] = opref(xs + sb * ns, 0, vst);
+    p.nout = 8;
+    for (int x = 0; x < 4; ++x) {
+      p.out[x] = outspec(mst + x * sb, 4 * st_sl, {0, 0, 0, 0}, 0, 1);
+      p.out[x].coef[x] = 1.0f;
+    }
+    p.out[4] = outspec(mct + 0 * sb, 4 * st_sl, {0, 0, 0, -1}, 1, 1);
+    p.out[5] = outspec(mct + 1 * sb, 4 * st_sl, {0, 0, -1, -1}, 1, 1);
+    p.out[6] = outspec(mct + 2 * sb, 4 * st_sl, {0, -1, 0, -1}, 1, 1);
+    p.out[7] = outspec(mct + 3 * sb, 4 * st_sl, {-1, -1, -1, -1}, 1, 1);
+    p.nhad = 4;
+    p.had_h = opref(gb64, np2);
+    for (int x = 0; x < 4; ++x) {
+      for (int y = 0; y < 4; ++y) p.had_coef[x][y] = 0.0f;
+      p.had_coef[x][x] = 1.0f;
+    }
+    p.had_part = mpart;
+    p.had_ntiles = mtiles;
+    P.push_back(p);
+    Prob w = prob0();
+    w.nA = 2;
+    w.a[0] = opref(vl_n, 0, 0, st_sl);
+    w.a[1] = opref(vs_n, 0, 0, st_sl);
+    w.b[0] = opref(gbst, gstride);
+    w.nout = 2;
+    w.out[0] = outspec(wz + 0 * ab, 4 * ac_sl, {1, 0}, 0, 0);
+    w.out[1] = outspec(wz + 1 * ab, 4 * ac_sl, {0, 1}, 0, 0);
+    P.push_back(w);
+    Prob z = prob0();
+    z.nB = 2;
+    z.a[0] = opref(gbst, gstride);
+    z.b[0] = opref(ul_t, 0, 0, st_sl);
+    z.b[1] = opref(us_t, 0, 0, st_sl);
+    z.nout = 2;
+    z.out[0] = outspec(wz + 2 * ab, 4 * ac_sl, {1, 0}, 0, 0);
+    z.out[1] = outspec(wz + 3 * ab, 4 * ac_sl, {0, 1}, 0, 0);
+    P.push_back(z);
+  }
+  const int s2_off = 2, s2_n = 3;
+  // S3: T_xy = M_xy Gb
+  for (int h = 0; h < 2; ++h) {
+    Prob p = prob0();
+    p.nA = 2;
+    p.a[0] = opref(mst + (2 * h) * sb, 0, 0, 4 * st_sl);
+    p.a[1] = opref(mst + (2 * h + 1) * sb, 0, 0, 4 * st_sl);
+    p.b[0] = opref(gbst, gstride);
+    p.nout = 2;
+    p.out[0] = outspec(tq + (2 * h) * sb, 4 * st_sl, {1, 0}, 0, 1);
+    p.out[1] = outspec(tq + (2 * h + 1) * sb, 4 * st_sl, {0, 1}, 0, 1);
+    P.push_back(p);
+  }
+  const int s3_off = 5, s3_n = 2;
+  // S4: exchange + cross terms as one K-concatenated product, direct term
+  // and the energy trace in the epilogue
+  {
+    Prob p = prob0();
+    p.nseg = 8;
+    for (int x = 0; x < 4; ++x) {
+      p.a[x] = opref(tq + x * sb, 0, 0, 4 * st_sl);
+      p.b[x] = opref(mct + x * sb, 0, 0, 4 * st_sl);
+    }
+    p.a[4] = opref(jw_l, 0, 0, st_sl);   p.b[4] = opref(vs_t, 0, 0, st_sl);
+    p.a[5] = opref(jw_s, 0, 0, st_sl);   p.b[5] = opref(vsum_t, 0, 0, st_sl);
+    p.a[6] = opref(ul_n, 0, 0, st_sl);   p.b[6] = opref(jz_st, 0, 0, st_sl);
+    p.a[7] = opref(us_n, 0, 0, st_sl);   p.b[7] = opref(jz_sum_t, 0, 0, st_sl);
+    p.nadd = 4;
+    for (int x = 0; x < 4; ++x) p.add[x] = opref(mst + x * sb, 0, 0, 4 * st_sl);
+    p.add_coef = coef;
+    p.nout = 1;
+    p.out[0] = outspec(sig, ac_sl, {1}, 0, 0);
+    p.nhad = 1;
+    p.had_h = opref(gb64, np2);
+    p.had_coef[0][0] = 1.0f;
+    p.had_part = epart;
+    p.had_ntiles = ftiles;
+    P.push_back(p);
+  }
+  const int s4_off = 7;
+  auto* dprobs = (Prob*)ctx_buf(ctx, "c_probs", P.size() * sizeof(Prob));
+  h2d(ctx, dprobs, P.data(), P.size());
+
+  // ---- unit lists of all chunks
+  std::vector<Unit> uall;
+  std::vector<std::pair<int64_t, int64_t>> chunks;   // (offset, count)
+  std::vector<std::pair<int32_t, int32_t>> trange;
+  for (int64_t sbk = 0; sbk < ns; sbk += sc)
+    for (int64_t tb = 0; tb < ntau; tb += tcnt) {
+      const int64_t off0 = (int64_t)uall.size();
+      int32_t slot = 0;
+      const int64_t t1 = std::min(ntau, tb + tcnt), s1 = std::min(ns, sbk + sc);
+      for (int64_t t = tb; t < t1; ++t)
+        for (int64_t s = sbk; s < s1; ++s) uall.push_back(Unit{(int32_t)t, (int32_t)(s0 + s), slot++, 0});
+      chunks.push_back({off0, (int64_t)uall.size() - off0});
+      trange.push_back({(int32_t)tb, (int32_t)t1});
+    }
+  // the vector arrays are indexed by s - s0
+  for (auto& u : uall) u.s -= (int32_t)s0;
+  auto* dunits = (Unit*)ctx_buf(ctx, "c_units", uall.size() * sizeof(Unit));
+  h2d(ctx, dunits, uall.data(), uall.size());
+
+  auto stage = [&](int off, int cnt, const Unit* units, int nunit) {
+    int mt = 0;
+    for (int i = 0; i < cnt; ++i) mt = std::max(mt, tiles_of(P[off + i], prec, n));
+    GemmLaunch L = chain_launch(dprobs + off, cnt, units, nunit, n, np, plane);
+    launch_gemm(prec, L, mt, st);
+  };
+  for (size_t c = 0; c < chunks.size(); ++c) {
+    const Unit* du = dunits + chunks[c].first;
+    const int nu = (int)chunks[c].second;
+    stage(s1_off, s1_n, du, nu);
+    stage(s2_off, s2_n, du, nu);
+    launch_trace_coef(mpart, mtiles, (int32_t)slots, coef, st);
+    launch_jk_blocks(accf64, wz, 4 * ac_sl, ac_sl, np, naux, nu, sp->w, sp->idx,
+                     accf64 ? (const void*)sp->blk : (const void*)sp->blk32, jblk, st);
+    launch_jk_scatter(accf64, jblk, naux, nu, sp->npat, sp->pat_ij, sp->pat_off, sp->pat_q, np, prec, plane,
+                      jw_l, jw_s, jz_st, jz_sum_t, st_sl, st);
+    stage(s3_off, s3_n, du, nu);
+    stage(s4_off, 1, du, nu);
+    launch_accumulate(du, nu, sig, accf64, ac_sl, n, np, Sigma_sum, trange[c].first, trange[c].second, st);
+    if (e_samples) launch_esamples(du, nu, epart, ftiles, 0, ntau, e_samples, st);
+    GF2_HIP(hipGetLastError());
+  }
+  GF2_HIP(hipStreamSynchronize(st));
+}
+
+void check_sampling(const gf2_split_h* sp, const gf2_sampling* s) {
+  GF2_REQUIRE(s, GF2_E_ARG, "sampling is null");
+  GF2_REQUIRE(s->ns >= 1 && s->s0 >= 0 && s->s0 + s->ns <= (1 << 30), GF2_E_ARG, "bad ns / s0");
+  GF2_REQUIRE(s->mode == GF2_SAMPLE_RADEMACHER || s->mode == GF2_SAMPLE_IMPORTANCE, GF2_E_ARG, "bad mode");
+  if (s->mode == GF2_SAMPLE_IMPORTANCE) {
+    GF2_REQUIRE(s->k >= 1 && s->k <= 64, GF2_E_ARG, "k must be in [1, 64]");
+    GF2_REQUIRE(s->p, GF2_E_ARG, "importance mode needs p");
+    double tot = 0.0;
+    for (int64_t q = 0; q < sp->naux; ++q) {
+      GF2_REQUIRE(s->p[q] > 0 && std::isfinite(s->p[q]), GF2_E_ARG, "proposal must be positive");
+      tot += s->p[q];
+    }
+    GF2_REQUIRE(std::fabs(tot - 1.0) < 1e-6, GF2_E_ARG, "proposal must sum to 1");
+  }
+}
+
+}  // namespace
+
+gf2_status gf2_sigma_stoch(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const double* G,
+                           const double* Gbar, int64_t ntau, const gf2_sampling* sampling,
+                           gf2_precision prec, double* Sigma_sum, double* e_samples) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(split && split->owner == ctx, GF2_E_STATE, "split handle of another context");
+    GF2_REQUIRE(B == split->bsrc, GF2_E_STATE, "split handle belongs to a different B");
+    GF2_REQUIRE(G && Gbar && Sigma_sum && ntau > 0 && ntau <= 4096, GF2_E_ARG, "bad sigma arguments");
+    check_sampling(split, sampling);
+    run_stoch(ctx, split, B, G, Gbar, ntau, sampling, to_prec(prec), Sigma_sum, e_samples);
+  });
+}
+
+gf2_status gf2_sigma_finalize(gf2_ctx* ctx, int64_t n, int64_t ntau, const double* Sigma_det,
+                              const double* Sigma_sum, int64_t ns_total, double* Sigma) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(n > 0 && ntau > 0 && ns_total > 0 && Sigma_det && Sigma_sum && Sigma, GF2_E_ARG,
+                "bad finalize arguments");
+    launch_finalize(Sigma_det, Sigma_sum, n, ntau, 0.5 / (double)ns_total, Sigma, ctx->stream);
+    GF2_HIP(hipGetLastError());
+    check_finite(ctx, Sigma, ntau * n * n, "Sigma");
+  });
+}
+
+gf2_status gf2_sigma_tau(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const double* G,
+                         const double* Gbar, int64_t ntau, const gf2_sampling* sampling, gf2_precision prec,
+                         double* Sigma, double* e_samples) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(split && split->owner == ctx, GF2_E_STATE, "split handle of another context");
+    GF2_REQUIRE(B == split->bsrc, GF2_E_STATE, "split handle belongs to a different B");
+    GF2_REQUIRE(G && Gbar && Sigma && ntau > 0 && ntau <= 4096, GF2_E_ARG, "bad sigma arguments");
+    check_sampling(split, sampling);
+    const int64_t n = split->n;
+    const size_t bytes = (size_t)(ntau * n * n) * 8;
+    auto* det = (double*)ctx_buf(ctx, "t_det", bytes);
+    auto* sum = (double*)ctx_buf(ctx, "t_sum", bytes, true);
+    launch_dblock(G, Gbar, n, ntau, split->wmax, split->w, split->idx, split->blk, split->row_off,
+                  split->row_q, det, ctx->stream);
+    run_stoch(ctx, split, B, G, Gbar, ntau, sampling, to_prec(prec), sum, e_samples);
+    launch_finalize(det, sum, n, ntau, 0.5 / (double)sampling->ns, Sigma, ctx->stream);
+    GF2_HIP(hipGetLastError());
+    check_finite(ctx, Sigma, ntau * n * n, "Sigma");
+  });
+}
+
+// ------------------------------------------------------------ energy ------
+gf2_status gf2_energy(gf2_ctx* ctx, int64_t n, int64_t ntau, const double* w, const double* Sigma,
+                      const double* Gbar, const double* e_samples, int64_t ns, double n_elec, double* E_tot,
+                      double* E_per_e, double* stderr_tot) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(n > 0 && ntau > 0 && ntau <= 512 && w && Sigma && Gbar, GF2_E_ARG, "bad energy arguments");
+    GF2_REQUIRE(n_elec > 0, GF2_E_ARG, "n_elec must be positive");
+    GF2_REQUIRE(!e_samples || ns >= 2, GF2_E_ARG, "a standard error needs ns >= 2");
+    auto* tr = (double*)ctx_buf(ctx, "e_tr", (size_t)ntau * 8);
+    auto* dw = (double*)ctx_buf(ctx, "e_w", (size_t)ntau * 8);
+    auto* res = (double*)ctx_buf(ctx, "e_res", 4 * 8);
+    h2d(ctx, dw, w, (size_t)ntau);
+    launch_trace_prod(Sigma, Gbar, n, ntau, tr, ctx->stream);
+    launch_energy_stats(tr, dw, ntau, e_samples, e_samples ? ns : 0, kGM, res, ctx->stream);
+    GF2_HIP(hipGetLastError());
+    double h[4];
+    d2h(ctx, h, res, 3);
+    GF2_REQUIRE(std::isfinite(h[0]) && std::isfinite(h[2]), GF2_E_NUMERIC, "non-finite energy");
+    if (E_tot) *E_tot = h[0];
+    if (E_per_e) *E_per_e = h[0] / n_elec;
+    if (stderr_tot) *stderr_tot = h[2];
+  });
+}
+
+}  // extern "C"

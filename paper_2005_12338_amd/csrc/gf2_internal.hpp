@@ -1,0 +1,151 @@
+// Internal definitions shared by the HIP sources of libgf2 (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "gf2.h"
+
+// ---------------------------------------------------------------- errors --
+
+struct Gf2Error {
+  gf2_status code;
+  std::string msg;
+};
+
+#define GF2_HIP(call)                                                         \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      throw Gf2Error{GF2_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define GF2_REQUIRE(cond, code, what)                                         \
+  do {                                                                        \
+    if (!(cond)) throw Gf2Error{code, std::string(what)};                    \
+  } while (0)
+
+// ---------------------------------------------------------------- types ---
+
+typedef unsigned short bf16_t;   // raw bfloat16 bits
+
+enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2, BF16X3 = 3 };
+
+// Element counts are padded: every N x N matrix of the chain is stored as
+// np x np with np = pad_dim(n), zero outside [0,n) x [0,n).
+inline int64_t pad_dim(int64_t n) { return (n + 31) / 32 * 32; }
+
+// Address of an operand for one (tau, sample, slot) unit, in elements.
+struct OpRef {
+  const void* base;
+  int64_t st_tau, st_s, st_slot;
+};
+
+// One output of a GEMM tile: a combination of the nA x nB products written
+// to `base` in accumulator (type 0) or storage (type 1) format, row-major
+// (layout 0) or transposed (layout 1).
+struct OutSpec {
+  void* base;
+  int64_t st_tau, st_s, st_slot;
+  float coef[4];
+  int32_t layout;
+  int32_t type;
+};
+
+constexpr int kMaxSeg = 8;
+constexpr int kMaxOut = 8;
+constexpr int kMaxHad = 4;
+constexpr int kMaxAdd = 4;
+
+// One GEMM sub-problem per unit.  nA = nB = 1 with nseg K-segments
+// (C = sum_s A_s B_s^T), or nseg = 1 with nA, nB in {1, 2}: the tile holds
+// the products A_a B_b for every pair (a, b).
+struct Prob {
+  int32_t nseg, nA, nB, nout, nhad, nadd;
+  OpRef a[kMaxSeg];
+  OpRef b[kMaxSeg];
+  OutSpec out[kMaxOut];
+  // Hadamard partial sums: part[(slot*nhad + h)*ntiles + tile] =
+  //   sum over the tile of (sum_ab had_coef[h][ab] P_ab)_ij * H_ij.
+  OpRef had_h;              // FP64 np x np
+  float had_coef[kMaxHad][4];
+  double* had_part;
+  int64_t had_ntiles;
+  // Addends (nA = nB = 1 only): P += sum_x add_coef[slot][x] * Add_x (storage
+  // format, row-major).
+  OpRef add[kMaxAdd];
+  const double* add_coef;   // [slot][kMaxAdd]
+};
+
+struct Unit {
+  int32_t tau, s, slot, pad;
+};
+
+// C (m x nc) = sum_s A_s (m x k, leading dim ld) B_s^T (nc x k, leading dim
+// ld); outputs use leading dim ld as well.  k must be a multiple of 8 and
+// the operands zero beyond their logical extent in k.
+struct GemmLaunch {
+  const Prob* probs;    // device
+  int32_t nprob;
+  const Unit* units;    // device
+  int32_t nunit;
+  int64_t m, nc, k;     // rows of C, columns of C, reduction length
+  int64_t ld;           // leading dimension of every operand and output
+  int64_t plane;        // element stride of the lo plane (BF16X3)
+};
+
+// Kernel launchers (device code in separate translation units).
+void launch_gemm(Prec p, const GemmLaunch& L, int max_tiles, hipStream_t st);
+// Chain launch: square n x n products stored with leading dimension np.
+inline GemmLaunch chain_launch(const Prob* probs, int nprob, const Unit* units, int nunit, int64_t n,
+                               int64_t np, int64_t plane) {
+  return GemmLaunch{probs, nprob, units, nunit, n, n, np, np, plane};
+}
+int gemm_tile_m(Prec p);     // BM
+int gemm_tile_n(Prec p);     // BN
+
+// ---------------------------------------------------------------- context -
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct gf2_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::vector<DevBuf> pool;       // scratch allocations owned by the context
+  int64_t max_units = 0;          // chunk size tuning (0 = automatic)
+  std::string chain_key;          // (n, np, precision) of the last chain layout
+};
+
+struct gf2_split_h {
+  gf2_ctx* owner = nullptr;
+  const void* bsrc = nullptr;
+  gf2_dtype dtype = GF2_F64;
+  int64_t n = 0, naux = 0, np = 0;
+  double eps = 0.0, kmax = 0.0, thresh = 0.0;
+  int64_t nnz = 0;
+  int32_t wmax = 0;
+  // device arrays
+  int32_t* w = nullptr;        // [naux]
+  int32_t* idx = nullptr;      // [naux][32], -1 padded
+  double* blk = nullptr;       // [naux][32][32]
+  float* blk32 = nullptr;      // same in FP32
+  // union pattern of the blocks: for every nonzero (i, j) of
+  // U_Q S_Q x S_Q (sorted row-major) the list of contributing (Q, a, b).
+  int64_t npat = 0;
+  int32_t* pat_ij = nullptr;   // [npat] i * np + j
+  int32_t* pat_off = nullptr;  // [npat + 1]
+  int32_t* pat_q = nullptr;    // [ncontrib] Q * 1024 + a * 32 + b
+  int64_t ncontrib = 0;
+  // rows: for each orbital i the (Q, a) with S_Q[a] = i
+  int32_t* row_off = nullptr;  // [n + 1]
+  int32_t* row_q = nullptr;    // [..] Q * 32 + a
+};
+
+constexpr int kWMax = 32;

@@ -1,0 +1,618 @@
+// Bandwidth-bound and small-block kernels of the RS-SRI-GF2 hot path:
+// synthetic factors, the range-separation scans, stochastic-vector builds,
+// the block-sparse Coulomb/exchange map JK, reductions and the energy.
+#include "kernels.hpp"
+
+namespace {
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z ^= z >> 30; z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27; z *= 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return z;
+}
+
+__device__ __forceinline__ bf16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (bf16_t)0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// Write v to a padded matrix in storage format `p` (planes at +plane).
+__device__ __forceinline__ void put_st(void* base, int64_t i, int64_t plane, Prec p, double v) {
+  switch (p) {
+    case Prec::F64: ((double*)base)[i] = v; break;
+    case Prec::F32: ((float*)base)[i] = (float)v; break;
+    case Prec::BF16: ((bf16_t*)base)[i] = f2bf((float)v); break;
+    case Prec::BF16X3: {
+      float f = (float)v;
+      bf16_t hi = f2bf(f);
+      ((bf16_t*)base)[i] = hi;
+      ((bf16_t*)base)[i + plane] = f2bf(f - bf2f(hi));
+    } break;
+  }
+}
+__device__ __forceinline__ double get_acc(const void* base, int64_t i, bool f64) {
+  return f64 ? ((const double*)base)[i] : (double)((const float*)base)[i];
+}
+
+// ------------------------------------------------------------- RNG words --
+__global__ void k_rng_words(uint64_t seed, uint32_t stream, uint32_t s, uint32_t q0,
+                            int64_t count, uint64_t* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  uint64_t ctr = ((uint64_t)stream << 62) | ((uint64_t)s << 32) | (uint64_t)(q0 + (uint32_t)i);
+  out[i] = mix64(seed * 0x9E3779B97F4A7C15ull + ctr + 1ull);
+}
+
+// theta[v][Q] = +-1 for vector v = (stream, s0 + s) with stream = v / ns.
+__global__ void k_theta(uint64_t seed, int64_t ns, int64_t s0, int64_t naux, int8_t* theta) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t total = 2 * ns * naux;
+  if (i >= total) return;
+  int64_t v = i / naux, q = i % naux;
+  uint64_t stream = (uint64_t)(v / ns), s = (uint64_t)(s0 + v % ns);
+  uint64_t ctr = (stream << 62) | (s << 32) | (uint64_t)q;
+  uint64_t w = mix64(seed * 0x9E3779B97F4A7C15ull + ctr + 1ull);
+  theta[i] = (w >> 63) ? (int8_t)-1 : (int8_t)1;
+}
+
+// Importance draws: for vector v (stream v / ns, sample s0 + v % ns) and
+// draw j: u from q = 2j, sign from q = 2j + 1; Q = min{i : u < cdf[i]}.
+__global__ void k_draws(uint64_t seed, int64_t ns, int64_t s0, int32_t k, const double* cdf,
+                        int64_t naux, const double* p, int32_t* qout, double* wout) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * ns * k) return;
+  int64_t v = i / k;
+  uint64_t j = (uint64_t)(i % k);
+  uint64_t stream = (uint64_t)(v / ns), s = (uint64_t)(s0 + v % ns);
+  uint64_t base = seed * 0x9E3779B97F4A7C15ull + ((stream << 62) | (s << 32)) + 1ull;
+  uint64_t wu = mix64(base + 2 * j);
+  uint64_t ws = mix64(base + 2 * j + 1);
+  double u = (double)(wu >> 11) * 0x1.0p-53;
+  int64_t lo = 0, hi = naux - 1;            // smallest index with u < cdf[index]
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (u < cdf[mid]) hi = mid; else lo = mid + 1;
+  }
+  qout[i] = (int32_t)lo;
+  double sg = (ws >> 63) ? -1.0 : 1.0;
+  wout[i] = sg / sqrt((double)k * p[lo]);
+}
+
+// ------------------------------------------------------------- B build ----
+__global__ void k_synth_b(int64_t n, int64_t naux, const double* x, const double* xq,
+                          double amp, double a, double c, void* out, int f64) {
+  int64_t total = naux * n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t q = e / (n * n), ij = e % (n * n), i = ij / n, j = ij % n;
+    double d = x[i] - x[j];
+    double m = xq[q] - 0.5 * (x[i] + x[j]);
+    double v = amp * exp(-a * d * d) * exp(-c * m * m);
+    if (f64) ((double*)out)[e] = v; else ((float*)out)[e] = (float)v;
+  }
+}
+
+// ------------------------------------------------------------- split ------
+__global__ void k_maxabs(const void* b, int f64, int64_t total, double* part) {
+  __shared__ double sm[256];
+  double m = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x)
+    m = fmax(m, fabs(get_acc(b, e, f64)));
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + d]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+// One wave per (Q, i): flag rows with a kept element, count kept elements.
+__global__ void k_rowflags(const void* b, int f64, int64_t n, int64_t naux, double thr,
+                           uint8_t* flags, unsigned long long* nnz) {
+  int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int lane = threadIdx.x & 63;
+  if (wid >= naux * n) return;
+  const int64_t base = wid * n;
+  int cnt = 0;
+  for (int64_t j = lane; j < n; j += 64) cnt += fabs(get_acc(b, base + j, f64)) >= thr ? 1 : 0;
+  for (int d = 32; d > 0; d >>= 1) cnt += __shfl_down(cnt, d, 64);
+  if (lane == 0) {
+    flags[wid] = cnt > 0;
+    if (cnt) atomicAdd(nnz, (unsigned long long)cnt);
+  }
+}
+
+__global__ void k_extract_blocks(const void* b, int f64, int64_t n, int64_t naux, double thr,
+                                 const int32_t* w, const int32_t* idx, double* blk, float* blk32) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= naux * kWMax * kWMax) return;
+  int64_t q = e / (kWMax * kWMax);
+  int r = (int)((e / kWMax) % kWMax), c = (int)(e % kWMax);
+  double v = 0.0;
+  if (r < w[q] && c < w[q]) {
+    int64_t i = idx[q * kWMax + r], j = idx[q * kWMax + c];
+    double x = get_acc(b, (q * n + i) * n + j, f64);
+    v = fabs(x) >= thr ? x : 0.0;
+  }
+  blk[e] = v;
+  blk32[e] = (float)v;
+}
+
+// ------------------------------------------------------------- R build ----
+// Dense pass over B for a batch of vectors: X_L = sum_Q theta_Q K^L_Q and
+// X_S = sum_Q theta_Q (B_Q - K^L_Q) (elements below the threshold), written
+// to padded storage.  One thread per (i, j) and RV vectors; theta staged in
+// LDS per chunk of Q.
+template <int RV, typename T>
+__global__ __launch_bounds__(256) void k_rbuild(const void* b, int f64, int64_t n, int64_t naux,
+                                                 double thr, const int8_t* theta, int64_t nvec,
+                                                 int64_t v0, Prec prec, void* xl, void* xs,
+                                                 int64_t np, int64_t plane, int64_t mstride) {
+  constexpr int QC = 64;
+  __shared__ T th[RV][QC];
+  const int64_t ij = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t vb = v0 + (int64_t)blockIdx.y * RV;
+  const bool ok = ij < n * n;
+  T al[RV], as[RV];
+#pragma unroll
+  for (int r = 0; r < RV; ++r) { al[r] = 0; as[r] = 0; }
+  for (int64_t q0 = 0; q0 < naux; q0 += QC) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < RV * QC; e += blockDim.x) {
+      int r = e / QC, qq = e % QC;
+      int64_t v = vb + r, q = q0 + qq;
+      th[r][qq] = (v < nvec && q < naux) ? (T)theta[v * naux + q] : (T)0;
+    }
+    __syncthreads();
+    if (ok) {
+      const int qe = (int)((naux - q0) < QC ? (naux - q0) : QC);
+      for (int qq = 0; qq < qe; ++qq) {
+        T x = f64 ? (T)((const double*)b)[(q0 + qq) * n * n + ij]
+                  : (T)((const float*)b)[(q0 + qq) * n * n + ij];
+        T sx = fabs((double)x) >= thr ? (T)0 : x;
+        T lx = x - sx;
+#pragma unroll
+        for (int r = 0; r < RV; ++r) {
+          al[r] += th[r][qq] * lx;
+          as[r] += th[r][qq] * sx;
+        }
+      }
+    }
+  }
+  if (!ok) return;
+  const int64_t i = ij / n, j = ij % n;
+#pragma unroll
+  for (int r = 0; r < RV; ++r) {
+    int64_t v = vb + r;
+    if (v >= nvec) break;
+    int64_t o = v * mstride + i * np + j;
+    put_st(xl, o, plane, prec, (double)al[r]);
+    put_st(xs, o, plane, prec, (double)as[r]);
+  }
+}
+
+// Importance vectors: X = sum_j wgt_j B_{Q_j} split into L and S parts.
+__global__ void k_rimportance(const void* b, int f64, int64_t n, double thr, const int32_t* q,
+                              const double* wgt, int32_t k, int64_t nvec, Prec prec, void* xl,
+                              void* xs, int64_t np, int64_t plane, int64_t mstride) {
+  const int64_t ij = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t v = blockIdx.y;
+  if (ij >= n * n || v >= nvec) return;
+  double al = 0.0, as = 0.0;
+  for (int j = 0; j < k; ++j) {
+    int64_t qq = q[v * k + j];
+    double x = get_acc(b, qq * n * n + ij, f64);
+    double sx = fabs(x) >= thr ? 0.0 : x;
+    al += wgt[v * k + j] * (x - sx);
+    as += wgt[v * k + j] * sx;
+  }
+  const int64_t i = ij / n, jj = ij % n;
+  int64_t o = v * mstride + i * np + jj;
+  put_st(xl, o, plane, prec, al);
+  put_st(xs, o, plane, prec, as);
+}
+
+// ------------------------------------------------------------- G ----------
+// A[t][i][k] = C[i][k] * exp(lw[t][k]) (padded), the left factor of
+// G = -C diag(weights) C^T.
+__global__ void k_scale_cols(const double* c, const double* lw, int64_t n, int64_t np,
+                             int64_t ntau, double* out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ntau * np * np) return;
+  int64_t t = e / (np * np), ik = e % (np * np), i = ik / np, k = ik % np;
+  double v = 0.0;
+  if (i < n && k < n) v = c[i * n + k] * exp(lw[t * n + k]);
+  out[e] = v;
+}
+
+// out[t] (n x n) = (P[t] + P[t]^T) / 2 * sign from padded P.
+__global__ void k_unpad_sym(const double* p, int64_t n, int64_t np, int64_t ntau, double sign,
+                            double* out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ntau * n * n) return;
+  int64_t t = e / (n * n), ij = e % (n * n), i = ij / n, j = ij % n;
+  const double* pt = p + t * np * np;
+  out[e] = sign * 0.5 * (pt[i * np + j] + pt[j * np + i]);
+}
+
+// Padded copies of G(tau) in storage format and FP64.
+__global__ void k_pad_convert(const double* g, int64_t n, int64_t np, int64_t ntau, Prec prec,
+                              void* st, int64_t plane, int64_t mstride, double* f64pad) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ntau * np * np) return;
+  int64_t t = e / (np * np), ij = e % (np * np), i = ij / np, j = ij % np;
+  double v = (i < n && j < n) ? g[(t * n + i) * n + j] : 0.0;
+  put_st(st, t * mstride + ij, plane, prec, v);
+  if (f64pad) f64pad[e] = v;
+}
+
+// ------------------------------------------------------------- JK ---------
+// For every (slot, m in 0..3, Q): J = 2 Tr(k W_SS) k - k W_SS k with W the
+// m-th matrix of the slot (accumulator format, row-major padded).  One wave
+// per (slot, m, Q); lanes walk the w x w block elements.
+template <typename T>
+__global__ __launch_bounds__(256) void k_jk_blocks(const void* wbase, int64_t w_st_slot,
+                                                    int64_t w_st_m, int64_t np, int64_t naux,
+                                                    int32_t nslot, const int32_t* wq,
+                                                    const int32_t* idx, const T* blk, T* jout) {
+  __shared__ T sk[4][kWMax * kWMax];
+  __shared__ T sw[4][kWMax * kWMax];
+  __shared__ T st[4][kWMax * kWMax];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t task = (int64_t)blockIdx.x * 4 + wv;
+  const int64_t total = (int64_t)nslot * 4 * naux;
+  const bool active = task < total;               // every wave reaches the barriers
+  const int64_t tk = active ? task : 0;
+  const int64_t q = tk % naux;
+  const int64_t m = (tk / naux) % 4;
+  const int64_t slot = tk / (naux * 4);
+  const int w = active ? wq[q] : 0;
+  T* out = jout + tk * kWMax * kWMax;
+  const T* W = (const T*)wbase + slot * w_st_slot + m * w_st_m;
+  const int32_t* s = idx + q * kWMax;
+  const int ww = w * w;
+  for (int e = lane; e < ww; e += 64) {
+    int a = e / w, c = e % w;
+    sk[wv][e] = blk[q * kWMax * kWMax + a * kWMax + c];
+    sw[wv][e] = W[(int64_t)s[a] * np + s[c]];
+  }
+  __syncthreads();
+  // t = Tr(k W) = sum_ab k_ab W_ba
+  T tr = 0;
+  for (int e = lane; e < ww; e += 64) {
+    int a = e / w, c = e % w;
+    tr += sk[wv][e] * sw[wv][c * w + a];
+  }
+  for (int d = 32; d > 0; d >>= 1) tr += __shfl_xor(tr, d, 64);
+  for (int e = lane; e < ww; e += 64) {
+    int a = e / w, c = e % w;
+    T acc = 0;
+    for (int x = 0; x < w; ++x) acc += sk[wv][a * w + x] * sw[wv][x * w + c];
+    st[wv][e] = acc;
+  }
+  __syncthreads();
+  for (int e = lane; e < ww; e += 64) {
+    int a = e / w, c = e % w;
+    T acc = 0;
+    for (int x = 0; x < w; ++x) acc += st[wv][a * w + x] * sk[wv][x * w + c];
+    out[a * kWMax + c] = 2 * tr * sk[wv][e] - acc;
+  }
+}
+
+// Scatter the J blocks onto the union pattern: for every pattern entry (i,j)
+// sum the contributions in their fixed order.  m = 0, 1 (W_L, W_S) go to
+// row-major outputs; m = 2, 3 (Z_L, Z_S) to transposed outputs, with the
+// second transposed output holding J(Z_L) + J(Z_S).
+template <typename T>
+__global__ void k_jk_scatter(const T* jblk, int64_t naux, int32_t nslot, int64_t npat,
+                             const int32_t* pat_ij, const int32_t* pat_off, const int32_t* pat_q,
+                             int64_t np, Prec prec, int64_t plane, void* jw_l, void* jw_s,
+                             void* jz_st, void* jz_sum_t, int64_t out_st_slot) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)nslot * npat) return;
+  int64_t slot = e / npat, p = e % npat;
+  int64_t ij = pat_ij[p], i = ij / np, j = ij % np;
+  double v[4] = {0, 0, 0, 0};
+  for (int m = 0; m < 4; ++m) {
+    const T* jb = jblk + ((slot * 4 + m) * naux) * kWMax * kWMax;
+    double acc = 0.0;
+    for (int c = pat_off[p]; c < pat_off[p + 1]; ++c) {
+      int32_t code = pat_q[c];
+      int64_t q = code >> 10;
+      int a = (code >> 5) & 31, b = code & 31;
+      acc += (double)jb[q * kWMax * kWMax + a * kWMax + b];
+    }
+    v[m] = acc;
+  }
+  int64_t o = slot * out_st_slot;
+  put_st(jw_l, o + i * np + j, plane, prec, v[0]);
+  put_st(jw_s, o + i * np + j, plane, prec, v[1]);
+  put_st(jz_st, o + j * np + i, plane, prec, v[3]);
+  put_st(jz_sum_t, o + j * np + i, plane, prec, v[2] + v[3]);
+}
+
+// ------------------------------------------------------------- reductions -
+// Direct-term coefficients from the Hadamard partials c_xy = Tr(M_xy Gb):
+// coef = 2 (c_SS, c_SL + c_SS, c_LS + c_SS, c_LL + c_LS + c_SL + c_SS).
+__global__ void k_trace_coef(const double* part, int64_t ntiles, int32_t nslot, double* coef) {
+  int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nslot) return;
+  double c[4];
+  for (int h = 0; h < 4; ++h) {
+    double s = 0.0;
+    const double* p = part + ((int64_t)slot * 4 + h) * ntiles;
+    for (int64_t t = 0; t < ntiles; ++t) s += p[t];
+    c[h] = s;
+  }
+  double* o = coef + (int64_t)slot * kMaxAdd;
+  o[0] = 2.0 * c[3];
+  o[1] = 2.0 * (c[2] + c[3]);
+  o[2] = 2.0 * (c[1] + c[3]);
+  o[3] = 2.0 * (c[0] + c[1] + c[2] + c[3]);
+}
+
+// Sigma_sum[tau] += sum of the chunk's Sigma_s in unit order; e_s(tau) from
+// the per-tile partials.  One thread per (tau-group, i, j).
+__global__ void k_accumulate(const Unit* units, int32_t nunit, const void* sig, int f64,
+                             int64_t sig_st_slot, int64_t n, int64_t np, double* sum,
+                             int32_t tau_lo, int32_t tau_hi) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t ntau = tau_hi - tau_lo;
+  if (e >= ntau * n * n) return;
+  int32_t t = tau_lo + (int32_t)(e / (n * n));
+  int64_t ij = e % (n * n), i = ij / n, j = ij % n;
+  double acc = sum[(int64_t)t * n * n + ij];
+  for (int u = 0; u < nunit; ++u) {
+    if (units[u].tau != t) continue;
+    acc += get_acc(sig, (int64_t)units[u].slot * sig_st_slot + i * np + j, f64);
+  }
+  sum[(int64_t)t * n * n + ij] = acc;
+}
+
+__global__ void k_esamples(const Unit* units, int32_t nunit, const double* part, int64_t ntiles,
+                           int64_t s0, int64_t ntau, double* es) {
+  int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= nunit) return;
+  const double* p = part + (int64_t)units[u].slot * ntiles;
+  double s = 0.0;
+  for (int64_t t = 0; t < ntiles; ++t) s += p[t];
+  es[((int64_t)units[u].s - s0) * ntau + units[u].tau] = s;
+}
+
+__global__ void k_finalize(const double* det, const double* sum, int64_t n, int64_t ntau,
+                           double inv2ns, double* out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ntau * n * n) return;
+  int64_t t = e / (n * n), ij = e % (n * n), i = ij / n, j = ij % n;
+  const double* s = sum + t * n * n;
+  out[e] = det[e] + inv2ns * (s[i * n + j] + s[j * n + i]);
+}
+
+// ------------------------------------------------------------- energy -----
+// tr[t] = sum_ij Sigma[t]_ij Gbar[t]_ji: one block per tau, fixed-order tree.
+__global__ void k_trace_prod(const double* sig, const double* gb, int64_t n, double* tr) {
+  __shared__ double sm[256];
+  const int64_t t = blockIdx.x;
+  const double* s = sig + t * n * n;
+  const double* g = gb + t * n * n;
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < n * n; e += blockDim.x) {
+    int64_t i = e / n, j = e % n;
+    acc += s[e] * g[j * n + i];
+  }
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) sm[threadIdx.x] += sm[threadIdx.x + d];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tr[t] = sm[0];
+}
+
+// out[0] = E_tot, out[1] = mean_s E_s - E_tot (~0), out[2] = stderr.
+__global__ void k_energy_stats(const double* tr, const double* w, int64_t ntau, const double* es,
+                               int64_t ns, double gm, double* out) {
+  __shared__ double sm[256];
+  __shared__ double ebar[512];
+  __shared__ double etot_s;
+  if (threadIdx.x == 0) {
+    double e = 0.0;
+    for (int64_t t = 0; t < ntau; ++t) e += w[t] * tr[t];
+    etot_s = -gm * e;
+  }
+  // mean over samples of e_s(tau), per tau (tau <= 512 handled in shared)
+  for (int64_t t = threadIdx.x; t < ntau && t < 512; t += blockDim.x) {
+    double m = 0.0;
+    for (int64_t s = 0; s < ns; ++s) m += es ? es[s * ntau + t] : 0.0;
+    ebar[t] = ns ? m / (double)ns : 0.0;
+  }
+  __syncthreads();
+  const double etot = etot_s;
+  double acc = 0.0, acc2 = 0.0;
+  for (int64_t s = threadIdx.x; s < ns && es; s += blockDim.x) {
+    double d = 0.0;
+    for (int64_t t = 0; t < ntau; ++t) d += w[t] * (es[s * ntau + t] - ebar[t]);
+    double e_s = etot - gm * d;
+    acc += e_s - etot;
+    acc2 += (e_s - etot) * (e_s - etot);
+  }
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) sm[threadIdx.x] += sm[threadIdx.x + d];
+    __syncthreads();
+  }
+  double sum1 = sm[0];
+  __syncthreads();
+  sm[threadIdx.x] = acc2;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) sm[threadIdx.x] += sm[threadIdx.x + d];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = etot;
+    out[1] = ns ? sum1 / (double)ns : 0.0;
+    double var = ns > 1 ? (sm[0] - sum1 * sum1 / (double)ns) / (double)(ns - 1) : 0.0;
+    out[2] = ns > 1 ? sqrt(fmax(var, 0.0) / (double)ns) : 0.0;
+  }
+}
+
+__global__ void k_count_nonfinite(const double* x, int64_t count, unsigned long long* bad) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count && !isfinite(x[e])) atomicAdd(bad, 1ull);
+}
+
+// dst[c * ld + r] = src[r][c] (src rows x cols, FP64 or FP32) into FP64.
+__global__ void k_transpose(const void* src, int f64, int64_t rows, int64_t cols, double* dst, int64_t ld) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  int64_t r = e / cols, c = e % cols;
+  dst[c * ld + r] = get_acc(src, e, f64);
+}
+// dst[c][r] = src[r * ld + c] for r < rows, c < cols (dst cols x rows).
+__global__ void k_untranspose(const double* src, int64_t rows, int64_t cols, int64_t ld, void* dst, int f64) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  int64_t c = e / rows, r = e % rows;
+  double v = src[r * ld + c];
+  if (f64) ((double*)dst)[e] = v; else ((float*)dst)[e] = (float)v;
+}
+
+inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers --
+
+void launch_rng_words(uint64_t seed, uint32_t stream, uint32_t s, uint32_t q0, int64_t count,
+                      uint64_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_rng_words, dim3(blocks(count)), dim3(256), 0, st, seed, stream, s, q0, count, out);
+}
+void launch_theta(uint64_t seed, int64_t ns, int64_t s0, int64_t naux, int8_t* theta, hipStream_t st) {
+  hipLaunchKernelGGL(k_theta, dim3(blocks(2 * ns * naux)), dim3(256), 0, st, seed, ns, s0, naux, theta);
+}
+void launch_draws(uint64_t seed, int64_t ns, int64_t s0, int32_t k, const double* cdf, int64_t naux,
+                  const double* p, int32_t* q, double* w, hipStream_t st) {
+  hipLaunchKernelGGL(k_draws, dim3(blocks(2 * ns * k)), dim3(256), 0, st, seed, ns, s0, k, cdf, naux, p, q, w);
+}
+void launch_synth_b(int64_t n, int64_t naux, const double* x, const double* xq, double amp, double a,
+                    double c, void* out, bool f64, hipStream_t st) {
+  int64_t total = naux * n * n;
+  unsigned g = (unsigned)std::min<int64_t>(blocks(total), 65536 * 4);
+  hipLaunchKernelGGL(k_synth_b, dim3(g), dim3(256), 0, st, n, naux, x, xq, amp, a, c, out, (int)f64);
+}
+void launch_maxabs(const void* b, bool f64, int64_t total, double* part, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_maxabs, dim3(nblk), dim3(256), 0, st, b, (int)f64, total, part);
+}
+void launch_rowflags(const void* b, bool f64, int64_t n, int64_t naux, double thr, uint8_t* flags,
+                     unsigned long long* nnz, hipStream_t st) {
+  int64_t waves = naux * n;
+  hipLaunchKernelGGL(k_rowflags, dim3(blocks(waves * 64)), dim3(256), 0, st, b, (int)f64, n, naux, thr, flags, nnz);
+}
+void launch_extract_blocks(const void* b, bool f64, int64_t n, int64_t naux, double thr,
+                           const int32_t* w, const int32_t* idx, double* blk, float* blk32,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_extract_blocks, dim3(blocks(naux * kWMax * kWMax)), dim3(256), 0, st, b,
+                     (int)f64, n, naux, thr, w, idx, blk, blk32);
+}
+void launch_rbuild(const void* b, bool f64, int64_t n, int64_t naux, double thr, const int8_t* theta,
+                   int64_t nvec, Prec prec, void* xl, void* xs, int64_t np, int64_t plane,
+                   int64_t mstride, hipStream_t st) {
+  constexpr int RV = 8;
+  dim3 grid(blocks(n * n), (unsigned)((nvec + RV - 1) / RV));
+  if (prec == Prec::F64)
+    hipLaunchKernelGGL((k_rbuild<RV, double>), grid, dim3(256), 0, st, b, (int)f64, n, naux, thr,
+                       theta, nvec, (int64_t)0, prec, xl, xs, np, plane, mstride);
+  else
+    hipLaunchKernelGGL((k_rbuild<RV, float>), grid, dim3(256), 0, st, b, (int)f64, n, naux, thr,
+                       theta, nvec, (int64_t)0, prec, xl, xs, np, plane, mstride);
+}
+void launch_rimportance(const void* b, bool f64, int64_t n, double thr, const int32_t* q,
+                        const double* w, int32_t k, int64_t nvec, Prec prec, void* xl, void* xs,
+                        int64_t np, int64_t plane, int64_t mstride, hipStream_t st) {
+  dim3 grid(blocks(n * n), (unsigned)nvec);
+  hipLaunchKernelGGL(k_rimportance, grid, dim3(256), 0, st, b, (int)f64, n, thr, q, w, k, nvec, prec,
+                     xl, xs, np, plane, mstride);
+}
+void launch_scale_cols(const double* c, const double* lw, int64_t n, int64_t np, int64_t ntau,
+                       double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_cols, dim3(blocks(ntau * np * np)), dim3(256), 0, st, c, lw, n, np, ntau, out);
+}
+void launch_unpad_sym(const double* p, int64_t n, int64_t np, int64_t ntau, double sign, double* out,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_unpad_sym, dim3(blocks(ntau * n * n)), dim3(256), 0, st, p, n, np, ntau, sign, out);
+}
+void launch_pad_convert(const double* g, int64_t n, int64_t np, int64_t ntau, Prec prec, void* stbuf,
+                        int64_t plane, int64_t mstride, double* f64pad, hipStream_t st) {
+  hipLaunchKernelGGL(k_pad_convert, dim3(blocks(ntau * np * np)), dim3(256), 0, st, g, n, np, ntau,
+                     prec, stbuf, plane, mstride, f64pad);
+}
+void launch_jk_blocks(bool f64, const void* wbase, int64_t w_st_slot, int64_t w_st_m, int64_t np,
+                      int64_t naux, int32_t nslot, const int32_t* wq, const int32_t* idx,
+                      const void* blk, void* jout, hipStream_t st) {
+  int64_t tasks = (int64_t)nslot * 4 * naux;
+  dim3 grid((unsigned)((tasks + 3) / 4));
+  if (f64)
+    hipLaunchKernelGGL((k_jk_blocks<double>), grid, dim3(256), 0, st, wbase, w_st_slot, w_st_m, np,
+                       naux, nslot, wq, idx, (const double*)blk, (double*)jout);
+  else
+    hipLaunchKernelGGL((k_jk_blocks<float>), grid, dim3(256), 0, st, wbase, w_st_slot, w_st_m, np,
+                       naux, nslot, wq, idx, (const float*)blk, (float*)jout);
+}
+void launch_jk_scatter(bool f64, const void* jblk, int64_t naux, int32_t nslot, int64_t npat,
+                       const int32_t* pat_ij, const int32_t* pat_off, const int32_t* pat_q, int64_t np,
+                       Prec prec, int64_t plane, void* jw_l, void* jw_s, void* jz_st, void* jz_sum_t,
+                       int64_t out_st_slot, hipStream_t st) {
+  dim3 grid(blocks((int64_t)nslot * npat));
+  if (f64)
+    hipLaunchKernelGGL((k_jk_scatter<double>), grid, dim3(256), 0, st, (const double*)jblk, naux, nslot,
+                       npat, pat_ij, pat_off, pat_q, np, prec, plane, jw_l, jw_s, jz_st, jz_sum_t,
+                       out_st_slot);
+  else
+    hipLaunchKernelGGL((k_jk_scatter<float>), grid, dim3(256), 0, st, (const float*)jblk, naux, nslot,
+                       npat, pat_ij, pat_off, pat_q, np, prec, plane, jw_l, jw_s, jz_st, jz_sum_t,
+                       out_st_slot);
+}
+void launch_trace_coef(const double* part, int64_t ntiles, int32_t nslot, double* coef, hipStream_t st) {
+  hipLaunchKernelGGL(k_trace_coef, dim3(blocks(nslot, 64)), dim3(64), 0, st, part, ntiles, nslot, coef);
+}
+void launch_accumulate(const Unit* units, int32_t nunit, const void* sig, bool f64, int64_t sig_st_slot,
+                       int64_t n, int64_t np, double* sum, int32_t tau_lo, int32_t tau_hi, hipStream_t st) {
+  int64_t total = (int64_t)(tau_hi - tau_lo) * n * n;
+  hipLaunchKernelGGL(k_accumulate, dim3(blocks(total)), dim3(256), 0, st, units, nunit, sig, (int)f64,
+                     sig_st_slot, n, np, sum, tau_lo, tau_hi);
+}
+void launch_esamples(const Unit* units, int32_t nunit, const double* part, int64_t ntiles, int64_t s0,
+                     int64_t ntau, double* es, hipStream_t st) {
+  hipLaunchKernelGGL(k_esamples, dim3(blocks(nunit, 64)), dim3(64), 0, st, units, nunit, part, ntiles, s0, ntau, es);
+}
+void launch_finalize(const double* det, const double* sum, int64_t n, int64_t ntau, double inv2ns,
+                     double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(blocks(ntau * n * n)), dim3(256), 0, st, det, sum, n, ntau, inv2ns, out);
+}
+void launch_trace_prod(const double* sig, const double* gb, int64_t n, int64_t ntau, double* tr,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_trace_prod, dim3((unsigned)ntau), dim3(256), 0, st, sig, gb, n, tr);
+}
+void launch_energy_stats(const double* tr, const double* w, int64_t ntau, const double* es, int64_t ns,
+                         double gm, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_stats, dim3(1), dim3(256), 0, st, tr, w, ntau, es, ns, gm, out);
+}
+void launch_transpose(const void* src, bool f64, int64_t rows, int64_t cols, double* dst, int64_t ld,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_transpose, dim3(blocks(rows * cols)), dim3(256), 0, st, src, (int)f64, rows, cols, dst, ld);
+}
+void launch_untranspose(const double* src, int64_t rows, int64_t cols, int64_t ld, void* dst, bool f64,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_untranspose, dim3(blocks(rows * cols)), dim3(256), 0, st, src, rows, cols, ld, dst, (int)f64);
+}
+void launch_count_nonfinite(const double* x, int64_t count, unsigned long long* bad, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_nonfinite, dim3(blocks(count)), dim3(256), 0, st, x, count, bad);
+}

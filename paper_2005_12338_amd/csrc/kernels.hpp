@@ -1,0 +1,66 @@
+// Launchers of the libgf2 kernels (host-callable, defined in the .hip files).
+#pragma once
+
+#include <algorithm>
+
+#include "gf2_internal.hpp"
+
+void launch_rng_words(uint64_t seed, uint32_t stream, uint32_t s, uint32_t q0, int64_t count,
+                      uint64_t* out, hipStream_t st);
+void launch_theta(uint64_t seed, int64_t ns, int64_t s0, int64_t naux, int8_t* theta, hipStream_t st);
+void launch_draws(uint64_t seed, int64_t ns, int64_t s0, int32_t k, const double* cdf, int64_t naux,
+                  const double* p, int32_t* q, double* w, hipStream_t st);
+void launch_synth_b(int64_t n, int64_t naux, const double* x, const double* xq, double amp, double a,
+                    double c, void* out, bool f64, hipStream_t st);
+void launch_maxabs(const void* b, bool f64, int64_t total, double* part, int nblk, hipStream_t st);
+void launch_rowflags(const void* b, bool f64, int64_t n, int64_t naux, double thr, uint8_t* flags,
+                     unsigned long long* nnz, hipStream_t st);
+void launch_extract_blocks(const void* b, bool f64, int64_t n, int64_t naux, double thr,
+                           const int32_t* w, const int32_t* idx, double* blk, float* blk32,
+                           hipStream_t st);
+void launch_rbuild(const void* b, bool f64, int64_t n, int64_t naux, double thr, const int8_t* theta,
+                   int64_t nvec, Prec prec, void* xl, void* xs, int64_t np, int64_t plane,
+                   int64_t mstride, hipStream_t st);
+void launch_rimportance(const void* b, bool f64, int64_t n, double thr, const int32_t* q,
+                        const double* w, int32_t k, int64_t nvec, Prec prec, void* xl, void* xs,
+                        int64_t np, int64_t plane, int64_t mstride, hipStream_t st);
+void launch_scale_cols(const double* c, const double* lw, int64_t n, int64_t np, int64_t ntau,
+                       double* out, hipStream_t st);
+void launch_unpad_sym(const double* p, int64_t n, int64_t np, int64_t ntau, double sign, double* out,
+                      hipStream_t st);
+void launch_pad_convert(const double* g, int64_t n, int64_t np, int64_t ntau, Prec prec, void* stbuf,
+                        int64_t plane, int64_t mstride, double* f64pad, hipStream_t st);
+void launch_jk_blocks(bool f64, const void* wbase, int64_t w_st_slot, int64_t w_st_m, int64_t np,
+                      int64_t naux, int32_t nslot, const int32_t* wq, const int32_t* idx,
+                      const void* blk, void* jout, hipStream_t st);
+void launch_jk_scatter(bool f64, const void* jblk, int64_t naux, int32_t nslot, int64_t npat,
+                       const int32_t* pat_ij, const int32_t* pat_off, const int32_t* pat_q, int64_t np,
+                       Prec prec, int64_t plane, void* jw_l, void* jw_s, void* jz_st, void* jz_sum_t,
+                       int64_t out_st_slot, hipStream_t st);
+void launch_trace_coef(const double* part, int64_t ntiles, int32_t nslot, double* coef, hipStream_t st);
+void launch_accumulate(const Unit* units, int32_t nunit, const void* sig, bool f64, int64_t sig_st_slot,
+                       int64_t n, int64_t np, double* sum, int32_t tau_lo, int32_t tau_hi,
+                       hipStream_t st);
+void launch_esamples(const Unit* units, int32_t nunit, const double* part, int64_t ntiles, int64_t s0,
+                     int64_t ntau, double* es, hipStream_t st);
+void launch_finalize(const double* det, const double* sum, int64_t n, int64_t ntau, double inv2ns,
+                     double* out, hipStream_t st);
+void launch_trace_prod(const double* sig, const double* gb, int64_t n, int64_t ntau, double* tr,
+                       hipStream_t st);
+void launch_energy_stats(const double* tr, const double* w, int64_t ntau, const double* es, int64_t ns,
+                         double gm, double* out, hipStream_t st);
+void launch_transpose(const void* src, bool f64, int64_t rows, int64_t cols, double* dst, int64_t ld,
+                      hipStream_t st);
+void launch_untranspose(const double* src, int64_t rows, int64_t cols, int64_t ld, void* dst, bool f64,
+                        hipStream_t st);
+void launch_count_nonfinite(const double* x, int64_t count, unsigned long long* bad, hipStream_t st);
+int dblock_tile();
+void launch_dblock(const double* G, const double* Gb, int64_t n, int64_t ntau, int32_t wmax,
+                   const int32_t* wq, const int32_t* idx, const double* blk, const int32_t* tq_off,
+                   const int32_t* tq, double* out, hipStream_t st);
+
+// Host numerics (eigen.cpp).
+// Symmetric eigendecomposition a = v diag(e) v^T (a row-major n x n,
+// overwritten); e ascending, v row-major with eigenvectors in columns.
+void sym_eigen(int64_t n, double* a, double* e, double* v);
+void gauss_legendre(int64_t n, double* x, double* w);

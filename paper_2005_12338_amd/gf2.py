@@ -1,0 +1,309 @@
+"""ctypes binding of libgf2 (include/gf2.h).
+
+Argument marshalling only: every step of the hot path runs in the
+library's HIP kernels.  PyTorch provides device memory and the stream.
+The functions keep the C names; ``Context`` wraps them for convenience.
+Loading fails loudly if the built library is missing -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgf2.so")
+
+GF2_OK, GF2_E_ARG, GF2_E_DEVICE, GF2_E_NOMEM, GF2_E_NUMERIC, GF2_E_STATE = 0, -1, -2, -3, -4, -5
+GF2_F64, GF2_F32 = 0, 1
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
+SAMPLE_RADEMACHER, SAMPLE_IMPORTANCE = 0, 1
+
+_STATUS = {GF2_E_ARG: "GF2_E_ARG", GF2_E_DEVICE: "GF2_E_DEVICE", GF2_E_NOMEM: "GF2_E_NOMEM",
+           GF2_E_NUMERIC: "GF2_E_NUMERIC", GF2_E_STATE: "GF2_E_STATE"}
+
+
+class Gf2Error(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ChainGeom(C.Structure):
+    _fields_ = [("n", C.c_int64), ("naux", C.c_int64), ("x", C.POINTER(C.c_double)),
+                ("xq", C.POINTER(C.c_double)), ("amp", C.c_double), ("a", C.c_double),
+                ("c", C.c_double)]
+
+
+class Sampling(C.Structure):
+    _fields_ = [("ns", C.c_int64), ("s0", C.c_int64), ("seed", C.c_uint64), ("mode", C.c_int32),
+                ("k", C.c_int32), ("p", C.POINTER(C.c_double))]
+
+
+_lib: Optional[C.CDLL] = None
+
+_SIGS = {
+    "gf2_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
+    "gf2_destroy": (None, [C.c_void_p]),
+    "gf2_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gf2_last_error": (C.c_char_p, [C.c_void_p]),
+    "gf2_version": (C.c_char_p, []),
+    "gf2_build_B": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.POINTER(C.c_double),
+                              C.POINTER(ChainGeom), C.c_int, C.c_void_p]),
+    "gf2_split": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_double,
+                            C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "gf2_split_free": (None, [C.c_void_p]),
+    "gf2_split_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.POINTER(C.c_double)]),
+    "gf2_tau_grid": (C.c_int, [C.c_double, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "gf2_green_tau": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                C.c_double, C.c_int64, C.c_double, C.c_int64, C.POINTER(C.c_double),
+                                C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "gf2_sigma_tau": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                C.POINTER(Sampling), C.c_int, C.c_void_p, C.c_void_p]),
+    "gf2_sigma_det": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "gf2_sigma_stoch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                  C.POINTER(Sampling), C.c_int, C.c_void_p, C.c_void_p]),
+    "gf2_sigma_finalize": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
+                                     C.c_void_p]),
+    "gf2_energy": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_double), C.c_void_p,
+                             C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.POINTER(C.c_double),
+                             C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "gf2_rng_words": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int64,
+                                C.POINTER(C.c_uint64)]),
+}
+
+
+def declared_symbols(header: Optional[str] = None):
+    """Names of the functions declared in include/gf2*.h."""
+    import re
+    inc = os.path.join(os.path.dirname(_PKG), "include")
+    names = []
+    for fn in sorted(os.listdir(inc)):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(inc, fn)).read()
+            names += re.findall(r"^\s*(?:gf2_status|void|const char\*|gf2_\w+\*?)\s+(gf2_\w+)\s*\(", txt, re.M)
+    return sorted(set(names))
+
+
+def load() -> C.CDLL:
+    """Load the built library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2005_12338_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def gf2_tau_grid(beta: float, ntau: int):
+    lib = load()
+    tau = np.zeros(ntau)
+    w = np.zeros(ntau)
+    st = lib.gf2_tau_grid(float(beta), int(ntau), _dp(tau), _dp(w))
+    if st != GF2_OK:
+        raise Gf2Error(st, "gf2_tau_grid")
+    return tau, w
+
+
+@dataclass
+class Split:
+    handle: C.c_void_p
+    n: int
+    naux: int
+    nnz: int
+    wmax: int
+    b_ptr: int
+    dtype: int
+    ctx: "Context"
+
+    def free(self):
+        if self.handle:
+            load().gf2_split_free(self.handle)
+            self.handle = None
+
+    def export(self):
+        """(w[naux], idx[naux][32], blocks[naux][32][32], kmax) on the host."""
+        w = np.zeros(self.naux, dtype=np.int32)
+        idx = np.zeros((self.naux, 32), dtype=np.int32)
+        blk = np.zeros((self.naux, 32, 32))
+        kmax = C.c_double(0)
+        self.ctx._check(load().gf2_split_export(self.ctx.h, self.handle, w.ctypes.data, idx.ctypes.data,
+                                                blk.ctypes.data, C.byref(kmax)))
+        return w, idx, blk, kmax.value
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """A gf2 context bound to a device and torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = C.c_void_p()
+        st = self.lib.gf2_create(C.byref(h), int(device), C.c_void_p(stream.cuda_stream))
+        if st != GF2_OK:
+            raise Gf2Error(st, "gf2_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gf2_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != GF2_OK:
+            raise Gf2Error(st, self.lib.gf2_last_error(self.h).decode())
+
+    # ---------------------------------------------------------------- B
+    def build_B(self, n: int, naux: int, geom=None, ijA=None, V: Optional[np.ndarray] = None,
+                dtype=None):
+        torch = self.torch
+        dtype = dtype or torch.float32
+        dt = GF2_F64 if dtype == torch.float64 else GF2_F32
+        B = torch.empty((naux, n, n), dtype=dtype, device=self.device)
+        g = None
+        keep = []
+        if ijA is None:
+            x = np.ascontiguousarray(geom.x, dtype=np.float64)
+            xq = np.ascontiguousarray(geom.xq, dtype=np.float64)
+            keep += [x, xq]
+            g = ChainGeom(n, naux, _dp(x), _dp(xq), geom.amp, geom.a, geom.c)
+        vp = None
+        if V is not None:
+            V = np.ascontiguousarray(V, dtype=np.float64)
+            keep.append(V)
+            vp = _dp(V)
+        self._check(self.lib.gf2_build_B(self.h, n, naux, _ptr(ijA), vp, C.byref(g) if g else None, dt,
+                                         B.data_ptr()))
+        return B
+
+    def split(self, B, eps: float) -> Split:
+        torch = self.torch
+        dt = GF2_F64 if B.dtype == torch.float64 else GF2_F32
+        naux, n, _ = B.shape
+        h = C.c_void_p()
+        nnz = C.c_int64()
+        wmax = C.c_int64()
+        self._check(self.lib.gf2_split(self.h, B.data_ptr(), dt, n, naux, float(eps), C.byref(h),
+                                       C.byref(nnz), C.byref(wmax)))
+        return Split(h, n, naux, nnz.value, wmax.value, B.data_ptr(), dt, self)
+
+    # ---------------------------------------------------------------- G
+    def green_tau(self, F: np.ndarray, tau: np.ndarray, beta: float, mu: float = 0.0, n_occ: int = 0,
+                  S: Optional[np.ndarray] = None):
+        torch = self.torch
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        tau = np.ascontiguousarray(tau, dtype=np.float64)
+        n = F.shape[0]
+        G = torch.empty((tau.shape[0], n, n), dtype=torch.float64, device=self.device)
+        Gb = torch.empty_like(G)
+        mu_out = C.c_double(0)
+        sp = None
+        if S is not None:
+            S = np.ascontiguousarray(S, dtype=np.float64)
+            sp = _dp(S)
+        self._check(self.lib.gf2_green_tau(self.h, n, _dp(F), sp, float(mu), int(n_occ), float(beta),
+                                           tau.shape[0], _dp(tau), G.data_ptr(), Gb.data_ptr(),
+                                           C.byref(mu_out)))
+        return G, Gb, mu_out.value
+
+    # ---------------------------------------------------------------- Sigma
+    @staticmethod
+    def _sampling(ns, seed, s0=0, p=None, k=1):
+        keep = None
+        if p is not None:
+            keep = np.ascontiguousarray(p, dtype=np.float64)
+            s = Sampling(ns, s0, seed, SAMPLE_IMPORTANCE, k, _dp(keep))
+        else:
+            s = Sampling(ns, s0, seed, SAMPLE_RADEMACHER, 1, None)
+        return s, keep
+
+    def sigma_tau(self, split: Split, B, G, Gb, ns: int, seed: int = 0, prec: str = "fp32", p=None, k=1,
+                  s0: int = 0, want_samples: bool = True):
+        torch = self.torch
+        ntau, n, _ = G.shape
+        Sigma = torch.empty((ntau, n, n), dtype=torch.float64, device=self.device)
+        es = torch.empty((ns, ntau), dtype=torch.float64, device=self.device) if want_samples else None
+        smp, keep = self._sampling(ns, seed, s0, p, k)
+        self._check(self.lib.gf2_sigma_tau(self.h, split.handle, B.data_ptr(), G.data_ptr(), Gb.data_ptr(),
+                                           ntau, C.byref(smp), PREC[prec], Sigma.data_ptr(), _ptr(es)))
+        return Sigma, es
+
+    def sigma_det(self, split: Split, G, Gb):
+        torch = self.torch
+        ntau, n, _ = G.shape
+        out = torch.empty((ntau, n, n), dtype=torch.float64, device=self.device)
+        self._check(self.lib.gf2_sigma_det(self.h, split.handle, G.data_ptr(), Gb.data_ptr(), ntau,
+                                           out.data_ptr()))
+        return out
+
+    def sigma_stoch(self, split: Split, B, G, Gb, Sigma_sum, ns: int, seed: int = 0, prec: str = "fp32",
+                    p=None, k=1, s0: int = 0, e_samples=None):
+        ntau = G.shape[0]
+        smp, keep = self._sampling(ns, seed, s0, p, k)
+        self._check(self.lib.gf2_sigma_stoch(self.h, split.handle, B.data_ptr(), G.data_ptr(),
+                                             Gb.data_ptr(), ntau, C.byref(smp), PREC[prec],
+                                             Sigma_sum.data_ptr(), _ptr(e_samples)))
+
+    def sigma_finalize(self, Sigma_det, Sigma_sum, ns_total: int):
+        out = self.torch.empty_like(Sigma_det)
+        ntau, n, _ = Sigma_det.shape
+        self._check(self.lib.gf2_sigma_finalize(self.h, n, ntau, Sigma_det.data_ptr(), Sigma_sum.data_ptr(),
+                                                int(ns_total), out.data_ptr()))
+        return out
+
+    # ---------------------------------------------------------------- energy
+    def energy(self, Sigma, Gb, w: np.ndarray, n_elec: float, e_samples=None):
+        ntau, n, _ = Sigma.shape
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        e = C.c_double()
+        epe = C.c_double()
+        se = C.c_double()
+        ns = 0 if e_samples is None else e_samples.shape[0]
+        self._check(self.lib.gf2_energy(self.h, n, ntau, _dp(w), Sigma.data_ptr(), Gb.data_ptr(),
+                                        _ptr(e_samples), ns, float(n_elec), C.byref(e), C.byref(epe),
+                                        C.byref(se)))
+        return e.value, epe.value, se.value
+
+    def rng_words(self, seed: int, stream: int, s: int, q0: int, count: int) -> np.ndarray:
+        out = np.zeros(count, dtype=np.uint64)
+        self._check(self.lib.gf2_rng_words(self.h, seed, stream, s, q0, count,
+                                            out.ctypes.data_as(C.POINTER(C.c_uint64))))
+        return out
