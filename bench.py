@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""Benchmark of the RS-SRI-GF2 hot path on one MI355X.
+
+Workload (default): synthetic hydrogen-dimer chain with 400 dimers,
+N = 800 orbitals, N_aux = 2400, beta = 100, 128 Gauss-Legendre tau points,
+N_s = 512 stochastic pairs, threshold eps = 1e-4; stochastic-block products
+in BF16 (FP32 accumulation), deterministic block, traces and energy in FP64.
+
+A timed "step" is one pass of the whole hot path over that input: factor
+tensor B, range separation, G(tau), the deterministic block, the N_s-pair
+stochastic chains for all tau points, and the energy with its standard
+error.  After the timed steps the metric itself is measured: wall time to
+reach a standard error of 1 mEh in the total correlation energy, by sampling
+pairs in batches until the running standard error is below the target
+(BF16, and the plain FP32 path for comparison).
+
+Prints one JSON line (rank 0).  --gpus above 1 is not supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12                        # B/s
+MFMA_PEAK = {"bf16": 2.5e15, "bf16x3": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import chain_inputs as ci
+    return {"n800": ci.N800, "n200": ci.N200, "tiny": ci.TINY}[name]
+
+
+class Problem:
+    def __init__(self, ctx, wl):
+        import chain_inputs as ci
+        from paper_2005_12338_amd import gf2
+        self.ctx, self.wl = ctx, wl
+        self.geo = ci.chain_geometry(wl.n_dimer)
+        self.F = ci.fock_tight_binding(self.geo.x)
+        self.tau, self.w = gf2.gf2_tau_grid(wl.beta, wl.ntau)
+
+    def setup(self):
+        """B, split, G(tau) and the deterministic block."""
+        import torch
+        ctx, wl, geo = self.ctx, self.wl, self.geo
+        B = ctx.build_B(geo.n, geo.naux, geom=geo, dtype=torch.float32)
+        spl = ctx.split(B, wl.eps)
+        G, Gb, mu = ctx.green_tau(self.F, self.tau, wl.beta, n_occ=wl.n_occ)
+        det = ctx.sigma_det(spl, G, Gb)
+        return B, spl, G, Gb, det
+
+    def full_pass(self, prec, ns):
+        B, spl, G, Gb, det = self.setup()
+        ctx, wl = self.ctx, self.wl
+        import torch
+        ssum = torch.zeros_like(det)
+        es = torch.empty((ns, wl.ntau), dtype=torch.float64, device=det.device)
+        ctx.sigma_stoch(spl, B, G, Gb, ssum, ns=ns, seed=wl.seed, prec=prec, e_samples=es)
+        sig = ctx.sigma_finalize(det, ssum, ns)
+        e, epe, se = ctx.energy(sig, Gb, self.w, wl.n_elec, es)
+        spl.free()
+        return e, se
+
+    def time_to_target(self, prec, target, batch=16, max_pairs=4096, p=None):
+        """Sample pairs in batches until the standard error of the total
+        E_corr is below `target` (Eh).  Returns (seconds, pairs, E, stderr)."""
+        import torch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B, spl, G, Gb, det = self.setup()
+        ctx, wl = self.ctx, self.wl
+        ssum = torch.zeros_like(det)
+        es = torch.empty((max_pairs, wl.ntau), dtype=torch.float64, device=det.device)
+        s = 0
+        while True:
+            ctx.sigma_stoch(spl, B, G, Gb, ssum, ns=batch, seed=wl.seed, prec=prec, s0=s,
+                            e_samples=es[s:s + batch], p=p)
+            s += batch
+            sig = ctx.sigma_finalize(det, ssum, s)
+            e, epe, se = ctx.energy(sig, Gb, self.w, wl.n_elec, es[:s])
+            if se < target or s + batch > max_pairs:
+                break
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        spl.free()
+        return t1 - t0, s, e, se
+
+
+def cpu_baseline(wl, pairs):
+    """The oracle (FP64 NumPy, as it stands) timed on a bounded sample of the
+    same workload and extrapolated to a time-to-target estimate (s)."""
+    import chain_inputs as ci
+    from oracle import green, integrals, rng, selfenergy as se, split as sp
+    geo = ci.chain_geometry(wl.n_dimer)
+    n, naux = geo.n, geo.naux
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    wall0 = time.perf_counter()
+    t0 = time.perf_counter()
+    f = ci.fock_tight_binding(geo.x)
+    e, c = green.orbitals(f)
+    mu = green.midgap_mu(e, wl.n_occ)
+    tau, w = green.tau_grid(wl.beta, wl.ntau)
+    t_eig = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g, gb = green.green_tau(e, c, mu, wl.beta, tau[wl.ntau // 3: wl.ntau // 3 + 1])
+    t_g = time.perf_counter() - t0
+
+    def slices(q0, q1):
+        return integrals.synthetic_b(geo.x, geo.xq[q0:q1], geo.amp, geo.a, geo.c)
+
+    def unit_time(nq):
+        """B for the first nq Q, their split, one vector pair, one unit."""
+        t0 = time.perf_counter()
+        b = slices(0, nq)
+        tb = time.perf_counter() - t0
+        spl = sp.split_b(b, wl.eps)
+        th = rng.rademacher(wl.seed, 0, 1, naux)[:, :nq]
+        thp = rng.rademacher(wl.seed, 1, 1, naux)[:, :nq]
+        t0 = time.perf_counter()
+        _, xl, xs = sp.r_vectors(b, spl, th)
+        _, yl, ys = sp.r_vectors(b, spl, thp)
+        tr = (time.perf_counter() - t0) / 2.0
+        tu = float("inf")
+        for _ in range(2):                     # the first call also warms up the BLAS threads
+            t0 = time.perf_counter()
+            se.sigma_pair(spl, xl[0], xs[0], yl[0], ys[0], g[0], gb[0])
+            tu = min(tu, time.perf_counter() - t0)
+        return tb, tr, tu, spl
+
+    q1, q2 = naux // 20, naux // 10
+    tb1, tr1, tu1, _ = unit_time(q1)
+    tb2, tr2, tu2, spl2 = unit_time(q2)
+    lin = lambda a1, a2: a1 + max(a2 - a1, 0.0) * (naux - q1) / (q2 - q1)     # linear in N_aux
+    t_b, t_r, t_unit = lin(tb1, tb2), lin(tr1, tr2), lin(tu1, tu2)
+    rows = list(range(0, q2, 4))
+    t0 = time.perf_counter()
+    se.sigma_dd(spl2, g[0], gb[0], q_rows=rows)
+    t_dd = (time.perf_counter() - t0) * naux / len(rows) * naux / q2     # all Q rows x all Q' columns
+    measured = time.perf_counter() - wall0
+    est = t_eig + wl.ntau * t_g + 2 * t_b + wl.ntau * t_dd + pairs * (2 * t_r + wl.ntau * t_unit)
+    return {"value": est, "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle on the N={n} chain, {measured:.1f} s measured: eigh, G at 1 of "
+                       f"{wl.ntau} tau, B/split/vectors/one (tau, pair) unit of eq:sigma_2 with the first "
+                       f"{q1} and {q2} of {naux} aux functions (linear in N_aux), the D x D block for "
+                       f"{len(rows)} of {q2} Q rows at one tau (scaled to {naux}^2 pairs); extrapolated to "
+                       f"{pairs} pairs x {wl.ntau} tau and 2 passes over B"),
+            "per_unit_s": t_unit, "dd_per_tau_s": t_dd}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="n800", choices=["n800", "n200", "tiny"])
+    ap.add_argument("--prec", default="bf16", choices=["bf16", "bf16x3", "fp32", "fp64"])
+    ap.add_argument("--ns", type=int, default=0, help="pairs per step (default: the workload's)")
+    ap.add_argument("--target-meh", type=float, default=1.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-target", action="store_true", help="skip the time-to-target runs")
+    ap.add_argument("--profile", action="store_true", help="print the per-kernel breakdown")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2005_12338_amd import gf2
+
+    wl = workload(args.workload)
+    ns = args.ns or wl.ns
+    ctx = gf2.Context(0)
+    pb = Problem(ctx, wl)
+    log(f"[bench] workload {wl.name}: N={wl.n} Naux={wl.naux} ntau={wl.ntau} Ns={ns} eps={wl.eps} "
+        f"prec={args.prec}")
+
+    for i in range(args.warmup):
+        e, se_ = pb.full_pass(args.prec, ns)
+        log(f"[bench] warmup {i}: E={e:.9f} stderr={se_:.3e}")
+    ctx.set_profiling(True)
+    ctx.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        e, se_ = pb.full_pass(args.prec, ns)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.set_profiling(False)
+    ms_step = (t1 - t0) * 1000.0 / args.steps
+    log(f"[bench] {args.steps} steps: {ms_step:.1f} ms/step, E={e:.9f} Eh stderr={se_:.3e} Eh")
+    gname = {"bf16": "gemm_bf16", "bf16x3": "gemm_bf16x3", "fp32": "gemm_f32", "fp64": "gemm_f64"}[args.prec]
+    gk = dict(launches=0, ms=0.0, flops=0.0, bytes=0.0)
+    for k, v in prof.items():                      # the GEMM kernel over all chain stages
+        if k == gname or k.startswith(gname + "."):
+            for f in gk:
+                gk[f] += v[f]
+    tot_ms = sum(v["ms"] for v in prof.values())
+    if args.profile:
+        for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"]):
+            rate = v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 and v["flops"] else 0.0
+            log(f"[bench]   {k:14s} launches={v['launches']:6d} total={v['ms']:9.2f} ms "
+                f"avg={v['ms'] / max(1, v['launches']):8.4f} ms  {rate:8.1f} TFLOP/s")
+        log(f"[bench]   kernel time {tot_ms:.1f} ms of {ms_step * args.steps:.1f} ms wall")
+    achieved = gk["flops"] / (gk["ms"] * 1e-3) if gk["ms"] > 0 else 0.0
+    peak = MFMA_PEAK[args.prec]
+
+    out = {
+        "metric": "time to 1 mEh stderr in E_corr, N=800 (learned+BF16 vs plain); MFMA TFLOP/s",
+        "value": None, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": f"{wl.name}: H2-dimer chain, {wl.n_dimer} dimers, N={wl.n}, Naux={wl.naux}, "
+                               f"beta={wl.beta}, ntau={wl.ntau}, Ns={ns}, eps={wl.eps}",
+                   "n": wl.n, "naux": wl.naux, "ntau": wl.ntau, "ns": ns, "eps": wl.eps, "beta": wl.beta},
+        "E_corr_total": e, "stderr_total": se_,
+        "chain_mfma_tflops": achieved / 1e12,
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None, "kernel": gname,
+                     "launches": gk["launches"], "avg_launch_ms": gk["ms"] / max(1, gk["launches"])},
+    }
+    if not args.no_target:
+        target = args.target_meh * 1e-3
+        t_b, pairs_b, e_b, se_b = pb.time_to_target(args.prec, target)
+        log(f"[bench] time to {args.target_meh} mEh ({args.prec}, uniform): {t_b:.3f} s, {pairs_b} pairs, "
+            f"E={e_b:.9f} stderr={se_b:.3e}")
+        t_f, pairs_f, e_f, se_f = pb.time_to_target("fp32", target)
+        log(f"[bench] time to {args.target_meh} mEh (fp32, uniform): {t_f:.3f} s, {pairs_f} pairs, "
+            f"E={e_f:.9f} stderr={se_f:.3e}")
+        out["value"] = t_b
+        out["time_to_target"] = {"target_mEh": args.target_meh,
+                                 args.prec + "_uniform": {"s": t_b, "pairs": pairs_b, "E": e_b, "stderr": se_b},
+                                 "fp32_uniform": {"s": t_f, "pairs": pairs_f, "E": e_f, "stderr": se_f},
+                                 "speedup_vs_plain_fp32": t_f / t_b if t_b > 0 else None}
+        pairs_for_cpu = pairs_b
+    else:
+        out["value"] = ms_step / 1000.0
+        pairs_for_cpu = ns
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(wl, pairs_for_cpu)
+        log(f"[bench] cpu baseline: {out['cpu_baseline']['value']:.1f} s (extrapolated)")
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -212,6 +212,17 @@ gf2_status gf2_energy(gf2_ctx* ctx, int64_t n, int64_t ntau, const double* w,
 gf2_status gf2_rng_words(gf2_ctx* ctx, uint64_t seed, uint32_t stream, uint32_t s,
                          uint32_t q0, int64_t count, uint64_t* out);
 
+/* ------------------------------------------------------------ profiling ---
+ * Optional timing of the library's launches with HIP events on the
+ * context's stream (off by default).  gf2_profile_read synchronises the
+ * stream, then reports up to `cap` kernel classes: names (host array of
+ * `cap` char[32]), launch counts, summed durations (ms), and the algorithmic
+ * flops and bytes the launches were charged with; *count receives the
+ * number of classes.  It clears the record.  */
+gf2_status gf2_set_profiling(gf2_ctx* ctx, int on);
+gf2_status gf2_profile_read(gf2_ctx* ctx, int32_t cap, char* names, int64_t* launches,
+                            double* total_ms, double* flops, double* bytes, int32_t* count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,12 +82,13 @@ def sigma_d_right(split: Split, a, b, g, gb) -> np.ndarray:
     return (a @ g) @ jk(split, gb @ b @ g)
 
 
-def sigma_dd(split: Split, g, gb) -> np.ndarray:
+def sigma_dd(split: Split, g, gb, q_rows=None) -> np.ndarray:
     """Sigma[D, D] = sum_{Q,Q'} Sigma[K_Q (x) K_Q, K_Q' (x) K_Q'] on blocks.
 
     For each pair: M = k_Q G[S_Q,S_Q'] k_Q', T = M Gb[S_Q',S_Q]; the pair adds
     2 Tr(T) M - T M to Sigma[S_Q, S_Q'] (the bilinear form restricted to the
-    supports)."""
+    supports).  q_rows restricts the first index Q to a subset (partial sums,
+    used only to time the oracle on a sample)."""
     n = g.shape[0]
     naux = split.naux
     wmax = max(split.wmax, 1)
@@ -97,7 +98,7 @@ def sigma_dd(split: Split, g, gb) -> np.ndarray:
         idx[q, :s.shape[0]] = s
         kb[q, :s.shape[0], :s.shape[0]] = k
     out = np.zeros((n, n))
-    for q in range(naux):
+    for q in (range(naux) if q_rows is None else q_rows):
         if split.support[q].shape[0] == 0:
             continue
         iq = idx[q]

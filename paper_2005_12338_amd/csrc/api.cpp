@@ -6,6 +6,7 @@
 #include <map>
 #include <numeric>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "kernels.hpp"
@@ -498,8 +499,11 @@ gf2_status gf2_sigma_det(gf2_ctx* ctx, const gf2_split_h* split, const double* G
   return guarded(ctx, [&] {
     GF2_REQUIRE(split && split->owner == ctx, GF2_E_STATE, "split handle of another context");
     GF2_REQUIRE(G && Gbar && Sigma_det && ntau > 0 && ntau <= 65535, GF2_E_ARG, "bad sigma_det arguments");
-    launch_dblock(G, Gbar, split->n, ntau, split->wmax, split->w, split->idx, split->blk, split->row_off,
-                  split->row_q, Sigma_det, ctx->stream);
+    {
+      ProfScope ps(ctx, "dblock");
+      launch_dblock(G, Gbar, split->n, ntau, split->wmax, split->w, split->idx, split->blk, split->row_off,
+                    split->row_q, Sigma_det, ctx->stream);
+    }
     GF2_HIP(hipStreamSynchronize(ctx->stream));
   });
 }
@@ -546,6 +550,7 @@ void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double*
   char* xs = CB("c_xs", sb * nvec);
   if (smp->mode == GF2_SAMPLE_RADEMACHER) {
     auto* theta = (int8_t*)ctx_buf(ctx, "c_theta", (size_t)(nvec * naux));
+    ProfScope ps(ctx, "rbuild", 4.0 * (double)nvec * naux * n * n, (double)naux * n * n * (bf64 ? 8 : 4));
     launch_theta(smp->seed, ns, s0, naux, theta, st);
     launch_rbuild(B, bf64, n, naux, sp->thresh, theta, nvec, prec, xl, xs, np, plane, mstride, st);
   } else {
@@ -576,8 +581,10 @@ void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double*
     slots = (int64_t)std::max(1.0, std::min(64.0, 4.0e9 / per_slot));
   }
   slots = std::min<int64_t>(slots, ntau * ns);
-  const int64_t sc = std::min<int64_t>(ns, std::max<int64_t>(1, slots / std::min<int64_t>(ntau, slots)));
-  const int64_t tcnt = std::max<int64_t>(1, slots / sc);
+  // several pairs per tau in a chunk, so each Sigma_sum[tau] is read and
+  // written once per chunk for all of them
+  const int64_t sc = std::min<int64_t>(ns, std::min<int64_t>(8, slots));
+  const int64_t tcnt = std::max<int64_t>(1, std::min<int64_t>(ntau, slots / sc));
   slots = sc * tcnt;
 
   // per-slot scratch
@@ -743,26 +750,37 @@ void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double*
   auto* dunits = (Unit*)ctx_buf(ctx, "c_units", uall.size() * sizeof(Unit));
   h2d(ctx, dunits, uall.data(), uall.size());
 
-  auto stage = [&](int off, int cnt, const Unit* units, int nunit) {
+  const double n3 = 2.0 * (double)n * (double)n * (double)n;     // flops of one n x n x n product
+  const char* gname = prec == Prec::F64 ? "gemm_f64" : prec == Prec::F32 ? "gemm_f32"
+                      : prec == Prec::BF16 ? "gemm_bf16" : "gemm_bf16x3";
+  auto stage = [&](int off, int cnt, const Unit* units, int nunit, int products, const char* tag) {
     int mt = 0;
     for (int i = 0; i < cnt; ++i) mt = std::max(mt, tiles_of(P[off + i], prec, n));
     GemmLaunch L = chain_launch(dprobs + off, cnt, units, nunit, n, np, plane);
+    std::string nm = std::string(gname) + tag;
+    ProfScope ps(ctx, nm.c_str(), n3 * products * nunit);
     launch_gemm(prec, L, mt, st);
   };
   for (size_t c = 0; c < chunks.size(); ++c) {
     const Unit* du = dunits + chunks[c].first;
     const int nu = (int)chunks[c].second;
-    stage(s1_off, s1_n, du, nu);
-    stage(s2_off, s2_n, du, nu);
-    launch_trace_coef(mpart, mtiles, (int32_t)slots, coef, st);
-    launch_jk_blocks(accf64, wz, 4 * ac_sl, ac_sl, np, naux, nu, sp->w, sp->idx,
-                     accf64 ? (const void*)sp->blk : (const void*)sp->blk32, jblk, st);
-    launch_jk_scatter(accf64, jblk, naux, nu, sp->npat, sp->pat_ij, sp->pat_off, sp->pat_q, np, prec, plane,
-                      jw_l, jw_s, jz_st, jz_sum_t, st_sl, st);
-    stage(s3_off, s3_n, du, nu);
-    stage(s4_off, 1, du, nu);
-    launch_accumulate(du, nu, sig, accf64, ac_sl, n, np, Sigma_sum, trange[c].first, trange[c].second, st);
-    if (e_samples) launch_esamples(du, nu, epart, ftiles, 0, ntau, e_samples, st);
+    stage(s1_off, s1_n, du, nu, 4, ".s1");
+    stage(s2_off, s2_n, du, nu, 8, ".s2");
+    {
+      ProfScope ps(ctx, "jk");
+      launch_trace_coef(mpart, mtiles, (int32_t)slots, coef, st);
+      launch_jk_blocks(accf64, wz, 4 * ac_sl, ac_sl, np, naux, nu, sp->w, sp->idx,
+                       accf64 ? (const void*)sp->blk : (const void*)sp->blk32, jblk, st);
+      launch_jk_scatter(accf64, jblk, naux, nu, sp->npat, sp->pat_ij, sp->pat_off, sp->pat_q, np, prec, plane,
+                        jw_l, jw_s, jz_st, jz_sum_t, st_sl, st);
+    }
+    stage(s3_off, s3_n, du, nu, 4, ".s3");
+    stage(s4_off, 1, du, nu, 8, ".s4");
+    {
+      ProfScope ps(ctx, "accumulate", 0.0, (double)nu * n * n * (accf64 ? 8 : 4) + 2.0 * (trange[c].second - trange[c].first) * n * n * 8);
+      launch_accumulate(du, nu, sig, accf64, ac_sl, n, np, Sigma_sum, trange[c].first, trange[c].second, st);
+      if (e_samples) launch_esamples(du, nu, epart, ftiles, 0, ntau, e_samples, st);
+    }
     GF2_HIP(hipGetLastError());
   }
   GF2_HIP(hipStreamSynchronize(st));
@@ -821,8 +839,11 @@ gf2_status gf2_sigma_tau(gf2_ctx* ctx, const gf2_split_h* split, const void* B, 
     const size_t bytes = (size_t)(ntau * n * n) * 8;
     auto* det = (double*)ctx_buf(ctx, "t_det", bytes);
     auto* sum = (double*)ctx_buf(ctx, "t_sum", bytes, true);
-    launch_dblock(G, Gbar, n, ntau, split->wmax, split->w, split->idx, split->blk, split->row_off,
-                  split->row_q, det, ctx->stream);
+    {
+      ProfScope ps(ctx, "dblock");
+      launch_dblock(G, Gbar, n, ntau, split->wmax, split->w, split->idx, split->blk, split->row_off,
+                    split->row_q, det, ctx->stream);
+    }
     run_stoch(ctx, split, B, G, Gbar, ntau, sampling, to_prec(prec), sum, e_samples);
     launch_finalize(det, sum, n, ntau, 0.5 / (double)sampling->ns, Sigma, ctx->stream);
     GF2_HIP(hipGetLastError());
@@ -851,6 +872,49 @@ gf2_status gf2_energy(gf2_ctx* ctx, int64_t n, int64_t ntau, const double* w, co
     if (E_tot) *E_tot = h[0];
     if (E_per_e) *E_per_e = h[0] / n_elec;
     if (stderr_tot) *stderr_tot = h[2];
+  });
+}
+
+gf2_status gf2_set_profiling(gf2_ctx* ctx, int on) {
+  if (!ctx) return GF2_E_ARG;
+  ctx->prof = on != 0;
+  return GF2_OK;
+}
+
+gf2_status gf2_profile_read(gf2_ctx* ctx, int32_t cap, char* names, int64_t* launches, double* total_ms,
+                            double* flops, double* bytes, int32_t* count) {
+  return guarded(ctx, [&] {
+    GF2_HIP(hipStreamSynchronize(ctx->stream));
+    std::vector<std::string> order;
+    std::map<std::string, std::tuple<int64_t, double, double, double>> agg;
+    for (auto& e : ctx->events) {
+      float ms = 0.0f;
+      GF2_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+      if (!agg.count(e.name)) order.push_back(e.name);
+      auto& t = agg[e.name];
+      std::get<0>(t) += 1;
+      std::get<1>(t) += ms;
+      std::get<2>(t) += e.flops;
+      std::get<3>(t) += e.bytes;
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    ctx->events.clear();
+    int32_t k = 0;
+    for (auto& nm : order) {
+      if (k >= cap) break;
+      auto& t = agg[nm];
+      if (names) {
+        std::memset(names + 32 * k, 0, 32);
+        std::strncpy(names + 32 * k, nm.c_str(), 31);
+      }
+      if (launches) launches[k] = std::get<0>(t);
+      if (total_ms) total_ms[k] = std::get<1>(t);
+      if (flops) flops[k] = std::get<2>(t);
+      if (bytes) bytes[k] = std::get<3>(t);
+      ++k;
+    }
+    if (count) *count = k;
   });
 }
 

@@ -1,20 +1,22 @@
 // Grouped MFMA GEMM for the dense N x N products of the RS-SRI chains.
 //
 // C = sum_s A_s B_s^T for every unit (tau, pair) of a launch, where every
-// operand is an np x np row-major matrix (B is passed as B^T, so both
-// operands stream rows with contiguous k).  A tile may also hold the four
-// products A_a B_b (a, b in {0, 1}) of two A and two B matrices at the same
-// output position, so that the epilogue can form sums of products (e.g.
-// M_SL + M_SS) without re-reading them from memory.
+// operand is a row-major matrix with leading dimension ld (B is passed as
+// B^T, so both operands stream rows with contiguous k).  A tile may also
+// hold the products A_a B_b of two A and/or two B matrices at the same
+// output positions; each wave then owns the same positions of every product,
+// so sums of products (e.g. M_SL + M_SS) are formed in registers.
 //
 // gfx950 matrix cores:
-//   FP64   v_mfma_f64_16x16x4_f64     64 x 64 tile, 4 waves of 32 x 32
-//   FP32   v_mfma_f32_32x32x2_f32     128 x 128 tile, 4 waves of 64 x 64
-//   BF16   v_mfma_f32_32x32x16_bf16   128 x 128 tile, 4 waves of 64 x 64
+//   FP64   v_mfma_f64_16x16x4_f64     64 x 64 tile, 4 waves
+//   FP32   v_mfma_f32_32x32x2_f32     128 x 128 tile, 4 waves
+//   BF16   v_mfma_f32_32x32x16_bf16   128 x 128 tile, 4 waves
 //   BF16X3 three bf16 MFMAs per step (hi*hi + hi*lo + lo*hi)
-// Operands are double-buffered through LDS (global -> registers -> LDS);
-// the accumulators are staged through LDS for the epilogue so that stores
-// are coalesced in both row-major and transposed layouts.
+// Operands are double-buffered through LDS (global -> registers -> LDS).
+// The epilogue writes straight from the accumulators: combinations of the
+// tile's products, row-major or transposed, in accumulator or storage
+// format, optional addends and FP64 Hadamard partial sums (deterministic
+// fixed-order block reduction).
 #include <type_traits>
 
 #include "gf2_internal.hpp"
@@ -25,30 +27,33 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+// 16-byte vector in the global address space (global_load, not flat_load)
+typedef __attribute__((address_space(1))) const u32x4_t GVec;
 
 template <Prec P> struct Cfg;
 template <> struct Cfg<Prec::F64> {
   using E = double; using Acc = double;
   static constexpr int BM = 64, BN = 64, BK = 16, PAD = 2, PLANES = 1;
-  static constexpr int MT = 16, TM = 2, TN = 2;    // wave tile 32 x 32
+  static constexpr int MT = 16, NACC = 4;
 };
 template <> struct Cfg<Prec::F32> {
   using E = float; using Acc = float;
   static constexpr int BM = 128, BN = 128, BK = 32, PAD = 4, PLANES = 1;
-  static constexpr int MT = 32, TM = 2, TN = 2;    // wave tile 64 x 64
+  static constexpr int MT = 32, NACC = 16;
 };
 template <> struct Cfg<Prec::BF16> {
   using E = bf16_t; using Acc = float;
   static constexpr int BM = 128, BN = 128, BK = 64, PAD = 8, PLANES = 1;
-  static constexpr int MT = 32, TM = 2, TN = 2;
+  static constexpr int MT = 32, NACC = 16;
 };
 template <> struct Cfg<Prec::BF16X3> {
   using E = bf16_t; using Acc = float;
   static constexpr int BM = 128, BN = 128, BK = 32, PAD = 8, PLANES = 2;
-  static constexpr int MT = 32, TM = 2, TN = 2;
+  static constexpr int MT = 32, NACC = 16;
 };
 
 constexpr int kThreads = 256;
+constexpr int TM = 2, TN = 2;           // MFMA tiles per wave along rows / columns
 
 __device__ __forceinline__ bf16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -65,7 +70,6 @@ __device__ __forceinline__ int64_t off(const OutSpec& r, const Unit& u) {
   return (int64_t)u.tau * r.st_tau + (int64_t)u.s * r.st_s + (int64_t)u.slot * r.st_slot;
 }
 
-// Storage-format load of one element as the accumulator type.
 template <Prec P>
 __device__ __forceinline__ typename Cfg<P>::Acc load_st(const void* base, int64_t i, int64_t plane) {
   if constexpr (P == Prec::F64) return ((const double*)base)[i];
@@ -75,24 +79,59 @@ __device__ __forceinline__ typename Cfg<P>::Acc load_st(const void* base, int64_
 }
 
 template <Prec P>
-__device__ __forceinline__ void store_st(void* base, int64_t i, int64_t plane, typename Cfg<P>::Acc v) {
-  if constexpr (P == Prec::F64) ((double*)base)[i] = v;
-  else if constexpr (P == Prec::F32) ((float*)base)[i] = v;
-  else if constexpr (P == Prec::BF16) ((bf16_t*)base)[i] = f2bf(v);
-  else {
-    bf16_t hi = f2bf(v);
-    ((bf16_t*)base)[i] = hi;
-    ((bf16_t*)base)[i + plane] = f2bf(v - bf2f(hi));
+__device__ __forceinline__ void store_out(int type, void* base, int64_t i, int64_t plane,
+                                          typename Cfg<P>::Acc v) {
+  if constexpr (P == Prec::F64) {
+    ((double*)base)[i] = v;
+  } else if constexpr (P == Prec::F32) {
+    ((float*)base)[i] = v;
+  } else {
+    if (type == 0) {
+      ((float*)base)[i] = v;
+    } else if constexpr (P == Prec::BF16) {
+      ((bf16_t*)base)[i] = f2bf(v);
+    } else {
+      bf16_t hi = f2bf(v);
+      ((bf16_t*)base)[i] = hi;
+      ((bf16_t*)base)[i + plane] = f2bf(v - bf2f(hi));
+    }
   }
 }
 
+// Four consecutive elements (i .. i+3) of one output row.
 template <Prec P>
-__device__ __forceinline__ void store_out(const OutSpec& o, int64_t i, int64_t plane, typename Cfg<P>::Acc v) {
-  if (o.type == 0) {
-    if constexpr (P == Prec::F64) ((double*)o.base)[i] = v;
-    else ((float*)o.base)[i] = v;
+__device__ __forceinline__ void store_out_vec4(int type, void* base, int64_t i, int64_t plane,
+                                               const typename Cfg<P>::Acc* v) {
+  if constexpr (P == Prec::F64) {
+    for (int e = 0; e < 4; ++e) ((double*)base)[i + e] = v[e];
   } else {
-    store_st<P>(o.base, i, plane, v);
+    if (type == 0 || P == Prec::F32) {
+      if ((i & 3) == 0) {
+        *(float4*)((float*)base + i) = make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+        for (int e = 0; e < 4; ++e) ((float*)base)[i + e] = v[e];
+      }
+    } else {
+      bf16_t h[4], l[4];
+      for (int e = 0; e < 4; ++e) {
+        h[e] = f2bf(v[e]);
+        l[e] = f2bf(v[e] - bf2f(h[e]));
+      }
+      uint2 hv = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+      if ((i & 3) == 0) {
+        *(uint2*)((bf16_t*)base + i) = hv;
+      } else {
+        for (int e = 0; e < 4; ++e) ((bf16_t*)base)[i + e] = h[e];
+      }
+      if constexpr (P == Prec::BF16X3) {
+        uint2 lv = make_uint2((uint32_t)l[0] | ((uint32_t)l[1] << 16), (uint32_t)l[2] | ((uint32_t)l[3] << 16));
+        if (((i + plane) & 3) == 0) {
+          *(uint2*)((bf16_t*)base + i + plane) = lv;
+        } else {
+          for (int e = 0; e < 4; ++e) ((bf16_t*)base)[i + plane + e] = l[e];
+        }
+      }
+    }
   }
 }
 
@@ -107,90 +146,115 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t wg, int64_t total) {
 }
 
 template <Prec P>
-__global__ __launch_bounds__(kThreads) void gemm_kernel(GemmLaunch L) {
+struct Smem {
+  using C = Cfg<P>;
+  using E = typename C::E;
+  static constexpr int PITCH = C::BK + C::PAD;
+  static constexpr int TILE_A = C::PLANES * C::BM * PITCH;
+  static constexpr int TILE_B = C::PLANES * C::BN * PITCH;
+  static constexpr int BYTES = 2 * (TILE_A + TILE_B) * (int)sizeof(E);
+};
+
+// Row (within the 32 x 32 or 16 x 16 MFMA tile) held by accumulator r of a lane.
+template <Prec P>
+__device__ __forceinline__ int acc_row(int lane, int r) {
+  if constexpr (P == Prec::F64) return (lane >> 4) + 4 * r;       // f64 16x16x4
+  else return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);           // 32x32 f32 / bf16
+}
+template <Prec P>
+__device__ __forceinline__ int acc_col(int lane) {
+  if constexpr (P == Prec::F64) return lane & 15;
+  else return lane & 31;
+}
+
+template <Prec P, int NA, int NB>
+__device__ __forceinline__ void gemm_body(const GemmLaunch& L, const Prob& pb, const Unit& u, int tile,
+                                          unsigned char* smem, double* red) {
   using C = Cfg<P>;
   using E = typename C::E;
   using Acc = typename C::Acc;
-  constexpr int BM = C::BM, BN = C::BN, BK = C::BK, PAD = C::PAD, PL = C::PLANES;
-  constexpr int PITCH = BK + PAD;                         // elements per LDS row
+  constexpr int BM = C::BM, BN = C::BN, BK = C::BK, PL = C::PLANES;
+  constexpr int PITCH = Smem<P>::PITCH;
   constexpr int VE = 16 / sizeof(E);                      // elements per 16 B vector
   constexpr int VPR = BK / VE;                            // vectors per tile row
-  constexpr int AVEC = BM * VPR * PL;                     // vectors per A tile
-  constexpr int BVEC = BN * VPR * PL;
-  constexpr int AV = AVEC / kThreads, BV = BVEC / kThreads;
-  static_assert(AVEC % kThreads == 0 && BVEC % kThreads == 0, "tile/threads");
-  constexpr int TILE_A = PL * BM * PITCH, TILE_B = PL * BN * PITCH;
-  constexpr int CPITCH = BN + 1;
-  constexpr int LDS_AB = 2 * (TILE_A + TILE_B) * (int)sizeof(E);
-  constexpr int LDS_C = BM * CPITCH * (int)sizeof(Acc);
-  constexpr int LDS_BYTES = LDS_AB > LDS_C ? LDS_AB : LDS_C;
-  __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES];
-  __shared__ double red[4 * kMaxHad];
+  constexpr int AV = BM * VPR * PL / kThreads, BV = BN * VPR * PL / kThreads;
+  static_assert(BM * VPR * PL % kThreads == 0 && BN * VPR * PL % kThreads == 0, "tile/threads");
+  constexpr int TILE_A = Smem<P>::TILE_A, TILE_B = Smem<P>::TILE_B;
+  constexpr int SM = BM / NA, SN = BN / NB;               // output rows / cols per tile
+  constexpr int MT = C::MT, NACC = C::NACC;
+  constexpr int WR = BM / 2, WC = BN / 2;                 // wave region in the LDS tile (normal mode)
 
   E* As = (E*)smem;                    // [2][PL][BM][PITCH]
   E* Bs = As + 2 * TILE_A;             // [2][PL][BN][PITCH]
-
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  const int64_t total = (int64_t)gridDim.x * gridDim.y;
-  const int64_t lin = xcd_remap((int64_t)blockIdx.y * gridDim.x + blockIdx.x, total);
-  const int tile = (int)(lin % gridDim.x);
-  const int py = (int)(lin / gridDim.x);
-  const int ui = py / L.nprob, pi = py % L.nprob;
-  const Prob& pb = L.probs[pi];
-  const Unit u = L.units[ui];
-  const int nA = pb.nA, nB = pb.nB;
-  const int SM = BM / nA, SN = BN / nB;                  // sub-tile extent
   const int64_t mrows = L.m, ncols = L.nc, kk = L.k, ld = L.ld;
   const int tiles_n = (int)((ncols + SN - 1) / SN);
   const int tiles_m = (int)((mrows + SM - 1) / SM);
   const int tm = tile / tiles_n, tn = tile % tiles_n;
   if (tm >= tiles_m) return;
   const int64_t row0 = (int64_t)tm * SM, col0 = (int64_t)tn * SN;
-
-  const int kps = (int)((kk + BK - 1) / BK);             // k tiles per segment
+  const int kps = (int)((kk + BK - 1) / BK);
   const int ktiles = kps * pb.nseg;
 
-  // -------- global -> register staging
-  u32x4_t ra[AV], rb[BV];
-  auto gload = [&](int kt) {
-    const int seg = kt / kps;
-    const int64_t k0 = (int64_t)(kt % kps) * BK;
+  // LDS row of MFMA row-fragment i (column fragment j) of this wave, and the
+  // output row (column) offset it covers.  With two A matrices the tile holds
+  // A_0 rows in [0, SM) and A_1 rows in [SM, 2 SM); fragment i is product i.
+  auto frag_row_lds = [&](int i) { return NA == 2 ? i * SM + wm * MT : wm * WR + i * MT; };
+  auto frag_col_lds = [&](int j) { return NB == 2 ? j * SN + wn * MT : wn * WC + j * MT; };
+  auto frag_row_out = [&](int i) { return NA == 2 ? wm * MT : wm * WR + i * MT; };
+  auto frag_col_out = [&](int j) { return NB == 2 ? wn * MT : wn * WC + j * MT; };
+
+  // Per-thread row pointers of the vectors this thread stages, for the
+  // current K segment (recomputed only when the segment changes).
+  const E* ap[AV];
+  const E* bp[BV];
+  bool aok[AV], bok[BV];
+  int akv[AV], bkv[BV];
+  auto set_seg = [&](int seg) {
 #pragma unroll
     for (int i = 0; i < AV; ++i) {
       const int v = tid + i * kThreads;
       const int pl = v / (BM * VPR);
       const int vv = v % (BM * VPR);
-      const int r = vv / VPR, kv = vv % VPR;
-      const int sel = r / SM;
+      const int r = vv / VPR;
+      akv[i] = (vv % VPR) * VE;
+      const int sel = NA == 2 ? r / SM : seg;
       const int64_t grow = row0 + (r % SM);
-      const int64_t k = k0 + (int64_t)kv * VE;
-      const OpRef& ar = pb.a[nA == 2 ? sel : seg];
-      u32x4_t val = {0u, 0u, 0u, 0u};
-      if (grow < mrows && k < kk) {
-        const E* p = (const E*)ar.base + off(ar, u) + (int64_t)pl * L.plane + grow * ld + k;
-        val = *(const u32x4_t*)p;
-      }
-      ra[i] = val;
+      aok[i] = grow < mrows;
+      const OpRef& ar = pb.a[sel];
+      ap[i] = (const E*)ar.base + off(ar, u) + (int64_t)pl * L.plane + (aok[i] ? grow : 0) * ld + akv[i];
     }
 #pragma unroll
     for (int i = 0; i < BV; ++i) {
       const int v = tid + i * kThreads;
       const int pl = v / (BN * VPR);
       const int vv = v % (BN * VPR);
-      const int r = vv / VPR, kv = vv % VPR;
-      const int sel = r / SN;
+      const int r = vv / VPR;
+      bkv[i] = (vv % VPR) * VE;
+      const int sel = NB == 2 ? r / SN : seg;
       const int64_t gcol = col0 + (r % SN);
-      const int64_t k = k0 + (int64_t)kv * VE;
-      const OpRef& br = pb.b[nB == 2 ? sel : seg];
+      bok[i] = gcol < ncols;
+      const OpRef& br = pb.b[sel];
+      bp[i] = (const E*)br.base + off(br, u) + (int64_t)pl * L.plane + (bok[i] ? gcol : 0) * ld + bkv[i];
+    }
+  };
+  u32x4_t ra[AV], rb[BV];
+  auto gload = [&](int kt) {
+    const int64_t k0 = (int64_t)(kt % kps) * BK;
+#pragma unroll
+    for (int i = 0; i < AV; ++i) {
       u32x4_t val = {0u, 0u, 0u, 0u};
-      if (gcol < ncols && k < kk) {
-        const E* p = (const E*)br.base + off(br, u) + (int64_t)pl * L.plane + gcol * ld + k;
-        val = *(const u32x4_t*)p;
-      }
+      if (aok[i] && k0 + akv[i] < kk) val = *(const GVec*)(ap[i] + k0);
+      ra[i] = val;
+    }
+#pragma unroll
+    for (int i = 0; i < BV; ++i) {
+      u32x4_t val = {0u, 0u, 0u, 0u};
+      if (bok[i] && k0 + bkv[i] < kk) val = *(const GVec*)(bp[i] + k0);
       rb[i] = val;
     }
   };
@@ -202,23 +266,17 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmLaunch L) {
       const int v = tid + i * kThreads;
       const int pl = v / (BM * VPR);
       const int vv = v % (BM * VPR);
-      const int r = vv / VPR, kv = vv % VPR;
-      *(u32x4_t*)(a + pl * BM * PITCH + r * PITCH + kv * VE) = ra[i];
+      *(u32x4_t*)(a + pl * BM * PITCH + (vv / VPR) * PITCH + (vv % VPR) * VE) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < BV; ++i) {
       const int v = tid + i * kThreads;
       const int pl = v / (BN * VPR);
       const int vv = v % (BN * VPR);
-      const int r = vv / VPR, kv = vv % VPR;
-      *(u32x4_t*)(b + pl * BN * PITCH + r * PITCH + kv * VE) = rb[i];
+      *(u32x4_t*)(b + pl * BN * PITCH + (vv / VPR) * PITCH + (vv % VPR) * VE) = rb[i];
     }
   };
 
-  // -------- accumulators
-  constexpr int MT = C::MT, TM = C::TM, TN = C::TN;
-  constexpr int WTM = MT * TM, WTN = MT * TN;             // wave tile
-  constexpr int NACC = (P == Prec::F64) ? 4 : 16;
   using AccV = typename std::conditional<P == Prec::F64, f64x4_t, f32x16_t>::type;
   AccV acc[TM][TN];
 #pragma unroll
@@ -237,13 +295,13 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmLaunch L) {
       double av[TM][4], bv[TN][4];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        const double* p = a + (wm * WTM + i * MT + lr) * PITCH + g * 4;
+        const double* p = a + (frag_row_lds(i) + lr) * PITCH + g * 4;
 #pragma unroll
         for (int q = 0; q < 4; ++q) av[i][q] = p[q];
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        const double* p = b + (wn * WTN + j * MT + lr) * PITCH + g * 4;
+        const double* p = b + (frag_col_lds(j) + lr) * PITCH + g * 4;
 #pragma unroll
         for (int q = 0; q < 4; ++q) bv[j][q] = p[q];
       }
@@ -262,14 +320,12 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmLaunch L) {
         float av[TM][4], bv[TN][4];
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
-          const float* p = a + (wm * WTM + i * MT + lr) * PITCH + g * 16 + kq * 4;
-          float4 t = *(const float4*)p;
+          float4 t = *(const float4*)(a + (frag_row_lds(i) + lr) * PITCH + g * 16 + kq * 4);
           av[i][0] = t.x; av[i][1] = t.y; av[i][2] = t.z; av[i][3] = t.w;
         }
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-          const float* p = b + (wn * WTN + j * MT + lr) * PITCH + g * 16 + kq * 4;
-          float4 t = *(const float4*)p;
+          float4 t = *(const float4*)(b + (frag_col_lds(j) + lr) * PITCH + g * 16 + kq * 4);
           bv[j][0] = t.x; bv[j][1] = t.y; bv[j][2] = t.z; bv[j][3] = t.w;
         }
 #pragma unroll
@@ -288,18 +344,18 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmLaunch L) {
         bf16x8_t ah[TM], bh[TN];
 #pragma unroll
         for (int i = 0; i < TM; ++i)
-          ah[i] = *(const bf16x8_t*)(a + (wm * WTM + i * MT + lr) * PITCH + ks * 16 + g * 8);
+          ah[i] = *(const bf16x8_t*)(a + (frag_row_lds(i) + lr) * PITCH + ks * 16 + g * 8);
 #pragma unroll
         for (int j = 0; j < TN; ++j)
-          bh[j] = *(const bf16x8_t*)(b + (wn * WTN + j * MT + lr) * PITCH + ks * 16 + g * 8);
+          bh[j] = *(const bf16x8_t*)(b + (frag_col_lds(j) + lr) * PITCH + ks * 16 + g * 8);
         if constexpr (P == Prec::BF16X3) {
           bf16x8_t al[TM], bl[TN];
 #pragma unroll
           for (int i = 0; i < TM; ++i)
-            al[i] = *(const bf16x8_t*)(a + BM * PITCH + (wm * WTM + i * MT + lr) * PITCH + ks * 16 + g * 8);
+            al[i] = *(const bf16x8_t*)(a + BM * PITCH + (frag_row_lds(i) + lr) * PITCH + ks * 16 + g * 8);
 #pragma unroll
           for (int j = 0; j < TN; ++j)
-            bl[j] = *(const bf16x8_t*)(b + BN * PITCH + (wn * WTN + j * MT + lr) * PITCH + ks * 16 + g * 8);
+            bl[j] = *(const bf16x8_t*)(b + BN * PITCH + (frag_col_lds(j) + lr) * PITCH + ks * 16 + g * 8);
 #pragma unroll
           for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -317,13 +373,15 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmLaunch L) {
     }
   };
 
-  // -------- main loop (double-buffered)
+  // -------- main loop (double-buffered, one barrier per k tile)
   if (ktiles > 0) {
+    set_seg(0);
     gload(0);
     sstore(0);
     __syncthreads();
     for (int kt = 0; kt < ktiles; ++kt) {
       const bool more = kt + 1 < ktiles;
+      if (more && (kt + 1) % kps == 0) set_seg((kt + 1) / kps);
       if (more) gload(kt + 1);
       compute(kt & 1);
       if (more) sstore((kt + 1) & 1);
@@ -331,101 +389,125 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmLaunch L) {
     }
   }
 
-  // -------- stage accumulators through LDS
-  Acc* Cs = (Acc*)smem;
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int r = 0; r < NACC; ++r) {
-        int rr, cc;
-        if constexpr (P == Prec::F64) {
-          // f64 16x16x4: accumulator r of lane l holds row l/16 + 4r
-          rr = (lane >> 4) + 4 * r;
-          cc = lane & 15;
-        } else {
-          rr = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-          cc = lane & 31;
-        }
-        Cs[(wm * WTM + i * MT + rr) * CPITCH + wn * WTN + j * MT + cc] = acc[i][j][r];
-      }
-  __syncthreads();
-
-  // -------- epilogue
-  const int np_ = nA * nB;
+  // -------- epilogue straight from the accumulators
+  constexpr int NPROD = NA * NB;
+  constexpr int GI = NA == 2 ? 1 : TM;        // distinct row positions
+  constexpr int GJ = NB == 2 ? 1 : TN;        // distinct column positions
   Acc addc[kMaxAdd];
   const void* addp[kMaxAdd];
-  for (int x = 0; x < pb.nadd; ++x) {
+  const int nadd = pb.nadd;
+  for (int x = 0; x < nadd; ++x) {
     addc[x] = (Acc)pb.add_coef[(int64_t)u.slot * kMaxAdd + x];
     addp[x] = (const char*)pb.add[x].base + off(pb.add[x], u) * (int64_t)sizeof(E);
   }
-  auto vals_at = [&](int r, int c, Acc* v) {
-    for (int a = 0; a < nA; ++a)
-      for (int b = 0; b < nB; ++b) v[a * nB + b] = Cs[(a * SM + r) * CPITCH + b * SN + c];
-    if (pb.nadd) {
-      const int64_t gi = (row0 + r) * ld + col0 + c;
-      for (int x = 0; x < pb.nadd; ++x) v[0] += addc[x] * load_st<P>(addp[x], gi, L.plane);
-    }
-  };
-  double hsum[kMaxHad] = {0.0, 0.0, 0.0, 0.0};
+  const int nout = pb.nout;
+  void* obase[kMaxOut];
+  for (int o = 0; o < nout; ++o)
+    obase[o] = (char*)pb.out[o].base +
+               off(pb.out[o], u) * (int64_t)(pb.out[o].type == 0 ? sizeof(Acc) : sizeof(E));
   const double* hmat = pb.nhad ? (const double*)pb.had_h.base + off(pb.had_h, u) : nullptr;
-  // row-major outputs, Hadamard sums
-  for (int e = tid; e < SM * SN; e += kThreads) {
-    const int r = e / SN, c = e % SN;
-    const int64_t gr = row0 + r, gc = col0 + c;
-    if (gr >= mrows || gc >= ncols) continue;
-    Acc v[4];
-    vals_at(r, c, v);
-    for (int o = 0; o < pb.nout; ++o) {
-      const OutSpec& os = pb.out[o];
-      if (os.layout != 0) continue;
-      Acc s = 0;
-      for (int q = 0; q < np_; ++q) s += (Acc)os.coef[q] * v[q];
-      store_out<P>(os, off(os, u) + gr * ld + gc, L.plane, s);
-    }
-    if (pb.nhad) {
-      const double h = hmat[gr * ld + gc];
-      for (int q = 0; q < pb.nhad; ++q) {
-        double s = 0.0;
-        for (int t = 0; t < np_; ++t) s += (double)pb.had_coef[q][t] * (double)v[t];
-        hsum[q] += s * h;
+  double hsum[kMaxHad] = {0.0, 0.0, 0.0, 0.0};
+  const int nh = pb.nhad;
+  const int ac = acc_col<P>(lane);
+  // Row-major outputs are written element by element (consecutive lanes hold
+  // consecutive columns).  For 32 x 32 tiles, accumulators 4q .. 4q+3 of a
+  // lane are four consecutive rows, so transposed outputs are written as one
+  // 4-element vector per lane.
+  constexpr int RG = (P == Prec::F64) ? 1 : 4;            // rows packed per transposed store
+#pragma unroll
+  for (int gi = 0; gi < GI; ++gi)
+#pragma unroll
+    for (int gj = 0; gj < GJ; ++gj) {
+      const int64_t rbase = row0 + frag_row_out(gi);
+      const int64_t gc = col0 + frag_col_out(gj) + ac;
+      const bool colok = gc < ncols;
+#pragma unroll
+      for (int q = 0; q < NACC / RG; ++q) {
+        Acc v[RG][NPROD];
+        int64_t grs[RG];
+#pragma unroll
+        for (int e = 0; e < RG; ++e) {
+          const int r = q * RG + e;
+          grs[e] = rbase + acc_row<P>(lane, r);
+#pragma unroll
+          for (int a = 0; a < NA; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) v[e][a * NB + b] = acc[NA == 2 ? a : gi][NB == 2 ? b : gj][r];
+          if (nadd && colok && grs[e] < mrows) {
+            const int64_t gn = grs[e] * ld + gc;
+            for (int x = 0; x < nadd; ++x) v[e][0] += addc[x] * load_st<P>(addp[x], gn, L.plane);
+          }
+        }
+        const bool full = colok && grs[RG - 1] < mrows;   // all RG rows in range (they are consecutive)
+        for (int o = 0; o < nout; ++o) {
+          const OutSpec& os = pb.out[o];
+          Acc sv[RG];
+#pragma unroll
+          for (int e = 0; e < RG; ++e) {
+            Acc s = 0;
+#pragma unroll
+            for (int t = 0; t < NPROD; ++t) s += (Acc)os.coef[t] * v[e][t];
+            sv[e] = s;
+          }
+          if (os.layout != 0 && RG == 4 && full) {
+            store_out_vec4<P>(os.type, obase[o], gc * ld + grs[0], L.plane, sv);
+          } else {
+#pragma unroll
+            for (int e = 0; e < RG; ++e) {
+              if (!colok || grs[e] >= mrows) continue;
+              store_out<P>(os.type, obase[o], os.layout == 0 ? grs[e] * ld + gc : gc * ld + grs[e], L.plane, sv[e]);
+            }
+          }
+        }
+        if (nh && colok) {
+#pragma unroll
+          for (int e = 0; e < RG; ++e) {
+            if (grs[e] >= mrows) continue;
+            const double h = hmat[grs[e] * ld + gc];
+            for (int hq = 0; hq < nh; ++hq) {
+              double s = 0.0;
+#pragma unroll
+              for (int t = 0; t < NPROD; ++t) s += (double)pb.had_coef[hq][t] * (double)v[e][t];
+              hsum[hq] += s * h;
+            }
+          }
+        }
       }
     }
-  }
-  // transposed outputs: consecutive threads walk down a column
-  bool anyT = false;
-  for (int o = 0; o < pb.nout; ++o) anyT |= pb.out[o].layout != 0;
-  if (anyT) {
-    for (int e = tid; e < SM * SN; e += kThreads) {
-      const int r = e % SM, c = e / SM;
-      const int64_t gr = row0 + r, gc = col0 + c;
-      if (gr >= mrows || gc >= ncols) continue;
-      Acc v[4];
-      vals_at(r, c, v);
-      for (int o = 0; o < pb.nout; ++o) {
-        const OutSpec& os = pb.out[o];
-        if (os.layout == 0) continue;
-        Acc s = 0;
-        for (int q = 0; q < np_; ++q) s += (Acc)os.coef[q] * v[q];
-        store_out<P>(os, off(os, u) + gc * ld + gr, L.plane, s);
-      }
-    }
-  }
-  if (pb.nhad) {
-    // deterministic block reduction: wave tree, then waves in order
-    for (int q = 0; q < pb.nhad; ++q) {
+  if (nh) {
+    // deterministic block reduction: wave tree, then the four waves in order
+    for (int q = 0; q < nh; ++q) {
       double s = hsum[q];
       for (int d = 32; d > 0; d >>= 1) s += __shfl_down(s, d, 64);
       if (lane == 0) red[wave * kMaxHad + q] = s;
     }
     __syncthreads();
-    if (tid < pb.nhad) {
+    if (tid < nh) {
       double s = red[0 * kMaxHad + tid] + red[1 * kMaxHad + tid];
       s += red[2 * kMaxHad + tid];
       s += red[3 * kMaxHad + tid];
-      pb.had_part[((int64_t)u.slot * pb.nhad + tid) * pb.had_ntiles + tile] = s;
+      pb.had_part[((int64_t)u.slot * nh + tid) * pb.had_ntiles + tile] = s;
     }
+  }
+}
+
+template <Prec P>
+__global__ __launch_bounds__(kThreads) void gemm_kernel(GemmLaunch L) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[Smem<P>::BYTES];
+  __shared__ double red[4 * kMaxHad];
+  const int64_t total = (int64_t)gridDim.x * gridDim.y;
+  const int64_t lin = xcd_remap((int64_t)blockIdx.y * gridDim.x + blockIdx.x, total);
+  const int tile = (int)(lin % gridDim.x);
+  const int py = (int)(lin / gridDim.x);
+  const int ui = py / L.nprob, pi = py % L.nprob;
+  const Prob& pb = L.probs[pi];
+  const Unit u = L.units[ui];
+  const int mode = (pb.nA == 2 ? 2 : 0) + (pb.nB == 2 ? 1 : 0);
+  switch (mode) {
+    case 0: gemm_body<P, 1, 1>(L, pb, u, tile, smem, red); break;
+    case 1: gemm_body<P, 1, 2>(L, pb, u, tile, smem, red); break;
+    case 2: gemm_body<P, 2, 1>(L, pb, u, tile, smem, red); break;
+    default: gemm_body<P, 2, 2>(L, pb, u, tile, smem, red); break;
   }
 }
 

@@ -121,6 +121,27 @@ struct gf2_ctx {
   std::vector<DevBuf> pool;       // scratch allocations owned by the context
   int64_t max_units = 0;          // chunk size tuning (0 = automatic)
   std::string chain_key;          // (n, np, precision) of the last chain layout
+  // optional per-kernel-class timing with HIP events on ctx->stream
+  bool prof = false;
+  struct Ev { std::string name; hipEvent_t a, b; double flops, bytes; };
+  std::vector<Ev> events;
+};
+
+// Records HIP events around one launch when profiling is on.
+struct ProfScope {
+  gf2_ctx* ctx;
+  size_t idx = (size_t)-1;
+  ProfScope(gf2_ctx* c, const char* name, double flops = 0.0, double bytes = 0.0) : ctx(c) {
+    if (!ctx->prof) return;
+    gf2_ctx::Ev e{name, nullptr, nullptr, flops, bytes};
+    if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) return;
+    (void)hipEventRecord(e.a, ctx->stream);
+    ctx->events.push_back(e);
+    idx = ctx->events.size() - 1;
+  }
+  ~ProfScope() {
+    if (idx != (size_t)-1) (void)hipEventRecord(ctx->events[idx].b, ctx->stream);
+  }
 };
 
 struct gf2_split_h {

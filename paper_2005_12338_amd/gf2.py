@@ -75,6 +75,9 @@ _SIGS = {
                              C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "gf2_rng_words": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int64,
                                 C.POINTER(C.c_uint64)]),
+    "gf2_set_profiling": (C.c_int, [C.c_void_p, C.c_int]),
+    "gf2_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.POINTER(C.c_int32)]),
 }
 
 
@@ -301,6 +304,27 @@ class Context:
                                         _ptr(e_samples), ns, float(n_elec), C.byref(e), C.byref(epe),
                                         C.byref(se)))
         return e.value, epe.value, se.value
+
+    def set_profiling(self, on: bool):
+        self._check(self.lib.gf2_set_profiling(self.h, 1 if on else 0))
+
+    def profile_read(self):
+        """{kernel class: dict(launches, ms, flops, bytes)} since the last read."""
+        cap = 64
+        names = C.create_string_buffer(32 * cap)
+        la = np.zeros(cap, dtype=np.int64)
+        ms = np.zeros(cap)
+        fl = np.zeros(cap)
+        by = np.zeros(cap)
+        cnt = C.c_int32()
+        self._check(self.lib.gf2_profile_read(self.h, cap, names, la.ctypes.data, ms.ctypes.data,
+                                              fl.ctypes.data, by.ctypes.data, C.byref(cnt)))
+        out = {}
+        raw = names.raw
+        for i in range(cnt.value):
+            nm = raw[32 * i:32 * (i + 1)].split(b"\0")[0].decode()
+            out[nm] = dict(launches=int(la[i]), ms=float(ms[i]), flops=float(fl[i]), bytes=float(by[i]))
+        return out
 
     def rng_words(self, seed: int, stream: int, s: int, q0: int, count: int) -> np.ndarray:
         out = np.zeros(count, dtype=np.uint64)
