@@ -223,6 +223,16 @@ gf2_status gf2_set_profiling(gf2_ctx* ctx, int on);
 gf2_status gf2_profile_read(gf2_ctx* ctx, int32_t cap, char* names, int64_t* launches,
                             double* total_ms, double* flops, double* bytes, int32_t* count);
 
+/* ------------------------------------------------------------ test hook ---
+ * The chain's GEMM kernel on its own: C[b] = A[b] B[b]^T for b < batch,
+ * square n x n operands (row-major, leading dimension ld = n rounded up to a
+ * multiple of 32, zero padded, device).  prec FP64: double operands and
+ * output; FP32: float; BF16: bf16 operands, float output; BF16X3: each
+ * operand is two bf16 planes (hi, lo) of ld*ld elements each.  For tests and
+ * benchmarks of the kernel itself. */
+gf2_status gf2_debug_gemm(gf2_ctx* ctx, gf2_precision prec, int64_t n, int64_t batch,
+                          const void* A, const void* Bt, void* C);
+
 #ifdef __cplusplus
 }
 #endif

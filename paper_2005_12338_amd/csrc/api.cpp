@@ -137,6 +137,9 @@ int tiles_of(const Prob& p, Prec prec, int64_t m, int64_t nc) {
 }
 int tiles_of(const Prob& p, Prec prec, int64_t n) { return tiles_of(p, prec, n, n); }
 
+void run_dd(gf2_ctx* ctx, const gf2_split_h* sp, const double* G, const double* Gb, int64_t ntau,
+            double* out);
+
 }  // namespace
 
 // ======================================================================= API
@@ -349,6 +352,18 @@ gf2_status gf2_split(gf2_ctx* ctx, const void* B, gf2_dtype dtype, int64_t n, in
     }
     toff[nbk] = (int32_t)tq.size();
 
+    // per-orbital (Q, a) lists, Q ascending
+    std::vector<int32_t> ooff(n + 1, 0), oq;
+    {
+      std::vector<std::vector<int32_t>> ol(n);
+      for (int64_t q = 0; q < naux; ++q)
+        for (int a = 0; a < w[q]; ++a) ol[idx[q * kWMax + a]].push_back((int32_t)((q << 5) | a));
+      for (int64_t i = 0; i < n; ++i) {
+        ooff[i] = (int32_t)oq.size();
+        oq.insert(oq.end(), ol[i].begin(), ol[i].end());
+      }
+      ooff[n] = (int32_t)oq.size();
+    }
     auto alloc = [&](void** p, size_t bytes) {
       if (bytes == 0) bytes = 16;
       hipError_t e = hipMalloc(p, bytes);
@@ -363,6 +378,10 @@ gf2_status gf2_split(gf2_ctx* ctx, const void* B, gf2_dtype dtype, int64_t n, in
     alloc((void**)&h->pat_q, pq.size() * 4);
     alloc((void**)&h->row_off, toff.size() * 4);
     alloc((void**)&h->row_q, tq.size() * 4);
+    alloc((void**)&h->orb_off, ooff.size() * 4);
+    alloc((void**)&h->orb_q, oq.size() * 4);
+    h2d(ctx, h->orb_off, ooff.data(), ooff.size());
+    if (!oq.empty()) h2d(ctx, h->orb_q, oq.data(), oq.size());
     h2d(ctx, h->w, w.data(), w.size());
     h2d(ctx, h->idx, idx.data(), idx.size());
     if (!pij.empty()) h2d(ctx, h->pat_ij, pij.data(), pij.size());
@@ -386,7 +405,8 @@ gf2_status gf2_split(gf2_ctx* ctx, const void* B, gf2_dtype dtype, int64_t n, in
 
 void gf2_split_free(gf2_split_h* h) {
   if (!h) return;
-  void* ps[] = {h->w, h->idx, h->blk, h->blk32, h->pat_ij, h->pat_off, h->pat_q, h->row_off, h->row_q};
+  void* ps[] = {h->w, h->idx, h->blk, h->blk32, h->pat_ij, h->pat_off, h->pat_q, h->row_off, h->row_q,
+                h->orb_off, h->orb_q};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   delete h;
@@ -499,16 +519,29 @@ gf2_status gf2_sigma_det(gf2_ctx* ctx, const gf2_split_h* split, const double* G
   return guarded(ctx, [&] {
     GF2_REQUIRE(split && split->owner == ctx, GF2_E_STATE, "split handle of another context");
     GF2_REQUIRE(G && Gbar && Sigma_det && ntau > 0 && ntau <= 65535, GF2_E_ARG, "bad sigma_det arguments");
-    {
-      ProfScope ps(ctx, "dblock");
-      launch_dblock(G, Gbar, split->n, ntau, split->wmax, split->w, split->idx, split->blk, split->row_off,
-                    split->row_q, Sigma_det, ctx->stream);
-    }
+    run_dd(ctx, split, G, Gbar, ntau, Sigma_det);
     GF2_HIP(hipStreamSynchronize(ctx->stream));
   });
 }
 
 namespace {
+
+// Sigma[D,D] for every tau: the register strip form when supports are at
+// most 8 orbitals wide, the LDS tile form otherwise.
+void run_dd(gf2_ctx* ctx, const gf2_split_h* sp, const double* G, const double* Gb, int64_t ntau,
+            double* out) {
+  ProfScope ps(ctx, "dblock");
+  if (sp->wmax <= 8) {
+    const int64_t per = dd_strip_bytes(sp->n, sp->naux, sp->wmax, 1);
+    const int64_t tb = std::max<int64_t>(1, std::min<int64_t>(ntau, (int64_t)2e9 / std::max<int64_t>(per, 1)));
+    auto* strip = (double*)ctx_buf(ctx, "dd_strip", (size_t)(per * tb));
+    launch_dd_strips(G, Gb, sp->n, sp->naux, ntau, sp->wmax, sp->w, sp->idx, sp->blk, sp->orb_off, sp->orb_q,
+                     strip, tb, out, ctx->stream);
+  } else {
+    launch_dblock(G, Gb, sp->n, ntau, sp->wmax, sp->w, sp->idx, sp->blk, sp->row_off, sp->row_q, out,
+                  ctx->stream);
+  }
+}
 
 struct ChainBufs {
   int64_t n, np, np2, plane;
@@ -839,11 +872,7 @@ gf2_status gf2_sigma_tau(gf2_ctx* ctx, const gf2_split_h* split, const void* B, 
     const size_t bytes = (size_t)(ntau * n * n) * 8;
     auto* det = (double*)ctx_buf(ctx, "t_det", bytes);
     auto* sum = (double*)ctx_buf(ctx, "t_sum", bytes, true);
-    {
-      ProfScope ps(ctx, "dblock");
-      launch_dblock(G, Gbar, n, ntau, split->wmax, split->w, split->idx, split->blk, split->row_off,
-                    split->row_q, det, ctx->stream);
-    }
+    run_dd(ctx, split, G, Gbar, ntau, det);
     run_stoch(ctx, split, B, G, Gbar, ntau, sampling, to_prec(prec), sum, e_samples);
     launch_finalize(det, sum, n, ntau, 0.5 / (double)sampling->ns, Sigma, ctx->stream);
     GF2_HIP(hipGetLastError());
@@ -872,6 +901,31 @@ gf2_status gf2_energy(gf2_ctx* ctx, int64_t n, int64_t ntau, const double* w, co
     if (E_tot) *E_tot = h[0];
     if (E_per_e) *E_per_e = h[0] / n_elec;
     if (stderr_tot) *stderr_tot = h[2];
+  });
+}
+
+gf2_status gf2_debug_gemm(gf2_ctx* ctx, gf2_precision prec, int64_t n, int64_t batch, const void* A,
+                          const void* Bt, void* C) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(n > 0 && batch > 0 && batch <= 65535 && A && Bt && C, GF2_E_ARG, "bad gemm arguments");
+    const Prec p = to_prec(prec);
+    const int64_t ld = pad_dim(n), ld2 = ld * ld;
+    const int64_t st = st_planes(p) * ld2;
+    Prob pb = prob0();
+    pb.a[0] = opref(A, 0, st);
+    pb.b[0] = opref(Bt, 0, st);
+    pb.nout = 1;
+    pb.out[0] = outspec(C, 0, {1.0f}, 0, 0);
+    pb.out[0].st_s = ld2;
+    auto* probs = (Prob*)ctx_buf(ctx, "dbg_prob", sizeof(Prob));
+    h2d(ctx, probs, &pb, 1);
+    std::vector<Unit> uh(batch);
+    for (int64_t b = 0; b < batch; ++b) uh[b] = Unit{0, (int32_t)b, 0, 0};
+    auto* units = (Unit*)ctx_buf(ctx, "dbg_units", uh.size() * sizeof(Unit));
+    h2d(ctx, units, uh.data(), uh.size());
+    GemmLaunch L = chain_launch(probs, 1, units, (int32_t)batch, n, ld, ld2);
+    ProfScope ps(ctx, "debug_gemm", 2.0 * (double)n * n * n * batch);
+    launch_gemm(p, L, tiles_of(pb, p, n), ctx->stream);
   });
 }
 

@@ -111,9 +111,202 @@ __global__ __launch_bounds__(64 * NW) void k_dblock(const double* G, const doubl
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register form for supports of at most W orbitals.  One workgroup per
+// (tau, Q) builds the strip P_Q[a][j] = sum_Q' sum_d [S_Q'(d) = j] C_QQ'[a][d]
+// (rows S_Q, all columns): each lane evaluates one pair (Q, Q') with its
+// W x W blocks in registers,
+//   u = k_Q G[S_Q, S_Q'],  M = u k_Q',  T = M Gb[S_Q', S_Q],
+//   C = 2 Tr(T) M - T M,
+// and writes C to LDS; the chunk's contributions are then added to the
+// strip column by column in increasing Q' (fixed order).  A second kernel
+// sums the strips of every (Q, a) with S_Q(a) = i into row i of Sigma.
+// ---------------------------------------------------------------------------
+template <int W, int CH>
+__global__ __launch_bounds__(256) void k_dd_strip(const double* G, const double* Gb, int64_t n,
+                                                  int64_t naux, int32_t tau0, const int32_t* wq,
+                                                  const int32_t* idx, const double* blk,
+                                                  const int32_t* col_off, const int32_t* col_q,
+                                                  double* strip) {
+  __shared__ double cbuf[CH * W * W];
+  __shared__ double kq[W * W];
+  __shared__ int32_t span[2];
+  const int tid = threadIdx.x;
+  const int64_t q = blockIdx.x;
+  const int64_t t = tau0 + blockIdx.y;
+  const double* g = G + t * n * n;
+  const double* gb = Gb + t * n * n;
+  double* st = strip + ((int64_t)blockIdx.y * naux + q) * W * n;
+  const int w1 = wq[q];
+  const int32_t* s1 = idx + q * kWMax;
+  for (int e = tid; e < W * W; e += blockDim.x) {
+    const int a = e / W, b = e % W;
+    kq[e] = (a < w1 && b < w1) ? blk[q * kWMax * kWMax + a * kWMax + b] : 0.0;
+  }
+  for (int64_t e = tid; e < (int64_t)W * n; e += blockDim.x) st[e] = 0.0;
+  int sq[W];
+#pragma unroll
+  for (int a = 0; a < W; ++a) sq[a] = a < w1 ? s1[a] : 0;
+  __syncthreads();
+  if (w1 == 0) return;
+
+  for (int64_t c0 = 0; c0 < naux; c0 += CH) {
+    const int64_t r = c0 + tid;
+    const bool act = tid < CH && r < naux;
+    if (tid == 0) { span[0] = (int32_t)n; span[1] = -1; }
+    __syncthreads();
+    if (act) {
+      const int w2 = wq[r];
+      const int32_t* s2 = idx + r * kWMax;
+      int sr[W];
+#pragma unroll
+      for (int c = 0; c < W; ++c) sr[c] = c < w2 ? s2[c] : 0;
+      if (w2 > 0) {
+        atomicMin(&span[0], sr[0]);
+        atomicMax(&span[1], sr[w2 - 1]);
+      }
+      // u = k_Q G[S_Q, S_Q']  (W x W)
+      double u[W][W];
+#pragma unroll
+      for (int a = 0; a < W; ++a)
+#pragma unroll
+        for (int c = 0; c < W; ++c) u[a][c] = 0.0;
+#pragma unroll
+      for (int b = 0; b < W; ++b) {
+        if (b >= w1) break;
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+          const double gv = c < w2 ? g[(int64_t)sq[b] * n + sr[c]] : 0.0;
+#pragma unroll
+          for (int a = 0; a < W; ++a) u[a][c] += kq[a * W + b] * gv;
+        }
+      }
+      // M = u k_Q'
+      double m[W][W];
+#pragma unroll
+      for (int a = 0; a < W; ++a)
+#pragma unroll
+        for (int d = 0; d < W; ++d) m[a][d] = 0.0;
+      const double* kr = blk + r * kWMax * kWMax;
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        double row[W];
+#pragma unroll
+        for (int d = 0; d < W; ++d) row[d] = kr[c * kWMax + d];   // zero padded beyond w2
+#pragma unroll
+        for (int a = 0; a < W; ++a)
+#pragma unroll
+          for (int d = 0; d < W; ++d) m[a][d] += u[a][c] * row[d];
+      }
+      // T = M Gb[S_Q', S_Q]
+      double tt[W][W];
+#pragma unroll
+      for (int a = 0; a < W; ++a)
+#pragma unroll
+        for (int f = 0; f < W; ++f) tt[a][f] = 0.0;
+#pragma unroll
+      for (int d = 0; d < W; ++d) {
+        double row[W];
+#pragma unroll
+        for (int f = 0; f < W; ++f) row[f] = (d < w2 && f < w1) ? gb[(int64_t)sr[d] * n + sq[f]] : 0.0;
+#pragma unroll
+        for (int a = 0; a < W; ++a)
+#pragma unroll
+          for (int f = 0; f < W; ++f) tt[a][f] += m[a][d] * row[f];
+      }
+      double tr = 0.0;
+#pragma unroll
+      for (int a = 0; a < W; ++a) tr += tt[a][a];
+      double* cb = cbuf + tid * W * W;
+#pragma unroll
+      for (int a = 0; a < W; ++a)
+#pragma unroll
+        for (int d = 0; d < W; ++d) {
+          double s = 0.0;
+#pragma unroll
+          for (int f = 0; f < W; ++f) s += tt[a][f] * m[f][d];
+          cb[a * W + d] = 2.0 * tr * m[a][d] - s;
+        }
+    }
+    __syncthreads();
+    // add the chunk to the strip: output (a, j), contributions from the
+    // chunk's Q' with S_Q'(d) = j in increasing Q'
+    const int jlo = span[0], jhi = span[1];
+    const int64_t nout = (jhi >= jlo) ? (int64_t)w1 * (jhi - jlo + 1) : 0;
+    for (int64_t e = tid; e < nout; e += blockDim.x) {
+      const int a = (int)(e % w1);
+      const int j = jlo + (int)(e / w1);
+      int lo = col_off[j], hi = col_off[j + 1];
+      // first entry with Q' >= c0 (entries sorted by Q')
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((col_q[mid] >> 5) < c0) lo = mid + 1; else hi = mid;
+      }
+      double acc = 0.0;
+      for (int k = lo; k < col_off[j + 1]; ++k) {
+        const int64_t rr = col_q[k] >> 5;
+        if (rr >= c0 + CH) break;
+        acc += cbuf[(rr - c0) * W * W + a * W + (col_q[k] & 31)];
+      }
+      st[(int64_t)a * n + j] += acc;
+    }
+    __syncthreads();
+  }
+}
+
+// Sigma[t][i][j] = sum over (Q, a) with S_Q(a) = i of strip[t][Q][a][j].
+template <int W>
+__global__ void k_dd_gather(const double* strip, int64_t n, int64_t naux, int32_t tau0, int32_t ntb,
+                            const int32_t* col_off, const int32_t* col_q, double* out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)ntb * n * n) return;
+  const int64_t tb = e / (n * n), ij = e % (n * n), i = ij / n, j = ij % n;
+  double acc = 0.0;
+  for (int k = col_off[i]; k < col_off[i + 1]; ++k) {
+    const int64_t q = col_q[k] >> 5;
+    const int a = col_q[k] & 31;
+    acc += strip[((tb * naux + q) * W + a) * n + j];
+  }
+  out[((tau0 + tb) * n + i) * n + j] = acc;
+}
+
 }  // namespace
 
 int dblock_tile() { return TD; }
+
+int64_t dd_strip_bytes(int64_t n, int64_t naux, int32_t wmax, int64_t ntau_batch) {
+  const int W = wmax <= 4 ? 4 : wmax <= 6 ? 6 : 8;
+  return ntau_batch * naux * W * n * (int64_t)sizeof(double);
+}
+
+bool launch_dd_strips(const double* G, const double* Gb, int64_t n, int64_t naux, int64_t ntau, int32_t wmax,
+                      const int32_t* wq, const int32_t* idx, const double* blk, const int32_t* col_off,
+                      const int32_t* col_q, double* strip, int64_t ntau_batch, double* out, hipStream_t st) {
+  if (wmax > 8) return false;
+  for (int64_t t0 = 0; t0 < ntau; t0 += ntau_batch) {
+    const int32_t ntb = (int32_t)std::min<int64_t>(ntau_batch, ntau - t0);
+    dim3 grid((unsigned)naux, (unsigned)ntb);
+    const unsigned gb = (unsigned)(((int64_t)ntb * n * n + 255) / 256);
+    if (wmax <= 4) {
+      hipLaunchKernelGGL((k_dd_strip<4, 256>), grid, dim3(256), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
+                         col_off, col_q, strip);
+      hipLaunchKernelGGL((k_dd_gather<4>), dim3(gb), dim3(256), 0, st, strip, n, naux, (int32_t)t0, ntb, col_off,
+                         col_q, out);
+    } else if (wmax <= 6) {
+      hipLaunchKernelGGL((k_dd_strip<6, 256>), grid, dim3(256), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
+                         col_off, col_q, strip);
+      hipLaunchKernelGGL((k_dd_gather<6>), dim3(gb), dim3(256), 0, st, strip, n, naux, (int32_t)t0, ntb, col_off,
+                         col_q, out);
+    } else {
+      hipLaunchKernelGGL((k_dd_strip<8, 128>), grid, dim3(256), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
+                         col_off, col_q, strip);
+      hipLaunchKernelGGL((k_dd_gather<8>), dim3(gb), dim3(256), 0, st, strip, n, naux, (int32_t)t0, ntb, col_off,
+                         col_q, out);
+    }
+    GF2_HIP(hipGetLastError());
+  }
+  return true;
+}
 
 void launch_dblock(const double* G, const double* Gb, int64_t n, int64_t ntau, int32_t wmax,
                    const int32_t* wq, const int32_t* idx, const double* blk, const int32_t* tq_off,

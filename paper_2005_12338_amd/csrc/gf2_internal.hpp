@@ -167,6 +167,9 @@ struct gf2_split_h {
   // rows: for each orbital i the (Q, a) with S_Q[a] = i
   int32_t* row_off = nullptr;  // [n + 1]
   int32_t* row_q = nullptr;    // [..] Q * 32 + a
+  // per orbital i: the (Q, a) with S_Q[a] = i, sorted by Q (Q << 5 | a)
+  int32_t* orb_off = nullptr;  // [n + 1]
+  int32_t* orb_q = nullptr;
 };
 
 constexpr int kWMax = 32;

@@ -59,6 +59,13 @@ void launch_dblock(const double* G, const double* Gb, int64_t n, int64_t ntau, i
                    const int32_t* wq, const int32_t* idx, const double* blk, const int32_t* tq_off,
                    const int32_t* tq, double* out, hipStream_t st);
 
+int64_t dd_strip_bytes(int64_t n, int64_t naux, int32_t wmax, int64_t ntau_batch);
+// Register form of the deterministic block for supports of at most 8
+// orbitals (returns false, launching nothing, for wider supports).
+bool launch_dd_strips(const double* G, const double* Gb, int64_t n, int64_t naux, int64_t ntau, int32_t wmax,
+                      const int32_t* wq, const int32_t* idx, const double* blk, const int32_t* col_off,
+                      const int32_t* col_q, double* strip, int64_t ntau_batch, double* out, hipStream_t st);
+
 // Host numerics (eigen.cpp).
 // Symmetric eigendecomposition a = v diag(e) v^T (a row-major n x n,
 // overwritten); e ascending, v row-major with eigenvectors in columns.

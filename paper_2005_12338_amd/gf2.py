@@ -76,6 +76,8 @@ _SIGS = {
     "gf2_rng_words": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int64,
                                 C.POINTER(C.c_uint64)]),
     "gf2_set_profiling": (C.c_int, [C.c_void_p, C.c_int]),
+    "gf2_debug_gemm": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                                 C.c_void_p]),
     "gf2_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.POINTER(C.c_int32)]),
 }
@@ -304,6 +306,11 @@ class Context:
                                         _ptr(e_samples), ns, float(n_elec), C.byref(e), C.byref(epe),
                                         C.byref(se)))
         return e.value, epe.value, se.value
+
+    def debug_gemm(self, prec: str, n: int, A, Bt, Cout, batch: int = 1):
+        """C[b] = A[b] Bt[b]^T with the chain's GEMM kernel (padded square operands)."""
+        self._check(self.lib.gf2_debug_gemm(self.h, PREC[prec], n, batch, A.data_ptr(), Bt.data_ptr(),
+                                            Cout.data_ptr()))
 
     def set_profiling(self, on: bool):
         self._check(self.lib.gf2_set_profiling(self.h, 1 if on else 0))

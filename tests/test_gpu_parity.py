@@ -121,8 +121,10 @@ def test_green_rejects_bad_tau(ctx):
         ctx.green_tau(f, np.array([0.5, 60.0]), 50.0, n_occ=3)
 
 
-def test_sigma_det_matches_oracle(ctx):
-    pb = chain(10, 50.0, 4, 1e-2)
+@pytest.mark.parametrize("n_dimer,eps", [(10, 1e-2), (12, 1e-3), (12, 1e-4), (9, 1e-6), (6, 0.0)])
+def test_sigma_det_matches_oracle(ctx, n_dimer, eps):
+    """Register strip form (supports <= 4, 6, 8) and the LDS tile form (wider)."""
+    pb = chain(n_dimer, 50.0, 4, eps)
     o = oracle_setup(pb)
     B, G, Gb, mu, tau, w = _gpu_inputs(ctx, pb, torch.float64)
     spl = ctx.split(B, pb["eps"])
@@ -225,3 +227,46 @@ def test_sigma_stoch_batches_equal_one_call(ctx):
     ctx.sigma_stoch(spl, B, G, Gb, s_b, ns=2, seed=2, prec="fp64", s0=4, e_samples=e_b[4:])
     assert torch.equal(e_all, e_b)
     assert torch.equal(s_all, s_b)
+
+
+@pytest.mark.parametrize("prec,n,batch", [("fp64", 70, 3), ("fp32", 150, 2), ("bf16", 200, 2), ("bf16x3", 130, 2)])
+def test_gemm_kernel_matches_torch_reference(ctx, prec, n, batch):
+    """The chain's GEMM kernel alone, against a plain PyTorch reference of the
+    same product (FP64 / FP32 on the CPU)."""
+    ld = (n + 31) // 32 * 32
+    g = torch.Generator().manual_seed(7)
+    a = torch.randn(batch, n, n, generator=g, dtype=torch.float64)
+    b = torch.randn(batch, n, n, generator=g, dtype=torch.float64)
+
+    def pad(x, dt):
+        out = torch.zeros(batch, ld, ld, dtype=dt)
+        out[:, :n, :n] = x.to(dt)
+        return out
+
+    if prec == "fp64":
+        A, Bt, ref = pad(a, torch.float64), pad(b, torch.float64), a @ b.transpose(1, 2)
+        cdt, tol = torch.float64, 1e-12
+    elif prec == "fp32":
+        A, Bt = pad(a, torch.float32), pad(b, torch.float32)
+        ref = A.double() @ Bt.double().transpose(1, 2)
+        ref = ref[:, :n, :n]
+        cdt, tol = torch.float32, 1e-5
+    elif prec == "bf16":
+        A, Bt = pad(a, torch.bfloat16), pad(b, torch.bfloat16)
+        ref = (A.float() @ Bt.float().transpose(1, 2))[:, :n, :n].double()
+        cdt, tol = torch.float32, 1e-5
+    else:
+        ah = a.to(torch.bfloat16)
+        al = (a - ah.double()).to(torch.bfloat16)
+        bh = b.to(torch.bfloat16)
+        bl = (b - bh.double()).to(torch.bfloat16)
+        A = torch.cat([pad(ah.double(), torch.bfloat16), pad(al.double(), torch.bfloat16)], dim=1)
+        Bt = torch.cat([pad(bh.double(), torch.bfloat16), pad(bl.double(), torch.bfloat16)], dim=1)
+        ref = a @ b.transpose(1, 2)
+        cdt, tol = torch.float32, 3e-5          # x3 products keep ~16 mantissa bits
+    C = torch.zeros(batch, ld, ld, dtype=cdt, device="cuda")
+    ctx.debug_gemm(prec, n, A.contiguous().cuda(), Bt.contiguous().cuda(), C, batch=batch)
+    got = C.cpu().double()[:, :n, :n]
+    err = (got - ref).abs().max().item() / ref.abs().max().item()
+    assert err < tol, err
+    assert torch.count_nonzero(C.cpu()[:, n:, :]) == 0 and torch.count_nonzero(C.cpu()[:, :, n:]) == 0
