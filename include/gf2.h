@@ -147,11 +147,13 @@ gf2_status gf2_tau_grid(double beta, int64_t ntau, double* tau, double* w);
  * F C = S C eps (C^T S C = I), e~ = eps - mu, f = 1/(1+exp(beta e~)),
  *   G[t]    = G(tau_t)        = -C diag((1-f) exp(-e~ tau_t)) C^T
  *   Gbar[t] = G(beta - tau_t) = -C diag(f exp(e~ tau_t)) C^T
- * F, S host [n][n] (S NULL = identity); tau host [ntau] in (0, beta).
+ * F, S host [n][n] (S NULL = identity); tau host [ntau] in [0, beta], with the
+ * end points read as one-sided limits (G(0+), G(beta-)): Gbar at tau = 0 is
+ * -C diag(f) C^T = -P/2 for the density matrix P.
  * If n_occ > 0, mu is replaced by the mid-gap value (eps[n_occ-1] +
  * eps[n_occ]) / 2; the value used is returned in *mu_out (host, may be
  * NULL).  G, Gbar: device [ntau][n][n] FP64.
- * Errors: GF2_E_ARG for beta <= 0, tau outside (0, beta), n_occ >= n, or an
+ * Errors: GF2_E_ARG for beta <= 0, tau outside [0, beta], n_occ >= n, or an
  * S that is not positive definite. */
 gf2_status gf2_green_tau(gf2_ctx* ctx, int64_t n, const double* F, const double* S,
                          double mu, int64_t n_occ, double beta, int64_t ntau,

@@ -10,6 +10,14 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "gf2_proposal.h"
+
+void launch_mlp_init(const double* phi, int64_t ntotal, uint64_t seed, const gf2_mlp& m, hipStream_t st);
+void launch_mlp_train(const gf2_mlp& m, int32_t nchains, const int64_t* coff, const double* phi, const double* that,
+                      int32_t steps, float lr, int64_t step0, float* z, float* dz, double* grad, double* loss,
+                      hipStream_t st);
+void launch_mlp_infer(const gf2_mlp& m, const double* phi, int64_t naux, int bf16, double alpha, float* z, double* p,
+                      hipStream_t st);
 
 namespace {
 
@@ -432,7 +440,7 @@ gf2_status gf2_green_tau(gf2_ctx* ctx, int64_t n, const double* F, const double*
     GF2_REQUIRE(beta > 0 && std::isfinite(beta), GF2_E_ARG, "beta must be positive");
     GF2_REQUIRE(n_occ < n, GF2_E_ARG, "n_occ must be < n");
     for (int64_t t = 0; t < ntau; ++t)
-      GF2_REQUIRE(tau[t] > 0 && tau[t] < beta, GF2_E_ARG, "tau outside (0, beta)");
+      GF2_REQUIRE(tau[t] >= 0 && tau[t] <= beta, GF2_E_ARG, "tau outside [0, beta]");
     std::vector<double> eps(n), c((size_t)(n * n));
     if (!S) {
       std::vector<double> a(F, F + n * n);
@@ -969,6 +977,116 @@ gf2_status gf2_profile_read(gf2_ctx* ctx, int32_t cap, char* names, int64_t* lau
       ++k;
     }
     if (count) *count = k;
+  });
+}
+
+// ------------------------------------------------------------ proposal ----
+gf2_status gf2_proposal_features(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const double* x,
+                                 const double* xq, const double* Gbeta, double* phi) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(split && split->owner == ctx, GF2_E_STATE, "split handle of another context");
+    GF2_REQUIRE(B == split->bsrc, GF2_E_STATE, "split handle belongs to a different B");
+    GF2_REQUIRE(x && xq && Gbeta && phi, GF2_E_ARG, "bad feature arguments");
+    auto* dx = (double*)ctx_buf(ctx, "pf_x", (size_t)split->n * 8);
+    auto* dq = (double*)ctx_buf(ctx, "pf_xq", (size_t)split->naux * 8);
+    h2d(ctx, dx, x, (size_t)split->n);
+    h2d(ctx, dq, xq, (size_t)split->naux);
+    launch_features(B, split->dtype == GF2_F64, split->n, split->naux, split->thresh, dx, dq, Gbeta, phi,
+                    ctx->stream);
+    GF2_HIP(hipGetLastError());
+    GF2_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+gf2_status gf2_proposal_targets(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const double* G,
+                                const double* Gbar, int64_t ntau, const double* w, double rel, double* t,
+                                double* tables) {
+  gf2_split_h* bt = nullptr;
+  gf2_status st = guarded(ctx, [&] {
+    GF2_REQUIRE(split && split->owner == ctx, GF2_E_STATE, "split handle of another context");
+    GF2_REQUIRE(B == split->bsrc, GF2_E_STATE, "split handle belongs to a different B");
+    GF2_REQUIRE(G && Gbar && w && t && ntau > 0 && rel > 0 && rel < 1, GF2_E_ARG, "bad target arguments");
+    GF2_REQUIRE(split->naux <= 8192, GF2_E_ARG, "targets need naux <= 8192");
+  });
+  if (st != GF2_OK) return st;
+  // truncated B on its numerical support, as a split with threshold rel
+  int64_t nnz = 0, wb = 0;
+  st = gf2_split(ctx, B, split->dtype, split->n, split->naux, rel, &bt, &nnz, &wb);
+  if (st != GF2_OK) return st;
+  st = guarded(ctx, [&] {
+    const int64_t naux = split->naux;
+    auto* dw = (double*)ctx_buf(ctx, "pt_w", (size_t)ntau * 8);
+    h2d(ctx, dw, w, (size_t)ntau);
+    double* tab = tables ? tables : (double*)ctx_buf(ctx, "pt_tab", (size_t)(4 * naux * naux) * 8);
+    launch_pair_tables(std::max<int>((int)wb, split->wmax), G, Gbar, split->n, ntau, dw, naux, bt->w, bt->idx,
+                       bt->blk, split->w, split->idx, split->blk, tab, ctx->stream);
+    launch_targets(tab, naux, t, ctx->stream);
+    GF2_HIP(hipGetLastError());
+    GF2_HIP(hipStreamSynchronize(ctx->stream));
+  });
+  gf2_split_free(bt);
+  return st;
+}
+
+gf2_status gf2_proposal_init(gf2_ctx* ctx, gf2_mlp* mlp, const double* phi, int64_t ntotal, uint64_t seed) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(mlp && phi && ntotal > 0, GF2_E_ARG, "bad init arguments");
+    launch_mlp_init(phi, ntotal, seed, *mlp, ctx->stream);
+    GF2_HIP(hipGetLastError());
+    GF2_HIP(hipStreamSynchronize(ctx->stream));
+    mlp->step = 0;
+  });
+}
+
+namespace {
+void mlp_run(gf2_ctx* ctx, const gf2_mlp* mlp, int32_t nchains, const int64_t* chain_off, const double* phi,
+             const double* t_hat, int32_t steps, double lr, double* loss, double* grad) {
+  GF2_REQUIRE(mlp && chain_off && phi && t_hat && nchains > 0 && nchains <= 1024, GF2_E_ARG,
+              "bad network arguments (1 <= nchains <= 1024)");
+  const int64_t ntotal = chain_off[nchains];
+  GF2_REQUIRE(ntotal > 0, GF2_E_ARG, "empty training set");
+  for (int32_t c = 0; c < nchains; ++c) GF2_REQUIRE(chain_off[c] <= chain_off[c + 1], GF2_E_ARG, "bad offsets");
+  auto* coff = (int64_t*)ctx_buf(ctx, "mlp_off", (size_t)(nchains + 1) * 8);
+  auto* z = (float*)ctx_buf(ctx, "mlp_z", (size_t)ntotal * 4);
+  auto* dz = (float*)ctx_buf(ctx, "mlp_dz", (size_t)ntotal * 4);
+  auto* g = (double*)ctx_buf(ctx, "mlp_g", (size_t)mlp_nparam() * 8);
+  auto* l = (double*)ctx_buf(ctx, "mlp_l", (size_t)std::max(1, steps) * 8);
+  h2d(ctx, coff, chain_off, (size_t)nchains + 1);
+  {
+    ProfScope ps(ctx, steps > 0 ? "mlp_train" : "mlp_grad");
+    launch_mlp_train(*mlp, nchains, coff, phi, t_hat, steps, (float)lr, mlp->step, z, dz, g, l, ctx->stream);
+  }
+  GF2_HIP(hipGetLastError());
+  if (loss) d2h(ctx, loss, l, (size_t)std::max(1, steps));
+  if (grad) d2h(ctx, grad, g, (size_t)mlp_nparam());
+  GF2_HIP(hipStreamSynchronize(ctx->stream));
+}
+}  // namespace
+
+gf2_status gf2_proposal_grad(gf2_ctx* ctx, const gf2_mlp* mlp, int32_t nchains, const int64_t* chain_off,
+                             const double* phi, const double* t_hat, double* loss, double* grad) {
+  return guarded(ctx, [&] { mlp_run(ctx, mlp, nchains, chain_off, phi, t_hat, 0, 0.0, loss, grad); });
+}
+
+gf2_status gf2_proposal_train(gf2_ctx* ctx, gf2_mlp* mlp, int32_t nchains, const int64_t* chain_off,
+                              const double* phi, const double* t_hat, int32_t steps, double lr, double* loss_hist) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(steps > 0 && lr > 0, GF2_E_ARG, "steps and lr must be positive");
+    mlp_run(ctx, mlp, nchains, chain_off, phi, t_hat, steps, lr, loss_hist, nullptr);
+    mlp->step += steps;
+  });
+}
+
+gf2_status gf2_proposal_infer(gf2_ctx* ctx, const gf2_mlp* mlp, const double* phi, int64_t naux, double alpha,
+                              int32_t bf16, double* p) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(mlp && phi && p && naux > 0 && alpha > 0 && alpha <= 1, GF2_E_ARG,
+                "bad inference arguments (0 < alpha <= 1 keeps p > 0)");
+    auto* z = (float*)ctx_buf(ctx, "mlp_zi", (size_t)naux * 4);
+    ProfScope ps(ctx, "mlp_infer");
+    launch_mlp_infer(*mlp, phi, naux, bf16, alpha, z, p, ctx->stream);
+    GF2_HIP(hipGetLastError());
+    GF2_HIP(hipStreamSynchronize(ctx->stream));
   });
 }
 

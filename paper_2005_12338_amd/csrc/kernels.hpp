@@ -66,6 +66,15 @@ bool launch_dd_strips(const double* G, const double* Gb, int64_t n, int64_t naux
                       const int32_t* wq, const int32_t* idx, const double* blk, const int32_t* col_off,
                       const int32_t* col_q, double* strip, int64_t ntau_batch, double* out, hipStream_t st);
 
+struct gf2_mlp;
+int mlp_nparam();
+void launch_features(const void* b, bool f64, int64_t n, int64_t naux, double thr, const double* x,
+                     const double* xq, const double* gbeta, double* phi, hipStream_t st);
+void launch_pair_tables(int wmax, const double* G, const double* Gb, int64_t n, int64_t ntau, const double* w,
+                        int64_t naux, const int32_t* wb, const int32_t* ib, const double* bb, const int32_t* wk,
+                        const int32_t* ik, const double* kb, double* tab, hipStream_t st);
+void launch_targets(const double* tab, int64_t naux, double* t, hipStream_t st);
+
 // Host numerics (eigen.cpp).
 // Symmetric eigendecomposition a = v diag(e) v^T (a row-major n x n,
 // overwritten); e ascending, v row-major with eigenvectors in columns.

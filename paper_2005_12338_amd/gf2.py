@@ -44,6 +44,14 @@ class Sampling(C.Structure):
                 ("k", C.c_int32), ("p", C.POINTER(C.c_double))]
 
 
+class MlpC(C.Structure):
+    _fields_ = [("w1", C.c_void_p), ("b1", C.c_void_p), ("w2", C.c_void_p), ("mean", C.c_void_p),
+                ("std", C.c_void_p), ("adam_m", C.c_void_p), ("adam_v", C.c_void_p), ("step", C.c_int64)]
+
+
+MLP_IN, MLP_HIDDEN = 4, 128
+MLP_NPARAM = MLP_HIDDEN * MLP_IN + 2 * MLP_HIDDEN
+
 _lib: Optional[C.CDLL] = None
 
 _SIGS = {
@@ -80,6 +88,17 @@ _SIGS = {
                                  C.c_void_p]),
     "gf2_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.POINTER(C.c_int32)]),
+    "gf2_proposal_features": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
+    "gf2_proposal_targets": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                       C.POINTER(C.c_double), C.c_double, C.c_void_p, C.c_void_p]),
+    "gf2_proposal_init": (C.c_int, [C.c_void_p, C.POINTER(MlpC), C.c_void_p, C.c_int64, C.c_uint64]),
+    "gf2_proposal_grad": (C.c_int, [C.c_void_p, C.POINTER(MlpC), C.c_int32, C.POINTER(C.c_int64), C.c_void_p,
+                                    C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "gf2_proposal_train": (C.c_int, [C.c_void_p, C.POINTER(MlpC), C.c_int32, C.POINTER(C.c_int64), C.c_void_p,
+                                     C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double)]),
+    "gf2_proposal_infer": (C.c_int, [C.c_void_p, C.POINTER(MlpC), C.c_void_p, C.c_int64, C.c_double, C.c_int32,
+                                     C.c_void_p]),
 }
 
 
@@ -333,8 +352,69 @@ class Context:
             out[nm] = dict(launches=int(la[i]), ms=float(ms[i]), flops=float(fl[i]), bytes=float(by[i]))
         return out
 
+    # ------------------------------------------------------------ proposal
+    def proposal_features(self, split: Split, B, x: np.ndarray, xq: np.ndarray, Gbeta, phi):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        xq = np.ascontiguousarray(xq, dtype=np.float64)
+        self._check(self.lib.gf2_proposal_features(self.h, split.handle, B.data_ptr(), _dp(x), _dp(xq),
+                                                   Gbeta.data_ptr(), phi.data_ptr()))
+
+    def proposal_targets(self, split: Split, B, G, Gb, w: np.ndarray, rel: float, t, tables=None):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        self._check(self.lib.gf2_proposal_targets(self.h, split.handle, B.data_ptr(), G.data_ptr(), Gb.data_ptr(),
+                                                  w.shape[0], _dp(w), float(rel), t.data_ptr(), _ptr(tables)))
+
+    def mlp(self):
+        """A network with device buffers (FP32) owned by the returned object."""
+        return Mlp(self.device)
+
+    def proposal_init(self, m: "Mlp", phi, seed: int):
+        self._check(self.lib.gf2_proposal_init(self.h, C.byref(m.c), phi.data_ptr(), phi.shape[0], seed))
+
+    def proposal_grad(self, m: "Mlp", chain_off: np.ndarray, phi, t_hat):
+        off = np.ascontiguousarray(chain_off, dtype=np.int64)
+        loss = C.c_double()
+        grad = np.zeros(MLP_NPARAM)
+        self._check(self.lib.gf2_proposal_grad(self.h, C.byref(m.c), off.shape[0] - 1,
+                                               off.ctypes.data_as(C.POINTER(C.c_int64)), phi.data_ptr(),
+                                               t_hat.data_ptr(), C.byref(loss), _dp(grad)))
+        return loss.value, grad
+
+    def proposal_train(self, m: "Mlp", chain_off: np.ndarray, phi, t_hat, steps: int, lr: float):
+        off = np.ascontiguousarray(chain_off, dtype=np.int64)
+        hist = np.zeros(steps)
+        self._check(self.lib.gf2_proposal_train(self.h, C.byref(m.c), off.shape[0] - 1,
+                                                off.ctypes.data_as(C.POINTER(C.c_int64)), phi.data_ptr(),
+                                                t_hat.data_ptr(), steps, float(lr), _dp(hist)))
+        return hist
+
+    def proposal_infer(self, m: "Mlp", phi, alpha: float, p, bf16: bool = False):
+        self._check(self.lib.gf2_proposal_infer(self.h, C.byref(m.c), phi.data_ptr(), phi.shape[0],
+                                                float(alpha), 1 if bf16 else 0, p.data_ptr()))
+
     def rng_words(self, seed: int, stream: int, s: int, q0: int, count: int) -> np.ndarray:
         out = np.zeros(count, dtype=np.uint64)
         self._check(self.lib.gf2_rng_words(self.h, seed, stream, s, q0, count,
                                             out.ctypes.data_as(C.POINTER(C.c_uint64))))
         return out
+
+
+class Mlp:
+    """Device buffers of one proposal network (gf2_mlp), FP32."""
+
+    def __init__(self, device):
+        import torch
+        kw = dict(dtype=torch.float32, device=device)
+        self.w1 = torch.zeros(MLP_HIDDEN, MLP_IN, **kw)
+        self.b1 = torch.zeros(MLP_HIDDEN, **kw)
+        self.w2 = torch.zeros(MLP_HIDDEN, **kw)
+        self.mean = torch.zeros(MLP_IN, **kw)
+        self.std = torch.ones(MLP_IN, **kw)
+        self.adam_m = torch.zeros(MLP_NPARAM, **kw)
+        self.adam_v = torch.zeros(MLP_NPARAM, **kw)
+        self.c = MlpC(self.w1.data_ptr(), self.b1.data_ptr(), self.w2.data_ptr(), self.mean.data_ptr(),
+                      self.std.data_ptr(), self.adam_m.data_ptr(), self.adam_v.data_ptr(), 0)
+
+    @property
+    def step(self) -> int:
+        return int(self.c.step)
