@@ -570,6 +570,7 @@ void launch_jk_scatter(bool f64, const void* jblk, int64_t naux, int32_t nslot, 
                        const int32_t* pat_ij, const int32_t* pat_off, const int32_t* pat_q, int64_t np,
                        Prec prec, int64_t plane, void* jw_l, void* jw_s, void* jz_st, void* jz_sum_t,
                        int64_t out_st_slot, hipStream_t st) {
+  if ((int64_t)nslot * npat == 0) return;     // no large part: J and K vanish
   dim3 grid(blocks((int64_t)nslot * npat));
   if (f64)
     hipLaunchKernelGGL((k_jk_scatter<double>), grid, dim3(256), 0, st, (const double*)jblk, naux, nslot,

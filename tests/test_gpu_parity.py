@@ -197,6 +197,17 @@ def test_sigma_eps_zero_has_no_stochastic_part(ctx):
         assert rel(Sigma[t].cpu().numpy(), se.sigma_ri(o["b"], o["g"][t], o["gb"][t])) < 1e-11
 
 
+def test_sigma_pure_sri_matches_oracle(ctx):
+    """Threshold above the maximum: B^L = 0, D = 0, and the estimator is the
+    plain stochastic RI of Section II (every element stochastic)."""
+    pb = chain(10, 50.0, 4, 2.0)
+    Sigma, es, o, (B, G, Gb, w, spl) = _check_sigma(ctx, pb, "fp64", torch.float64, 6, 5, 1e-10)
+    assert spl.wmax == 0 and spl.nnz == 0
+    for t in range(pb["ntau"]):
+        assert np.abs(se.sigma_dd(o["split"], o["g"][t], o["gb"][t])).max() == 0.0
+    _check_sigma(ctx, chain(40, 100.0, 2, 2.0), "fp32", torch.float32, 3, 1, 1e-5)
+
+
 def test_sigma_importance_mode_matches_oracle(ctx):
     pb = chain(8, 50.0, 3, 1e-2)
     o = oracle_setup(pb)
