@@ -34,6 +34,27 @@ HBM_PEAK = 8.0e12                        # B/s
 MFMA_PEAK = {"bf16": 2.5e15, "bf16x3": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}
 
 
+# HBM bytes per launch of the chain GEMM from two rocprofv3 PMC passes
+# (FETCH_SIZE x 2.0 + WRITE_SIZE, KiB x 1024; the factors come from a plain
+# 256 MiB copy in the same runs), recorded with the hash of the kernel source
+# they were taken on: reported only while that source is unchanged.
+GEMM_TRAFFIC = {
+    ("bf16", "n800"): {"bytes_per_launch": (724611.3 * 1.9997 + 650603.7) * 1024.0,
+                       "gemm_src_sha256_16": "6472492015324317",
+                       "profile": "profiles/chain_n800_bf16.md"},
+}
+
+
+def gemm_traffic(prec, wl_key):
+    import hashlib
+    rec = GEMM_TRAFFIC.get((prec, wl_key))
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, "paper_2005_12338_amd", "csrc", "gemm.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return rec["bytes_per_launch"] if sha == rec["gemm_src_sha256_16"] else None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -52,14 +73,30 @@ class Problem:
         self.F = ci.fock_tight_binding(self.geo.x)
         self.tau, self.w = gf2.gf2_tau_grid(wl.beta, wl.ntau)
 
+    phase_log = False
+
+    def _mark(self, name, t0):
+        if not self.phase_log:
+            return t0
+        import torch
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        log(f"[bench]     {name:10s} {1e3 * (t1 - t0):8.1f} ms")
+        return t1
+
     def setup(self):
         """B, split, G(tau) and the deterministic block."""
         import torch
         ctx, wl, geo = self.ctx, self.wl, self.geo
+        t = self._mark("start", time.perf_counter()) if self.phase_log else 0.0
         B = ctx.build_B(geo.n, geo.naux, geom=geo, dtype=torch.float32)
+        t = self._mark("B", t)
         spl = ctx.split(B, wl.eps)
+        t = self._mark("split", t)
         G, Gb, mu = ctx.green_tau(self.F, self.tau, wl.beta, n_occ=wl.n_occ)
+        t = self._mark("G(tau)", t)
         det = ctx.sigma_det(spl, G, Gb)
+        self._mark("D-block", t)
         return B, spl, G, Gb, det
 
     def full_pass(self, prec, ns):
@@ -140,12 +177,12 @@ def cpu_baseline(wl, pairs):
             tu = min(tu, time.perf_counter() - t0)
         return tb, tr, tu, spl
 
-    q1, q2 = naux // 20, naux // 10
+    q1, q2 = naux // 10, naux // 5
     tb1, tr1, tu1, _ = unit_time(q1)
     tb2, tr2, tu2, spl2 = unit_time(q2)
     lin = lambda a1, a2: a1 + max(a2 - a1, 0.0) * (naux - q1) / (q2 - q1)     # linear in N_aux
     t_b, t_r, t_unit = lin(tb1, tb2), lin(tr1, tr2), lin(tu1, tu2)
-    rows = list(range(0, q2, 4))
+    rows = list(range(0, q2, 2))
     t0 = time.perf_counter()
     se.sigma_dd(spl2, g[0], gb[0], q_rows=rows)
     t_dd = (time.perf_counter() - t0) * naux / len(rows) * naux / q2     # all Q rows x all Q' columns
@@ -172,6 +209,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-target", action="store_true", help="skip the time-to-target runs")
     ap.add_argument("--profile", action="store_true", help="print the per-kernel breakdown")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 256 MiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -187,9 +226,19 @@ def main():
     log(f"[bench] workload {wl.name}: N={wl.n} Naux={wl.naux} ntau={wl.ntau} Ns={ns} eps={wl.eps} "
         f"prec={args.prec}")
 
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 268435456 bytes read, 268435456 bytes written")
+        del src, dst
+    pb.phase_log = args.profile
     for i in range(args.warmup):
         e, se_ = pb.full_pass(args.prec, ns)
         log(f"[bench] warmup {i}: E={e:.9f} stderr={se_:.3e}")
+    pb.phase_log = False
     ctx.set_profiling(True)
     ctx.profile_read()
     torch.cuda.synchronize()
@@ -229,7 +278,8 @@ def main():
         "E_corr_total": e, "stderr_total": se_,
         "chain_mfma_tflops": achieved / 1e12,
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None, "kernel": gname,
+                     "frac": achieved / peak, "traffic": gemm_traffic(args.prec, args.workload),
+                     "traffic_unit": "bytes per launch", "kernel": gname,
                      "launches": gk["launches"], "avg_launch_ms": gk["ms"] / max(1, gk["launches"])},
     }
     if not args.no_target:
