@@ -112,28 +112,20 @@ class Problem:
         return e, se
 
     def time_to_target(self, prec, target, batch=16, max_pairs=4096, p=None):
-        """Sample pairs in batches until the standard error of the total
-        E_corr is below `target` (Eh).  Returns (seconds, pairs, E, stderr)."""
+        """Set-up plus adaptive sampling (pairs in batches) until the standard
+        error of the total E_corr is below `target` (Eh), in the library's
+        adaptive call.  Returns (seconds, info)."""
         import torch
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         B, spl, G, Gb, det = self.setup()
         ctx, wl = self.ctx, self.wl
-        ssum = torch.zeros_like(det)
-        es = torch.empty((max_pairs, wl.ntau), dtype=torch.float64, device=det.device)
-        s = 0
-        while True:
-            ctx.sigma_stoch(spl, B, G, Gb, ssum, ns=batch, seed=wl.seed, prec=prec, s0=s,
-                            e_samples=es[s:s + batch], p=p)
-            s += batch
-            sig = ctx.sigma_finalize(det, ssum, s)
-            e, epe, se = ctx.energy(sig, Gb, self.w, wl.n_elec, es[:s])
-            if se < target or s + batch > max_pairs:
-                break
+        _, _, info = ctx.energy_adaptive(spl, B, G, Gb, self.w, det, wl.n_elec, target, batch=batch,
+                                         max_pairs=max_pairs, seed=wl.seed, prec=prec, p=p)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         spl.free()
-        return t1 - t0, s, e, se
+        return t1 - t0, info
 
 
 def cpu_baseline(wl, pairs):
@@ -284,18 +276,18 @@ def main():
     }
     if not args.no_target:
         target = args.target_meh * 1e-3
-        t_b, pairs_b, e_b, se_b = pb.time_to_target(args.prec, target)
-        log(f"[bench] time to {args.target_meh} mEh ({args.prec}, uniform): {t_b:.3f} s, {pairs_b} pairs, "
-            f"E={e_b:.9f} stderr={se_b:.3e}")
-        t_f, pairs_f, e_f, se_f = pb.time_to_target("fp32", target)
-        log(f"[bench] time to {args.target_meh} mEh (fp32, uniform): {t_f:.3f} s, {pairs_f} pairs, "
-            f"E={e_f:.9f} stderr={se_f:.3e}")
-        out["value"] = t_b
-        out["time_to_target"] = {"target_mEh": args.target_meh,
-                                 args.prec + "_uniform": {"s": t_b, "pairs": pairs_b, "E": e_b, "stderr": se_b},
-                                 "fp32_uniform": {"s": t_f, "pairs": pairs_f, "E": e_f, "stderr": se_f},
-                                 "speedup_vs_plain_fp32": t_f / t_b if t_b > 0 else None}
-        pairs_for_cpu = pairs_b
+        tt = {"target_mEh": args.target_meh}
+        for name, prec in (("auto", "auto"), ("bf16", "bf16"), ("fp32", "fp32")):
+            pb.time_to_target(prec, target)                     # warm the adaptive path once
+            t_s, info = pb.time_to_target(prec, target)
+            log(f"[bench] time to {args.target_meh} mEh ({name}, uniform): {t_s:.3f} s, {info['pairs']} pairs, "
+                f"E={info['E']:.9f} stderr={info['stderr']:.3e} precision={info['precision']} "
+                f"bias_probe={info['bias_probe']:.2e}")
+            tt[name + "_uniform"] = dict(s=t_s, **info)
+        out["value"] = tt["auto_uniform"]["s"]
+        tt["speedup_vs_plain_fp32"] = tt["fp32_uniform"]["s"] / out["value"]
+        out["time_to_target"] = tt
+        pairs_for_cpu = tt["auto_uniform"]["pairs"]
     else:
         out["value"] = ms_step / 1000.0
         pairs_for_cpu = ns

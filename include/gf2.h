@@ -59,7 +59,10 @@ typedef enum {
   GF2_PREC_FP64 = 0,
   GF2_PREC_FP32 = 1,
   GF2_PREC_BF16 = 2,
-  GF2_PREC_BF16X3 = 3
+  GF2_PREC_BF16X3 = 3,
+  GF2_PREC_AUTO = 4    /* gf2_energy_adaptive only: BF16, switching to
+                          BF16X3 when the measured BF16 rounding of a probe
+                          pair exceeds 0.1x the standard error reached     */
 } gf2_precision;
 
 /* How the stochastic orbitals are drawn (counter-based SplitMix64, see
@@ -232,6 +235,45 @@ gf2_status gf2_profile_read(gf2_ctx* ctx, int32_t cap, char* names, int64_t* lau
  * output; FP32: float; BF16: bf16 operands, float output; BF16X3: each
  * operand is two bf16 planes (hi, lo) of ld*ld elements each.  For tests and
  * benchmarks of the kernel itself. */
+/* ------------------------------------------------------------ adaptive ---
+ * Sampling until a target standard error (the accuracy criterion of the
+ * results section: statistical error of the total E_corr of eq:corr).
+ * Pairs are drawn in batches of sampling->ns (sampling->s0 is ignored; pair
+ * indices run 0, 1, ...) until the standard error of the total E_corr is
+ * below `target` (Eh) or `max_pairs` is reached; at least two pairs.
+ *
+ * prec GF2_PREC_AUTO: the batches run in BF16.  Pairs 0 and 1 are also
+ * evaluated in BF16X3; the largest differences of their energies,
+ * b = max |E_s(BF16) - E_s(BF16X3)|, and of their per-tau traces e_s(tau)
+ * estimate the BF16 rounding of a pair.  If 2b >= 0.1 x the standard error
+ * reached, or, for some tau, twice the trace difference >= the larger of
+ * 0.1 x the standard error of that tau's mean trace and 1e-5 x the trace
+ * Tr(Sigma(tau) Gbar(tau)), every pair is recomputed in BF16X3 (same theta)
+ * and sampling continues in BF16X3.  batch must then be >= 2.
+ *
+ * Inputs as gf2_sigma_stoch; w host [ntau] quadrature weights; Sigma_det
+ * device [ntau][n][n] (gf2_sigma_det).  Outputs: Sigma device [ntau][n][n]
+ * FP64 (= Sigma_det + symmetrised mean); e_samples device [max_pairs][ntau]
+ * (rows 0 .. pairs-1 written); *res host.  The library keeps the running
+ * sum in its own workspace.
+ * Errors: as gf2_sigma_stoch; GF2_E_ARG for target <= 0, max_pairs < 2,
+ * ntau > 512. */
+typedef struct {
+  double e_corr;          /* total E_corr (Eh)                               */
+  double e_corr_per_e;    /* E_corr / n_elec                                 */
+  double stderr_tot;      /* standard error of the total E_corr              */
+  int64_t pairs;          /* pairs used                                      */
+  int32_t precision;      /* gf2_precision the final pairs were computed in  */
+  double bias_probe;      /* AUTO: b above (0 otherwise)                     */
+} gf2_adaptive_result;
+
+gf2_status gf2_energy_adaptive(gf2_ctx* ctx, const gf2_split_h* split, const void* B,
+                               const double* G, const double* Gbar, int64_t ntau,
+                               const double* w, const double* Sigma_det, double n_elec,
+                               const gf2_sampling* sampling, gf2_precision prec, double target,
+                               int64_t max_pairs, double* Sigma, double* e_samples,
+                               gf2_adaptive_result* res);
+
 gf2_status gf2_debug_gemm(gf2_ctx* ctx, gf2_precision prec, int64_t n, int64_t batch,
                           const void* A, const void* Bt, void* C);
 

@@ -20,8 +20,16 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled for all device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Host code targets AVX2/FMA-class x86-64 (the host eigensolver vectorises).
+HOST_FLAGS = ["-Xarch_host", "-march=x86-64-v3"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.join(ROOT, "include"),
-          "-I", CSRC, "-fopenmp", "-Wno-unused-result"]
+          "-I", CSRC, "-fopenmp", "-Wno-unused-result", *HOST_FLAGS]
+
+
+# Plain C++ host files (no HIP), built by the host compiler.
+HOST_ONLY = {"eigen.cpp"}
+HOST_CXX = os.environ.get("CXX_HOST", "g++")
+HOST_CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-march=x86-64-v3", "-I", CSRC]
 
 
 def _sources():
@@ -31,7 +39,9 @@ def _sources():
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src + ".o")
     cmd = [HIPCC, *COMMON, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-    if src.endswith(".cpp"):
+    if src in HOST_ONLY:
+        cmd = [HOST_CXX, *HOST_CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    elif src.endswith(".cpp"):
         cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj, *DEVICE_FLAGS]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

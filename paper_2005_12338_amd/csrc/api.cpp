@@ -318,6 +318,15 @@ gf2_status gf2_split(gf2_ctx* ctx, const void* B, gf2_dtype dtype, int64_t n, in
       wm = std::max(wm, c);
     }
     h->wmax = wm;
+    for (int64_t c0 = 0; c0 < naux; c0 += 128) {
+      int32_t lo = (int32_t)n, hi = -1;
+      for (int64_t q = c0; q < std::min<int64_t>(naux, c0 + 128); ++q)
+        if (w[q] > 0) {
+          lo = std::min(lo, idx[q * kWMax]);
+          hi = std::max(hi, idx[q * kWMax + w[q] - 1]);
+        }
+      h->span128 = std::max(h->span128, hi - lo + 1);
+    }
     // union pattern with its contribution lists (ordered by Q, a, b)
     std::vector<std::pair<int64_t, int32_t>> contrib;
     for (int64_t q = 0; q < naux; ++q)
@@ -543,7 +552,7 @@ void run_dd(gf2_ctx* ctx, const gf2_split_h* sp, const double* G, const double* 
     const int64_t per = dd_strip_bytes(sp->n, sp->naux, sp->wmax, 1);
     const int64_t tb = std::max<int64_t>(1, std::min<int64_t>(ntau, (int64_t)2e9 / std::max<int64_t>(per, 1)));
     auto* strip = (double*)ctx_buf(ctx, "dd_strip", (size_t)(per * tb));
-    launch_dd_strips(G, Gb, sp->n, sp->naux, ntau, sp->wmax, sp->w, sp->idx, sp->blk, sp->orb_off, sp->orb_q,
+    launch_dd_strips(G, Gb, sp->n, sp->naux, ntau, sp->wmax, sp->span128, sp->w, sp->idx, sp->blk, sp->orb_off, sp->orb_q,
                      strip, tb, out, ctx->stream);
   } else {
     launch_dblock(G, Gb, sp->n, ntau, sp->wmax, sp->w, sp->idx, sp->blk, sp->row_off, sp->row_q, out,
@@ -909,6 +918,129 @@ gf2_status gf2_energy(gf2_ctx* ctx, int64_t n, int64_t ntau, const double* w, co
     if (E_tot) *E_tot = h[0];
     if (E_per_e) *E_per_e = h[0] / n_elec;
     if (stderr_tot) *stderr_tot = h[2];
+  });
+}
+
+// ------------------------------------------------------------ adaptive ----
+gf2_status gf2_energy_adaptive(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const double* G,
+                               const double* Gbar, int64_t ntau, const double* w, const double* Sigma_det,
+                               double n_elec, const gf2_sampling* sampling, gf2_precision prec, double target,
+                               int64_t max_pairs, double* Sigma, double* e_samples, gf2_adaptive_result* res) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(split && split->owner == ctx, GF2_E_STATE, "split handle of another context");
+    GF2_REQUIRE(B == split->bsrc, GF2_E_STATE, "split handle belongs to a different B");
+    GF2_REQUIRE(G && Gbar && w && Sigma_det && Sigma && e_samples && res, GF2_E_ARG, "bad adaptive arguments");
+    GF2_REQUIRE(ntau > 0 && ntau <= 512 && n_elec > 0 && target > 0 && max_pairs >= 2, GF2_E_ARG,
+                "bad adaptive arguments (ntau <= 512, target > 0, max_pairs >= 2)");
+    check_sampling(split, sampling);
+    const bool autop = prec == GF2_PREC_AUTO;
+    GF2_REQUIRE(!autop || sampling->ns >= 2, GF2_E_ARG, "AUTO needs batches of at least 2 pairs");
+    Prec wp = autop ? Prec::BF16 : to_prec(prec);
+    const int64_t n = split->n, batch = sampling->ns;
+    const size_t mat = (size_t)(ntau * n * n);
+    auto* sum = (double*)ctx_buf(ctx, "a_sum", mat * 8, true);
+    auto* tr = (double*)ctx_buf(ctx, "a_tr", (size_t)ntau * 8);
+    auto* dw = (double*)ctx_buf(ctx, "a_w", (size_t)ntau * 8);
+    auto* stats = (double*)ctx_buf(ctx, "a_stats", 4 * 8);
+    h2d(ctx, dw, w, (size_t)ntau);
+    launch_trace_prod(Sigma_det, Gbar, n, ntau, tr, ctx->stream);   // Tr(Sigma_det Gbar) per tau
+    GF2_HIP(hipGetLastError());
+    gf2_sampling smp = *sampling;
+    auto run = [&](int64_t s0, int64_t cnt, Prec p) {
+      smp.s0 = s0;
+      smp.ns = cnt;
+      run_stoch(ctx, split, B, G, Gbar, ntau, &smp, p, sum, e_samples + s0 * ntau);
+    };
+    auto stat = [&](int64_t pairs, double* h) {
+      launch_energy_stats(tr, dw, ntau, e_samples, pairs, kGM, stats, ctx->stream, true);
+      GF2_HIP(hipGetLastError());
+      d2h(ctx, h, stats, 3);
+      GF2_HIP(hipStreamSynchronize(ctx->stream));
+      GF2_REQUIRE(std::isfinite(h[0]) && std::isfinite(h[2]), GF2_E_NUMERIC, "non-finite energy");
+    };
+    // AUTO: pairs 0 and 1 also in BF16X3; their energies and per-tau traces
+    // against the BF16 ones measure the BF16 rounding of a pair.
+    constexpr int kProbe = 2;
+    std::vector<double> e_hi, d_probe;
+    double bias = 0.0;
+    if (autop) {
+      auto* ssum = (double*)ctx_buf(ctx, "a_probe_sum", mat * 8, true);
+      auto* eprobe = (double*)ctx_buf(ctx, "a_probe_e", (size_t)(kProbe * ntau) * 8);
+      smp.s0 = 0;
+      smp.ns = kProbe;
+      run_stoch(ctx, split, B, G, Gbar, ntau, &smp, Prec::BF16X3, ssum, eprobe);
+      e_hi.resize((size_t)(kProbe * ntau));
+      d2h(ctx, e_hi.data(), eprobe, e_hi.size());
+    }
+    // BF16 is kept only if the probe's rounding, with a safety factor of 2,
+    // is below 0.1x the standard error of the total, and, for every tau,
+    // below 0.1x the standard error of the mean trace or 1e-5 of the trace
+    // Tr(Sigma(tau) Gbar(tau)) itself (the FP32 path's relative tolerance;
+    // at tau points where the stochastic part vanishes its standard error
+    // does too).
+    auto bf16_ok = [&](int64_t pairs, double se_tot) {
+      if (2.0 * bias >= 0.1 * se_tot) return false;
+      std::vector<double> es((size_t)(pairs * ntau)), trh((size_t)ntau);
+      d2h(ctx, es.data(), e_samples, es.size());
+      d2h(ctx, trh.data(), tr, trh.size());
+      for (int64_t t = 0; t < ntau; ++t) {
+        double m = 0.0, v = 0.0;
+        for (int64_t q = 0; q < pairs; ++q) m += es[q * ntau + t];
+        m /= (double)pairs;
+        for (int64_t q = 0; q < pairs; ++q) v += (es[q * ntau + t] - m) * (es[q * ntau + t] - m);
+        const double se_t = std::sqrt(v / (double)(pairs - 1) / (double)pairs);
+        const double bar = std::max(0.1 * se_t, 1e-5 * std::fabs(trh[t] + m));
+        if (2.0 * d_probe[t] >= bar) return false;
+      }
+      return true;
+    };
+    int64_t pairs = 0;
+    double h[4] = {0, 0, 0, 0};
+    bool probed = false;
+    while (true) {
+      const int64_t cnt = std::min(batch, max_pairs - pairs);
+      if (cnt <= 0) break;
+      run(pairs, cnt, wp);
+      pairs += cnt;
+      if (autop && !probed && pairs >= kProbe) {
+        std::vector<double> e_lo((size_t)(kProbe * ntau));
+        d2h(ctx, e_lo.data(), e_samples, e_lo.size());
+        d_probe.assign(ntau, 0.0);
+        for (int q = 0; q < kProbe; ++q) {
+          double d = 0.0;
+          for (int64_t t = 0; t < ntau; ++t) {
+            const double dt = e_lo[q * ntau + t] - e_hi[q * ntau + t];
+            d_probe[t] = std::max(d_probe[t], std::fabs(dt));
+            d += w[t] * dt;
+          }
+          bias = std::max(bias, std::fabs(kGM * d));
+        }
+        probed = true;
+      }
+      if (pairs < 2) continue;
+      stat(pairs, h);
+      bool done = h[2] < target || pairs >= max_pairs;
+      if (done && autop && wp == Prec::BF16 && !bf16_ok(pairs, h[2])) {
+        // BF16 rounding is not negligible at this error: redo every pair in
+        // BF16X3 (same theta) and go on sampling in BF16X3
+        wp = Prec::BF16X3;
+        GF2_HIP(hipMemsetAsync(sum, 0, mat * 8, ctx->stream));
+        for (int64_t s0 = 0; s0 < pairs; s0 += batch) run(s0, std::min(batch, pairs - s0), wp);
+        stat(pairs, h);
+        done = h[2] < target || pairs >= max_pairs;
+      }
+      if (done) break;
+    }
+    launch_finalize(Sigma_det, sum, n, ntau, 0.5 / (double)pairs, Sigma, ctx->stream);
+    GF2_HIP(hipGetLastError());
+    check_finite(ctx, Sigma, (int64_t)mat, "Sigma");
+    res->e_corr = h[0];
+    res->e_corr_per_e = h[0] / n_elec;
+    res->stderr_tot = h[2];
+    res->pairs = pairs;
+    res->precision = wp == Prec::F64 ? GF2_PREC_FP64 : wp == Prec::F32 ? GF2_PREC_FP32
+                     : wp == Prec::BF16 ? GF2_PREC_BF16 : GF2_PREC_BF16X3;
+    res->bias_probe = bias;
   });
 }
 

@@ -254,6 +254,147 @@ __global__ __launch_bounds__(256) void k_dd_strip(const double* G, const double*
   }
 }
 
+// ---------------------------------------------------------------------------
+// Row-staged form of the same strip (G and Gb symmetric, as G(tau) is for a
+// real symmetric F and S).  Pairs (Q, Q') are taken in chunks of CH
+// consecutive Q'; the orbitals those supports touch form a column window
+// [jlo, jhi] of at most kDdSpan columns.  The workgroup stages
+//   u[a][j] = sum_b k_Q[a][b] G[S_Q(b)][j]   and   gq[f][j] = Gb[S_Q(f)][j]
+// over the window in LDS, so that each lane's pair needs only its own k_Q'
+// block from memory:
+//   M = u[:, S_Q'] k_Q',  T = M Gb[S_Q', S_Q],  C = 2 Tr(T) M - T M.
+// Sums run in the same order as the register form, so the two agree bitwise.
+// ---------------------------------------------------------------------------
+template <int W, int CH>
+__global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* Gb, int64_t n, int64_t naux,
+                                                int32_t tau0, const int32_t* wq, const int32_t* idx,
+                                                const double* blk, const int32_t* col_off,
+                                                const int32_t* col_q, double* strip) {
+  __shared__ double cbuf[CH * W * W];
+  __shared__ double uq[W * kDdSpan];
+  __shared__ double gq[W * kDdSpan];
+  __shared__ double kq[W * W];
+  __shared__ int32_t span[2];
+  const int tid = threadIdx.x;
+  const int64_t q = blockIdx.x;
+  const int64_t t = tau0 + blockIdx.y;
+  const double* g = G + t * n * n;
+  const double* gb = Gb + t * n * n;
+  double* st = strip + ((int64_t)blockIdx.y * naux + q) * W * n;
+  const int w1 = wq[q];
+  const int32_t* s1 = idx + q * kWMax;
+  for (int e = tid; e < W * W; e += CH) {
+    const int a = e / W, b = e % W;
+    kq[e] = (a < w1 && b < w1) ? blk[q * kWMax * kWMax + a * kWMax + b] : 0.0;
+  }
+  for (int64_t e = tid; e < (int64_t)W * n; e += CH) st[e] = 0.0;
+  int sq[W];
+#pragma unroll
+  for (int a = 0; a < W; ++a) sq[a] = a < w1 ? s1[a] : 0;
+  __syncthreads();
+  if (w1 == 0) return;
+
+  for (int64_t c0 = 0; c0 < naux; c0 += CH) {
+    const int64_t r = c0 + tid;
+    const bool act = r < naux;
+    if (tid == 0) { span[0] = (int32_t)n; span[1] = -1; }
+    __syncthreads();
+    const int w2 = act ? wq[r] : 0;
+    const int32_t* s2 = idx + (act ? r : 0) * kWMax;
+    int sr[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) sr[c] = c < w2 ? s2[c] : 0;
+    if (w2 > 0) {
+      atomicMin(&span[0], sr[0]);
+      atomicMax(&span[1], sr[w2 - 1]);
+    }
+    __syncthreads();
+    const int jlo = span[0], jhi = span[1];
+    const int width = jhi - jlo + 1;          // <= kDdSpan (checked on the host)
+    for (int e = tid; e < W * width; e += CH) {
+      const int a = e / width, jj = e % width;
+      const int64_t j = jlo + jj;
+      double s = 0.0;
+      for (int b = 0; b < w1; ++b) s += kq[a * W + b] * g[(int64_t)sq[b] * n + j];
+      uq[a * kDdSpan + jj] = s;
+      gq[a * kDdSpan + jj] = a < w1 ? gb[(int64_t)sq[a] * n + j] : 0.0;
+    }
+    __syncthreads();
+    if (act) {
+      // M = u[:, S_Q'] k_Q'
+      double m[W][W];
+#pragma unroll
+      for (int a = 0; a < W; ++a)
+#pragma unroll
+        for (int d = 0; d < W; ++d) m[a][d] = 0.0;
+      const double* kr = blk + r * kWMax * kWMax;
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        if (c >= w2) break;
+        double row[W];
+#pragma unroll
+        for (int d = 0; d < W; ++d) row[d] = kr[c * kWMax + d];   // zero padded beyond w2
+        const int col = sr[c] - jlo;            // c < w2: inside the window
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+          const double uv = uq[a * kDdSpan + col];
+#pragma unroll
+          for (int d = 0; d < W; ++d) m[a][d] += uv * row[d];
+        }
+      }
+      // T = M Gb[S_Q', S_Q]
+      double tt[W][W];
+#pragma unroll
+      for (int a = 0; a < W; ++a)
+#pragma unroll
+        for (int f = 0; f < W; ++f) tt[a][f] = 0.0;
+#pragma unroll
+      for (int d = 0; d < W; ++d) {
+        double row[W];
+        const int col = d < w2 ? sr[d] - jlo : 0;
+#pragma unroll
+        for (int f = 0; f < W; ++f) row[f] = d < w2 ? gq[f * kDdSpan + col] : 0.0;
+#pragma unroll
+        for (int a = 0; a < W; ++a)
+#pragma unroll
+          for (int f = 0; f < W; ++f) tt[a][f] += m[a][d] * row[f];
+      }
+      double tr = 0.0;
+#pragma unroll
+      for (int a = 0; a < W; ++a) tr += tt[a][a];
+      double* cb = cbuf + tid * W * W;
+#pragma unroll
+      for (int a = 0; a < W; ++a)
+#pragma unroll
+        for (int d = 0; d < W; ++d) {
+          double s = 0.0;
+#pragma unroll
+          for (int f = 0; f < W; ++f) s += tt[a][f] * m[f][d];
+          cb[a * W + d] = 2.0 * tr * m[a][d] - s;
+        }
+    }
+    __syncthreads();
+    const int64_t nout = (jhi >= jlo) ? (int64_t)w1 * width : 0;
+    for (int64_t e = tid; e < nout; e += CH) {
+      const int a = (int)(e % w1);
+      const int j = jlo + (int)(e / w1);
+      int lo = col_off[j], hi = col_off[j + 1];
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((col_q[mid] >> 5) < c0) lo = mid + 1; else hi = mid;
+      }
+      double acc = 0.0;
+      for (int k = lo; k < col_off[j + 1]; ++k) {
+        const int64_t rr = col_q[k] >> 5;
+        if (rr >= c0 + CH) break;
+        acc += cbuf[(rr - c0) * W * W + a * W + (col_q[k] & 31)];
+      }
+      st[(int64_t)a * n + j] += acc;
+    }
+    __syncthreads();
+  }
+}
+
 // Sigma[t][i][j] = sum over (Q, a) with S_Q(a) = i of strip[t][Q][a][j].
 template <int W>
 __global__ void k_dd_gather(const double* strip, int64_t n, int64_t naux, int32_t tau0, int32_t ntb,
@@ -280,14 +421,37 @@ int64_t dd_strip_bytes(int64_t n, int64_t naux, int32_t wmax, int64_t ntau_batch
 }
 
 bool launch_dd_strips(const double* G, const double* Gb, int64_t n, int64_t naux, int64_t ntau, int32_t wmax,
-                      const int32_t* wq, const int32_t* idx, const double* blk, const int32_t* col_off,
-                      const int32_t* col_q, double* strip, int64_t ntau_batch, double* out, hipStream_t st) {
+                      int32_t span128, const int32_t* wq, const int32_t* idx, const double* blk,
+                      const int32_t* col_off, const int32_t* col_q, double* strip, int64_t ntau_batch, double* out,
+                      hipStream_t st) {
   if (wmax > 8) return false;
+  const bool rows = span128 <= kDdSpan;
   for (int64_t t0 = 0; t0 < ntau; t0 += ntau_batch) {
     const int32_t ntb = (int32_t)std::min<int64_t>(ntau_batch, ntau - t0);
     dim3 grid((unsigned)naux, (unsigned)ntb);
     const unsigned gb = (unsigned)(((int64_t)ntb * n * n + 255) / 256);
-    if (wmax <= 4) {
+    if (rows) {
+      if (wmax <= 4)
+        hipLaunchKernelGGL((k_dd_rows<4, 128>), grid, dim3(128), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
+                           col_off, col_q, strip);
+      else if (wmax <= 6)
+        hipLaunchKernelGGL((k_dd_rows<6, 128>), grid, dim3(128), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
+                           col_off, col_q, strip);
+      else
+        hipLaunchKernelGGL((k_dd_rows<8, 64>), grid, dim3(64), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
+                           col_off, col_q, strip);
+      GF2_HIP(hipGetLastError());
+      const int W = wmax <= 4 ? 4 : wmax <= 6 ? 6 : 8;
+      if (W == 4)
+        hipLaunchKernelGGL((k_dd_gather<4>), dim3(gb), dim3(256), 0, st, strip, n, naux, (int32_t)t0, ntb, col_off,
+                           col_q, out);
+      else if (W == 6)
+        hipLaunchKernelGGL((k_dd_gather<6>), dim3(gb), dim3(256), 0, st, strip, n, naux, (int32_t)t0, ntb, col_off,
+                           col_q, out);
+      else
+        hipLaunchKernelGGL((k_dd_gather<8>), dim3(gb), dim3(256), 0, st, strip, n, naux, (int32_t)t0, ntb, col_off,
+                           col_q, out);
+    } else if (wmax <= 4) {
       hipLaunchKernelGGL((k_dd_strip<4, 256>), grid, dim3(256), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
                          col_off, col_q, strip);
       hipLaunchKernelGGL((k_dd_gather<4>), dim3(gb), dim3(256), 0, st, strip, n, naux, (int32_t)t0, ntb, col_off,

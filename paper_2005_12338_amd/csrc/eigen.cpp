@@ -4,27 +4,82 @@
 // tridiagonal form followed by the implicit-shift QL iteration on the
 // tridiagonal matrix (the textbook two-phase method, e.g. Golub & Van Loan,
 // "Matrix Computations", sections 8.3).  The transforms are accumulated in a
-// column-major copy so that every update runs over contiguous memory; the
-// O(n^2)-per-step updates are spread over OpenMP threads.
+// transposed copy Q^T so that every update runs over contiguous memory; the
+// O(n^2)-per-step updates are spread over OpenMP threads in blocks of
+// columns.  Each QL sweep records its plane rotations and then applies them
+// to Q^T one column block per thread, which is the same arithmetic in the
+// same order per element as applying them one at a time.
 //
 // gauss_legendre: nodes are the roots of P_n found by Newton's method from
 // the Chebyshev-like guess cos(pi (i + 3/4) / (n + 1/2)); weights
 // 2 / ((1 - x^2) P_n'(x)^2).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <numeric>
 #include <vector>
 
-#include "kernels.hpp"
+#include "host_numerics.hpp"
+
+namespace {
+constexpr int64_t kColBlock = 64;
+// The per-step updates are O(n^2); beyond a few threads the fork/join cost
+// outweighs the work at the sizes of the hot path.
+constexpr int kThreads = 4;
+
+// x . y with four interleaved partial sums (vectorises without reassociation
+// flags; a fixed summation order either way).
+inline double dot4(const double* x, const double* y, int64_t m) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t j = 0;
+  for (; j + 4 <= m; j += 4) {
+    s0 += x[j] * y[j];
+    s1 += x[j + 1] * y[j + 1];
+    s2 += x[j + 2] * y[j + 2];
+    s3 += x[j + 3] * y[j + 3];
+  }
+  for (; j < m; ++j) s0 += x[j] * y[j];
+  return (s0 + s1) + (s2 + s3);
+}
+
+// Apply the rotations of one QL sweep, rows i = hi-1 down to lo, to the
+// rows of Q^T, one block of columns per thread.  Rotation i leaves row i+1
+// final and row i as the input of rotation i-1, so the running row stays in
+// registers and every element is read and written once.
+void apply_sweep(double* qt, int64_t n, int64_t lo, int64_t hi, const double* cs, const double* sn) {
+  const int64_t nb = (n + kColBlock - 1) / kColBlock;
+#pragma omp parallel for num_threads(kThreads) schedule(static) if ((hi - lo) * n > 65536)
+  for (int64_t bk = 0; bk < nb; ++bk) {
+    const int64_t k0 = bk * kColBlock, k1 = std::min(n, k0 + kColBlock), kn = k1 - k0;
+    double carry[kColBlock];
+    const double* top = qt + hi * n + k0;
+    for (int64_t k = 0; k < kn; ++k) carry[k] = top[k];
+    for (int64_t i = hi - 1; i >= lo; --i) {
+      const double s = sn[i], c = cs[i];
+      double* zi = qt + i * n + k0;
+      double* zj = qt + (i + 1) * n + k0;
+      for (int64_t k = 0; k < kn; ++k) {
+        const double fz = carry[k], xi = zi[k];
+        zj[k] = s * xi + c * fz;
+        carry[k] = c * xi - s * fz;
+      }
+    }
+    double* bot = qt + lo * n + k0;
+    for (int64_t k = 0; k < kn; ++k) bot[k] = carry[k];
+  }
+}
+}  // namespace
 
 void sym_eigen(int64_t n, double* a, double* e_out, double* v_out) {
-  std::vector<double> qt((size_t)(n * n), 0.0);   // Q^T, row r = column r of Q
-  for (int64_t i = 0; i < n; ++i) qt[i * n + i] = 1.0;
-  std::vector<double> vv(n), p(n), w(n), q(n);
+  // reflector k: v_k (length n-k-1, stored in row k of refl) and beta_k;
+  // H_k = I - beta_k v_k v_k^T acts on indices k+1..n-1.
+  std::vector<double> refl((size_t)(n * n), 0.0), betas(n, 0.0);
+  std::vector<double> p(n), w(n);
 
   // ---- Householder: A <- H A H, zeroing column k below the sub-diagonal
   for (int64_t k = 0; k + 2 < n; ++k) {
     const int64_t m = n - k - 1;        // length of x = a[k+1.., k]
+    double* vv = refl.data() + k * n;
     double nrm = 0.0;
     for (int64_t i = 0; i < m; ++i) nrm += a[(k + 1 + i) * n + k] * a[(k + 1 + i) * n + k];
     nrm = std::sqrt(nrm);
@@ -37,20 +92,18 @@ void sym_eigen(int64_t n, double* a, double* e_out, double* v_out) {
     for (int64_t i = 0; i < m; ++i) vn2 += vv[i] * vv[i];
     if (vn2 == 0.0) continue;
     const double beta = 2.0 / vn2;
+    betas[k] = beta;
     // p = beta * A22 v
-#pragma omp parallel for schedule(static) if (m > 256)
+#pragma omp parallel for num_threads(kThreads) schedule(static) if (m > 256)
     for (int64_t i = 0; i < m; ++i) {
-      const double* row = a + (k + 1 + i) * n + (k + 1);
-      double s = 0.0;
-      for (int64_t j = 0; j < m; ++j) s += row[j] * vv[j];
-      p[i] = beta * s;
+      p[i] = beta * dot4(a + (k + 1 + i) * n + (k + 1), vv, m);
     }
     double kk = 0.0;
     for (int64_t i = 0; i < m; ++i) kk += vv[i] * p[i];
     kk *= 0.5 * beta;
     for (int64_t i = 0; i < m; ++i) w[i] = p[i] - kk * vv[i];
     // A22 -= v w^T + w v^T
-#pragma omp parallel for schedule(static) if (m > 256)
+#pragma omp parallel for num_threads(kThreads) schedule(static) if (m > 256)
     for (int64_t i = 0; i < m; ++i) {
       double* row = a + (k + 1 + i) * n + (k + 1);
       const double vi = vv[i], wi = w[i];
@@ -62,19 +115,24 @@ void sym_eigen(int64_t n, double* a, double* e_out, double* v_out) {
       a[(k + 1 + i) * n + k] = 0.0;
       a[k * n + k + 1 + i] = 0.0;
     }
-    // Q <- Q H:  rows k+1.. of Q^T change by -beta v (v^T Q^T[k+1..])
-    std::fill(q.begin(), q.end(), 0.0);
-#pragma omp parallel for schedule(static) if (m > 256)
-    for (int64_t r = 0; r < n; ++r) {
-      double s = 0.0;
-      for (int64_t i = 0; i < m; ++i) s += vv[i] * qt[(k + 1 + i) * n + r];
-      q[r] = beta * s;
-    }
-#pragma omp parallel for schedule(static) if (m > 256)
+  }
+
+  // ---- Q^T = H_{n-3} ... H_0, accumulated backwards: X <- X H_k for
+  // k = n-3 .. 0 starting from X = I.  Before step k, X differs from I only
+  // in rows/columns k+2.., so the step touches the block X[k+1.., k+1..].
+  std::vector<double> qt((size_t)(n * n), 0.0);   // Q^T, row r = column r of Q
+  for (int64_t i = 0; i < n; ++i) qt[i * n + i] = 1.0;
+  for (int64_t k = n - 3; k >= 0; --k) {
+    const double beta = betas[k];
+    if (beta == 0.0) continue;
+    const int64_t m = n - k - 1;
+    const double* vv = refl.data() + k * n;
+    // y = X[k+1.., k+1..] v (rows contiguous), then X -= beta y v^T
+#pragma omp parallel for num_threads(kThreads) schedule(static) if (m > 128)
     for (int64_t i = 0; i < m; ++i) {
-      double* row = qt.data() + (k + 1 + i) * n;
-      const double vi = vv[i];
-      for (int64_t r = 0; r < n; ++r) row[r] -= vi * q[r];
+      double* row = qt.data() + (k + 1 + i) * n + (k + 1);
+      const double bs = beta * dot4(row, vv, m);
+      for (int64_t j = 0; j < m; ++j) row[j] -= bs * vv[j];
     }
   }
   std::vector<double> d(n), e(n, 0.0);
@@ -83,6 +141,7 @@ void sym_eigen(int64_t n, double* a, double* e_out, double* v_out) {
 
   // ---- implicit QL on (d, e); rotations act on rows i, i+1 of Q^T
   const double tiny = 2.220446049250313e-16;
+  std::vector<double> rc(n), rs(n);
   for (int64_t l = 0; l < n; ++l) {
     for (int iter = 0; iter < 200; ++iter) {
       int64_t m = l;
@@ -96,6 +155,7 @@ void sym_eigen(int64_t n, double* a, double* e_out, double* v_out) {
       g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
       double s = 1.0, c = 1.0, pp = 0.0;
       bool early = false;
+      int64_t ilo = m;                  // rotations recorded for rows ilo .. m-1
       for (int64_t i = m - 1; i >= l; --i) {
         const double f = s * e[i], b = c * e[i];
         r = std::hypot(f, g);
@@ -113,14 +173,11 @@ void sym_eigen(int64_t n, double* a, double* e_out, double* v_out) {
         pp = s * r;
         d[i + 1] = g + pp;
         g = c * r - b;
-        double* zi = qt.data() + i * n;
-        double* zj = qt.data() + (i + 1) * n;
-        for (int64_t k = 0; k < n; ++k) {
-          const double fz = zj[k];
-          zj[k] = s * zi[k] + c * fz;
-          zi[k] = c * zi[k] - s * fz;
-        }
+        rc[i] = c;
+        rs[i] = s;
+        ilo = i;
       }
+      apply_sweep(qt.data(), n, ilo, m, rc.data(), rs.data());
       if (early) continue;
       d[l] -= pp;
       e[l] = g;

@@ -135,6 +135,9 @@ __device__ __forceinline__ void store_out_vec4(int type, void* base, int64_t i, 
   }
 }
 
+// Sixteen zero bytes: the source of every out-of-range operand vector.
+__device__ __attribute__((aligned(16))) const u32x4_t kZeroVec = {0u, 0u, 0u, 0u};
+
 // Remap the linear workgroup id so that consecutive tiles of one problem
 // land on the same XCD (workgroups are dispatched round-robin over 8 XCDs,
 // each with its own L2).
@@ -208,72 +211,66 @@ __device__ __forceinline__ void gemm_body(const GemmLaunch& L, const Prob& pb, c
   auto frag_row_out = [&](int i) { return NA == 2 ? wm * MT : wm * WR + i * MT; };
   auto frag_col_out = [&](int j) { return NB == 2 ? wn * MT : wn * WC + j * MT; };
 
-  // Per-thread row pointers of the vectors this thread stages, for the
-  // current K segment (recomputed only when the segment changes).
-  const E* ap[AV];
-  const E* bp[BV];
-  bool aok[AV], bok[BV];
-  int akv[AV], bkv[BV];
+  // Staging geometry.  Vector i of thread t covers tile row trow + c_i
+  // (c_i = (i * RSTEP) % rows) of plane (i * RSTEP) / rows and k offset kv;
+  // everything but trow and kv is uniform over the workgroup, so each load
+  // is a uniform base plus one per-thread offset.
+  constexpr int RSTEP = kThreads / VPR;
+  static_assert(BM % RSTEP == 0 && BN % RSTEP == 0 && SM % RSTEP == 0 && SN % RSTEP == 0, "staging rows");
+  const int trow = tid / VPR;
+  const int kv = (tid % VPR) * VE;
+  const int64_t toff = (int64_t)trow * ld + kv;
+  const E* abase[AV];
+  const E* bbase[BV];
+  int adr[AV], bdr[BV];                  // row offset of the vector in its matrix (uniform)
   auto set_seg = [&](int seg) {
 #pragma unroll
     for (int i = 0; i < AV; ++i) {
-      const int v = tid + i * kThreads;
-      const int pl = v / (BM * VPR);
-      const int vv = v % (BM * VPR);
-      const int r = vv / VPR;
-      akv[i] = (vv % VPR) * VE;
-      const int sel = NA == 2 ? r / SM : seg;
-      const int64_t grow = row0 + (r % SM);
-      aok[i] = grow < mrows;
+      const int pl = (i * RSTEP) / BM, c = (i * RSTEP) % BM;
+      const int sel = NA == 2 ? c / SM : seg;
+      adr[i] = NA == 2 ? c % SM : c;
       const OpRef& ar = pb.a[sel];
-      ap[i] = (const E*)ar.base + off(ar, u) + (int64_t)pl * L.plane + (aok[i] ? grow : 0) * ld + akv[i];
+      abase[i] = (const E*)ar.base + off(ar, u) + (int64_t)pl * L.plane + (row0 + adr[i]) * ld;
     }
 #pragma unroll
     for (int i = 0; i < BV; ++i) {
-      const int v = tid + i * kThreads;
-      const int pl = v / (BN * VPR);
-      const int vv = v % (BN * VPR);
-      const int r = vv / VPR;
-      bkv[i] = (vv % VPR) * VE;
-      const int sel = NB == 2 ? r / SN : seg;
-      const int64_t gcol = col0 + (r % SN);
-      bok[i] = gcol < ncols;
+      const int pl = (i * RSTEP) / BN, c = (i * RSTEP) % BN;
+      const int sel = NB == 2 ? c / SN : seg;
+      bdr[i] = NB == 2 ? c % SN : c;
       const OpRef& br = pb.b[sel];
-      bp[i] = (const E*)br.base + off(br, u) + (int64_t)pl * L.plane + (bok[i] ? gcol : 0) * ld + bkv[i];
+      bbase[i] = (const E*)br.base + off(br, u) + (int64_t)pl * L.plane + (col0 + bdr[i]) * ld;
     }
   };
-  u32x4_t ra[AV], rb[BV];
-  auto gload = [&](int kt) {
+  // Loads are unconditional: out-of-range vectors read 16 zero bytes from
+  // kZeroVec instead, so every k tile issues the same instruction stream
+  // without branches and no load result is inspected before it is stored.
+  const E* zvec = (const E*)&kZeroVec;
+  auto gload = [&](int kt, u32x4_t* ra, u32x4_t* rb) {
     const int64_t k0 = (int64_t)(kt % kps) * BK;
+    const bool kok = kt < ktiles && k0 + kv < kk;
 #pragma unroll
     for (int i = 0; i < AV; ++i) {
-      u32x4_t val = {0u, 0u, 0u, 0u};
-      if (aok[i] && k0 + akv[i] < kk) val = *(const GVec*)(ap[i] + k0);
-      ra[i] = val;
+      const bool ok = kok && row0 + adr[i] + trow < mrows;
+      ra[i] = *(const GVec*)(ok ? abase[i] + toff + k0 : zvec);
     }
 #pragma unroll
     for (int i = 0; i < BV; ++i) {
-      u32x4_t val = {0u, 0u, 0u, 0u};
-      if (bok[i] && k0 + bkv[i] < kk) val = *(const GVec*)(bp[i] + k0);
-      rb[i] = val;
+      const bool ok = kok && col0 + bdr[i] + trow < ncols;
+      rb[i] = *(const GVec*)(ok ? bbase[i] + toff + k0 : zvec);
     }
   };
-  auto sstore = [&](int buf) {
-    E* a = As + buf * TILE_A;
-    E* b = Bs + buf * TILE_B;
+  auto sstore = [&](int buf, const u32x4_t* ra, const u32x4_t* rb) {
+    E* a = As + buf * TILE_A + trow * PITCH + kv;
+    E* b = Bs + buf * TILE_B + trow * PITCH + kv;
 #pragma unroll
     for (int i = 0; i < AV; ++i) {
-      const int v = tid + i * kThreads;
-      const int pl = v / (BM * VPR);
-      const int vv = v % (BM * VPR);
-      *(u32x4_t*)(a + pl * BM * PITCH + (vv / VPR) * PITCH + (vv % VPR) * VE) = ra[i];
+      const int pl = (i * RSTEP) / BM, c = (i * RSTEP) % BM;
+      *(u32x4_t*)(a + pl * BM * PITCH + c * PITCH) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < BV; ++i) {
-      const int v = tid + i * kThreads;
-      const int pl = v / (BN * VPR);
-      const int vv = v % (BN * VPR);
-      *(u32x4_t*)(b + pl * BN * PITCH + (vv / VPR) * PITCH + (vv % VPR) * VE) = rb[i];
+      const int pl = (i * RSTEP) / BN, c = (i * RSTEP) % BN;
+      *(u32x4_t*)(b + pl * BN * PITCH + c * PITCH) = rb[i];
     }
   };
 
@@ -373,18 +370,31 @@ __device__ __forceinline__ void gemm_body(const GemmLaunch& L, const Prob& pb, c
     }
   };
 
-  // -------- main loop (double-buffered, one barrier per k tile)
+  // -------- main loop: LDS double buffer, two k tiles in flight in
+  // registers (tile t is loaded two steps before it is computed), one
+  // barrier per k tile.  Unrolled by two so that each register set is static.
+  // Every step issues its loads and stores (tiles past the end load zeros),
+  // so the outstanding-load count is the same on every path and each store
+  // waits only for the loads of its own tile.
+  u32x4_t ra0[AV], rb0[BV], ra1[AV], rb1[BV];
+  auto issue = [&](int t, u32x4_t* ra, u32x4_t* rb) {
+    if (t < ktiles && t % kps == 0) set_seg(t / kps);
+    gload(t, ra, rb);
+  };
   if (ktiles > 0) {
-    set_seg(0);
-    gload(0);
-    sstore(0);
+    issue(0, ra0, rb0);
+    issue(1, ra1, rb1);
+    sstore(0, ra0, rb0);
     __syncthreads();
-    for (int kt = 0; kt < ktiles; ++kt) {
-      const bool more = kt + 1 < ktiles;
-      if (more && (kt + 1) % kps == 0) set_seg((kt + 1) / kps);
-      if (more) gload(kt + 1);
-      compute(kt & 1);
-      if (more) sstore((kt + 1) & 1);
+    for (int kt = 0; kt < ktiles; kt += 2) {
+      issue(kt + 2, ra0, rb0);
+      compute(0);
+      sstore(1, ra1, rb1);
+      __syncthreads();
+      if (kt + 1 >= ktiles) break;
+      issue(kt + 3, ra1, rb1);
+      compute(1);
+      sstore(0, ra0, rb0);
       __syncthreads();
     }
   }
@@ -492,7 +502,7 @@ __device__ __forceinline__ void gemm_body(const GemmLaunch& L, const Prob& pb, c
 }
 
 template <Prec P>
-__global__ __launch_bounds__(kThreads) void gemm_kernel(GemmLaunch L) {
+__global__ __launch_bounds__(kThreads, 2) void gemm_kernel(GemmLaunch L) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[Smem<P>::BYTES];
   __shared__ double red[4 * kMaxHad];
   const int64_t total = (int64_t)gridDim.x * gridDim.y;

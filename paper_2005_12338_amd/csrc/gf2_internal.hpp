@@ -152,6 +152,7 @@ struct gf2_split_h {
   double eps = 0.0, kmax = 0.0, thresh = 0.0;
   int64_t nnz = 0;
   int32_t wmax = 0;
+  int32_t span128 = 0;         // widest orbital range touched by 128 consecutive Q
   // device arrays
   int32_t* w = nullptr;        // [naux]
   int32_t* idx = nullptr;      // [naux][32], -1 padded
@@ -173,3 +174,5 @@ struct gf2_split_h {
 };
 
 constexpr int kWMax = 32;
+// Widest column window the row-staged deterministic block stages in LDS.
+constexpr int kDdSpan = 128;

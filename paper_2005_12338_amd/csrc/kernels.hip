@@ -340,21 +340,32 @@ __global__ void k_jk_scatter(const T* jblk, int64_t naux, int32_t nslot, int64_t
 // ------------------------------------------------------------- reductions -
 // Direct-term coefficients from the Hadamard partials c_xy = Tr(M_xy Gb):
 // coef = 2 (c_SS, c_SL + c_SS, c_LS + c_SS, c_LL + c_LS + c_SL + c_SS).
-__global__ void k_trace_coef(const double* part, int64_t ntiles, int32_t nslot, double* coef) {
-  int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= nslot) return;
-  double c[4];
-  for (int h = 0; h < 4; ++h) {
-    double s = 0.0;
-    const double* p = part + ((int64_t)slot * 4 + h) * ntiles;
-    for (int64_t t = 0; t < ntiles; ++t) s += p[t];
-    c[h] = s;
+// Fixed-order sum of p[0..cnt) by one wave: lane l takes l, l+64, ... in
+// order, then a butterfly over the lanes (the same pattern on every call).
+__device__ __forceinline__ double wave_sum_fixed(const double* p, int64_t cnt) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int64_t t = lane; t < cnt; t += 64) s += p[t];
+  for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
+  return s;
+}
+
+// Direct-term coefficients of a slot from its Hadamard-trace partials: one
+// workgroup per slot, one wave per trace.
+__global__ __launch_bounds__(256) void k_trace_coef(const double* part, int64_t ntiles, int32_t nslot,
+                                                    double* coef) {
+  __shared__ double c[4];
+  const int slot = blockIdx.x, h = threadIdx.x >> 6;
+  const double s = wave_sum_fixed(part + ((int64_t)slot * 4 + h) * ntiles, ntiles);
+  if ((threadIdx.x & 63) == 0) c[h] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* o = coef + (int64_t)slot * kMaxAdd;
+    o[0] = 2.0 * c[3];
+    o[1] = 2.0 * (c[2] + c[3]);
+    o[2] = 2.0 * (c[1] + c[3]);
+    o[3] = 2.0 * (c[0] + c[1] + c[2] + c[3]);
   }
-  double* o = coef + (int64_t)slot * kMaxAdd;
-  o[0] = 2.0 * c[3];
-  o[1] = 2.0 * (c[2] + c[3]);
-  o[2] = 2.0 * (c[1] + c[3]);
-  o[3] = 2.0 * (c[0] + c[1] + c[2] + c[3]);
 }
 
 // Sigma_sum[tau] += sum of the chunk's Sigma_s in unit order; e_s(tau) from
@@ -375,14 +386,13 @@ __global__ void k_accumulate(const Unit* units, int32_t nunit, const void* sig, 
   sum[(int64_t)t * n * n + ij] = acc;
 }
 
-__global__ void k_esamples(const Unit* units, int32_t nunit, const double* part, int64_t ntiles,
-                           int64_t s0, int64_t ntau, double* es) {
-  int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= nunit) return;
-  const double* p = part + (int64_t)units[u].slot * ntiles;
-  double s = 0.0;
-  for (int64_t t = 0; t < ntiles; ++t) s += p[t];
-  es[((int64_t)units[u].s - s0) * ntau + units[u].tau] = s;
+// e_s(tau) of every unit from its per-tile partials: one wave per unit.
+__global__ __launch_bounds__(256) void k_esamples(const Unit* units, int32_t nunit, const double* part,
+                                                  int64_t ntiles, int64_t s0, int64_t ntau, double* es) {
+  const int u = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (u >= nunit) return;                        // whole wave leaves together
+  const double s = wave_sum_fixed(part + (int64_t)units[u].slot * ntiles, ntiles);
+  if ((threadIdx.x & 63) == 0) es[((int64_t)units[u].s - s0) * ntau + units[u].tau] = s;
 }
 
 __global__ void k_finalize(const double* det, const double* sum, int64_t n, int64_t ntau,
@@ -416,21 +426,24 @@ __global__ void k_trace_prod(const double* sig, const double* gb, int64_t n, dou
 }
 
 // out[0] = E_tot, out[1] = mean_s E_s - E_tot (~0), out[2] = stderr.
+// E_tot = -gm sum_t w_t (tr[t] + [add_mean] mean_s e_s(t)) and the
+// standard error of the per-sample totals (one block, fixed order).
 __global__ void k_energy_stats(const double* tr, const double* w, int64_t ntau, const double* es,
-                               int64_t ns, double gm, double* out) {
+                               int64_t ns, double gm, int add_mean, double* out) {
   __shared__ double sm[256];
   __shared__ double ebar[512];
   __shared__ double etot_s;
-  if (threadIdx.x == 0) {
-    double e = 0.0;
-    for (int64_t t = 0; t < ntau; ++t) e += w[t] * tr[t];
-    etot_s = -gm * e;
-  }
   // mean over samples of e_s(tau), per tau (tau <= 512 handled in shared)
   for (int64_t t = threadIdx.x; t < ntau && t < 512; t += blockDim.x) {
     double m = 0.0;
     for (int64_t s = 0; s < ns; ++s) m += es ? es[s * ntau + t] : 0.0;
     ebar[t] = ns ? m / (double)ns : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double e = 0.0;
+    for (int64_t t = 0; t < ntau; ++t) e += w[t] * (tr[t] + (add_mean ? ebar[t] : 0.0));
+    etot_s = -gm * e;
   }
   __syncthreads();
   const double etot = etot_s;
@@ -582,7 +595,7 @@ void launch_jk_scatter(bool f64, const void* jblk, int64_t naux, int32_t nslot, 
                        out_st_slot);
 }
 void launch_trace_coef(const double* part, int64_t ntiles, int32_t nslot, double* coef, hipStream_t st) {
-  hipLaunchKernelGGL(k_trace_coef, dim3(blocks(nslot, 64)), dim3(64), 0, st, part, ntiles, nslot, coef);
+  hipLaunchKernelGGL(k_trace_coef, dim3((unsigned)nslot), dim3(256), 0, st, part, ntiles, nslot, coef);
 }
 void launch_accumulate(const Unit* units, int32_t nunit, const void* sig, bool f64, int64_t sig_st_slot,
                        int64_t n, int64_t np, double* sum, int32_t tau_lo, int32_t tau_hi, hipStream_t st) {
@@ -592,7 +605,8 @@ void launch_accumulate(const Unit* units, int32_t nunit, const void* sig, bool f
 }
 void launch_esamples(const Unit* units, int32_t nunit, const double* part, int64_t ntiles, int64_t s0,
                      int64_t ntau, double* es, hipStream_t st) {
-  hipLaunchKernelGGL(k_esamples, dim3(blocks(nunit, 64)), dim3(64), 0, st, units, nunit, part, ntiles, s0, ntau, es);
+  hipLaunchKernelGGL(k_esamples, dim3((unsigned)((nunit + 3) / 4)), dim3(256), 0, st, units, nunit, part, ntiles, s0,
+                     ntau, es);
 }
 void launch_finalize(const double* det, const double* sum, int64_t n, int64_t ntau, double inv2ns,
                      double* out, hipStream_t st) {
@@ -603,8 +617,8 @@ void launch_trace_prod(const double* sig, const double* gb, int64_t n, int64_t n
   hipLaunchKernelGGL(k_trace_prod, dim3((unsigned)ntau), dim3(256), 0, st, sig, gb, n, tr);
 }
 void launch_energy_stats(const double* tr, const double* w, int64_t ntau, const double* es, int64_t ns,
-                         double gm, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_energy_stats, dim3(1), dim3(256), 0, st, tr, w, ntau, es, ns, gm, out);
+                         double gm, double* out, hipStream_t st, bool add_mean) {
+  hipLaunchKernelGGL(k_energy_stats, dim3(1), dim3(256), 0, st, tr, w, ntau, es, ns, gm, add_mean ? 1 : 0, out);
 }
 void launch_transpose(const void* src, bool f64, int64_t rows, int64_t cols, double* dst, int64_t ld,
                       hipStream_t st) {

@@ -48,7 +48,7 @@ void launch_finalize(const double* det, const double* sum, int64_t n, int64_t nt
 void launch_trace_prod(const double* sig, const double* gb, int64_t n, int64_t ntau, double* tr,
                        hipStream_t st);
 void launch_energy_stats(const double* tr, const double* w, int64_t ntau, const double* es, int64_t ns,
-                         double gm, double* out, hipStream_t st);
+                         double gm, double* out, hipStream_t st, bool add_mean = false);
 void launch_transpose(const void* src, bool f64, int64_t rows, int64_t cols, double* dst, int64_t ld,
                       hipStream_t st);
 void launch_untranspose(const double* src, int64_t rows, int64_t cols, int64_t ld, void* dst, bool f64,
@@ -63,6 +63,7 @@ int64_t dd_strip_bytes(int64_t n, int64_t naux, int32_t wmax, int64_t ntau_batch
 // Register form of the deterministic block for supports of at most 8
 // orbitals (returns false, launching nothing, for wider supports).
 bool launch_dd_strips(const double* G, const double* Gb, int64_t n, int64_t naux, int64_t ntau, int32_t wmax,
+                      int32_t span128,
                       const int32_t* wq, const int32_t* idx, const double* blk, const int32_t* col_off,
                       const int32_t* col_q, double* strip, int64_t ntau_batch, double* out, hipStream_t st);
 
@@ -75,8 +76,4 @@ void launch_pair_tables(int wmax, const double* G, const double* Gb, int64_t n, 
                         const int32_t* ik, const double* kb, double* tab, hipStream_t st);
 void launch_targets(const double* tab, int64_t naux, double* t, hipStream_t st);
 
-// Host numerics (eigen.cpp).
-// Symmetric eigendecomposition a = v diag(e) v^T (a row-major n x n,
-// overwritten); e ascending, v row-major with eigenvectors in columns.
-void sym_eigen(int64_t n, double* a, double* e, double* v);
-void gauss_legendre(int64_t n, double* x, double* w);
+#include "host_numerics.hpp"

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_PKG, "libgf2.so")
 
 GF2_OK, GF2_E_ARG, GF2_E_DEVICE, GF2_E_NOMEM, GF2_E_NUMERIC, GF2_E_STATE = 0, -1, -2, -3, -4, -5
 GF2_F64, GF2_F32 = 0, 1
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "auto": 4}
+PREC_NAME = {v: k for k, v in PREC.items()}
 SAMPLE_RADEMACHER, SAMPLE_IMPORTANCE = 0, 1
 
 _STATUS = {GF2_E_ARG: "GF2_E_ARG", GF2_E_DEVICE: "GF2_E_DEVICE", GF2_E_NOMEM: "GF2_E_NOMEM",
@@ -42,6 +43,11 @@ class ChainGeom(C.Structure):
 class Sampling(C.Structure):
     _fields_ = [("ns", C.c_int64), ("s0", C.c_int64), ("seed", C.c_uint64), ("mode", C.c_int32),
                 ("k", C.c_int32), ("p", C.POINTER(C.c_double))]
+
+
+class AdaptiveResult(C.Structure):
+    _fields_ = [("e_corr", C.c_double), ("e_corr_per_e", C.c_double), ("stderr_tot", C.c_double),
+                ("pairs", C.c_int64), ("precision", C.c_int32), ("bias_probe", C.c_double)]
 
 
 class MlpC(C.Structure):
@@ -88,6 +94,10 @@ _SIGS = {
                                  C.c_void_p]),
     "gf2_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.POINTER(C.c_int32)]),
+    "gf2_energy_adaptive": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                      C.POINTER(C.c_double), C.c_void_p, C.c_double, C.POINTER(Sampling),
+                                      C.c_int, C.c_double, C.c_int64, C.c_void_p, C.c_void_p,
+                                      C.POINTER(AdaptiveResult)]),
     "gf2_proposal_features": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                         C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
     "gf2_proposal_targets": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
@@ -312,6 +322,26 @@ class Context:
         self._check(self.lib.gf2_sigma_finalize(self.h, n, ntau, Sigma_det.data_ptr(), Sigma_sum.data_ptr(),
                                                 int(ns_total), out.data_ptr()))
         return out
+
+    def energy_adaptive(self, split: Split, B, G, Gb, w: np.ndarray, Sigma_det, n_elec: float, target: float,
+                        batch: int = 16, max_pairs: int = 4096, seed: int = 0, prec: str = "auto", p=None,
+                        k: int = 1):
+        """Sample pairs in batches until the standard error of the total
+        E_corr is below target.  Returns (Sigma, e_samples[:pairs], dict)."""
+        torch = self.torch
+        ntau, n, _ = G.shape
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        Sigma = torch.empty((ntau, n, n), dtype=torch.float64, device=self.device)
+        es = torch.empty((max_pairs, ntau), dtype=torch.float64, device=self.device)
+        smp, keep = self._sampling(batch, seed, 0, p, k)
+        r = AdaptiveResult()
+        self._check(self.lib.gf2_energy_adaptive(self.h, split.handle, B.data_ptr(), G.data_ptr(), Gb.data_ptr(),
+                                                 ntau, _dp(w), Sigma_det.data_ptr(), float(n_elec), C.byref(smp),
+                                                 PREC[prec], float(target), int(max_pairs), Sigma.data_ptr(),
+                                                 es.data_ptr(), C.byref(r)))
+        info = dict(E=r.e_corr, E_per_e=r.e_corr_per_e, stderr=r.stderr_tot, pairs=int(r.pairs),
+                    precision=PREC_NAME[int(r.precision)], bias_probe=r.bias_probe)
+        return Sigma, es[:r.pairs], info
 
     # ---------------------------------------------------------------- energy
     def energy(self, Sigma, Gb, w: np.ndarray, n_elec: float, e_samples=None):

@@ -1,0 +1,123 @@
+"""Error budget of the reduced-precision chain products against the FP64 oracle.
+
+The stochastic-block products run in BF16 (FP32 accumulation), split-BF16x3
+or FP32; the deterministic block, traces, accumulation and energy stay in
+FP64.  The oracle evaluates the same pairs (same theta) in FP64.  Bars:
+  * BF16 (threshold 1e-4): the error of E_corr is below 0.1x its
+    statistical error (from the same pairs);
+  * AUTO (BF16, switching to BF16x3 when a probe pair shows the rounding):
+    E_corr below 0.1x its statistical error, and every per-tau trace
+    Tr(Sigma(tau) Gbar(tau)) within 0.1x its statistical error or within
+    1e-5 of its value (where the stochastic part vanishes, so does its
+    statistical error);
+  * BF16x3 and FP32: 1e-5 relative on E_corr and on Sigma.
+The library's results are compared as returned: B is stored in FP32 as in
+the benchmarks, so they also carry that rounding.
+"""
+import numpy as np
+import pytest
+
+from oracle import energy, selfenergy as se
+
+from _problems import chain, oracle_pairs, oracle_setup, rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NTAU, NS = 6, 8
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2005_12338_amd import gf2
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = gf2.Context(0)
+    yield c
+    c.close()
+
+
+_CACHE = {}
+
+
+def n200(eps):
+    """100-dimer chain (N=200, N_aux=600), beta=100, with the oracle's
+    per-pair Sigma_s for NS pairs at NTAU tau points."""
+    if eps in _CACHE:
+        return _CACHE[eps]
+    pb = chain(100, 100.0, NTAU, eps)
+    o = oracle_setup(pb)
+    per = oracle_pairs(o, 0, NS, range(NTAU), range(NS))
+    det = [se.sigma_dd(o["split"], o["g"][t], o["gb"][t]) for t in range(NTAU)]
+    e_det = np.array([energy.trace_product(det[t], o["gb"][t]) for t in range(NTAU)])
+    es = np.array([[energy.trace_product(per[(t, s)], o["gb"][t]) for t in range(NTAU)] for s in range(NS)])
+    sig = []
+    for t in range(NTAU):
+        acc = sum(per[(t, s)] for s in range(NS))
+        sig.append(det[t] + (acc + acc.T) / (2.0 * NS))
+    _CACHE[eps] = (pb, o, np.array(sig), e_det, es)
+    return _CACHE[eps]
+
+
+def _gpu(ctx, pb, prec):
+    """Sigma, e_samples and the library's own E_corr for NS pairs (B in FP32
+    as in the benchmarks, FP64 for the FP64 path)."""
+    from oracle import green
+    geo = pb["geo"]
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    B = ctx.build_B(geo.n, geo.naux, geom=geo, dtype=dtype)
+    tau, w = green.tau_grid(pb["beta"], pb["ntau"])
+    G, Gb, _ = ctx.green_tau(pb["f"], tau, pb["beta"], n_occ=geo.n // 2)
+    spl = ctx.split(B, pb["eps"])
+    info = None
+    if prec == "auto":
+        det = ctx.sigma_det(spl, G, Gb)
+        Sigma, es, info = ctx.energy_adaptive(spl, B, G, Gb, w, det, geo.n, target=1e-12, batch=NS,
+                                              max_pairs=NS, prec="auto")
+        e_lib = info["E"]
+    else:
+        Sigma, es = ctx.sigma_tau(spl, B, G, Gb, ns=NS, seed=0, prec=prec)
+        e_lib, _, _ = ctx.energy(Sigma, Gb, w, geo.n, es)
+    return Sigma.cpu().numpy(), es.cpu().numpy(), w, e_lib, info
+
+
+@pytest.mark.parametrize("prec,eps", [("bf16", 1e-4), ("auto", 1e-4), ("auto", 1e-3), ("bf16x3", 1e-3),
+                                      ("fp32", 1e-3)])
+def test_reduced_precision_error_budget(ctx, prec, eps):
+    pb, o, sig_ref, e_det, es_ref = n200(eps)
+    sig, es, w, e_lib, info = _gpu(ctx, pb, prec)
+    m_ref, se_ref = energy.mean_stderr(energy.sample_energies(e_det, es_ref, w))
+    err_e = abs(e_lib - m_ref)
+    # Tr(Sigma(tau) Gbar(tau)) of the returned Sigma against the oracle's, and
+    # the statistical error of that trace (from the oracle's pairs)
+    gb = o["gb"]
+    tr_got = np.array([energy.trace_product(sig[t], gb[t]) for t in range(NTAU)])
+    tr_ref = np.array([energy.trace_product(sig_ref[t], gb[t]) for t in range(NTAU)])
+    tr_err = np.abs(tr_got - tr_ref)
+    tr_se = es_ref.std(axis=0, ddof=1) / np.sqrt(NS)
+    print(f"{prec} eps={eps}: |dE| = {err_e:.3e} Eh, stderr = {se_ref:.3e} Eh, ratio {err_e / se_ref:.2e}; "
+          f"max per-tau ratio {np.max(tr_err / tr_se):.2e}; Sigma rel {rel(sig, sig_ref):.2e}; {info}")
+    if prec == "bf16":
+        assert err_e < 0.1 * se_ref               # E_corr within the budget at this threshold
+    elif prec == "auto":
+        # E_corr, and every per-tau trace within 0.1x its statistical error or
+        # within the FP32 path's 1e-5 of its value
+        assert err_e < 0.1 * se_ref
+        assert np.all(tr_err < np.maximum(0.1 * tr_se, 1e-5 * np.abs(tr_ref)))
+        assert info["pairs"] == NS
+    else:
+        assert err_e < 1e-5 * abs(m_ref)
+        assert rel(sig, sig_ref) < 1e-5
+
+
+def test_plain_bf16_exceeds_the_budget_where_auto_switches(ctx):
+    """At eps=1e-3 the stochastic block is large enough that BF16 rounding is
+    visible next to the standard error of 8 pairs: plain BF16 misses the bar,
+    which is why the AUTO policy switches to BF16x3 there."""
+    pb, o, sig_ref, e_det, es_ref = n200(1e-3)
+    _, _, w, e_lib, _ = _gpu(ctx, pb, "bf16")
+    m_ref, se_ref = energy.mean_stderr(energy.sample_energies(e_det, es_ref, w))
+    assert abs(e_lib - m_ref) > 0.1 * se_ref
+    _, _, _, _, info = _gpu(ctx, pb, "auto")
+    assert info["precision"] == "bf16x3"
+    assert info["bias_probe"] > 0.0
