@@ -235,6 +235,36 @@ gf2_status gf2_profile_read(gf2_ctx* ctx, int32_t cap, char* names, int64_t* lau
  * output; FP32: float; BF16: bf16 operands, float output; BF16X3: each
  * operand is two bf16 planes (hi, lo) of ld*ld elements each.  For tests and
  * benchmarks of the kernel itself. */
+/* ------------------------------------------------------------ batch -------
+ * Many chains of uneven size in one schedule: every instance's (tau, pair)
+ * units go through the same grouped product launches (each unit carries its
+ * instance; tiles beyond an instance's size are skipped), so small instances
+ * fill the GPU together.  Per instance the result equals gf2_sigma_tau:
+ *   Sigma = Sigma[D,D] + (1/N_s) sum_s (Sigma_s + Sigma_s^T)/2  (eq:sigma_2)
+ * and e_samples [ns][ntau] (may be NULL).
+ * flags: GF2_BATCH_GRAPH records the chunk loop of the call into one HIP
+ * graph and launches it; GF2_BATCH_AUTOTUNE times candidate launch shapes
+ * (pairs x tau points per chunk, persistent grid or not) on the first chunks
+ * and keeps the fastest for this batch signature (cached in ctx).
+ * The library allocates per-instance workspace (freed by gf2_destroy).
+ * Errors: as gf2_sigma_tau for any item; GF2_E_ARG for nitem < 1. */
+typedef struct {
+  const gf2_split_h* split;
+  const void* B;
+  const double* G;          /* device [ntau][n][n]                              */
+  const double* Gbar;       /* device [ntau][n][n]                              */
+  int64_t ntau;
+  gf2_sampling sampling;    /* ns pairs from s0, seed, mode, k, p               */
+  double* Sigma;            /* out, device [ntau][n][n]                         */
+  double* e_samples;        /* out, device [ns][ntau] or NULL                   */
+} gf2_batch_item;
+
+#define GF2_BATCH_GRAPH 1
+#define GF2_BATCH_AUTOTUNE 2
+
+gf2_status gf2_sigma_batch(gf2_ctx* ctx, int32_t nitem, const gf2_batch_item* items,
+                           gf2_precision prec, int32_t flags);
+
 /* ------------------------------------------------------------ adaptive ---
  * Sampling until a target standard error (the accuracy criterion of the
  * results section: statistical error of the total E_corr of eq:corr).

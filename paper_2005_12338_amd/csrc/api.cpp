@@ -264,7 +264,7 @@ gf2_status gf2_build_B(gf2_ctx* ctx, int64_t n, int64_t naux, const void* ijA, c
     Unit uh{0, 0, 0, 0};
     auto* units = (Unit*)ctx_buf(ctx, "bunit", sizeof(Unit));
     h2d(ctx, units, &uh, 1);
-    GemmLaunch L{probs, 1, units, 1, nn, naux, kp, kp, 0};
+    GemmLaunch L{probs, 1, 0, units, 1, InstGeo{nn, naux, kp, kp, 0}, nullptr, 0, 0};
     launch_gemm(Prec::F64, L, tiles_of(pb, Prec::F64, nn, naux), ctx->stream);
     launch_untranspose(tout, nn, naux, kp, B, f64, ctx->stream);
     GF2_HIP(hipGetLastError());
@@ -567,31 +567,101 @@ struct ChainBufs {
   int32_t slots;
 };
 
-void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double* G, const double* Gbar,
-               int64_t ntau, const gf2_sampling* smp, Prec prec, double* Sigma_sum, double* e_samples) {
-  const int64_t n = sp->n, np = sp->np, np2 = np * np, naux = sp->naux;
-  const int64_t ns = smp->ns, s0 = smp->s0;
+// One instance's chain schedule: buffers, problem tables and unit lists,
+// set up once; the chunks are then launched by chain_stage / chain_jk /
+// chain_acc (one instance) or by the batch path (many instances at once).
+struct ChainPlan {
+  const gf2_split_h* sp = nullptr;
+  Prec prec = Prec::F32;
+  int64_t n = 0, np = 0, np2 = 0, naux = 0, ntau = 0, ns = 0, plane = 0;
+  bool accf64 = false;
+  size_t sb = 0, ab = 0;
+  int64_t slots = 0, sc = 0, tcnt = 0;
+  int mtiles = 0, ftiles = 0;
+  double *mpart = nullptr, *epart = nullptr, *coef = nullptr, *gb64 = nullptr;
+  char *wz = nullptr, *jw_l = nullptr, *jw_s = nullptr, *jz_st = nullptr, *jz_sum_t = nullptr, *jblk = nullptr;
+  char* sig = nullptr;
+  int64_t st_sl = 0, ac_sl = 0;
+  std::vector<Prob> P;
+  Prob* dprobs = nullptr;
+  std::vector<Unit> uall;
+  Unit* dunits = nullptr;
+  std::vector<std::pair<int64_t, int64_t>> chunks;   // (offset, count) into uall
+  std::vector<std::pair<int32_t, int32_t>> trange;   // tau range of each chunk
+  double* Sigma_sum = nullptr;
+  double* e_samples = nullptr;
+};
+
+// The four product stages of one chunk: (first problem, problems, products per unit).
+constexpr int kStageOff[4] = {0, 2, 5, 7};
+constexpr int kStageCnt[4] = {2, 3, 2, 1};
+constexpr int kStageProducts[4] = {4, 8, 4, 8};
+constexpr int kProbsPerPlan = 8;
+
+const char* gemm_name(Prec prec) {
+  return prec == Prec::F64 ? "gemm_f64" : prec == Prec::F32 ? "gemm_f32"
+         : prec == Prec::BF16 ? "gemm_bf16" : "gemm_bf16x3";
+}
+
+// Slots (units per chunk) that keep the per-slot scratch near 4 GB.
+int64_t auto_slots(int64_t n, Prec prec) {
+  const int64_t np = pad_dim(n), np2 = np * np;
+  const size_t sb = (size_t)st_planes(prec) * np2 * st_elem(prec);
+  const size_t ab = (size_t)np2 * acc_elem(prec);
+  const double per_slot = 30.0 * (double)std::max(sb, ab);
+  return (int64_t)std::max(1.0, std::min(64.0, 4.0e9 / per_slot));
+}
+
+// Buffers (tags prefixed by pfx), G conversions, stochastic vectors, problem
+// tables and unit lists of one instance.  sc / tcnt > 0 force the chunk shape.
+void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_split_h* sp, const void* B,
+                const double* G, const double* Gbar, int64_t ntau, const gf2_sampling* smp, Prec prec,
+                double* Sigma_sum, double* e_samples, int64_t force_sc = 0, int64_t force_tcnt = 0) {
+  c.sp = sp;
+  c.prec = prec;
+  c.n = sp->n;
+  c.np = sp->np;
+  c.np2 = c.np * c.np;
+  c.naux = sp->naux;
+  c.ntau = ntau;
+  c.ns = smp->ns;
+  c.Sigma_sum = Sigma_sum;
+  c.e_samples = e_samples;
+  const int64_t n = c.n, np = c.np, np2 = c.np2, naux = c.naux, ns = c.ns, s0 = smp->s0;
   const bool bf64 = sp->dtype == GF2_F64;
   const int planes = st_planes(prec);
-  const int64_t plane = np2;
-  const size_t sb = (size_t)planes * np2 * st_elem(prec);     // one storage matrix
-  const size_t ab = (size_t)np2 * acc_elem(prec);             // one accumulator matrix
-  const bool accf64 = prec == Prec::F64;
+  c.plane = np2;
+  const int64_t plane = c.plane;
+  c.sb = (size_t)planes * np2 * st_elem(prec);     // one storage matrix
+  c.ab = (size_t)np2 * acc_elem(prec);             // one accumulator matrix
+  const size_t sb = c.sb, ab = c.ab;
+  c.accf64 = prec == Prec::F64;
   hipStream_t st = ctx->stream;
+
+  // ---- chunking: units (tau, s), s outer so that every Sigma_sum[tau]
+  // receives its pairs in increasing s; several pairs per tau in a chunk, so
+  // each Sigma_sum[tau] is read and written once per chunk for all of them.
+  int64_t slots = ctx->max_units > 0 ? ctx->max_units : auto_slots(n, prec);
+  slots = std::min<int64_t>(slots, ntau * ns);
+  c.sc = force_sc > 0 ? std::min(force_sc, ns) : std::min<int64_t>(ns, std::min<int64_t>(8, slots));
+  c.tcnt = force_tcnt > 0 ? std::min(force_tcnt, ntau) : std::max<int64_t>(1, std::min<int64_t>(ntau, slots / c.sc));
+  c.slots = slots = c.sc * c.tcnt;
+
   // The products run over the zero padding of every np x np matrix, so a
   // change of layout clears all chain buffers (new allocations are zeroed).
   const std::string key = std::to_string(n) + ":" + std::to_string(np) + ":" + std::to_string((int)prec);
-  const bool reset = ctx->chain_key != key;
-  ctx->chain_key = key;
-  auto CB = [&](const char* tag, size_t bytes) { return (char*)ctx_buf(ctx, tag, bytes, reset); };
+  std::string& prev = ctx->chain_keys[pfx];
+  const bool reset = prev != key;
+  prev = key;
+  auto CB = [&](const char* tag, size_t bytes) { return (char*)ctx_buf(ctx, pfx + tag, bytes, reset); };
 
   // ---- G, Gbar in padded storage format and FP64
   char* gst = CB("c_gst", sb * ntau);
   char* gbst = CB("c_gbst", sb * ntau);
-  double* gb64 = (double*)CB("c_gb64", (size_t)ntau * np2 * 8);
+  c.gb64 = (double*)CB("c_gb64", (size_t)ntau * np2 * 8);
   const int64_t mstride = (int64_t)planes * np2;              // elements per storage matrix
   launch_pad_convert(G, n, np, ntau, prec, gst, plane, mstride, nullptr, st);
-  launch_pad_convert(Gbar, n, np, ntau, prec, gbst, plane, mstride, gb64, st);
+  launch_pad_convert(Gbar, n, np, ntau, prec, gbst, plane, mstride, c.gb64, st);
   GF2_HIP(hipGetLastError());
 
   // ---- stochastic vectors: [0, ns) first vertex (xi), [ns, 2ns) second (eta)
@@ -599,7 +669,7 @@ void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double*
   char* xl = CB("c_xl", sb * nvec);
   char* xs = CB("c_xs", sb * nvec);
   if (smp->mode == GF2_SAMPLE_RADEMACHER) {
-    auto* theta = (int8_t*)ctx_buf(ctx, "c_theta", (size_t)(nvec * naux));
+    auto* theta = (int8_t*)ctx_buf(ctx, pfx + "c_theta", (size_t)(nvec * naux));
     ProfScope ps(ctx, "rbuild", 4.0 * (double)nvec * naux * n * n, (double)naux * n * n * (bf64 ? 8 : 4));
     launch_theta(smp->seed, ns, s0, naux, theta, st);
     launch_rbuild(B, bf64, n, naux, sp->thresh, theta, nvec, prec, xl, xs, np, plane, mstride, st);
@@ -611,10 +681,10 @@ void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double*
       cdf[q] = acc;
     }
     cdf[naux - 1] = 1.0;
-    auto* dcdf = (double*)ctx_buf(ctx, "c_cdf", (size_t)naux * 8);
-    auto* dp = (double*)ctx_buf(ctx, "c_p", (size_t)naux * 8);
-    auto* dq = (int32_t*)ctx_buf(ctx, "c_q", (size_t)(nvec * smp->k) * 4);
-    auto* dw = (double*)ctx_buf(ctx, "c_w", (size_t)(nvec * smp->k) * 8);
+    auto* dcdf = (double*)ctx_buf(ctx, pfx + "c_cdf", (size_t)naux * 8);
+    auto* dp = (double*)ctx_buf(ctx, pfx + "c_p", (size_t)naux * 8);
+    auto* dq = (int32_t*)ctx_buf(ctx, pfx + "c_q", (size_t)(nvec * smp->k) * 4);
+    auto* dw = (double*)ctx_buf(ctx, pfx + "c_w", (size_t)(nvec * smp->k) * 8);
     h2d(ctx, dcdf, cdf.data(), cdf.size());
     h2d(ctx, dp, smp->p, (size_t)naux);
     launch_draws(smp->seed, ns, s0, smp->k, dcdf, naux, dp, dq, dw, st);
@@ -622,43 +692,36 @@ void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double*
   }
   GF2_HIP(hipGetLastError());
 
-  // ---- chunking: units (tau, s), s outer so that every Sigma_sum[tau]
-  // receives its pairs in increasing s.
-  int64_t slots = ctx->max_units > 0 ? ctx->max_units : 0;
-  if (slots <= 0) {
-    // keep per-slot scratch near 4 GB and the grid well above 256 CUs
-    const double per_slot = 30.0 * (double)std::max(sb, ab);
-    slots = (int64_t)std::max(1.0, std::min(64.0, 4.0e9 / per_slot));
-  }
-  slots = std::min<int64_t>(slots, ntau * ns);
-  // several pairs per tau in a chunk, so each Sigma_sum[tau] is read and
-  // written once per chunk for all of them
-  const int64_t sc = std::min<int64_t>(ns, std::min<int64_t>(8, slots));
-  const int64_t tcnt = std::max<int64_t>(1, std::min<int64_t>(ntau, slots / sc));
-  slots = sc * tcnt;
-
   // per-slot scratch
-  auto S = [&](const char* tag, size_t bytes) { return (char*)ctx_buf(ctx, tag, bytes * slots, reset); };
+  auto S = [&](const char* tag, size_t bytes) { return (char*)ctx_buf(ctx, pfx + tag, bytes * slots, reset); };
   char *ul_n = S("c_uln", sb), *ul_t = S("c_ult", sb), *us_n = S("c_usn", sb), *us_t = S("c_ust", sb);
   char *vl_n = S("c_vln", sb), *vs_n = S("c_vsn", sb), *vs_t = S("c_vst", sb), *vsum_t = S("c_vsumt", sb);
   char* mst = S("c_mst", 4 * sb);
   char* mct = S("c_mct", 4 * sb);
-  char* wz = S("c_wz", 4 * ab);
+  c.wz = S("c_wz", 4 * ab);
+  char* wz = c.wz;
   char* tq = S("c_t", 4 * sb);
-  char* sig = S("c_sig", ab);
-  // pattern-only outputs of JK: zero once, only pattern entries are written
-  char* jk = (char*)ctx_buf(ctx, "c_jk", 4 * sb * slots, true);
-  char *jw_l = jk, *jw_s = jk + sb * slots, *jz_st = jk + 2 * sb * slots, *jz_sum_t = jk + 3 * sb * slots;
-  // (each JK output array is [slot][plane][np][np])
-  const size_t jbytes = (size_t)slots * 4 * naux * kWMax * kWMax * (accf64 ? 8 : 4);
-  char* jblk = (char*)ctx_buf(ctx, "c_jblk", jbytes);
-  const int64_t st_sl = (int64_t)(sb / st_elem(prec));        // elements per storage slot
-  const int64_t ac_sl = (int64_t)np2;
+  c.sig = S("c_sig", ab);
+  char* sig = c.sig;
+  // pattern-only outputs of JK: zeroed once here, only pattern entries are
+  // written (each JK output array is [slot][plane][np][np])
+  char* jk = (char*)ctx_buf(ctx, pfx + "c_jk", 4 * sb * slots, true);
+  c.jw_l = jk;
+  c.jw_s = jk + sb * slots;
+  c.jz_st = jk + 2 * sb * slots;
+  c.jz_sum_t = jk + 3 * sb * slots;
+  char *jw_l = c.jw_l, *jw_s = c.jw_s, *jz_st = c.jz_st, *jz_sum_t = c.jz_sum_t;
+  const size_t jbytes = (size_t)slots * 4 * naux * kWMax * kWMax * (c.accf64 ? 8 : 4);
+  c.jblk = (char*)ctx_buf(ctx, pfx + "c_jblk", jbytes);
+  c.st_sl = (int64_t)(sb / st_elem(prec));        // elements per storage slot
+  c.ac_sl = (int64_t)np2;
+  const int64_t st_sl = c.st_sl, ac_sl = c.ac_sl;
 
   // ---- problem tables
   const int64_t vst = planes * np2;                            // one vector
   const int64_t gstride = planes * np2;                        // one tau of G storage
-  std::vector<Prob> P;
+  std::vector<Prob>& P = c.P;
+  P.clear();
   // S1: U = X G (dual A), V = G Y (dual B)
   {
     Prob p = prob0();
@@ -684,15 +747,14 @@ void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double*
     q.out[3] = outspec(vsum_t, st_sl, {1, 1}, 1, 1);
     P.push_back(q);
   }
-  const int s1_off = 0, s1_n = 2;
   Prob quad = prob0();
   quad.nA = 2; quad.nB = 2;
-  const int mtiles = tiles_of(quad, prec, n);
+  c.mtiles = tiles_of(quad, prec, n);
   Prob single = prob0();
-  const int ftiles = tiles_of(single, prec, n);
-  double* mpart = (double*)S("c_mpart", 4 * mtiles * 8);
-  double* epart = (double*)S("c_epart", ftiles * 8);
-  double* coef = (double*)S("c_coef", kMaxAdd * 8);
+  c.ftiles = tiles_of(single, prec, n);
+  c.mpart = (double*)S("c_mpart", 4 * c.mtiles * 8);
+  c.epart = (double*)S("c_epart", c.ftiles * 8);
+  c.coef = (double*)S("c_coef", kMaxAdd * 8);
   // S2: M quad, W = V Gb (dual A), Z = Gb U (dual B)
   {
     Prob p = prob0();
@@ -711,13 +773,13 @@ void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double*
     p.out[6] = outspec(mct + 2 * sb, 4 * st_sl, {0, -1, 0, -1}, 1, 1);
     p.out[7] = outspec(mct + 3 * sb, 4 * st_sl, {-1, -1, -1, -1}, 1, 1);
     p.nhad = 4;
-    p.had_h = opref(gb64, np2);
+    p.had_h = opref(c.gb64, np2);
     for (int x = 0; x < 4; ++x) {
       for (int y = 0; y < 4; ++y) p.had_coef[x][y] = 0.0f;
       p.had_coef[x][x] = 1.0f;
     }
-    p.had_part = mpart;
-    p.had_ntiles = mtiles;
+    p.had_part = c.mpart;
+    p.had_ntiles = c.mtiles;
     P.push_back(p);
     Prob w = prob0();
     w.nA = 2;
@@ -738,7 +800,6 @@ void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double*
     z.out[1] = outspec(wz + 3 * ab, 4 * ac_sl, {0, 1}, 0, 0);
     P.push_back(z);
   }
-  const int s2_off = 2, s2_n = 3;
   // S3: T_xy = M_xy Gb
   for (int h = 0; h < 2; ++h) {
     Prob p = prob0();
@@ -751,7 +812,6 @@ void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double*
     p.out[1] = outspec(tq + (2 * h + 1) * sb, 4 * st_sl, {0, 1}, 0, 1);
     P.push_back(p);
   }
-  const int s3_off = 5, s3_n = 2;
   // S4: exchange + cross terms as one K-concatenated product, direct term
   // and the energy trace in the epilogue
   {
@@ -767,73 +827,85 @@ void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double*
     p.a[7] = opref(us_n, 0, 0, st_sl);   p.b[7] = opref(jz_sum_t, 0, 0, st_sl);
     p.nadd = 4;
     for (int x = 0; x < 4; ++x) p.add[x] = opref(mst + x * sb, 0, 0, 4 * st_sl);
-    p.add_coef = coef;
+    p.add_coef = c.coef;
     p.nout = 1;
     p.out[0] = outspec(sig, ac_sl, {1}, 0, 0);
     p.nhad = 1;
-    p.had_h = opref(gb64, np2);
+    p.had_h = opref(c.gb64, np2);
     p.had_coef[0][0] = 1.0f;
-    p.had_part = epart;
-    p.had_ntiles = ftiles;
+    p.had_part = c.epart;
+    p.had_ntiles = c.ftiles;
     P.push_back(p);
   }
-  const int s4_off = 7;
-  auto* dprobs = (Prob*)ctx_buf(ctx, "c_probs", P.size() * sizeof(Prob));
-  h2d(ctx, dprobs, P.data(), P.size());
+  c.dprobs = (Prob*)ctx_buf(ctx, pfx + "c_probs", P.size() * sizeof(Prob));
+  h2d(ctx, c.dprobs, P.data(), P.size());
 
-  // ---- unit lists of all chunks
-  std::vector<Unit> uall;
-  std::vector<std::pair<int64_t, int64_t>> chunks;   // (offset, count)
-  std::vector<std::pair<int32_t, int32_t>> trange;
-  for (int64_t sbk = 0; sbk < ns; sbk += sc)
-    for (int64_t tb = 0; tb < ntau; tb += tcnt) {
-      const int64_t off0 = (int64_t)uall.size();
+  // ---- unit lists of all chunks (vector arrays are indexed by s - s0)
+  c.uall.clear();
+  c.chunks.clear();
+  c.trange.clear();
+  for (int64_t sbk = 0; sbk < ns; sbk += c.sc)
+    for (int64_t tb = 0; tb < ntau; tb += c.tcnt) {
+      const int64_t off0 = (int64_t)c.uall.size();
       int32_t slot = 0;
-      const int64_t t1 = std::min(ntau, tb + tcnt), s1 = std::min(ns, sbk + sc);
+      const int64_t t1 = std::min(ntau, tb + c.tcnt), s1 = std::min(ns, sbk + c.sc);
       for (int64_t t = tb; t < t1; ++t)
-        for (int64_t s = sbk; s < s1; ++s) uall.push_back(Unit{(int32_t)t, (int32_t)(s0 + s), slot++, 0});
-      chunks.push_back({off0, (int64_t)uall.size() - off0});
-      trange.push_back({(int32_t)tb, (int32_t)t1});
+        for (int64_t s = sbk; s < s1; ++s) c.uall.push_back(Unit{(int32_t)t, (int32_t)s, slot++, 0});
+      c.chunks.push_back({off0, (int64_t)c.uall.size() - off0});
+      c.trange.push_back({(int32_t)tb, (int32_t)t1});
     }
-  // the vector arrays are indexed by s - s0
-  for (auto& u : uall) u.s -= (int32_t)s0;
-  auto* dunits = (Unit*)ctx_buf(ctx, "c_units", uall.size() * sizeof(Unit));
-  h2d(ctx, dunits, uall.data(), uall.size());
+  c.dunits = (Unit*)ctx_buf(ctx, pfx + "c_units", c.uall.size() * sizeof(Unit));
+  h2d(ctx, c.dunits, c.uall.data(), c.uall.size());
+}
 
-  const double n3 = 2.0 * (double)n * (double)n * (double)n;     // flops of one n x n x n product
-  const char* gname = prec == Prec::F64 ? "gemm_f64" : prec == Prec::F32 ? "gemm_f32"
-                      : prec == Prec::BF16 ? "gemm_bf16" : "gemm_bf16x3";
-  auto stage = [&](int off, int cnt, const Unit* units, int nunit, int products, const char* tag) {
-    int mt = 0;
-    for (int i = 0; i < cnt; ++i) mt = std::max(mt, tiles_of(P[off + i], prec, n));
-    GemmLaunch L = chain_launch(dprobs + off, cnt, units, nunit, n, np, plane);
-    std::string nm = std::string(gname) + tag;
-    ProfScope ps(ctx, nm.c_str(), n3 * products * nunit);
-    launch_gemm(prec, L, mt, st);
-  };
-  for (size_t c = 0; c < chunks.size(); ++c) {
-    const Unit* du = dunits + chunks[c].first;
-    const int nu = (int)chunks[c].second;
-    stage(s1_off, s1_n, du, nu, 4, ".s1");
-    stage(s2_off, s2_n, du, nu, 8, ".s2");
-    {
-      ProfScope ps(ctx, "jk");
-      launch_trace_coef(mpart, mtiles, (int32_t)slots, coef, st);
-      launch_jk_blocks(accf64, wz, 4 * ac_sl, ac_sl, np, naux, nu, sp->w, sp->idx,
-                       accf64 ? (const void*)sp->blk : (const void*)sp->blk32, jblk, st);
-      launch_jk_scatter(accf64, jblk, naux, nu, sp->npat, sp->pat_ij, sp->pat_off, sp->pat_q, np, prec, plane,
-                        jw_l, jw_s, jz_st, jz_sum_t, st_sl, st);
-    }
-    stage(s3_off, s3_n, du, nu, 4, ".s3");
-    stage(s4_off, 1, du, nu, 8, ".s4");
-    {
-      ProfScope ps(ctx, "accumulate", 0.0, (double)nu * n * n * (accf64 ? 8 : 4) + 2.0 * (trange[c].second - trange[c].first) * n * n * 8);
-      launch_accumulate(du, nu, sig, accf64, ac_sl, n, np, Sigma_sum, trange[c].first, trange[c].second, st);
-      if (e_samples) launch_esamples(du, nu, epart, ftiles, 0, ntau, e_samples, st);
-    }
+void chain_stage(gf2_ctx* ctx, const ChainPlan& c, int stage, int64_t ci) {
+  const int off = kStageOff[stage], cnt = kStageCnt[stage];
+  int mt = 0;
+  for (int i = 0; i < cnt; ++i) mt = std::max(mt, tiles_of(c.P[off + i], c.prec, c.n));
+  const int nu = (int)c.chunks[ci].second;
+  GemmLaunch L = chain_launch(c.dprobs + off, cnt, c.dunits + c.chunks[ci].first, nu, c.n, c.np, c.plane);
+  static const char* tag[4] = {".s1", ".s2", ".s3", ".s4"};
+  const std::string nm = std::string(gemm_name(c.prec)) + tag[stage];
+  ProfScope ps(ctx, nm.c_str(), 2.0 * (double)c.n * c.n * c.n * kStageProducts[stage] * nu);
+  launch_gemm(c.prec, L, mt, ctx->stream);
+}
+
+void chain_jk(gf2_ctx* ctx, const ChainPlan& c, int64_t ci) {
+  const gf2_split_h* sp = c.sp;
+  const int nu = (int)c.chunks[ci].second;
+  ProfScope ps(ctx, "jk");
+  launch_trace_coef(c.mpart, c.mtiles, (int32_t)c.slots, c.coef, ctx->stream);
+  launch_jk_blocks(c.accf64, c.wz, 4 * c.ac_sl, c.ac_sl, c.np, c.naux, nu, sp->w, sp->idx,
+                   c.accf64 ? (const void*)sp->blk : (const void*)sp->blk32, c.jblk, ctx->stream);
+  launch_jk_scatter(c.accf64, c.jblk, c.naux, nu, sp->npat, sp->pat_ij, sp->pat_off, sp->pat_q, c.np, c.prec,
+                    c.plane, c.jw_l, c.jw_s, c.jz_st, c.jz_sum_t, c.st_sl, ctx->stream);
+}
+
+void chain_acc(gf2_ctx* ctx, const ChainPlan& c, int64_t ci) {
+  const Unit* du = c.dunits + c.chunks[ci].first;
+  const int nu = (int)c.chunks[ci].second;
+  const int64_t n = c.n;
+  ProfScope ps(ctx, "accumulate", 0.0,
+               (double)nu * n * n * (c.accf64 ? 8 : 4) + 2.0 * (c.trange[ci].second - c.trange[ci].first) * n * n * 8);
+  launch_accumulate(du, nu, c.sig, c.accf64, c.ac_sl, n, c.np, c.Sigma_sum, c.trange[ci].first,
+                    c.trange[ci].second, ctx->stream);
+  if (c.e_samples) launch_esamples(du, nu, c.epart, c.ftiles, 0, c.ntau, c.e_samples, ctx->stream);
+}
+
+void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double* G, const double* Gbar,
+               int64_t ntau, const gf2_sampling* smp, Prec prec, double* Sigma_sum, double* e_samples) {
+  ChainPlan c;
+  plan_chain(ctx, c, "", sp, B, G, Gbar, ntau, smp, prec, Sigma_sum, e_samples);
+  for (size_t ci = 0; ci < c.chunks.size(); ++ci) {
+    chain_stage(ctx, c, 0, (int64_t)ci);
+    chain_stage(ctx, c, 1, (int64_t)ci);
+    chain_jk(ctx, c, (int64_t)ci);
+    chain_stage(ctx, c, 2, (int64_t)ci);
+    chain_stage(ctx, c, 3, (int64_t)ci);
+    chain_acc(ctx, c, (int64_t)ci);
     GF2_HIP(hipGetLastError());
   }
-  GF2_HIP(hipStreamSynchronize(st));
+  GF2_HIP(hipStreamSynchronize(ctx->stream));
 }
 
 void check_sampling(const gf2_split_h* sp, const gf2_sampling* s) {
@@ -918,6 +990,233 @@ gf2_status gf2_energy(gf2_ctx* ctx, int64_t n, int64_t ntau, const double* w, co
     if (E_tot) *E_tot = h[0];
     if (E_per_e) *E_per_e = h[0] / n_elec;
     if (stderr_tot) *stderr_tot = h[2];
+  });
+}
+
+// ------------------------------------------------------------ batch -------
+namespace {
+
+struct BatchShape {
+  int32_t tcnt, persist;
+};
+
+// All instances' chunks in lockstep: step c runs chunk c of every instance
+// that has one; the product stages of a step are single launches over the
+// units of all instances (largest instances first).
+struct BatchRun {
+  std::vector<ChainPlan> plans;
+  Prob* dprobs = nullptr;          // [ninst][kProbsPerPlan]
+  InstGeo* dgeo = nullptr;         // [ninst]
+  Unit* dunits = nullptr;          // all steps' merged unit lists
+  std::vector<std::pair<int64_t, int64_t>> steps;   // (offset, count) into dunits
+  int tiles[4] = {0, 0, 0, 0};     // per stage, max over instances
+  int64_t nsteps = 0;
+  int32_t persist = 0;
+};
+
+void batch_plan(gf2_ctx* ctx, BatchRun& R, int32_t nitem, const gf2_batch_item* items, Prec prec,
+                const std::vector<double*>& sums, BatchShape shape) {
+  R.plans.assign(nitem, ChainPlan());
+  for (int32_t i = 0; i < nitem; ++i) {
+    const gf2_batch_item& it = items[i];
+    plan_chain(ctx, R.plans[i], "b" + std::to_string(i) + ":", it.split, it.B, it.G, it.Gbar, it.ntau,
+               &it.sampling, prec, sums[i], it.e_samples, 8, shape.tcnt);
+  }
+  std::vector<Prob> ph((size_t)nitem * kProbsPerPlan);
+  std::vector<InstGeo> gh(nitem);
+  for (int32_t i = 0; i < nitem; ++i) {
+    const ChainPlan& c = R.plans[i];
+    for (int j = 0; j < kProbsPerPlan; ++j) ph[(size_t)i * kProbsPerPlan + j] = c.P[j];
+    gh[i] = InstGeo{c.n, c.n, c.np, c.np, c.plane};
+    for (int st = 0; st < 4; ++st)
+      for (int j = 0; j < kStageCnt[st]; ++j)
+        R.tiles[st] = std::max(R.tiles[st], tiles_of(c.P[kStageOff[st] + j], prec, c.n));
+  }
+  R.dprobs = (Prob*)ctx_buf(ctx, "bt_probs", ph.size() * sizeof(Prob));
+  R.dgeo = (InstGeo*)ctx_buf(ctx, "bt_geo", gh.size() * sizeof(InstGeo));
+  h2d(ctx, R.dprobs, ph.data(), ph.size());
+  h2d(ctx, R.dgeo, gh.data(), gh.size());
+  // merged units, instances by decreasing size within each step
+  std::vector<int32_t> order(nitem);
+  for (int32_t i = 0; i < nitem; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return R.plans[a].n > R.plans[b].n; });
+  R.nsteps = 0;
+  for (const ChainPlan& c : R.plans) R.nsteps = std::max<int64_t>(R.nsteps, (int64_t)c.chunks.size());
+  std::vector<Unit> uh;
+  R.steps.clear();
+  for (int64_t st = 0; st < R.nsteps; ++st) {
+    const int64_t off0 = (int64_t)uh.size();
+    for (int32_t i : order) {
+      const ChainPlan& c = R.plans[i];
+      if (st >= (int64_t)c.chunks.size()) continue;
+      for (int64_t q = 0; q < c.chunks[st].second; ++q) {
+        Unit u = c.uall[c.chunks[st].first + q];
+        u.inst = i;
+        uh.push_back(u);
+      }
+    }
+    R.steps.push_back({off0, (int64_t)uh.size() - off0});
+  }
+  R.dunits = (Unit*)ctx_buf(ctx, "bt_units", uh.size() * sizeof(Unit));
+  h2d(ctx, R.dunits, uh.data(), uh.size());
+  R.persist = shape.persist;
+}
+
+// Launch steps [s0, s1) of the batch (kernels only: no allocation, copy or
+// fill, so the sequence can be recorded into a graph).
+void batch_steps(gf2_ctx* ctx, const BatchRun& R, Prec prec, int64_t s0, int64_t s1) {
+  static const char* tag[4] = {".s1", ".s2", ".s3", ".s4"};
+  GF2_REQUIRE(0 <= s0 && s0 <= s1 && s1 <= R.nsteps && R.nsteps == (int64_t)R.steps.size(), GF2_E_STATE,
+              "batch step range out of bounds");
+  for (int64_t st = s0; st < s1; ++st) {
+    const int nu = (int)R.steps[st].second;
+    for (int stage = 0; stage < 4; ++stage) {
+      GemmLaunch L{R.dprobs + kStageOff[stage], kStageCnt[stage], kProbsPerPlan, R.dunits + R.steps[st].first, nu,
+                   InstGeo{0, 0, 0, 0, 0}, R.dgeo, 0, R.persist};
+      double fl = 0.0;
+      for (const ChainPlan& c : R.plans)
+        if (st < (int64_t)c.chunks.size())
+          fl += 2.0 * (double)c.n * c.n * c.n * kStageProducts[stage] * c.chunks[st].second;
+      {
+        const std::string nm = std::string(gemm_name(prec)) + tag[stage];
+        ProfScope ps(ctx, nm.c_str(), fl);
+        launch_gemm(prec, L, R.tiles[stage], ctx->stream);
+      }
+      if (stage == 1)
+        for (const ChainPlan& c : R.plans)
+          if (st < (int64_t)c.chunks.size()) chain_jk(ctx, c, st);
+    }
+    for (const ChainPlan& c : R.plans)
+      if (st < (int64_t)c.chunks.size()) chain_acc(ctx, c, st);
+  }
+}
+
+std::string batch_signature(int32_t nitem, const gf2_batch_item* items, Prec prec) {
+  std::string sig = std::to_string((int)prec);
+  for (int32_t i = 0; i < nitem; ++i)
+    sig += ";" + std::to_string(items[i].split->n) + "," + std::to_string(items[i].ntau) + "," +
+           std::to_string(items[i].sampling.ns);
+  return sig;
+}
+
+}  // namespace
+
+gf2_status gf2_sigma_batch(gf2_ctx* ctx, int32_t nitem, const gf2_batch_item* items, gf2_precision prec,
+                           int32_t flags) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(nitem >= 1 && items, GF2_E_ARG, "empty batch");
+    const Prec p = to_prec(prec);
+    for (int32_t i = 0; i < nitem; ++i) {
+      const gf2_batch_item& it = items[i];
+      GF2_REQUIRE(it.split && it.split->owner == ctx, GF2_E_STATE, "split handle of another context");
+      GF2_REQUIRE(it.B == it.split->bsrc, GF2_E_STATE, "split handle belongs to a different B");
+      GF2_REQUIRE(it.G && it.Gbar && it.Sigma && it.ntau > 0 && it.ntau <= 4096, GF2_E_ARG,
+                  "bad batch item " + std::to_string(i));
+      check_sampling(it.split, &it.sampling);
+    }
+    // deterministic blocks and zeroed sums
+    std::vector<double*> dets(nitem), sums(nitem);
+    for (int32_t i = 0; i < nitem; ++i) {
+      const int64_t n = items[i].split->n;
+      const size_t bytes = (size_t)(items[i].ntau * n * n) * 8;
+      dets[i] = (double*)ctx_buf(ctx, "b" + std::to_string(i) + ":det", bytes);
+      sums[i] = (double*)ctx_buf(ctx, "b" + std::to_string(i) + ":sum", bytes, true);
+      run_dd(ctx, items[i].split, items[i].G, items[i].Gbar, items[i].ntau, dets[i]);
+    }
+    // launch shape: tuned (cached per signature) or the default
+    BatchShape shape{8, 0};
+    const std::string sig = batch_signature(nitem, items, p);
+    auto hit = ctx->tuned.find(sig);
+    if (hit != ctx->tuned.end()) {
+      shape = BatchShape{hit->second.first, hit->second.second};
+    } else if (flags & GF2_BATCH_AUTOTUNE) {
+      int dev_cus = 256;
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) dev_cus = prop.multiProcessorCount;
+      const BatchShape cand[] = {{8, 0}, {4, 0}, {2, 0}, {8, 2 * dev_cus}, {4, 2 * dev_cus}};
+      double best = 1e300;
+      const bool prof = ctx->prof;
+      ctx->prof = false;
+      for (const BatchShape& cs : cand) {
+        BatchRun R;
+        batch_plan(ctx, R, nitem, items, p, sums, cs);
+        // warm with step 0, time steps [t0, t1) (step 0 again if it is the only one)
+        const int64_t t0 = R.nsteps >= 2 ? 1 : 0;
+        const int64_t t1 = R.nsteps >= 2 ? std::min<int64_t>(R.nsteps, 4) : 1;
+        batch_steps(ctx, R, p, 0, 1);
+        hipEvent_t a, b;
+        GF2_HIP(hipEventCreate(&a));
+        GF2_HIP(hipEventCreate(&b));
+        GF2_HIP(hipEventRecord(a, ctx->stream));
+        batch_steps(ctx, R, p, t0, t1);
+        GF2_HIP(hipEventRecord(b, ctx->stream));
+        GF2_HIP(hipEventSynchronize(b));
+        float ms = 0.0f;
+        GF2_HIP(hipEventElapsedTime(&ms, a, b));
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        int64_t units = 0;
+        for (int64_t st = t0; st < t1; ++st) units += R.steps[st].second;
+        const double per_unit = units > 0 ? ms / (double)units : 1e300;
+        if (per_unit < best) {
+          best = per_unit;
+          shape = cs;
+        }
+      }
+      ctx->prof = prof;
+      ctx->tuned[sig] = {shape.tcnt, shape.persist};
+      // the trial steps added to the sums: start again from zero
+      for (int32_t i = 0; i < nitem; ++i)
+        sums[i] = (double*)ctx_buf(ctx, "b" + std::to_string(i) + ":sum",
+                                   (size_t)(items[i].ntau * items[i].split->n * items[i].split->n) * 8, true);
+    }
+    BatchRun R;
+    batch_plan(ctx, R, nitem, items, p, sums, shape);
+    if (flags & GF2_BATCH_GRAPH) {
+      // record on a stream of our own (the caller's may be the legacy
+      // default stream, which cannot capture), launch on the caller's
+      GF2_HIP(hipStreamSynchronize(ctx->stream));
+      hipStream_t cap = nullptr;
+      GF2_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      const bool prof = ctx->prof;
+      hipStream_t user = ctx->stream;
+      ctx->prof = false;                       // no event records inside the graph
+      ctx->stream = cap;
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        try {
+          batch_steps(ctx, R, p, 0, R.nsteps);
+        } catch (...) {
+          (void)hipStreamEndCapture(cap, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          ctx->stream = user;
+          ctx->prof = prof;
+          (void)hipStreamDestroy(cap);
+          throw;
+        }
+        e = hipStreamEndCapture(cap, &graph);
+      }
+      ctx->stream = user;
+      ctx->prof = prof;
+      if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (e == hipSuccess) e = hipGraphLaunch(exec, ctx->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipStreamDestroy(cap);
+      GF2_HIP(e);
+    } else {
+      batch_steps(ctx, R, p, 0, R.nsteps);
+    }
+    for (int32_t i = 0; i < nitem; ++i) {
+      const int64_t n = items[i].split->n, ntau = items[i].ntau;
+      launch_finalize(dets[i], sums[i], n, ntau, 0.5 / (double)items[i].sampling.ns, items[i].Sigma, ctx->stream);
+      GF2_HIP(hipGetLastError());
+      check_finite(ctx, items[i].Sigma, ntau * n * n, "Sigma");
+    }
+    GF2_HIP(hipStreamSynchronize(ctx->stream));
   });
 }
 

@@ -171,7 +171,7 @@ __device__ __forceinline__ int acc_col(int lane) {
 }
 
 template <Prec P, int NA, int NB>
-__device__ __forceinline__ void gemm_body(const GemmLaunch& L, const Prob& pb, const Unit& u, int tile,
+__device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, const Unit& u, int tile,
                                           unsigned char* smem, double* red) {
   using C = Cfg<P>;
   using E = typename C::E;
@@ -502,22 +502,43 @@ __device__ __forceinline__ void gemm_body(const GemmLaunch& L, const Prob& pb, c
 }
 
 template <Prec P>
+__device__ __forceinline__ void gemm_item(const GemmLaunch& L, int tile, int py, unsigned char* smem,
+                                          double* red) {
+  const int ui = py / L.nprob, pi = py % L.nprob;
+  const Unit u = L.units[ui];
+  const Prob& pb = L.probs[(int64_t)u.inst * L.pstride + pi];
+  const InstGeo g = L.geo ? L.geo[u.inst] : L.g;
+  const int mode = (pb.nA == 2 ? 2 : 0) + (pb.nB == 2 ? 1 : 0);
+  switch (mode) {
+    case 0: gemm_body<P, 1, 1>(g, pb, u, tile, smem, red); break;
+    case 1: gemm_body<P, 1, 2>(g, pb, u, tile, smem, red); break;
+    case 2: gemm_body<P, 2, 1>(g, pb, u, tile, smem, red); break;
+    default: gemm_body<P, 2, 2>(g, pb, u, tile, smem, red); break;
+  }
+}
+
+template <Prec P>
 __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(GemmLaunch L) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[Smem<P>::BYTES];
   __shared__ double red[4 * kMaxHad];
-  const int64_t total = (int64_t)gridDim.x * gridDim.y;
-  const int64_t lin = xcd_remap((int64_t)blockIdx.y * gridDim.x + blockIdx.x, total);
-  const int tile = (int)(lin % gridDim.x);
-  const int py = (int)(lin / gridDim.x);
-  const int ui = py / L.nprob, pi = py % L.nprob;
-  const Prob& pb = L.probs[pi];
-  const Unit u = L.units[ui];
-  const int mode = (pb.nA == 2 ? 2 : 0) + (pb.nB == 2 ? 1 : 0);
-  switch (mode) {
-    case 0: gemm_body<P, 1, 1>(L, pb, u, tile, smem, red); break;
-    case 1: gemm_body<P, 1, 2>(L, pb, u, tile, smem, red); break;
-    case 2: gemm_body<P, 2, 1>(L, pb, u, tile, smem, red); break;
-    default: gemm_body<P, 2, 2>(L, pb, u, tile, smem, red); break;
+  if (L.persist == 0) {
+    const int64_t total = (int64_t)gridDim.x * gridDim.y;
+    const int64_t lin = xcd_remap((int64_t)blockIdx.y * gridDim.x + blockIdx.x, total);
+    gemm_item<P>(L, (int)(lin % gridDim.x), (int)(lin / gridDim.x), smem, red);
+    return;
+  }
+  // Persistent: workgroup b runs on XCD x = b % 8 and takes the items
+  // (py, tile) with py = x (mod 8), all tiles of one (unit, problem) on one
+  // XCD, in a grid-stride loop over that XCD's items.
+  const int x = blockIdx.x & 7;
+  const int64_t lb = blockIdx.x >> 3, nbx = gridDim.x >> 3;
+  const int64_t npy = (int64_t)L.nunit * L.nprob;
+  const int64_t px = npy > x ? (npy - x + 7) / 8 : 0;
+  const int64_t items = px * L.tiles;
+  for (int64_t j = lb; j < items; j += nbx) {
+    const int py = (int)(x + 8 * (j / L.tiles));
+    gemm_item<P>(L, (int)(j % L.tiles), py, smem, red);
+    __syncthreads();                     // LDS of the next item
   }
 }
 
@@ -530,9 +551,14 @@ int gemm_tile_n(Prec p) {
   return p == Prec::F64 ? Cfg<Prec::F64>::BN : Cfg<Prec::F32>::BN;
 }
 
-void launch_gemm(Prec p, const GemmLaunch& L, int max_tiles, hipStream_t st) {
-  if (L.nunit <= 0 || L.nprob <= 0 || max_tiles <= 0) return;
+void launch_gemm(Prec p, const GemmLaunch& Lin, int max_tiles, hipStream_t st) {
+  if (Lin.nunit <= 0 || Lin.nprob <= 0 || max_tiles <= 0) return;
+  GemmLaunch L = Lin;
+  L.tiles = max_tiles;
+  // more (unit, problem) pairs than a grid dimension holds: run persistent
+  if (L.persist == 0 && (int64_t)L.nunit * L.nprob > 65535) L.persist = 8192;
   dim3 grid((unsigned)max_tiles, (unsigned)(L.nunit * L.nprob));
+  if (L.persist > 0) grid = dim3((unsigned)(((L.persist + 7) / 8) * 8), 1);
   switch (p) {
     case Prec::F64: hipLaunchKernelGGL(gemm_kernel<Prec::F64>, grid, dim3(kThreads), 0, st, L); break;
     case Prec::F32: hipLaunchKernelGGL(gemm_kernel<Prec::F32>, grid, dim3(kThreads), 0, st, L); break;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -81,20 +82,30 @@ struct Prob {
 };
 
 struct Unit {
-  int32_t tau, s, slot, pad;
+  int32_t tau, s, slot, inst;   // inst: instance of a multi-instance launch (0 otherwise)
+};
+
+// Geometry of one instance of a launch.
+struct InstGeo {
+  int64_t m, nc, k;     // rows of C, columns of C, reduction length
+  int64_t ld;           // leading dimension of every operand and output
+  int64_t plane;        // element stride of the lo plane (BF16X3)
 };
 
 // C (m x nc) = sum_s A_s (m x k, leading dim ld) B_s^T (nc x k, leading dim
 // ld); outputs use leading dim ld as well.  k must be a multiple of 8 and
 // the operands zero beyond their logical extent in k.
 struct GemmLaunch {
-  const Prob* probs;    // device
+  const Prob* probs;    // device; problem j of instance i at probs[i * pstride + j]
   int32_t nprob;
+  int32_t pstride;
   const Unit* units;    // device
   int32_t nunit;
-  int64_t m, nc, k;     // rows of C, columns of C, reduction length
-  int64_t ld;           // leading dimension of every operand and output
-  int64_t plane;        // element stride of the lo plane (BF16X3)
+  InstGeo g;            // geometry when geo is null (single instance)
+  const InstGeo* geo;   // device, per instance, or null
+  int32_t tiles;        // tiles per (unit, problem) covered by the launch
+  int32_t persist;      // 0: one workgroup per work item; else a grid-stride
+                        // loop over the items (grid a multiple of 8)
 };
 
 // Kernel launchers (device code in separate translation units).
@@ -102,7 +113,7 @@ void launch_gemm(Prec p, const GemmLaunch& L, int max_tiles, hipStream_t st);
 // Chain launch: square n x n products stored with leading dimension np.
 inline GemmLaunch chain_launch(const Prob* probs, int nprob, const Unit* units, int nunit, int64_t n,
                                int64_t np, int64_t plane) {
-  return GemmLaunch{probs, nprob, units, nunit, n, n, np, np, plane};
+  return GemmLaunch{probs, nprob, 0, units, nunit, InstGeo{n, n, np, np, plane}, nullptr, 0, 0};
 }
 int gemm_tile_m(Prec p);     // BM
 int gemm_tile_n(Prec p);     // BN
@@ -120,7 +131,10 @@ struct gf2_ctx {
   std::string err;
   std::vector<DevBuf> pool;       // scratch allocations owned by the context
   int64_t max_units = 0;          // chunk size tuning (0 = automatic)
-  std::string chain_key;          // (n, np, precision) of the last chain layout
+  // (n, np, precision) of the last chain layout per buffer-tag prefix
+  std::map<std::string, std::string> chain_keys;
+  // launch shapes chosen by the batch autotuner, per batch signature
+  std::map<std::string, std::pair<int32_t, int32_t>> tuned;
   // optional per-kernel-class timing with HIP events on ctx->stream
   bool prof = false;
   struct Ev { std::string name; hipEvent_t a, b; double flops, bytes; };

@@ -45,6 +45,14 @@ class Sampling(C.Structure):
                 ("k", C.c_int32), ("p", C.POINTER(C.c_double))]
 
 
+class BatchItem(C.Structure):
+    _fields_ = [("split", C.c_void_p), ("B", C.c_void_p), ("G", C.c_void_p), ("Gbar", C.c_void_p),
+                ("ntau", C.c_int64), ("sampling", Sampling), ("Sigma", C.c_void_p), ("e_samples", C.c_void_p)]
+
+
+BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
+
+
 class AdaptiveResult(C.Structure):
     _fields_ = [("e_corr", C.c_double), ("e_corr_per_e", C.c_double), ("stderr_tot", C.c_double),
                 ("pairs", C.c_int64), ("precision", C.c_int32), ("bias_probe", C.c_double)]
@@ -94,6 +102,7 @@ _SIGS = {
                                  C.c_void_p]),
     "gf2_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.POINTER(C.c_int32)]),
+    "gf2_sigma_batch": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int, C.c_int32]),
     "gf2_energy_adaptive": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                       C.POINTER(C.c_double), C.c_void_p, C.c_double, C.POINTER(Sampling),
                                       C.c_int, C.c_double, C.c_int64, C.c_void_p, C.c_void_p,
@@ -322,6 +331,25 @@ class Context:
         self._check(self.lib.gf2_sigma_finalize(self.h, n, ntau, Sigma_det.data_ptr(), Sigma_sum.data_ptr(),
                                                 int(ns_total), out.data_ptr()))
         return out
+
+    def sigma_batch(self, items, prec: str = "fp32", graph: bool = False, autotune: bool = False):
+        """items: list of dict(split, B, G, Gb, ns, seed[, s0, p, k]).  Returns
+        [(Sigma, e_samples)] in item order."""
+        torch = self.torch
+        arr = (BatchItem * len(items))()
+        outs, keep = [], []
+        for i, it in enumerate(items):
+            ntau, n, _ = it["G"].shape
+            Sigma = torch.empty((ntau, n, n), dtype=torch.float64, device=self.device)
+            es = torch.empty((it["ns"], ntau), dtype=torch.float64, device=self.device)
+            smp, kp = self._sampling(it["ns"], it.get("seed", 0), it.get("s0", 0), it.get("p"), it.get("k", 1))
+            keep.append(kp)
+            arr[i] = BatchItem(it["split"].handle, it["B"].data_ptr(), it["G"].data_ptr(), it["Gb"].data_ptr(),
+                               ntau, smp, Sigma.data_ptr(), es.data_ptr())
+            outs.append((Sigma, es))
+        flags = (BATCH_GRAPH if graph else 0) | (BATCH_AUTOTUNE if autotune else 0)
+        self._check(self.lib.gf2_sigma_batch(self.h, len(items), C.addressof(arr), PREC[prec], flags))
+        return outs
 
     def energy_adaptive(self, split: Split, B, G, Gb, w: np.ndarray, Sigma_det, n_elec: float, target: float,
                         batch: int = 16, max_pairs: int = 4096, seed: int = 0, prec: str = "auto", p=None,

@@ -1,0 +1,92 @@
+"""Batched chains of uneven size (gf2_sigma_batch) against one call per
+instance and against the oracle.
+
+With the same chunk shape the batch runs the same per-unit arithmetic in the
+same order as single-instance calls, so results agree bitwise; a tuned shape
+regroups the accumulation of pairs (1e-12 relative).
+"""
+import numpy as np
+import pytest
+
+from oracle import energy, green
+
+from _problems import chain, oracle_pairs, oracle_setup, rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2005_12338_amd import gf2
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = gf2.Context(0)
+    yield c
+    c.close()
+
+
+def _instances(ctx, dimers, ntau, eps, dtype, ns):
+    out = []
+    for i, nd in enumerate(dimers):
+        pb = chain(nd, 50.0, ntau, eps)
+        geo = pb["geo"]
+        B = ctx.build_B(geo.n, geo.naux, geom=geo, dtype=dtype)
+        tau, w = green.tau_grid(pb["beta"], ntau)
+        G, Gb, _ = ctx.green_tau(pb["f"], tau, pb["beta"], n_occ=geo.n // 2)
+        out.append(dict(pb=pb, split=ctx.split(B, eps), B=B, G=G, Gb=Gb, ns=ns, seed=i, w=w))
+    return out
+
+
+def _singles(ctx, inst, prec):
+    return [ctx.sigma_tau(it["split"], it["B"], it["G"], it["Gb"], ns=it["ns"], seed=it["seed"], prec=prec)
+            for it in inst]
+
+
+def test_batch_fp64_uneven_equals_single_calls_and_oracle(ctx):
+    inst = _instances(ctx, [7, 12, 20, 35], 3, 1e-2, torch.float64, 5)
+    got = ctx.sigma_batch(inst, prec="fp64")
+    ref = _singles(ctx, inst, "fp64")
+    for (S, es), (Sr, esr) in zip(got, ref):
+        assert torch.equal(S, Sr)
+        assert torch.equal(es, esr)
+    # the smallest instance against the oracle, pair by pair
+    pb = inst[0]["pb"]
+    o = oracle_setup(pb)
+    per = oracle_pairs(o, 0, 5, range(3), range(5))
+    e_ref = np.array([[energy.trace_product(per[(t, s)], o["gb"][t]) for t in range(3)] for s in range(5)])
+    assert rel(got[0][1].cpu().numpy(), e_ref) < 1e-10
+
+
+def test_batch_graph_equals_plain_launches(ctx):
+    inst = _instances(ctx, [9, 16, 30], 4, 1e-2, torch.float64, 6)
+    a = ctx.sigma_batch(inst, prec="fp64")
+    b = ctx.sigma_batch(inst, prec="fp64", graph=True)
+    b2 = ctx.sigma_batch(inst, prec="fp64", graph=True)          # a second recording of the same batch
+    for (S, es), (Sb, esb), (Sb2, esb2) in zip(a, b, b2):
+        assert torch.equal(S, Sb) and torch.equal(S, Sb2)
+        assert torch.equal(es, esb) and torch.equal(es, esb2)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batch_ragged_tiles_autotuned(ctx, prec):
+    """Instances spanning one to several 128-wide tiles with ragged tails,
+    with the launch shape chosen by the autotuner (persistent or not)."""
+    inst = _instances(ctx, [20, 33, 64, 70, 100, 41], 5, 1e-3, torch.float32, 4)
+    ref = _singles(ctx, inst, prec)
+    got = ctx.sigma_batch(inst, prec=prec, autotune=True, graph=True)
+    for (S, es), (Sr, esr) in zip(got, ref):
+        assert rel(S.cpu().numpy(), Sr.cpu().numpy()) < 1e-12
+        assert rel(es.cpu().numpy(), esr.cpu().numpy()) < 1e-12
+    # the cached shape is reused on the next call: identical results
+    again = ctx.sigma_batch(inst, prec=prec, autotune=True)
+    for (S, es), (S2, es2) in zip(got, again):
+        assert torch.equal(S, S2) and torch.equal(es, es2)
+
+
+def test_batch_rejects_foreign_split(ctx):
+    from paper_2005_12338_amd import gf2
+    inst = _instances(ctx, [6, 8], 2, 1e-2, torch.float64, 2)
+    inst[1] = dict(inst[1], B=inst[0]["B"])
+    with pytest.raises(gf2.Gf2Error):
+        ctx.sigma_batch(inst, prec="fp64")
