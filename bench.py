@@ -128,6 +128,70 @@ class Problem:
         return t1 - t0, info
 
 
+def batch_bench(args):
+    """The uneven-size batch: 96 chains (20..200 dimers), 64 tau, 128 pairs,
+    eps = 1e-3.  One pass = B, split, G(tau) for every chain, then all chains'
+    self-energies: one call per chain, or one batched call (plain, recorded
+    into a HIP graph, autotuned)."""
+    import torch
+    import chain_inputs as ci
+    from paper_2005_12338_amd import gf2
+    wls = ci.batch_workloads(args.batch_count)
+    ctx = gf2.Context(0)
+    prec = args.prec if args.prec != "bf16" or args.batch_prec_bf16 else "fp32"
+
+    def setup():
+        items = []
+        for wl in wls:
+            geo = ci.chain_geometry(wl.n_dimer)
+            tau, w = gf2.gf2_tau_grid(wl.beta, wl.ntau)
+            B = ctx.build_B(geo.n, geo.naux, geom=geo, dtype=torch.float32)
+            spl = ctx.split(B, wl.eps)
+            G, Gb, _ = ctx.green_tau(ci.fock_tight_binding(geo.x), tau, wl.beta, n_occ=wl.n_occ)
+            items.append(dict(split=spl, B=B, G=G, Gb=Gb, ns=wl.ns, seed=wl.seed, w=w, n=geo.n))
+        return items
+
+    flops = sum(48.0 * wl.n ** 3 * wl.ntau * wl.ns for wl in wls)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    items = setup()
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    log(f"[bench] batch of {len(wls)} chains (N={min(w.n for w in wls)}..{max(w.n for w in wls)}), "
+        f"setup {t_setup:.2f} s, chain work {flops:.3e} flop, prec={prec}")
+    res = {}
+
+    def timed(name, fn):
+        fn()                                      # warm (allocations, tuning)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        res[name] = {"s": dt, "chain_tflops": flops / dt / 1e12}
+        log(f"[bench]   {name:10s} {dt:8.3f} s  {flops / dt / 1e12:7.1f} TFLOP/s")
+        return out
+
+    seq = timed("per_chain", lambda: [ctx.sigma_tau(it["split"], it["B"], it["G"], it["Gb"], ns=it["ns"],
+                                                    seed=it["seed"], prec=prec) for it in items])
+    bat = timed("batched", lambda: ctx.sigma_batch(items, prec=prec))
+    timed("graph", lambda: ctx.sigma_batch(items, prec=prec, graph=True))
+    tun = timed("tuned", lambda: ctx.sigma_batch(items, prec=prec, graph=True, autotune=True))
+    dev = max(float((a[0] - b[0]).abs().max() / b[0].abs().max()) for a, b in zip(tun, seq))
+    log(f"[bench]   max relative difference batched vs per-chain Sigma: {dev:.2e}")
+    best = min(("batched", "graph", "tuned"), key=lambda k: res[k]["s"])
+    out = {"metric": "batch pass time, 96 uneven chains (N=40..400, 64 tau, 128 pairs)", "value":
+           t_setup + res[best]["s"], "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": prec,
+           "data": "synthetic", "vs_baseline": None,
+           "config": {"workload": f"batch: {len(wls)} H2-dimer chains, dimer counts from "
+                                  f"default_rng(12345).integers(20, 201, {len(wls)}), beta=100, ntau=64, "
+                                  f"Ns=128, eps=1e-3"},
+           "setup_s": t_setup, "sigma_s": res, "best": best, "speedup_vs_per_chain": res["per_chain"]["s"] /
+           res[best]["s"], "max_rel_diff_vs_per_chain": dev}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def cpu_baseline(wl, pairs):
     """The oracle (FP64 NumPy, as it stands) timed on a bounded sample of the
     same workload and extrapolated to a time-to-target estimate (s)."""
@@ -194,7 +258,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="n800", choices=["n800", "n200", "tiny"])
+    ap.add_argument("--workload", default="n800", choices=["n800", "n200", "tiny", "batch"])
+    ap.add_argument("--batch-count", type=int, default=96, help="chains in the batch workload")
+    ap.add_argument("--batch-prec-bf16", action="store_true", help="run the batch in BF16 (default FP32)")
     ap.add_argument("--prec", default="bf16", choices=["bf16", "bf16x3", "fp32", "fp64"])
     ap.add_argument("--ns", type=int, default=0, help="pairs per step (default: the workload's)")
     ap.add_argument("--target-meh", type=float, default=1.0)
@@ -207,6 +273,10 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+
+    if args.workload == "batch":
+        batch_bench(args)
+        return
 
     import torch
     from paper_2005_12338_amd import gf2

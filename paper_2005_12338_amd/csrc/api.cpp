@@ -1,6 +1,7 @@
 // C ABI of libgf2: argument checking, device buffers, and the launch
 // schedule of the RS-SRI-GF2 hot path (see include/gf2.h).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -264,7 +265,7 @@ gf2_status gf2_build_B(gf2_ctx* ctx, int64_t n, int64_t naux, const void* ijA, c
     Unit uh{0, 0, 0, 0};
     auto* units = (Unit*)ctx_buf(ctx, "bunit", sizeof(Unit));
     h2d(ctx, units, &uh, 1);
-    GemmLaunch L{probs, 1, 0, units, 1, InstGeo{nn, naux, kp, kp, 0}, nullptr, 0, 0};
+    GemmLaunch L{probs, 1, 0, units, 1, InstGeo{nn, naux, kp, kp, 0}, nullptr, 0, 0, nullptr, 0, 0};
     launch_gemm(Prec::F64, L, tiles_of(pb, Prec::F64, nn, naux), ctx->stream);
     launch_untranspose(tout, nn, naux, kp, B, f64, ctx->stream);
     GF2_HIP(hipGetLastError());
@@ -1010,6 +1011,8 @@ struct BatchRun {
   Unit* dunits = nullptr;          // all steps' merged unit lists
   std::vector<std::pair<int64_t, int64_t>> steps;   // (offset, count) into dunits
   int tiles[4] = {0, 0, 0, 0};     // per stage, max over instances
+  BatchSeg* dsegs = nullptr;       // work lists of all (step, stage)
+  std::vector<int64_t> segoff, nseg, nitems;         // per step * 4 + stage
   int64_t nsteps = 0;
   int32_t persist = 0;
 };
@@ -1042,21 +1045,49 @@ void batch_plan(gf2_ctx* ctx, BatchRun& R, int32_t nitem, const gf2_batch_item* 
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return R.plans[a].n > R.plans[b].n; });
   R.nsteps = 0;
   for (const ChainPlan& c : R.plans) R.nsteps = std::max<int64_t>(R.nsteps, (int64_t)c.chunks.size());
+  // per instance and stage: tiles of its largest problem of the stage
+  std::vector<std::array<int32_t, 4>> itiles(nitem);
+  for (int32_t i = 0; i < nitem; ++i)
+    for (int st = 0; st < 4; ++st) {
+      int32_t t = 0;
+      for (int j = 0; j < kStageCnt[st]; ++j) t = std::max(t, tiles_of(R.plans[i].P[kStageOff[st] + j], prec, R.plans[i].n));
+      itiles[i][st] = t;
+    }
   std::vector<Unit> uh;
+  std::vector<BatchSeg> sh;
   R.steps.clear();
+  R.segoff.clear();
+  R.nseg.clear();
+  R.nitems.clear();
   for (int64_t st = 0; st < R.nsteps; ++st) {
     const int64_t off0 = (int64_t)uh.size();
+    std::vector<std::pair<int32_t, std::pair<int32_t, int32_t>>> runs;   // (inst, (unit0, nunits))
     for (int32_t i : order) {
       const ChainPlan& c = R.plans[i];
       if (st >= (int64_t)c.chunks.size()) continue;
+      const int32_t u0 = (int32_t)(uh.size() - off0);
       for (int64_t q = 0; q < c.chunks[st].second; ++q) {
         Unit u = c.uall[c.chunks[st].first + q];
         u.inst = i;
         uh.push_back(u);
       }
+      runs.push_back({i, {u0, (int32_t)c.chunks[st].second}});
     }
     R.steps.push_back({off0, (int64_t)uh.size() - off0});
+    for (int stage = 0; stage < 4; ++stage) {
+      R.segoff.push_back((int64_t)sh.size());
+      int64_t item = 0;
+      for (const auto& r : runs) {
+        const int32_t t = itiles[r.first][stage];
+        sh.push_back(BatchSeg{item, r.second.first, r.second.second, t, 0});
+        item += (int64_t)r.second.second * kStageCnt[stage] * t;
+      }
+      R.nseg.push_back((int64_t)runs.size());
+      R.nitems.push_back(item);
+    }
   }
+  R.dsegs = (BatchSeg*)ctx_buf(ctx, "bt_segs", std::max<size_t>(1, sh.size()) * sizeof(BatchSeg));
+  if (!sh.empty()) h2d(ctx, R.dsegs, sh.data(), sh.size());
   R.dunits = (Unit*)ctx_buf(ctx, "bt_units", uh.size() * sizeof(Unit));
   h2d(ctx, R.dunits, uh.data(), uh.size());
   R.persist = shape.persist;
@@ -1071,8 +1102,10 @@ void batch_steps(gf2_ctx* ctx, const BatchRun& R, Prec prec, int64_t s0, int64_t
   for (int64_t st = s0; st < s1; ++st) {
     const int nu = (int)R.steps[st].second;
     for (int stage = 0; stage < 4; ++stage) {
+      const int64_t k = st * 4 + stage;
       GemmLaunch L{R.dprobs + kStageOff[stage], kStageCnt[stage], kProbsPerPlan, R.dunits + R.steps[st].first, nu,
-                   InstGeo{0, 0, 0, 0, 0}, R.dgeo, 0, R.persist};
+                   InstGeo{0, 0, 0, 0, 0}, R.dgeo, 0, R.persist, R.dsegs + R.segoff[k], (int32_t)R.nseg[k],
+                   R.nitems[k]};
       double fl = 0.0;
       for (const ChainPlan& c : R.plans)
         if (st < (int64_t)c.chunks.size())

@@ -517,27 +517,49 @@ __device__ __forceinline__ void gemm_item(const GemmLaunch& L, int tile, int py,
   }
 }
 
+// Work item -> (tile, unit * nprob + problem).
+__device__ __forceinline__ void decode_item(const GemmLaunch& L, int64_t item, int& tile, int& py) {
+  if (!L.segs) {
+    tile = (int)(item % L.tiles);
+    py = (int)(item / L.tiles);
+    return;
+  }
+  int lo = 0, hi = L.nseg - 1;                 // last run with item0 <= item
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (L.segs[mid].item0 <= item) lo = mid; else hi = mid - 1;
+  }
+  const BatchSeg sg = L.segs[lo];
+  const int64_t local = item - sg.item0;
+  const int64_t per_unit = (int64_t)L.nprob * sg.tiles;
+  const int64_t ui = sg.unit0 + local / per_unit;
+  const int64_t rem = local % per_unit;
+  tile = (int)(rem % sg.tiles);
+  py = (int)(ui * L.nprob + rem / sg.tiles);
+}
+
 template <Prec P>
 __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(GemmLaunch L) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[Smem<P>::BYTES];
   __shared__ double red[4 * kMaxHad];
+  const int64_t items = L.segs ? L.nitems : (int64_t)L.tiles * L.nunit * L.nprob;
+  int tile, py;
   if (L.persist == 0) {
-    const int64_t total = (int64_t)gridDim.x * gridDim.y;
-    const int64_t lin = xcd_remap((int64_t)blockIdx.y * gridDim.x + blockIdx.x, total);
-    gemm_item<P>(L, (int)(lin % gridDim.x), (int)(lin / gridDim.x), smem, red);
+    decode_item(L, xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x), tile, py);
+    gemm_item<P>(L, tile, py, smem, red);
     return;
   }
-  // Persistent: workgroup b runs on XCD x = b % 8 and takes the items
-  // (py, tile) with py = x (mod 8), all tiles of one (unit, problem) on one
-  // XCD, in a grid-stride loop over that XCD's items.
+  // Persistent: XCD x = b % 8 takes the contiguous x-th eighth of the items
+  // (consecutive items share a (unit, problem)), its workgroups striding
+  // through it.
   const int x = blockIdx.x & 7;
   const int64_t lb = blockIdx.x >> 3, nbx = gridDim.x >> 3;
-  const int64_t npy = (int64_t)L.nunit * L.nprob;
-  const int64_t px = npy > x ? (npy - x + 7) / 8 : 0;
-  const int64_t items = px * L.tiles;
-  for (int64_t j = lb; j < items; j += nbx) {
-    const int py = (int)(x + 8 * (j / L.tiles));
-    gemm_item<P>(L, (int)(j % L.tiles), py, smem, red);
+  const int64_t per = items / 8, rem = items % 8;
+  const int64_t lo = x * per + (x < rem ? x : rem);
+  const int64_t hi = lo + per + (x < rem ? 1 : 0);
+  for (int64_t j = lo + lb; j < hi; j += nbx) {
+    decode_item(L, j, tile, py);
+    gemm_item<P>(L, tile, py, smem, red);
     __syncthreads();                     // LDS of the next item
   }
 }
@@ -555,10 +577,11 @@ void launch_gemm(Prec p, const GemmLaunch& Lin, int max_tiles, hipStream_t st) {
   if (Lin.nunit <= 0 || Lin.nprob <= 0 || max_tiles <= 0) return;
   GemmLaunch L = Lin;
   L.tiles = max_tiles;
-  // more (unit, problem) pairs than a grid dimension holds: run persistent
-  if (L.persist == 0 && (int64_t)L.nunit * L.nprob > 65535) L.persist = 8192;
-  dim3 grid((unsigned)max_tiles, (unsigned)(L.nunit * L.nprob));
-  if (L.persist > 0) grid = dim3((unsigned)(((L.persist + 7) / 8) * 8), 1);
+  const int64_t items = L.segs ? L.nitems : (int64_t)max_tiles * L.nunit * L.nprob;
+  if (items <= 0) return;
+  // a grid of at most 2^31 - 1 workgroups; beyond, run persistent
+  if (L.persist == 0 && items > 0x7fffffffLL) L.persist = 8192;
+  dim3 grid(L.persist > 0 ? (unsigned)(((L.persist + 7) / 8) * 8) : (unsigned)items);
   switch (p) {
     case Prec::F64: hipLaunchKernelGGL(gemm_kernel<Prec::F64>, grid, dim3(kThreads), 0, st, L); break;
     case Prec::F32: hipLaunchKernelGGL(gemm_kernel<Prec::F32>, grid, dim3(kThreads), 0, st, L); break;

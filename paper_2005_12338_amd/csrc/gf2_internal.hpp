@@ -95,6 +95,17 @@ struct InstGeo {
 // C (m x nc) = sum_s A_s (m x k, leading dim ld) B_s^T (nc x k, leading dim
 // ld); outputs use leading dim ld as well.  k must be a multiple of 8 and
 // the operands zero beyond their logical extent in k.
+// A run of consecutive units of one instance in a multi-instance launch: its
+// work items are the (unit, problem, tile) triples, tile fastest, with
+// `tiles` tiles per (unit, problem) (the instance's largest problem).
+struct BatchSeg {
+  int64_t item0;        // first work item of the run
+  int32_t unit0;        // first unit (index into GemmLaunch::units)
+  int32_t nunits;
+  int32_t tiles;
+  int32_t pad;
+};
+
 struct GemmLaunch {
   const Prob* probs;    // device; problem j of instance i at probs[i * pstride + j]
   int32_t nprob;
@@ -106,6 +117,9 @@ struct GemmLaunch {
   int32_t tiles;        // tiles per (unit, problem) covered by the launch
   int32_t persist;      // 0: one workgroup per work item; else a grid-stride
                         // loop over the items (grid a multiple of 8)
+  const BatchSeg* segs; // device work list (multi-instance), or null: items are
+  int32_t nseg;         // tile + tiles * (unit * nprob + problem)
+  int64_t nitems;       // items of the work list
 };
 
 // Kernel launchers (device code in separate translation units).
@@ -113,7 +127,7 @@ void launch_gemm(Prec p, const GemmLaunch& L, int max_tiles, hipStream_t st);
 // Chain launch: square n x n products stored with leading dimension np.
 inline GemmLaunch chain_launch(const Prob* probs, int nprob, const Unit* units, int nunit, int64_t n,
                                int64_t np, int64_t plane) {
-  return GemmLaunch{probs, nprob, 0, units, nunit, InstGeo{n, n, np, np, plane}, nullptr, 0, 0};
+  return GemmLaunch{probs, nprob, 0, units, nunit, InstGeo{n, n, np, np, plane}, nullptr, 0, 0, nullptr, 0, 0};
 }
 int gemm_tile_m(Prec p);     // BM
 int gemm_tile_n(Prec p);     // BN
