@@ -21,6 +21,14 @@
 
 #include "gf2_internal.hpp"
 
+// BF16 block tile (the other precisions use fixed tiles).
+#ifndef GF2_BF16_BM
+#define GF2_BF16_BM 128
+#endif
+#ifndef GF2_BF16_BN
+#define GF2_BF16_BN 128
+#endif
+
 namespace {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
@@ -31,29 +39,29 @@ typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const u32x4_t GVec;
 
 template <Prec P> struct Cfg;
+// BM x BN block tile, 2 x 2 waves, each TM x TN MFMA tiles of MT x MT.
 template <> struct Cfg<Prec::F64> {
   using E = double; using Acc = double;
   static constexpr int BM = 64, BN = 64, BK = 16, PAD = 2, PLANES = 1;
-  static constexpr int MT = 16, NACC = 4;
+  static constexpr int MT = 16, NACC = 4, TM = 2, TN = 2;
 };
 template <> struct Cfg<Prec::F32> {
   using E = float; using Acc = float;
   static constexpr int BM = 128, BN = 128, BK = 32, PAD = 4, PLANES = 1;
-  static constexpr int MT = 32, NACC = 16;
+  static constexpr int MT = 32, NACC = 16, TM = 2, TN = 2;
 };
 template <> struct Cfg<Prec::BF16> {
   using E = bf16_t; using Acc = float;
-  static constexpr int BM = 128, BN = 128, BK = 64, PAD = 8, PLANES = 1;
-  static constexpr int MT = 32, NACC = 16;
+  static constexpr int BM = GF2_BF16_BM, BN = GF2_BF16_BN, BK = 64, PAD = 8, PLANES = 1;
+  static constexpr int MT = 32, NACC = 16, TM = BM / 64, TN = BN / 64;
 };
 template <> struct Cfg<Prec::BF16X3> {
   using E = bf16_t; using Acc = float;
   static constexpr int BM = 128, BN = 128, BK = 32, PAD = 8, PLANES = 2;
-  static constexpr int MT = 32, NACC = 16;
+  static constexpr int MT = 32, NACC = 16, TM = 2, TN = 2;
 };
 
 constexpr int kThreads = 256;
-constexpr int TM = 2, TN = 2;           // MFMA tiles per wave along rows / columns
 
 __device__ __forceinline__ bf16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -185,7 +193,9 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
   constexpr int TILE_A = Smem<P>::TILE_A, TILE_B = Smem<P>::TILE_B;
   constexpr int SM = BM / NA, SN = BN / NB;               // output rows / cols per tile
   constexpr int MT = C::MT, NACC = C::NACC;
-  constexpr int WR = BM / 2, WC = BN / 2;                 // wave region in the LDS tile (normal mode)
+  constexpr int TM = C::TM, TN = C::TN;                   // MFMA tiles per wave
+  constexpr int FR = TM / NA, FC = TN / NB;               // ... per product
+  static_assert(TM % NA == 0 && TN % NB == 0 && FR * MT * 2 == SM && FC * MT * 2 == SN, "wave tiling");
 
   E* As = (E*)smem;                    // [2][PL][BM][PITCH]
   E* Bs = As + 2 * TILE_A;             // [2][PL][BN][PITCH]
@@ -205,11 +215,12 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
 
   // LDS row of MFMA row-fragment i (column fragment j) of this wave, and the
   // output row (column) offset it covers.  With two A matrices the tile holds
-  // A_0 rows in [0, SM) and A_1 rows in [SM, 2 SM); fragment i is product i.
-  auto frag_row_lds = [&](int i) { return NA == 2 ? i * SM + wm * MT : wm * WR + i * MT; };
-  auto frag_col_lds = [&](int j) { return NB == 2 ? j * SN + wn * MT : wn * WC + j * MT; };
-  auto frag_row_out = [&](int i) { return NA == 2 ? wm * MT : wm * WR + i * MT; };
-  auto frag_col_out = [&](int j) { return NB == 2 ? wn * MT : wn * WC + j * MT; };
+  // A_0 rows in [0, SM) and A_1 rows in [SM, 2 SM); fragments
+  // [a FR, (a+1) FR) belong to product a and cover the same output rows.
+  auto frag_row_lds = [&](int i) { return (i / FR) * SM + wm * (FR * MT) + (i % FR) * MT; };
+  auto frag_col_lds = [&](int j) { return (j / FC) * SN + wn * (FC * MT) + (j % FC) * MT; };
+  auto frag_row_out = [&](int i) { return wm * (FR * MT) + i * MT; };   // i < FR
+  auto frag_col_out = [&](int j) { return wn * (FC * MT) + j * MT; };   // j < FC
 
   // Staging geometry.  Vector i of thread t covers tile row trow + c_i
   // (c_i = (i * RSTEP) % rows) of plane (i * RSTEP) / rows and k offset kv;
@@ -401,8 +412,8 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
 
   // -------- epilogue straight from the accumulators
   constexpr int NPROD = NA * NB;
-  constexpr int GI = NA == 2 ? 1 : TM;        // distinct row positions
-  constexpr int GJ = NB == 2 ? 1 : TN;        // distinct column positions
+  constexpr int GI = FR;                      // distinct row positions
+  constexpr int GJ = FC;                      // distinct column positions
   Acc addc[kMaxAdd];
   const void* addp[kMaxAdd];
   const int nadd = pb.nadd;
@@ -442,7 +453,7 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
 #pragma unroll
           for (int a = 0; a < NA; ++a)
 #pragma unroll
-            for (int b = 0; b < NB; ++b) v[e][a * NB + b] = acc[NA == 2 ? a : gi][NB == 2 ? b : gj][r];
+            for (int b = 0; b < NB; ++b) v[e][a * NB + b] = acc[a * FR + gi][b * FC + gj][r];
           if (nadd && colok && grs[e] < mrows) {
             const int64_t gn = grs[e] * ld + gc;
             for (int x = 0; x < nadd; ++x) v[e][0] += addc[x] * load_st<P>(addp[x], gn, L.plane);
@@ -501,13 +512,13 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
   }
 }
 
-template <Prec P>
+template <Prec P, bool MI>
 __device__ __forceinline__ void gemm_item(const GemmLaunch& L, int tile, int py, unsigned char* smem,
                                           double* red) {
   const int ui = py / L.nprob, pi = py % L.nprob;
   const Unit u = L.units[ui];
-  const Prob& pb = L.probs[(int64_t)u.inst * L.pstride + pi];
-  const InstGeo g = L.geo ? L.geo[u.inst] : L.g;
+  const Prob& pb = MI ? L.probs[(int64_t)u.inst * L.pstride + pi] : L.probs[pi];
+  const InstGeo g = MI ? L.geo[u.inst] : L.g;
   const int mode = (pb.nA == 2 ? 2 : 0) + (pb.nB == 2 ? 1 : 0);
   switch (mode) {
     case 0: gemm_body<P, 1, 1>(g, pb, u, tile, smem, red); break;
@@ -518,8 +529,9 @@ __device__ __forceinline__ void gemm_item(const GemmLaunch& L, int tile, int py,
 }
 
 // Work item -> (tile, unit * nprob + problem).
+template <bool MI>
 __device__ __forceinline__ void decode_item(const GemmLaunch& L, int64_t item, int& tile, int& py) {
-  if (!L.segs) {
+  if (!MI) {
     tile = (int)(item % L.tiles);
     py = (int)(item / L.tiles);
     return;
@@ -538,39 +550,52 @@ __device__ __forceinline__ void decode_item(const GemmLaunch& L, int64_t item, i
   py = (int)(ui * L.nprob + rem / sg.tiles);
 }
 
-template <Prec P>
+// MI: a multi-instance launch (per-unit instance geometry and problems, work
+// list of runs); otherwise one instance, items tile-major per (unit, problem).
+// PERSIST: a grid-stride loop over the items, else one item per workgroup
+// (kept loop-free, so nothing is hoisted across items).
+template <Prec P, bool MI, bool PERSIST>
 __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(GemmLaunch L) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[Smem<P>::BYTES];
   __shared__ double red[4 * kMaxHad];
-  const int64_t items = L.segs ? L.nitems : (int64_t)L.tiles * L.nunit * L.nprob;
   int tile, py;
-  if (L.persist == 0) {
-    decode_item(L, xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x), tile, py);
-    gemm_item<P>(L, tile, py, smem, red);
-    return;
-  }
-  // Persistent: XCD x = b % 8 takes the contiguous x-th eighth of the items
-  // (consecutive items share a (unit, problem)), its workgroups striding
-  // through it.
-  const int x = blockIdx.x & 7;
-  const int64_t lb = blockIdx.x >> 3, nbx = gridDim.x >> 3;
-  const int64_t per = items / 8, rem = items % 8;
-  const int64_t lo = x * per + (x < rem ? x : rem);
-  const int64_t hi = lo + per + (x < rem ? 1 : 0);
-  for (int64_t j = lo + lb; j < hi; j += nbx) {
-    decode_item(L, j, tile, py);
-    gemm_item<P>(L, tile, py, smem, red);
-    __syncthreads();                     // LDS of the next item
+  if constexpr (!PERSIST) {
+    decode_item<MI>(L, xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x), tile, py);
+    gemm_item<P, MI>(L, tile, py, smem, red);
+  } else {
+    // XCD x = b % 8 takes the contiguous x-th eighth of the items
+    // (consecutive items share a (unit, problem)); its workgroups stride
+    // through it.
+    const int64_t items = MI ? L.nitems : (int64_t)L.tiles * L.nunit * L.nprob;
+    const int x = blockIdx.x & 7;
+    const int64_t per = items / 8, rem = items % 8;
+    const int64_t lo = x * per + (x < rem ? x : rem);
+    const int64_t hi = lo + per + (x < rem ? 1 : 0);
+    for (int64_t j = lo + (blockIdx.x >> 3); j < hi; j += gridDim.x >> 3) {
+      decode_item<MI>(L, j, tile, py);
+      gemm_item<P, MI>(L, tile, py, smem, red);
+      __syncthreads();                   // LDS of the next item
+    }
   }
 }
 
 }  // namespace
 
 int gemm_tile_m(Prec p) {
-  return p == Prec::F64 ? Cfg<Prec::F64>::BM : Cfg<Prec::F32>::BM;
+  switch (p) {
+    case Prec::F64: return Cfg<Prec::F64>::BM;
+    case Prec::F32: return Cfg<Prec::F32>::BM;
+    case Prec::BF16: return Cfg<Prec::BF16>::BM;
+    default: return Cfg<Prec::BF16X3>::BM;
+  }
 }
 int gemm_tile_n(Prec p) {
-  return p == Prec::F64 ? Cfg<Prec::F64>::BN : Cfg<Prec::F32>::BN;
+  switch (p) {
+    case Prec::F64: return Cfg<Prec::F64>::BN;
+    case Prec::F32: return Cfg<Prec::F32>::BN;
+    case Prec::BF16: return Cfg<Prec::BF16>::BN;
+    default: return Cfg<Prec::BF16X3>::BN;
+  }
 }
 
 void launch_gemm(Prec p, const GemmLaunch& Lin, int max_tiles, hipStream_t st) {
@@ -581,12 +606,31 @@ void launch_gemm(Prec p, const GemmLaunch& Lin, int max_tiles, hipStream_t st) {
   if (items <= 0) return;
   // a grid of at most 2^31 - 1 workgroups; beyond, run persistent
   if (L.persist == 0 && items > 0x7fffffffLL) L.persist = 8192;
+  if (!L.segs) L.persist = 0;    // single-instance launches: one item per workgroup
   dim3 grid(L.persist > 0 ? (unsigned)(((L.persist + 7) / 8) * 8) : (unsigned)items);
+  const bool mi = L.segs != nullptr, pers = L.persist > 0;
+  auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(kThreads), 0, st, L); };
   switch (p) {
-    case Prec::F64: hipLaunchKernelGGL(gemm_kernel<Prec::F64>, grid, dim3(kThreads), 0, st, L); break;
-    case Prec::F32: hipLaunchKernelGGL(gemm_kernel<Prec::F32>, grid, dim3(kThreads), 0, st, L); break;
-    case Prec::BF16: hipLaunchKernelGGL(gemm_kernel<Prec::BF16>, grid, dim3(kThreads), 0, st, L); break;
-    case Prec::BF16X3: hipLaunchKernelGGL(gemm_kernel<Prec::BF16X3>, grid, dim3(kThreads), 0, st, L); break;
+    case Prec::F64:
+      if (!mi) go(gemm_kernel<Prec::F64, false, false>);
+      else if (pers) go(gemm_kernel<Prec::F64, true, true>);
+      else go(gemm_kernel<Prec::F64, true, false>);
+      break;
+    case Prec::F32:
+      if (!mi) go(gemm_kernel<Prec::F32, false, false>);
+      else if (pers) go(gemm_kernel<Prec::F32, true, true>);
+      else go(gemm_kernel<Prec::F32, true, false>);
+      break;
+    case Prec::BF16:
+      if (!mi) go(gemm_kernel<Prec::BF16, false, false>);
+      else if (pers) go(gemm_kernel<Prec::BF16, true, true>);
+      else go(gemm_kernel<Prec::BF16, true, false>);
+      break;
+    case Prec::BF16X3:
+      if (!mi) go(gemm_kernel<Prec::BF16X3, false, false>);
+      else if (pers) go(gemm_kernel<Prec::BF16X3, true, true>);
+      else go(gemm_kernel<Prec::BF16X3, true, false>);
+      break;
   }
   GF2_HIP(hipGetLastError());
 }
