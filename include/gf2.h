@@ -70,8 +70,21 @@ typedef enum {
  *   RADEMACHER : theta_Q = +-1 for every Q (the paper's orbitals, Sec. II).
  *   IMPORTANCE : theta = (1/sqrt k) sum_j e_j u_{Q_j} / sqrt(p_{Q_j}) with
  *                Q_j drawn from the proposal p and e_j = +-1 (unbiased for
- *                any p > 0 since E[theta theta^T] = I).                    */
-typedef enum { GF2_SAMPLE_RADEMACHER = 0, GF2_SAMPLE_IMPORTANCE = 1 } gf2_sample_mode;
+ *                any p > 0 since E[theta theta^T] = I).
+ *   STRATIFIED : the auxiliary index is split into k classes Q = c (mod k);
+ *                each vector draws one class with probability
+ *                pi_c = sum_{Q = c mod k} p_Q (sequential sums, then divided
+ *                by their sequential total) from the uniform of word(seed,
+ *                stream, s, 0xFFFFFFFF), and theta_Q = e_Q / sqrt(pi_c) on
+ *                the class members (e_Q the RADEMACHER sign of the same
+ *                (stream, s, Q)), 0 elsewhere.  Members of one class are k
+ *                auxiliary functions apart, so the +-1 cross terms between
+ *                neighbouring Q vanish; E[theta theta^T] = I for any pi > 0. */
+typedef enum {
+  GF2_SAMPLE_RADEMACHER = 0,
+  GF2_SAMPLE_IMPORTANCE = 1,
+  GF2_SAMPLE_STRATIFIED = 2
+} gf2_sample_mode;
 
 typedef struct gf2_ctx gf2_ctx;
 typedef struct gf2_split_h gf2_split_h;
@@ -90,8 +103,10 @@ typedef struct {
   int64_t s0;          /* index of the first pair (counter offset)          */
   uint64_t seed;
   int32_t mode;        /* gf2_sample_mode                                   */
-  int32_t k;           /* draws per vector in IMPORTANCE mode (>= 1)        */
-  const double* p;     /* host [naux] proposal (IMPORTANCE), sums to 1      */
+  int32_t k;           /* draws per vector (IMPORTANCE, >= 1) or classes
+                          (STRATIFIED, 2 .. naux)                           */
+  const double* p;     /* host [naux] proposal (IMPORTANCE, STRATIFIED),
+                          positive, sums to 1                               */
 } gf2_sampling;
 
 /* ---------------------------------------------------------------- context */

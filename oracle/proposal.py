@@ -210,3 +210,35 @@ def importance_theta(p: np.ndarray, seed: int, stream: int, ns: int, k: int = 1,
         for j in range(k):
             theta[s, q[s, j]] += sgn[s, j] / np.sqrt(k * p[q[s, j]])
     return theta
+
+
+# ---------------------------------------------------------------------------
+# Stratified stochastic orbitals (project form)
+# ---------------------------------------------------------------------------
+
+def class_probabilities(p: np.ndarray, nclass: int) -> np.ndarray:
+    """pi_c = sum of p_Q over the class Q = c (mod nclass), normalised; all
+    sums sequential in index order (the class draw compares against them)."""
+    p = np.asarray(p, dtype=np.float64)
+    pi = [0.0] * nclass
+    for q in range(p.shape[0]):
+        pi[q % nclass] += float(p[q])
+    tot = 0.0
+    for c in range(nclass):
+        tot += pi[c]
+    return np.array([x / tot for x in pi])
+
+
+def stratified_theta(p: np.ndarray, nclass: int, seed: int, stream: int, ns: int,
+                     s0: int = 0) -> np.ndarray:
+    """theta[s]: one class c ~ pi per vector (pi from class_probabilities),
+    theta_Q = e_Q / sqrt(pi_c) for Q = c (mod nclass) with e_Q the +-1 orbital
+    of the same (stream, s, Q), and 0 elsewhere.  E[theta theta^T] = I for
+    any pi > 0: Q sits in exactly one class, drawn with probability pi_c, and
+    distinct Q carry independent signs."""
+    naux = p.shape[0]
+    pi = class_probabilities(p, nclass)
+    c = _rng.class_draws(seed, stream, ns, _rng.proposal_cdf(pi), s0)
+    e = _rng.rademacher(seed, stream, ns, naux, s0)
+    member = (np.arange(naux)[None, :] % nclass) == c[:, None]
+    return np.where(member, e / np.sqrt(pi[c])[:, None], 0.0)

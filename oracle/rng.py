@@ -19,7 +19,9 @@ all modulo 2^64.  stream 0 draws the first vertex's orbitals (theta), stream
   u     = (word >> 11) * 2^-53  in [0, 1)
 
 Importance draw j of vector (stream, s) uses q = 2j for its uniform and
-q = 2j + 1 for its sign.
+q = 2j + 1 for its sign.  A stratified vector (stream, s) draws its class
+from the uniform of q = CLASS_Q and takes the signs of its members from
+the same words as the +-1 orbitals (q = Q).
 """
 from __future__ import annotations
 
@@ -81,6 +83,17 @@ def importance_draws(seed: int, stream: int, ns: int, k: int, cdf: np.ndarray,
     q = np.searchsorted(cdf, u, side="right")
     q = np.minimum(q, cdf.shape[0] - 1)
     return q.astype(np.int64), sign
+
+
+CLASS_Q = 0xFFFFFFFF
+
+
+def class_draws(seed: int, stream: int, ns: int, cdf: np.ndarray, s0: int = 0) -> np.ndarray:
+    """One class per vector: the smallest c with u < cdf[c], u from q = CLASS_Q."""
+    s = np.arange(s0, s0 + ns, dtype=np.uint64)
+    u = uniform_from_word(words(seed, stream, s, np.uint64(CLASS_Q)))
+    c = np.searchsorted(cdf, u, side="right")
+    return np.minimum(c, cdf.shape[0] - 1).astype(np.int64)
 
 
 def proposal_cdf(p: np.ndarray) -> np.ndarray:

@@ -674,6 +674,29 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
     ProfScope ps(ctx, "rbuild", 4.0 * (double)nvec * naux * n * n, (double)naux * n * n * (bf64 ? 8 : 4));
     launch_theta(smp->seed, ns, s0, naux, theta, st);
     launch_rbuild(B, bf64, n, naux, sp->thresh, theta, nvec, prec, xl, xs, np, plane, mstride, st);
+  } else if (smp->mode == GF2_SAMPLE_STRATIFIED) {
+    // class probabilities and their CDF, sequential FP64 sums
+    const int32_t nc = smp->k;
+    std::vector<double> pi(nc, 0.0), cdf(nc);
+    for (int64_t q = 0; q < naux; ++q) pi[q % nc] += smp->p[q];
+    double tot = 0.0;
+    for (int32_t c = 0; c < nc; ++c) tot += pi[c];
+    double acc = 0.0;
+    for (int32_t c = 0; c < nc; ++c) {
+      pi[c] /= tot;
+      acc += pi[c];
+      cdf[c] = acc;
+    }
+    cdf[nc - 1] = 1.0;
+    auto* dpi = (double*)ctx_buf(ctx, pfx + "c_pi", (size_t)nc * 8);
+    auto* dcdf = (double*)ctx_buf(ctx, pfx + "c_ccdf", (size_t)nc * 8);
+    auto* theta = (int8_t*)ctx_buf(ctx, pfx + "c_theta", (size_t)(nvec * naux));
+    auto* vsc = (double*)ctx_buf(ctx, pfx + "c_vscale", (size_t)nvec * 8);
+    h2d(ctx, dpi, pi.data(), pi.size());
+    h2d(ctx, dcdf, cdf.data(), cdf.size());
+    ProfScope ps(ctx, "rbuild", 4.0 * (double)nvec * naux * n * n, (double)naux * n * n * (bf64 ? 8 : 4));
+    launch_theta_strat(smp->seed, ns, s0, naux, nc, dcdf, dpi, theta, vsc, st);
+    launch_rbuild(B, bf64, n, naux, sp->thresh, theta, nvec, prec, xl, xs, np, plane, mstride, st, vsc);
   } else {
     std::vector<double> cdf(naux);
     double acc = 0.0;
@@ -912,9 +935,12 @@ void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double*
 void check_sampling(const gf2_split_h* sp, const gf2_sampling* s) {
   GF2_REQUIRE(s, GF2_E_ARG, "sampling is null");
   GF2_REQUIRE(s->ns >= 1 && s->s0 >= 0 && s->s0 + s->ns <= (1 << 30), GF2_E_ARG, "bad ns / s0");
-  GF2_REQUIRE(s->mode == GF2_SAMPLE_RADEMACHER || s->mode == GF2_SAMPLE_IMPORTANCE, GF2_E_ARG, "bad mode");
-  if (s->mode == GF2_SAMPLE_IMPORTANCE) {
-    GF2_REQUIRE(s->k >= 1 && s->k <= 64, GF2_E_ARG, "k must be in [1, 64]");
+  GF2_REQUIRE(s->mode == GF2_SAMPLE_RADEMACHER || s->mode == GF2_SAMPLE_IMPORTANCE ||
+                  s->mode == GF2_SAMPLE_STRATIFIED, GF2_E_ARG, "bad mode");
+  if (s->mode == GF2_SAMPLE_STRATIFIED)
+    GF2_REQUIRE(s->k >= 2 && s->k <= sp->naux, GF2_E_ARG, "stratified sampling needs 2 <= classes <= naux");
+  if (s->mode != GF2_SAMPLE_RADEMACHER) {
+    if (s->mode == GF2_SAMPLE_IMPORTANCE) GF2_REQUIRE(s->k >= 1 && s->k <= 64, GF2_E_ARG, "k must be in [1, 64]");
     GF2_REQUIRE(s->p, GF2_E_ARG, "importance mode needs p");
     double tot = 0.0;
     for (int64_t q = 0; q < sp->naux; ++q) {

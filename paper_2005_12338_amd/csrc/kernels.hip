@@ -82,6 +82,28 @@ __global__ void k_draws(uint64_t seed, int64_t ns, int64_t s0, int32_t k, const 
   wout[i] = sg / sqrt((double)k * p[lo]);
 }
 
+// Stratified vectors: vector v (stream v / ns, sample s0 + v % ns) draws its
+// class c (u of q = 0xFFFFFFFF, smallest c with u < cdf[c]); theta[v][Q] is
+// the +-1 sign of (stream, s, Q) on the class members (Q = c mod nclass), 0
+// elsewhere, and vscale[v] = 1 / sqrt(pi_c).
+__global__ void k_theta_strat(uint64_t seed, int64_t ns, int64_t s0, int64_t naux, int32_t nclass,
+                              const double* cdf, const double* pi, int8_t* theta, double* vscale) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * ns * naux) return;
+  int64_t v = i / naux, q = i % naux;
+  uint64_t stream = (uint64_t)(v / ns), s = (uint64_t)(s0 + v % ns);
+  uint64_t base = seed * 0x9E3779B97F4A7C15ull + ((stream << 62) | (s << 32)) + 1ull;
+  const double u = (double)(mix64(base + 0xFFFFFFFFull) >> 11) * 0x1.0p-53;
+  int lo = 0, hi = nclass - 1;               // smallest class with u < cdf[class]
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (u < cdf[mid]) hi = mid; else lo = mid + 1;
+  }
+  const uint64_t w = mix64(base + (uint64_t)q);
+  theta[i] = (q % nclass == lo) ? ((w >> 63) ? (int8_t)-1 : (int8_t)1) : (int8_t)0;
+  if (q == 0) vscale[v] = 1.0 / sqrt(pi[lo]);
+}
+
 // ------------------------------------------------------------- B build ----
 __global__ void k_synth_b(int64_t n, int64_t naux, const double* x, const double* xq,
                           double amp, double a, double c, void* out, int f64) {
@@ -153,7 +175,8 @@ template <int RV, typename T>
 __global__ __launch_bounds__(256) void k_rbuild(const void* b, int f64, int64_t n, int64_t naux,
                                                  double thr, const int8_t* theta, int64_t nvec,
                                                  int64_t v0, Prec prec, void* xl, void* xs,
-                                                 int64_t np, int64_t plane, int64_t mstride) {
+                                                 int64_t np, int64_t plane, int64_t mstride,
+                                                 const double* vscale) {
   constexpr int QC = 64;
   __shared__ T th[RV][QC];
   const int64_t ij = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -192,8 +215,9 @@ __global__ __launch_bounds__(256) void k_rbuild(const void* b, int f64, int64_t 
     int64_t v = vb + r;
     if (v >= nvec) break;
     int64_t o = v * mstride + i * np + j;
-    put_st(xl, o, plane, prec, (double)al[r]);
-    put_st(xs, o, plane, prec, (double)as[r]);
+    const double sc = vscale ? vscale[v] : 1.0;     // stratified vectors: 1/sqrt(pi_c)
+    put_st(xl, o, plane, prec, (double)al[r] * sc);
+    put_st(xs, o, plane, prec, (double)as[r] * sc);
   }
 }
 
@@ -537,15 +561,20 @@ void launch_extract_blocks(const void* b, bool f64, int64_t n, int64_t naux, dou
 }
 void launch_rbuild(const void* b, bool f64, int64_t n, int64_t naux, double thr, const int8_t* theta,
                    int64_t nvec, Prec prec, void* xl, void* xs, int64_t np, int64_t plane,
-                   int64_t mstride, hipStream_t st) {
+                   int64_t mstride, hipStream_t st, const double* vscale) {
   constexpr int RV = 8;
   dim3 grid(blocks(n * n), (unsigned)((nvec + RV - 1) / RV));
   if (prec == Prec::F64)
     hipLaunchKernelGGL((k_rbuild<RV, double>), grid, dim3(256), 0, st, b, (int)f64, n, naux, thr,
-                       theta, nvec, (int64_t)0, prec, xl, xs, np, plane, mstride);
+                       theta, nvec, (int64_t)0, prec, xl, xs, np, plane, mstride, vscale);
   else
     hipLaunchKernelGGL((k_rbuild<RV, float>), grid, dim3(256), 0, st, b, (int)f64, n, naux, thr,
-                       theta, nvec, (int64_t)0, prec, xl, xs, np, plane, mstride);
+                       theta, nvec, (int64_t)0, prec, xl, xs, np, plane, mstride, vscale);
+}
+void launch_theta_strat(uint64_t seed, int64_t ns, int64_t s0, int64_t naux, int32_t nclass, const double* cdf,
+                        const double* pi, int8_t* theta, double* vscale, hipStream_t st) {
+  hipLaunchKernelGGL(k_theta_strat, dim3(blocks(2 * ns * naux)), dim3(256), 0, st, seed, ns, s0, naux, nclass, cdf,
+                     pi, theta, vscale);
 }
 void launch_rimportance(const void* b, bool f64, int64_t n, double thr, const int32_t* q,
                         const double* w, int32_t k, int64_t nvec, Prec prec, void* xl, void* xs,

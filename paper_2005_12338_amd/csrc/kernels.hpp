@@ -20,7 +20,9 @@ void launch_extract_blocks(const void* b, bool f64, int64_t n, int64_t naux, dou
                            hipStream_t st);
 void launch_rbuild(const void* b, bool f64, int64_t n, int64_t naux, double thr, const int8_t* theta,
                    int64_t nvec, Prec prec, void* xl, void* xs, int64_t np, int64_t plane,
-                   int64_t mstride, hipStream_t st);
+                   int64_t mstride, hipStream_t st, const double* vscale = nullptr);
+void launch_theta_strat(uint64_t seed, int64_t ns, int64_t s0, int64_t naux, int32_t nclass, const double* cdf,
+                        const double* pi, int8_t* theta, double* vscale, hipStream_t st);
 void launch_rimportance(const void* b, bool f64, int64_t n, double thr, const int32_t* q,
                         const double* w, int32_t k, int64_t nvec, Prec prec, void* xl, void* xs,
                         int64_t np, int64_t plane, int64_t mstride, hipStream_t st);

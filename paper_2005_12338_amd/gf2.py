@@ -22,7 +22,7 @@ GF2_OK, GF2_E_ARG, GF2_E_DEVICE, GF2_E_NOMEM, GF2_E_NUMERIC, GF2_E_STATE = 0, -1
 GF2_F64, GF2_F32 = 0, 1
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "auto": 4}
 PREC_NAME = {v: k for k, v in PREC.items()}
-SAMPLE_RADEMACHER, SAMPLE_IMPORTANCE = 0, 1
+SAMPLE_RADEMACHER, SAMPLE_IMPORTANCE, SAMPLE_STRATIFIED = 0, 1, 2
 
 _STATUS = {GF2_E_ARG: "GF2_E_ARG", GF2_E_DEVICE: "GF2_E_DEVICE", GF2_E_NOMEM: "GF2_E_NOMEM",
            GF2_E_NUMERIC: "GF2_E_NUMERIC", GF2_E_STATE: "GF2_E_STATE"}
@@ -289,9 +289,17 @@ class Context:
 
     # ---------------------------------------------------------------- Sigma
     @staticmethod
-    def _sampling(ns, seed, s0=0, p=None, k=1):
+    def _sampling(ns, seed, s0=0, p=None, k=1, classes=0):
+        """classes > 0: stratified vectors over that many classes, with class
+        weights from p (uniform if p is None); else importance draws if p is
+        given, else +-1 orbitals."""
         keep = None
-        if p is not None:
+        if classes:
+            if p is None:
+                raise ValueError("stratified sampling needs the per-Q weights p")
+            keep = np.ascontiguousarray(p, dtype=np.float64)
+            s = Sampling(ns, s0, seed, SAMPLE_STRATIFIED, int(classes), _dp(keep))
+        elif p is not None:
             keep = np.ascontiguousarray(p, dtype=np.float64)
             s = Sampling(ns, s0, seed, SAMPLE_IMPORTANCE, k, _dp(keep))
         else:
@@ -299,12 +307,12 @@ class Context:
         return s, keep
 
     def sigma_tau(self, split: Split, B, G, Gb, ns: int, seed: int = 0, prec: str = "fp32", p=None, k=1,
-                  s0: int = 0, want_samples: bool = True):
+                  s0: int = 0, want_samples: bool = True, classes: int = 0):
         torch = self.torch
         ntau, n, _ = G.shape
         Sigma = torch.empty((ntau, n, n), dtype=torch.float64, device=self.device)
         es = torch.empty((ns, ntau), dtype=torch.float64, device=self.device) if want_samples else None
-        smp, keep = self._sampling(ns, seed, s0, p, k)
+        smp, keep = self._sampling(ns, seed, s0, p, k, classes)
         self._check(self.lib.gf2_sigma_tau(self.h, split.handle, B.data_ptr(), G.data_ptr(), Gb.data_ptr(),
                                            ntau, C.byref(smp), PREC[prec], Sigma.data_ptr(), _ptr(es)))
         return Sigma, es
@@ -318,9 +326,9 @@ class Context:
         return out
 
     def sigma_stoch(self, split: Split, B, G, Gb, Sigma_sum, ns: int, seed: int = 0, prec: str = "fp32",
-                    p=None, k=1, s0: int = 0, e_samples=None):
+                    p=None, k=1, s0: int = 0, e_samples=None, classes: int = 0):
         ntau = G.shape[0]
-        smp, keep = self._sampling(ns, seed, s0, p, k)
+        smp, keep = self._sampling(ns, seed, s0, p, k, classes)
         self._check(self.lib.gf2_sigma_stoch(self.h, split.handle, B.data_ptr(), G.data_ptr(),
                                              Gb.data_ptr(), ntau, C.byref(smp), PREC[prec],
                                              Sigma_sum.data_ptr(), _ptr(e_samples)))
@@ -342,7 +350,8 @@ class Context:
             ntau, n, _ = it["G"].shape
             Sigma = torch.empty((ntau, n, n), dtype=torch.float64, device=self.device)
             es = torch.empty((it["ns"], ntau), dtype=torch.float64, device=self.device)
-            smp, kp = self._sampling(it["ns"], it.get("seed", 0), it.get("s0", 0), it.get("p"), it.get("k", 1))
+            smp, kp = self._sampling(it["ns"], it.get("seed", 0), it.get("s0", 0), it.get("p"), it.get("k", 1),
+                                     it.get("classes", 0))
             keep.append(kp)
             arr[i] = BatchItem(it["split"].handle, it["B"].data_ptr(), it["G"].data_ptr(), it["Gb"].data_ptr(),
                                ntau, smp, Sigma.data_ptr(), es.data_ptr())
@@ -353,7 +362,7 @@ class Context:
 
     def energy_adaptive(self, split: Split, B, G, Gb, w: np.ndarray, Sigma_det, n_elec: float, target: float,
                         batch: int = 16, max_pairs: int = 4096, seed: int = 0, prec: str = "auto", p=None,
-                        k: int = 1):
+                        k: int = 1, classes: int = 0):
         """Sample pairs in batches until the standard error of the total
         E_corr is below target.  Returns (Sigma, e_samples[:pairs], dict)."""
         torch = self.torch
@@ -361,7 +370,7 @@ class Context:
         w = np.ascontiguousarray(w, dtype=np.float64)
         Sigma = torch.empty((ntau, n, n), dtype=torch.float64, device=self.device)
         es = torch.empty((max_pairs, ntau), dtype=torch.float64, device=self.device)
-        smp, keep = self._sampling(batch, seed, 0, p, k)
+        smp, keep = self._sampling(batch, seed, 0, p, k, classes)
         r = AdaptiveResult()
         self._check(self.lib.gf2_energy_adaptive(self.h, split.handle, B.data_ptr(), G.data_ptr(), Gb.data_ptr(),
                                                  ntau, _dp(w), Sigma_det.data_ptr(), float(n_elec), C.byref(smp),

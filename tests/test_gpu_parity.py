@@ -223,6 +223,24 @@ def test_sigma_importance_mode_matches_oracle(ctx):
     assert rel(es.cpu().numpy(), e_ref) < 1e-10
 
 
+@pytest.mark.parametrize("nclass", [3, 7])
+def test_sigma_stratified_mode_matches_oracle(ctx, nclass):
+    """Stratified vectors (one class per vector, +-1/sqrt(pi_c) on its
+    members), class weights from a random p, pair by pair."""
+    pb = chain(8, 50.0, 3, 1e-2)
+    o = oracle_setup(pb)
+    B, G, Gb, mu, tau, w = _gpu_inputs(ctx, pb, torch.float64)
+    spl = ctx.split(B, pb["eps"])
+    p = ci.random_weights(pb["naux"], 19)
+    ns = 6
+    Sigma, es = ctx.sigma_tau(spl, B, G, Gb, ns=ns, seed=8, prec="fp64", p=p, classes=nclass)
+    th = pr.stratified_theta(p, nclass, 8, 0, ns)
+    thp = pr.stratified_theta(p, nclass, 8, 1, ns)
+    per = oracle_pairs(o, 8, ns, range(3), range(ns), th, thp)
+    e_ref = np.array([[energy.trace_product(per[(t, s)], o["gb"][t]) for t in range(3)] for s in range(ns)])
+    assert rel(es.cpu().numpy(), e_ref) < 1e-10
+
+
 def test_sigma_stoch_batches_equal_one_call(ctx):
     """Adaptive sampling in batches (s0 offsets) reproduces one call bitwise."""
     pb = chain(8, 50.0, 3, 1e-2)

@@ -331,3 +331,46 @@ def test_enumeration_of_importance_draws_is_exact():
     assert np.all(nzc == 1)
     qs = np.argmax(np.abs(th), axis=1)
     assert np.allclose(np.abs(th[np.arange(50), qs]), 1.0 / np.sqrt(p[qs]))
+
+
+def _stratified_states(naux, nclass, pi):
+    """Every (class, sign pattern) state of one stratified vector and its
+    probability: class c with pi_c, signs of the class members uniform."""
+    states, probs = [], []
+    for c in range(nclass):
+        members = np.arange(naux)[np.arange(naux) % nclass == c]
+        for sg in itertools.product([1.0, -1.0], repeat=members.shape[0]):
+            th = np.zeros(naux)
+            th[members] = np.array(sg) / np.sqrt(pi[c])
+            states.append(th)
+            probs.append(pi[c] / 2.0 ** members.shape[0])
+    return np.array(states), np.array(probs)
+
+
+def test_enumeration_of_stratified_vectors_is_exact():
+    """Stratified vectors (one class drawn per vector, +-1 on its members,
+    scaled by 1/sqrt(pi_c)): E[theta theta^T] = I, and the pair estimate
+    averaged over all states of both vectors is Sigma_RI - Sigma[D,D]."""
+    from oracle import proposal
+    b, spl, g, gb = _enumerate_setup()
+    naux = b.shape[0]
+    p = ci.random_weights(naux, 47)
+    nclass = 3
+    pi = proposal.class_probabilities(p, nclass)
+    th, pr_ = _stratified_states(naux, nclass, pi)
+    assert abs(pr_.sum() - 1.0) < 1e-14
+    assert _rel(np.einsum("s,si,sj->ij", pr_, th, th), np.eye(naux)) < 1e-14
+    _, rl, rs = sp.r_vectors(b, spl, th)
+    tot = np.zeros((4, 4))
+    for a in range(th.shape[0]):
+        for c in range(th.shape[0]):
+            tot += pr_[a] * pr_[c] * se.sigma_pair(spl, rl[a], rs[a], rl[c], rs[c], g, gb)
+    ref = se.sigma_ri(b, g, gb) - se.sigma_dd(spl, g, gb)
+    assert _rel(tot, ref) < 1e-12
+    # the generator draws only such states: one class, +-1/sqrt(pi_c) on it
+    thg = proposal.stratified_theta(p, nclass, 5, 1, 40)
+    for v in thg:
+        nz = np.nonzero(v)[0]
+        assert np.all(nz % nclass == nz[0] % nclass)
+        assert np.allclose(np.abs(v[nz]), 1.0 / np.sqrt(pi[nz[0] % nclass]))
+        assert nz.shape[0] == np.count_nonzero(np.arange(naux) % nclass == nz[0] % nclass)

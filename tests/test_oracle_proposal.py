@@ -102,3 +102,42 @@ def test_importance_variance_gain_by_enumeration():
     vt, mt = variance(pt)
     assert abs(mu_ - mt) < 1e-10 * abs(mu_)         # both unbiased for the same value
     assert vt < vu
+
+
+def test_stratified_variance_gain_by_enumeration():
+    """Stratified vectors with class weights from the targets (pi_c summed over
+    the class members' t_Q) against equal class weights: both unbiased for the
+    same value, the targeted ones with lower variance (exact, enumerating
+    every class and sign state of both vectors)."""
+    import itertools
+    b, bt, spl, g, gb, w, tab = _tiny_tables()
+    t = pr.targets_from_tables(tab)
+    naux, nclass = b.shape[0], 6
+
+    def states(pi):
+        th, prob = [], []
+        for c in range(nclass):
+            mem = np.arange(naux)[np.arange(naux) % nclass == c]
+            for sg in itertools.product([1.0, -1.0], repeat=mem.shape[0]):
+                v = np.zeros(naux)
+                v[mem] = np.array(sg) / np.sqrt(pi[c])
+                th.append(v)
+                prob.append(pi[c] / 2.0 ** mem.shape[0])
+        return np.array(th), np.array(prob)
+
+    def moments(pi):
+        th, prob = states(pi)
+        _, rl, rs = sp.r_vectors(b, spl, th)
+        m1 = m2 = 0.0
+        for a in range(th.shape[0]):
+            for c in range(th.shape[0]):
+                e = sum(w[k] * energy.trace_product(se.sigma_pair(spl, rl[a], rs[a], rl[c], rs[c], g[k], gb[k]), gb[k])
+                        for k in range(len(w)))
+                m1 += prob[a] * prob[c] * e
+                m2 += prob[a] * prob[c] * e * e
+        return m1, m2 - m1 * m1
+
+    mu_u, var_u = moments(np.full(nclass, 1.0 / nclass))
+    mu_t, var_t = moments(pr.class_probabilities(t / t.sum(), nclass))
+    assert abs(mu_u - mu_t) < 1e-10 * abs(mu_u)
+    assert var_t < var_u
