@@ -111,21 +111,76 @@ class Problem:
         spl.free()
         return e, se
 
-    def time_to_target(self, prec, target, batch=16, max_pairs=4096, p=None):
+    def time_to_target(self, prec, target, batch=16, max_pairs=4096, mlp=None, classes=0):
         """Set-up plus adaptive sampling (pairs in batches) until the standard
         error of the total E_corr is below `target` (Eh), in the library's
-        adaptive call.  Returns (seconds, info)."""
+        adaptive call.  With a trained network (mlp), its class weights for
+        stratified vectors are inferred inside the timed region (features,
+        inference).  Returns (seconds, info)."""
         import torch
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         B, spl, G, Gb, det = self.setup()
         ctx, wl = self.ctx, self.wl
+        p = None
+        if mlp is not None:
+            p = torch.empty(wl.naux, dtype=torch.float64, device="cuda")
+            ctx.proposal_infer(mlp, self.features(spl, B), PROPOSAL_ALPHA, p, bf16=True)
+            p = p.cpu().numpy()
         _, _, info = ctx.energy_adaptive(spl, B, G, Gb, self.w, det, wl.n_elec, target, batch=batch,
-                                         max_pairs=max_pairs, seed=wl.seed, prec=prec, p=p)
+                                         max_pairs=max_pairs, seed=wl.seed, prec=prec, p=p, classes=classes)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         spl.free()
         return t1 - t0, info
+
+    def features(self, spl, B):
+        """Per-Q features of this chain (centre, ||B^Q||, local density)."""
+        import torch
+        from paper_2005_12338_amd import gf2
+        ctx, wl, geo = self.ctx, self.wl, self.geo
+        _, Gb0, _ = ctx.green_tau(self.F, np.array([0.0]), wl.beta, n_occ=wl.n_occ)
+        phi = torch.empty((wl.naux, 4), dtype=torch.float64, device="cuda")
+        ctx.proposal_features(spl, B, geo.x, geo.xq, Gb0[0].contiguous(), phi)
+        return phi
+
+
+PROPOSAL_ALPHA = 0.05     # floor: every Q keeps at least alpha / N_aux of the weight
+PROPOSAL_CLASSES = 12     # stratified classes Q mod K
+
+
+def train_proposal(ctx, eps, beta, steps=2000, ntau=16):
+    """Train the network on the per-Q targets of the small training chains
+    (10..48 dimers) with the library's training kernels.  Returns
+    (mlp, seconds, first loss, last loss)."""
+    import torch
+    import chain_inputs as ci
+    from paper_2005_12338_amd import gf2
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phis, ts, off = [], [], [0]
+    for nd in ci.training_dimer_counts():
+        geo = ci.chain_geometry(nd)
+        f = ci.fock_tight_binding(geo.x)
+        B = ctx.build_B(geo.n, geo.naux, geom=geo, dtype=torch.float32)
+        spl = ctx.split(B, eps)
+        tau, w = gf2.gf2_tau_grid(beta, ntau)
+        G, Gb, _ = ctx.green_tau(f, tau, beta, n_occ=geo.n // 2)
+        _, Gb0, _ = ctx.green_tau(f, np.array([0.0]), beta, n_occ=geo.n // 2)
+        phi = torch.empty((geo.naux, 4), dtype=torch.float64, device="cuda")
+        ctx.proposal_features(spl, B, geo.x, geo.xq, Gb0[0].contiguous(), phi)
+        t = torch.empty(geo.naux, dtype=torch.float64, device="cuda")
+        ctx.proposal_targets(spl, B, G, Gb, w, 1e-10, t)
+        phis.append(phi)
+        ts.append(t / t.sum())
+        off.append(off[-1] + geo.naux)
+        spl.free()
+    m = ctx.mlp()
+    phi_all, t_all = torch.cat(phis).contiguous(), torch.cat(ts).contiguous()
+    ctx.proposal_init(m, phi_all, seed=0)
+    hist = ctx.proposal_train(m, np.array(off), phi_all, t_all, steps=steps, lr=1e-2)
+    torch.cuda.synchronize()
+    return m, time.perf_counter() - t0, float(hist[0]), float(hist[-1])
 
 
 def batch_bench(args):
@@ -264,6 +319,8 @@ def main():
     ap.add_argument("--prec", default="bf16", choices=["bf16", "bf16x3", "fp32", "fp64"])
     ap.add_argument("--ns", type=int, default=0, help="pairs per step (default: the workload's)")
     ap.add_argument("--target-meh", type=float, default=1.0)
+    ap.add_argument("--tight-target-ueh", type=float, default=0.5,
+                    help="second target (micro-Eh) for the learned-proposal comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-target", action="store_true", help="skip the time-to-target runs")
     ap.add_argument("--profile", action="store_true", help="print the per-kernel breakdown")
@@ -356,6 +413,23 @@ def main():
             tt[name + "_uniform"] = dict(s=t_s, **info)
         out["value"] = tt["auto_uniform"]["s"]
         tt["speedup_vs_plain_fp32"] = tt["fp32_uniform"]["s"] / out["value"]
+        # the learned proposal: class weights of stratified vectors from the
+        # network trained on the small chains (training is a one-off cost,
+        # reported on its own), against +-1 vectors, at this target and at
+        # a tight one where the number of pairs matters
+        mlp, t_train, l0, l1 = train_proposal(ctx, wl.eps, wl.beta)
+        log(f"[bench] proposal network trained in {t_train:.2f} s (loss {l0:.4f} -> {l1:.4f})")
+        learned = {"train_s": t_train, "loss_first": l0, "loss_last": l1, "classes": PROPOSAL_CLASSES}
+        for tgt in (target, args.tight_target_ueh * 1e-6):
+            row = {}
+            for name, kw in (("uniform_pm1", {}), ("learned_stratified", dict(mlp=mlp, classes=PROPOSAL_CLASSES))):
+                pb.time_to_target("auto", tgt, **kw)
+                t_s, info = pb.time_to_target("auto", tgt, **kw)
+                log(f"[bench] time to {tgt * 1e3:.4g} mEh (auto, {name}): {t_s:.3f} s, {info['pairs']} pairs, "
+                    f"stderr={info['stderr']:.3e}")
+                row[name] = dict(s=t_s, **info)
+            learned[f"target_{tgt * 1e3:.4g}_mEh"] = row
+        tt["learned"] = learned
         out["time_to_target"] = tt
         pairs_for_cpu = tt["auto_uniform"]["pairs"]
     else:

@@ -196,7 +196,10 @@ gf2_status gf2_sigma_tau(gf2_ctx* ctx, const gf2_split_h* split, const void* B,
                          double* Sigma, double* e_samples);
 
 /* The two halves of gf2_sigma_tau, for adaptive or batched sampling:
- * gf2_sigma_det writes Sigma[D,D] (device [ntau][n][n] FP64);
+ * gf2_sigma_det writes Sigma[D,D] (device [ntau][n][n] FP64); G and Gbar
+ * must be symmetric (as gf2_green_tau returns them for a real symmetric
+ * Fock matrix): Sigma[D,D] is then symmetric, and supports of at most 8
+ * orbitals form its upper triangle and mirror it;
  * gf2_sigma_stoch ADDS sum_s Sigma_s (unsymmetrised, FP64) into Sigma_sum
  * (device [ntau][n][n]; zero it before the first batch) and writes
  * e_samples [ns][ntau] for pairs s0 .. s0+ns-1; gf2_sigma_finalize writes

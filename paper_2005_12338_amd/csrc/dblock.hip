@@ -121,6 +121,11 @@ __global__ __launch_bounds__(64 * NW) void k_dblock(const double* G, const doubl
 // and writes C to LDS; the chunk's contributions are then added to the
 // strip column by column in increasing Q' (fixed order).  A second kernel
 // sums the strips of every (Q, a) with S_Q(a) = i into row i of Sigma.
+//
+// With G and Gb symmetric, C_Q'Q = C_QQ'^T and Sigma[D,D] is symmetric, so
+// only its upper triangle is formed: strip Q keeps the columns j >= min S_Q,
+// and a pair whose S_Q' lies wholly below min S_Q (it touches no such
+// column) is skipped, about half of all pairs.  The gather mirrors the rest.
 // ---------------------------------------------------------------------------
 template <int W, int CH>
 __global__ __launch_bounds__(256) void k_dd_strip(const double* G, const double* Gb, int64_t n,
@@ -150,13 +155,16 @@ __global__ __launch_bounds__(256) void k_dd_strip(const double* G, const double*
   __syncthreads();
   if (w1 == 0) return;
 
+  const int qlo = sq[0];                    // lowest orbital of S_Q
   for (int64_t c0 = 0; c0 < naux; c0 += CH) {
     const int64_t r = c0 + tid;
-    const bool act = tid < CH && r < naux;
+    // pairs whose S_Q' lies wholly below S_Q feed only the lower triangle
+    const int w2r = (tid < CH && r < naux) ? wq[r] : 0;
+    const bool act = w2r > 0 && idx[r * kWMax + w2r - 1] >= qlo;
     if (tid == 0) { span[0] = (int32_t)n; span[1] = -1; }
     __syncthreads();
     if (act) {
-      const int w2 = wq[r];
+      const int w2 = w2r;
       const int32_t* s2 = idx + r * kWMax;
       int sr[W];
 #pragma unroll
@@ -230,8 +238,9 @@ __global__ __launch_bounds__(256) void k_dd_strip(const double* G, const double*
     }
     __syncthreads();
     // add the chunk to the strip: output (a, j), contributions from the
-    // chunk's Q' with S_Q'(d) = j in increasing Q'
-    const int jlo = span[0], jhi = span[1];
+    // chunk's Q' with S_Q'(d) = j in increasing Q'; only columns j >= qlo
+    // (the upper triangle of every row of S_Q) are kept
+    const int jlo = max(span[0], qlo), jhi = span[1];
     const int64_t nout = (jhi >= jlo) ? (int64_t)w1 * (jhi - jlo + 1) : 0;
     for (int64_t e = tid; e < nout; e += blockDim.x) {
       const int a = (int)(e % w1);
@@ -294,12 +303,15 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
   __syncthreads();
   if (w1 == 0) return;
 
+  const int qlo = sq[0];                    // lowest orbital of S_Q
   for (int64_t c0 = 0; c0 < naux; c0 += CH) {
     const int64_t r = c0 + tid;
-    const bool act = r < naux;
+    // pairs whose S_Q' lies wholly below S_Q feed only the lower triangle
+    const int w2r = r < naux ? wq[r] : 0;
+    const bool act = w2r > 0 && idx[r * kWMax + w2r - 1] >= qlo;
     if (tid == 0) { span[0] = (int32_t)n; span[1] = -1; }
     __syncthreads();
-    const int w2 = act ? wq[r] : 0;
+    const int w2 = act ? w2r : 0;
     const int32_t* s2 = idx + (act ? r : 0) * kWMax;
     int sr[W];
 #pragma unroll
@@ -310,6 +322,10 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
     }
     __syncthreads();
     const int jlo = span[0], jhi = span[1];
+    if (jhi < jlo) {                          // no pair of this chunk is needed
+      __syncthreads();                        // span is reset only after every lane read it
+      continue;
+    }
     const int width = jhi - jlo + 1;          // <= kDdSpan (checked on the host)
     for (int e = tid; e < W * width; e += CH) {
       const int a = e / width, jj = e % width;
@@ -374,10 +390,12 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
         }
     }
     __syncthreads();
-    const int64_t nout = (jhi >= jlo) ? (int64_t)w1 * width : 0;
+    // columns j >= qlo only (the upper triangle of every row of S_Q)
+    const int jl = max(jlo, qlo);
+    const int64_t nout = (jhi >= jl) ? (int64_t)w1 * (jhi - jl + 1) : 0;
     for (int64_t e = tid; e < nout; e += CH) {
       const int a = (int)(e % w1);
-      const int j = jlo + (int)(e / w1);
+      const int j = jl + (int)(e / w1);
       int lo = col_off[j], hi = col_off[j + 1];
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -395,18 +413,21 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
   }
 }
 
-// Sigma[t][i][j] = sum over (Q, a) with S_Q(a) = i of strip[t][Q][a][j].
+// Sigma[t][i][j] = sum over (Q, a) with S_Q(a) = i of strip[t][Q][a][j] for
+// j >= i; the strips hold only the upper triangle, and Sigma[D,D] is
+// symmetric, so an element below the diagonal takes its mirror's value.
 template <int W>
 __global__ void k_dd_gather(const double* strip, int64_t n, int64_t naux, int32_t tau0, int32_t ntb,
                             const int32_t* col_off, const int32_t* col_q, double* out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)ntb * n * n) return;
   const int64_t tb = e / (n * n), ij = e % (n * n), i = ij / n, j = ij % n;
+  const int64_t ru = i < j ? i : j, cu = i < j ? j : i;
   double acc = 0.0;
-  for (int k = col_off[i]; k < col_off[i + 1]; ++k) {
+  for (int k = col_off[ru]; k < col_off[ru + 1]; ++k) {
     const int64_t q = col_q[k] >> 5;
     const int a = col_q[k] & 31;
-    acc += strip[((tb * naux + q) * W + a) * n + j];
+    acc += strip[((tb * naux + q) * W + a) * n + cu];
   }
   out[((tau0 + tb) * n + i) * n + j] = acc;
 }
