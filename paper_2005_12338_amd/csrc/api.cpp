@@ -382,6 +382,16 @@ gf2_status gf2_split(gf2_ctx* ctx, const void* B, gf2_dtype dtype, int64_t n, in
       }
       ooff[n] = (int32_t)oq.size();
     }
+    // chunk starts of every orbital's list, at a granularity of 64 Q
+    const int32_t ncs = (int32_t)((naux + 63) / 64 + 1);
+    std::vector<int32_t> ocs((size_t)(n * ncs));
+    for (int64_t i = 0; i < n; ++i) {
+      int32_t k = ooff[i];
+      for (int32_t c = 0; c < ncs; ++c) {
+        while (k < ooff[i + 1] && (oq[k] >> 5) < 64 * c) ++k;
+        ocs[(size_t)(i * ncs + c)] = k;
+      }
+    }
     auto alloc = [&](void** p, size_t bytes) {
       if (bytes == 0) bytes = 16;
       hipError_t e = hipMalloc(p, bytes);
@@ -398,6 +408,9 @@ gf2_status gf2_split(gf2_ctx* ctx, const void* B, gf2_dtype dtype, int64_t n, in
     alloc((void**)&h->row_q, tq.size() * 4);
     alloc((void**)&h->orb_off, ooff.size() * 4);
     alloc((void**)&h->orb_q, oq.size() * 4);
+    alloc((void**)&h->orb_cs, ocs.size() * 4);
+    h->orb_ncs = ncs;
+    h2d(ctx, h->orb_cs, ocs.data(), ocs.size());
     h2d(ctx, h->orb_off, ooff.data(), ooff.size());
     if (!oq.empty()) h2d(ctx, h->orb_q, oq.data(), oq.size());
     h2d(ctx, h->w, w.data(), w.size());
@@ -424,7 +437,7 @@ gf2_status gf2_split(gf2_ctx* ctx, const void* B, gf2_dtype dtype, int64_t n, in
 void gf2_split_free(gf2_split_h* h) {
   if (!h) return;
   void* ps[] = {h->w, h->idx, h->blk, h->blk32, h->pat_ij, h->pat_off, h->pat_q, h->row_off, h->row_q,
-                h->orb_off, h->orb_q};
+                h->orb_off, h->orb_q, h->orb_cs};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   delete h;
@@ -554,7 +567,7 @@ void run_dd(gf2_ctx* ctx, const gf2_split_h* sp, const double* G, const double* 
     const int64_t tb = std::max<int64_t>(1, std::min<int64_t>(ntau, (int64_t)2e9 / std::max<int64_t>(per, 1)));
     auto* strip = (double*)ctx_buf(ctx, "dd_strip", (size_t)(per * tb));
     launch_dd_strips(G, Gb, sp->n, sp->naux, ntau, sp->wmax, sp->span128, sp->w, sp->idx, sp->blk, sp->orb_off, sp->orb_q,
-                     strip, tb, out, ctx->stream);
+                     sp->orb_cs, sp->orb_ncs, strip, tb, out, ctx->stream);
   } else {
     launch_dblock(G, Gb, sp->n, ntau, sp->wmax, sp->w, sp->idx, sp->blk, sp->row_off, sp->row_q, out,
                   ctx->stream);

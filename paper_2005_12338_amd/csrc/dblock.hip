@@ -111,6 +111,31 @@ __global__ __launch_bounds__(64 * NW) void k_dblock(const double* G, const doubl
   }
 }
 
+// Add one chunk's blocks C_QQ' (cbuf, one W x W block per Q' of the chunk) to
+// column j of the strip: every row a of S_Q at once, contributions in
+// increasing Q' (the entries of column j with Q' in [c0, c0 + CH)).  One
+// lane per column, so the strip is read and written along contiguous j.
+template <int W, int CH>
+__device__ __forceinline__ void add_column(const double* cbuf, const int32_t* col_q, const int32_t* col_cs,
+                                           int32_t ncs, int64_t c0, int j, int w1, int64_t n, double* st) {
+  const int32_t* cs = col_cs + (int64_t)j * ncs;
+  const int c64 = (int)(c0 >> 6);
+  const int lo = cs[c64], hi = cs[min(c64 + CH / 64, ncs - 1)];
+  double acc[W];
+#pragma unroll
+  for (int a = 0; a < W; ++a) acc[a] = 0.0;
+  for (int k = lo; k < hi; ++k) {
+    const int32_t cq = col_q[k];
+    const double* cb = cbuf + ((cq >> 5) - c0) * W * W + (cq & 31);
+#pragma unroll
+    for (int a = 0; a < W; ++a)
+      if (a < w1) acc[a] += cb[a * W];
+  }
+#pragma unroll
+  for (int a = 0; a < W; ++a)
+    if (a < w1) st[(int64_t)a * n + j] += acc[a];
+}
+
 // ---------------------------------------------------------------------------
 // Register form for supports of at most W orbitals.  One workgroup per
 // (tau, Q) builds the strip P_Q[a][j] = sum_Q' sum_d [S_Q'(d) = j] C_QQ'[a][d]
@@ -131,8 +156,8 @@ template <int W, int CH>
 __global__ __launch_bounds__(256) void k_dd_strip(const double* G, const double* Gb, int64_t n,
                                                   int64_t naux, int32_t tau0, const int32_t* wq,
                                                   const int32_t* idx, const double* blk,
-                                                  const int32_t* col_off, const int32_t* col_q,
-                                                  double* strip) {
+                                                  const int32_t* col_q, const int32_t* col_cs,
+                                                  int32_t ncs, double* strip) {
   __shared__ double cbuf[CH * W * W];
   __shared__ double kq[W * W];
   __shared__ int32_t span[2];
@@ -241,24 +266,7 @@ __global__ __launch_bounds__(256) void k_dd_strip(const double* G, const double*
     // chunk's Q' with S_Q'(d) = j in increasing Q'; only columns j >= qlo
     // (the upper triangle of every row of S_Q) are kept
     const int jlo = max(span[0], qlo), jhi = span[1];
-    const int64_t nout = (jhi >= jlo) ? (int64_t)w1 * (jhi - jlo + 1) : 0;
-    for (int64_t e = tid; e < nout; e += blockDim.x) {
-      const int a = (int)(e % w1);
-      const int j = jlo + (int)(e / w1);
-      int lo = col_off[j], hi = col_off[j + 1];
-      // first entry with Q' >= c0 (entries sorted by Q')
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((col_q[mid] >> 5) < c0) lo = mid + 1; else hi = mid;
-      }
-      double acc = 0.0;
-      for (int k = lo; k < col_off[j + 1]; ++k) {
-        const int64_t rr = col_q[k] >> 5;
-        if (rr >= c0 + CH) break;
-        acc += cbuf[(rr - c0) * W * W + a * W + (col_q[k] & 31)];
-      }
-      st[(int64_t)a * n + j] += acc;
-    }
+    for (int j = jlo + tid; j <= jhi; j += blockDim.x) add_column<W, CH>(cbuf, col_q, col_cs, ncs, c0, j, w1, n, st);
     __syncthreads();
   }
 }
@@ -277,8 +285,8 @@ __global__ __launch_bounds__(256) void k_dd_strip(const double* G, const double*
 template <int W, int CH>
 __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* Gb, int64_t n, int64_t naux,
                                                 int32_t tau0, const int32_t* wq, const int32_t* idx,
-                                                const double* blk, const int32_t* col_off,
-                                                const int32_t* col_q, double* strip) {
+                                                const double* blk, const int32_t* col_q,
+                                                const int32_t* col_cs, int32_t ncs, double* strip) {
   __shared__ double cbuf[CH * W * W];
   __shared__ double uq[W * kDdSpan];
   __shared__ double gq[W * kDdSpan];
@@ -392,23 +400,7 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
     __syncthreads();
     // columns j >= qlo only (the upper triangle of every row of S_Q)
     const int jl = max(jlo, qlo);
-    const int64_t nout = (jhi >= jl) ? (int64_t)w1 * (jhi - jl + 1) : 0;
-    for (int64_t e = tid; e < nout; e += CH) {
-      const int a = (int)(e % w1);
-      const int j = jl + (int)(e / w1);
-      int lo = col_off[j], hi = col_off[j + 1];
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((col_q[mid] >> 5) < c0) lo = mid + 1; else hi = mid;
-      }
-      double acc = 0.0;
-      for (int k = lo; k < col_off[j + 1]; ++k) {
-        const int64_t rr = col_q[k] >> 5;
-        if (rr >= c0 + CH) break;
-        acc += cbuf[(rr - c0) * W * W + a * W + (col_q[k] & 31)];
-      }
-      st[(int64_t)a * n + j] += acc;
-    }
+    for (int j = jl + tid; j <= jhi; j += CH) add_column<W, CH>(cbuf, col_q, col_cs, ncs, c0, j, w1, n, st);
     __syncthreads();
   }
 }
@@ -443,8 +435,8 @@ int64_t dd_strip_bytes(int64_t n, int64_t naux, int32_t wmax, int64_t ntau_batch
 
 bool launch_dd_strips(const double* G, const double* Gb, int64_t n, int64_t naux, int64_t ntau, int32_t wmax,
                       int32_t span128, const int32_t* wq, const int32_t* idx, const double* blk,
-                      const int32_t* col_off, const int32_t* col_q, double* strip, int64_t ntau_batch, double* out,
-                      hipStream_t st) {
+                      const int32_t* col_off, const int32_t* col_q, const int32_t* col_cs, int32_t ncs,
+                      double* strip, int64_t ntau_batch, double* out, hipStream_t st) {
   if (wmax > 8) return false;
   const bool rows = span128 <= kDdSpan;
   for (int64_t t0 = 0; t0 < ntau; t0 += ntau_batch) {
@@ -454,13 +446,13 @@ bool launch_dd_strips(const double* G, const double* Gb, int64_t n, int64_t naux
     if (rows) {
       if (wmax <= 4)
         hipLaunchKernelGGL((k_dd_rows<4, 128>), grid, dim3(128), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
-                           col_off, col_q, strip);
+                           col_q, col_cs, ncs, strip);
       else if (wmax <= 6)
         hipLaunchKernelGGL((k_dd_rows<6, 128>), grid, dim3(128), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
-                           col_off, col_q, strip);
+                           col_q, col_cs, ncs, strip);
       else
         hipLaunchKernelGGL((k_dd_rows<8, 64>), grid, dim3(64), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
-                           col_off, col_q, strip);
+                           col_q, col_cs, ncs, strip);
       GF2_HIP(hipGetLastError());
       const int W = wmax <= 4 ? 4 : wmax <= 6 ? 6 : 8;
       if (W == 4)
@@ -474,17 +466,17 @@ bool launch_dd_strips(const double* G, const double* Gb, int64_t n, int64_t naux
                            col_q, out);
     } else if (wmax <= 4) {
       hipLaunchKernelGGL((k_dd_strip<4, 256>), grid, dim3(256), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
-                         col_off, col_q, strip);
+                         col_q, col_cs, ncs, strip);
       hipLaunchKernelGGL((k_dd_gather<4>), dim3(gb), dim3(256), 0, st, strip, n, naux, (int32_t)t0, ntb, col_off,
                          col_q, out);
     } else if (wmax <= 6) {
       hipLaunchKernelGGL((k_dd_strip<6, 256>), grid, dim3(256), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
-                         col_off, col_q, strip);
+                         col_q, col_cs, ncs, strip);
       hipLaunchKernelGGL((k_dd_gather<6>), dim3(gb), dim3(256), 0, st, strip, n, naux, (int32_t)t0, ntb, col_off,
                          col_q, out);
     } else {
       hipLaunchKernelGGL((k_dd_strip<8, 128>), grid, dim3(256), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
-                         col_off, col_q, strip);
+                         col_q, col_cs, ncs, strip);
       hipLaunchKernelGGL((k_dd_gather<8>), dim3(gb), dim3(256), 0, st, strip, n, naux, (int32_t)t0, ntb, col_off,
                          col_q, out);
     }

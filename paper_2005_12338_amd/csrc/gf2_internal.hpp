@@ -199,6 +199,10 @@ struct gf2_split_h {
   // per orbital i: the (Q, a) with S_Q[a] = i, sorted by Q (Q << 5 | a)
   int32_t* orb_off = nullptr;  // [n + 1]
   int32_t* orb_q = nullptr;
+  // orb_cs[i * orb_ncs + c]: first entry of orbital i's list with Q >= 64 c
+  // (c = 0 .. orb_ncs - 1; the last is orb_off[i + 1])
+  int32_t* orb_cs = nullptr;
+  int32_t orb_ncs = 0;
 };
 
 constexpr int kWMax = 32;

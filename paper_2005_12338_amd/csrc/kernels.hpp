@@ -67,7 +67,8 @@ int64_t dd_strip_bytes(int64_t n, int64_t naux, int32_t wmax, int64_t ntau_batch
 bool launch_dd_strips(const double* G, const double* Gb, int64_t n, int64_t naux, int64_t ntau, int32_t wmax,
                       int32_t span128,
                       const int32_t* wq, const int32_t* idx, const double* blk, const int32_t* col_off,
-                      const int32_t* col_q, double* strip, int64_t ntau_batch, double* out, hipStream_t st);
+                      const int32_t* col_q, const int32_t* col_cs, int32_t ncs, double* strip,
+                      int64_t ntau_batch, double* out, hipStream_t st);
 
 struct gf2_mlp;
 int mlp_nparam();
