@@ -312,27 +312,61 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
   if (w1 == 0) return;
 
   const int qlo = sq[0];                    // lowest orbital of S_Q
+  // Every dependent global round trip of a chunk costs a memory latency, so
+  // the loads whose addresses are known early are issued early: the next
+  // chunk's supports during this chunk, and the column entries of the
+  // accumulation before the pair products.
+  int w2n;
+  int srn[W];
+  auto load_meta = [&](int64_t cc) {
+    const int64_t rr = cc + tid;
+    w2n = rr < naux ? wq[rr] : 0;
+#pragma unroll
+    for (int c = 0; c < W; ++c) srn[c] = rr < naux ? idx[rr * kWMax + c] : -1;
+  };
+  load_meta(0);
+  constexpr int NJ = kDdSpan / CH;          // strip columns per lane and chunk
+  constexpr int NPRE = 8;                   // column entries fetched ahead
   for (int64_t c0 = 0; c0 < naux; c0 += CH) {
     const int64_t r = c0 + tid;
+    const int w2r = w2n;
+    int sr[W];
+    int hi2 = -1;                             // last orbital of S_Q' (ascending)
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      sr[c] = srn[c];
+      if (c < w2r) hi2 = sr[c];
+    }
     // pairs whose S_Q' lies wholly below S_Q feed only the lower triangle
-    const int w2r = r < naux ? wq[r] : 0;
-    const bool act = w2r > 0 && idx[r * kWMax + w2r - 1] >= qlo;
+    const bool act = w2r > 0 && hi2 >= qlo;
+    const int w2 = act ? w2r : 0;
     if (tid == 0) { span[0] = (int32_t)n; span[1] = -1; }
     __syncthreads();
-    const int w2 = act ? w2r : 0;
-    const int32_t* s2 = idx + (act ? r : 0) * kWMax;
-    int sr[W];
-#pragma unroll
-    for (int c = 0; c < W; ++c) sr[c] = c < w2 ? s2[c] : 0;
     if (w2 > 0) {
       atomicMin(&span[0], sr[0]);
-      atomicMax(&span[1], sr[w2 - 1]);
+      atomicMax(&span[1], hi2);
     }
+    if (c0 + CH < naux) load_meta(c0 + CH);
     __syncthreads();
     const int jlo = span[0], jhi = span[1];
     if (jhi < jlo) {                          // no pair of this chunk is needed
       __syncthreads();                        // span is reset only after every lane read it
       continue;
+    }
+    // accumulation operands of this lane's strip columns j >= qlo (the upper
+    // triangle of every row of S_Q): entry range of column j for this chunk
+    const int jl = max(jlo, qlo);
+    const int c64 = (int)(c0 >> 6);
+    int klo[NJ], khi[NJ];
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      const int j = jl + tid + u * CH;
+      klo[u] = khi[u] = 0;
+      if (j <= jhi) {
+        const int32_t* cs = col_cs + (int64_t)j * ncs;
+        klo[u] = cs[c64];
+        khi[u] = cs[min(c64 + CH / 64, ncs - 1)];
+      }
     }
     const int width = jhi - jlo + 1;          // <= kDdSpan (checked on the host)
     for (int e = tid; e < W * width; e += CH) {
@@ -398,9 +432,37 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
         }
     }
     __syncthreads();
-    // columns j >= qlo only (the upper triangle of every row of S_Q)
-    const int jl = max(jlo, qlo);
-    for (int j = jl + tid; j <= jhi; j += CH) add_column<W, CH>(cbuf, col_q, col_cs, ncs, c0, j, w1, n, st);
+    // add the chunk to the strip: output (a, j), contributions from the
+    // chunk's Q' with S_Q'(d) = j in increasing Q'
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      const int j = jl + tid + u * CH;
+      if (j > jhi) continue;
+      int cq[NPRE];
+#pragma unroll
+      for (int x = 0; x < NPRE; ++x) cq[x] = klo[u] + x < khi[u] ? col_q[klo[u] + x] : 0;
+      double acc[W];
+#pragma unroll
+      for (int a = 0; a < W; ++a) acc[a] = 0.0;
+#pragma unroll
+      for (int x = 0; x < NPRE; ++x) {
+        if (klo[u] + x >= khi[u]) break;
+        const double* cb = cbuf + ((cq[x] >> 5) - c0) * W * W + (cq[x] & 31);
+#pragma unroll
+        for (int a = 0; a < W; ++a)
+          if (a < w1) acc[a] += cb[a * W];
+      }
+      for (int k = klo[u] + NPRE; k < khi[u]; ++k) {
+        const int32_t c = col_q[k];
+        const double* cb = cbuf + ((c >> 5) - c0) * W * W + (c & 31);
+#pragma unroll
+        for (int a = 0; a < W; ++a)
+          if (a < w1) acc[a] += cb[a * W];
+      }
+#pragma unroll
+      for (int a = 0; a < W; ++a)
+        if (a < w1) st[(int64_t)a * n + j] += acc[a];
+    }
     __syncthreads();
   }
 }
