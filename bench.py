@@ -111,7 +111,7 @@ class Problem:
         spl.free()
         return e, se
 
-    def time_to_target(self, prec, target, batch=16, max_pairs=4096, mlp=None, classes=0):
+    def time_to_target(self, prec, target, batch=8, max_pairs=4096, mlp=None, classes=0):
         """Set-up plus adaptive sampling (pairs in batches) until the standard
         error of the total E_corr is below `target` (Eh), in the library's
         adaptive call.  With a trained network (mlp), its class weights for

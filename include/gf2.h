@@ -288,7 +288,11 @@ gf2_status gf2_sigma_batch(gf2_ctx* ctx, int32_t nitem, const gf2_batch_item* it
  * results section: statistical error of the total E_corr of eq:corr).
  * Pairs are drawn in batches of sampling->ns (sampling->s0 is ignored; pair
  * indices run 0, 1, ...) until the standard error of the total E_corr is
- * below `target` (Eh) or `max_pairs` is reached; at least two pairs.
+ * below `target` (Eh) with 95% confidence, or `max_pairs` is reached; at
+ * least two pairs.  The stopping test uses the one-sided 95% upper bound of
+ * the standard error estimated from the pairs so far (chi-square with
+ * pairs - 1 degrees of freedom; 1.80x the estimate at 8 pairs, 1.26x at 32),
+ * so a small first batch cannot stop on a lucky low estimate.
  *
  * prec GF2_PREC_AUTO: the batches run in BF16.  Pairs 0 and 1 are also
  * evaluated in BF16X3; the largest differences of their energies,

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <limits>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -1293,6 +1294,22 @@ gf2_status gf2_sigma_batch(gf2_ctx* ctx, int32_t nitem, const gf2_batch_item* it
 }
 
 // ------------------------------------------------------------ adaptive ----
+namespace {
+// One-sided 95% upper confidence bound of a standard error estimated from
+// `pairs` samples: se * sqrt(k / chi2_{0.05}(k)), k = pairs - 1, with the
+// chi-square quantile from the Wilson-Hilferty cube-root normal
+// approximation (Wilson & Hilferty 1931): chi2_p(k) = k (1 - 2/(9k) +
+// z_p sqrt(2/(9k)))^3, z_0.05 = -1.6448536.  At k = 7 it is 2.15 (tables:
+// 2.17), so the bound is 1.80 se.
+double stderr_upper(double se, int64_t pairs) {
+  const double k = (double)(pairs - 1);
+  const double a = 2.0 / (9.0 * k);
+  const double c = 1.0 - a - 1.6448536269514722 * std::sqrt(a);
+  if (c <= 0.0) return std::numeric_limits<double>::infinity();   // too few samples for a bound
+  return se * std::sqrt(k / (k * c * c * c));
+}
+}  // namespace
+
 gf2_status gf2_energy_adaptive(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const double* G,
                                const double* Gbar, int64_t ntau, const double* w, const double* Sigma_det,
                                double n_elec, const gf2_sampling* sampling, gf2_precision prec, double target,
@@ -1390,7 +1407,7 @@ gf2_status gf2_energy_adaptive(gf2_ctx* ctx, const gf2_split_h* split, const voi
       }
       if (pairs < 2) continue;
       stat(pairs, h);
-      bool done = h[2] < target || pairs >= max_pairs;
+      bool done = stderr_upper(h[2], pairs) < target || pairs >= max_pairs;
       if (done && autop && wp == Prec::BF16 && !bf16_ok(pairs, h[2])) {
         // BF16 rounding is not negligible at this error: redo every pair in
         // BF16X3 (same theta) and go on sampling in BF16X3
@@ -1398,7 +1415,7 @@ gf2_status gf2_energy_adaptive(gf2_ctx* ctx, const gf2_split_h* split, const voi
         GF2_HIP(hipMemsetAsync(sum, 0, mat * 8, ctx->stream));
         for (int64_t s0 = 0; s0 < pairs; s0 += batch) run(s0, std::min(batch, pairs - s0), wp);
         stat(pairs, h);
-        done = h[2] < target || pairs >= max_pairs;
+        done = stderr_upper(h[2], pairs) < target || pairs >= max_pairs;
       }
       if (done) break;
     }

@@ -1,0 +1,78 @@
+"""The adaptive entry point (gf2_energy_adaptive): its stopping rule, and its
+result against one call over the same pairs.
+
+The rule stops at the first batch boundary where the one-sided 95% upper
+confidence bound of the standard error of the total E_corr is below the
+target.  The bound is checked here with the exact chi-square quantile
+(scipy), against which the library's closed-form approximation is
+conservative (larger)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import energy, green
+
+from _problems import chain, rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2005_12338_amd import gf2
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = gf2.Context(0)
+    yield c
+    c.close()
+
+
+def _setup(ctx, dtype=torch.float64):
+    pb = chain(12, 50.0, 6, 1e-2)
+    geo = pb["geo"]
+    B = ctx.build_B(geo.n, geo.naux, geom=geo, dtype=dtype)
+    tau, w = green.tau_grid(pb["beta"], pb["ntau"])
+    G, Gb, _ = ctx.green_tau(pb["f"], tau, pb["beta"], n_occ=geo.n // 2)
+    spl = ctx.split(B, pb["eps"])
+    det = ctx.sigma_det(spl, G, Gb)
+    return pb, geo, B, spl, G, Gb, w, det
+
+
+def _upper_exact(se, n):
+    from scipy.stats import chi2
+    k = n - 1
+    return se * math.sqrt(k / chi2.ppf(0.05, k))
+
+
+def test_adaptive_stops_at_the_first_confident_batch(ctx):
+    pb, geo, B, spl, G, Gb, w, det = _setup(ctx)
+    batch, max_pairs = 4, 128
+    # per-pair spread from a pilot run, then a target that needs many batches
+    _, es0 = ctx.sigma_tau(spl, B, G, Gb, ns=64, seed=0, prec="fp64")
+    e_det = np.array([float((det[t] * Gb[t]).sum()) for t in range(pb["ntau"])])
+    sig = np.std(energy.sample_energies(e_det, es0.cpu().numpy(), w), ddof=1)
+    target = sig / math.sqrt(24.0)
+    Sigma, es, info = ctx.energy_adaptive(spl, B, G, Gb, w, det, geo.n, target, batch=batch,
+                                          max_pairs=max_pairs, prec="fp64")
+    pairs = info["pairs"]
+    assert pairs % batch == 0 and 24 < pairs < max_pairs
+    tot = energy.sample_energies(e_det, es.cpu().numpy(), w)
+    m, se = energy.mean_stderr(tot)
+    assert abs(info["E"] - m) < 1e-12 * abs(m)
+    assert abs(info["stderr"] - se) < 1e-10 * se
+    assert _upper_exact(se, pairs) < target                      # stopped below the target ...
+    _, se_prev = energy.mean_stderr(tot[:pairs - batch])
+    assert _upper_exact(se_prev, pairs - batch) > 0.97 * target  # ... and not a batch later than needed
+    # the same pairs in one call: same Sigma and samples
+    S1, es1 = ctx.sigma_tau(spl, B, G, Gb, ns=pairs, seed=0, prec="fp64")
+    assert rel(es.cpu().numpy(), es1.cpu().numpy()) < 1e-12
+    assert rel(Sigma.cpu().numpy(), S1.cpu().numpy()) < 1e-12
+
+
+def test_adaptive_reaches_max_pairs_when_the_target_is_out_of_reach(ctx):
+    pb, geo, B, spl, G, Gb, w, det = _setup(ctx)
+    _, es, info = ctx.energy_adaptive(spl, B, G, Gb, w, det, geo.n, 1e-30, batch=3, max_pairs=10,
+                                      prec="fp64")
+    assert info["pairs"] == 10 and es.shape[0] == 10
