@@ -84,8 +84,8 @@ class Problem:
         log(f"[bench]     {name:10s} {1e3 * (t1 - t0):8.1f} ms")
         return t1
 
-    def setup(self):
-        """B, split, G(tau) and the deterministic block."""
+    def setup(self, with_det=True):
+        """B, split, G(tau) and (with_det) the deterministic block."""
         import torch
         ctx, wl, geo = self.ctx, self.wl, self.geo
         t = self._mark("start", time.perf_counter()) if self.phase_log else 0.0
@@ -95,6 +95,8 @@ class Problem:
         t = self._mark("split", t)
         G, Gb, mu = ctx.green_tau(self.F, self.tau, wl.beta, n_occ=wl.n_occ)
         t = self._mark("G(tau)", t)
+        if not with_det:
+            return B, spl, G, Gb
         det = ctx.sigma_det(spl, G, Gb)
         self._mark("D-block", t)
         return B, spl, G, Gb, det
@@ -120,15 +122,17 @@ class Problem:
         import torch
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        B, spl, G, Gb, det = self.setup()
+        B, spl, G, Gb = self.setup(with_det=False)
         ctx, wl = self.ctx, self.wl
         p = None
         if mlp is not None:
             p = torch.empty(wl.naux, dtype=torch.float64, device="cuda")
             ctx.proposal_infer(mlp, self.features(spl, B), PROPOSAL_ALPHA, p, bf16=True)
             p = p.cpu().numpy()
-        _, _, info = ctx.energy_adaptive(spl, B, G, Gb, self.w, det, wl.n_elec, target, batch=batch,
-                                         max_pairs=max_pairs, seed=wl.seed, prec=prec, p=p, classes=classes)
+        # the deterministic block runs inside, overlapped with the first pairs
+        _, _, _, info = ctx.energy_adaptive_det(spl, B, G, Gb, self.w, wl.n_elec, target, batch=batch,
+                                                max_pairs=max_pairs, seed=wl.seed, prec=prec, p=p,
+                                                classes=classes)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         spl.free()
@@ -181,6 +185,48 @@ def train_proposal(ctx, eps, beta, steps=2000, ntau=16):
     hist = ctx.proposal_train(m, np.array(off), phi_all, t_all, steps=steps, lr=1e-2)
     torch.cuda.synchronize()
     return m, time.perf_counter() - t0, float(hist[0]), float(hist[-1])
+
+
+def gemm_reference(args):
+    """The chain GEMM kernel alone (gf2_debug_gemm: C = A B^T, BF16 operands,
+    FP32 output) next to the vendor library (torch.bmm on hipBLASLt/rocBLAS,
+    BF16 in and out) on the same shapes: the N=800 chain shape batched as in
+    one launch, and large square products."""
+    import torch
+    from paper_2005_12338_amd import gf2
+    ctx = gf2.Context(0)
+
+    def timed(fn, it=10):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(it):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / it
+
+    rows = []
+    for n, batch in ((800, 48), (896, 48), (1024, 48), (4096, 1), (8192, 1)):
+        g = torch.Generator(device="cuda").manual_seed(n)
+        a = torch.randn(batch, n, n, device="cuda", generator=g).to(torch.bfloat16)
+        b = torch.randn(batch, n, n, device="cuda", generator=g).to(torch.bfloat16)
+        ld = (n + 31) // 32 * 32
+        ap = torch.zeros(batch, ld, ld, dtype=torch.bfloat16, device="cuda")
+        bp = torch.zeros_like(ap)
+        ap[:, :n, :n] = a
+        bp[:, :n, :n] = b
+        c = torch.zeros(batch, ld, ld, dtype=torch.float32, device="cuda")
+        flop = 2.0 * n ** 3 * batch
+        t_lib = timed(lambda: torch.bmm(a, b))
+        t_own = timed(lambda: ctx.debug_gemm("bf16", n, ap, bp, c, batch))
+        rows.append({"n": n, "batch": batch, "own_tflops": flop / t_own / 1e12, "torch_bmm_tflops": flop / t_lib / 1e12})
+        log(f"[bench] gemm n={n} batch={batch}: own {rows[-1]['own_tflops']:.1f} TFLOP/s, "
+            f"torch.bmm {rows[-1]['torch_bmm_tflops']:.1f} TFLOP/s")
+        del a, b, ap, bp, c
+    print(json.dumps({"metric": "BF16 GEMM TFLOP/s, chain kernel vs torch.bmm", "unit": "TFLOP/s",
+                      "peak": MFMA_PEAK["bf16"] / 1e12, "rows": rows}), flush=True)
+    ctx.close()
 
 
 def batch_bench(args):
@@ -318,6 +364,8 @@ def main():
     ap.add_argument("--batch-prec-bf16", action="store_true", help="run the batch in BF16 (default FP32)")
     ap.add_argument("--prec", default="bf16", choices=["bf16", "bf16x3", "fp32", "fp64"])
     ap.add_argument("--ns", type=int, default=0, help="pairs per step (default: the workload's)")
+    ap.add_argument("--gemm-reference", action="store_true",
+                    help="only compare the chain GEMM kernel with torch.bmm on the same shapes")
     ap.add_argument("--target-meh", type=float, default=1.0)
     ap.add_argument("--tight-target-ueh", type=float, default=0.5,
                     help="second target (micro-Eh) for the learned-proposal comparison")
@@ -331,6 +379,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
+    if args.gemm_reference:
+        gemm_reference(args)
+        return
     if args.workload == "batch":
         batch_bench(args)
         return

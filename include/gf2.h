@@ -326,6 +326,19 @@ gf2_status gf2_energy_adaptive(gf2_ctx* ctx, const gf2_split_h* split, const voi
                                int64_t max_pairs, double* Sigma, double* e_samples,
                                gf2_adaptive_result* res);
 
+/* gf2_energy_adaptive with the deterministic block computed inside:
+ * Sigma_det (device [ntau][n][n] FP64, output) is formed as by gf2_sigma_det
+ * on a second stream of the context while the first batch of pairs runs,
+ * and the energy statistics wait for it.  Results are those of
+ * gf2_sigma_det followed by gf2_energy_adaptive.  The call returns after
+ * both streams have finished.  Errors: as gf2_energy_adaptive. */
+gf2_status gf2_energy_adaptive_det(gf2_ctx* ctx, const gf2_split_h* split, const void* B,
+                                   const double* G, const double* Gbar, int64_t ntau,
+                                   const double* w, double n_elec, const gf2_sampling* sampling,
+                                   gf2_precision prec, double target, int64_t max_pairs,
+                                   double* Sigma_det, double* Sigma, double* e_samples,
+                                   gf2_adaptive_result* res);
+
 gf2_status gf2_debug_gemm(gf2_ctx* ctx, gf2_precision prec, int64_t n, int64_t batch,
                           const void* A, const void* Bt, void* C);
 

@@ -176,6 +176,10 @@ void gf2_destroy(gf2_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->aux) {
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+  }
   free_scratch(ctx);
   delete ctx;
 }
@@ -1310,11 +1314,31 @@ double stderr_upper(double se, int64_t pairs) {
 }
 }  // namespace
 
-gf2_status gf2_energy_adaptive(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const double* G,
-                               const double* Gbar, int64_t ntau, const double* w, const double* Sigma_det,
-                               double n_elec, const gf2_sampling* sampling, gf2_precision prec, double target,
-                               int64_t max_pairs, double* Sigma, double* e_samples, gf2_adaptive_result* res) {
-  return guarded(ctx, [&] {
+namespace {
+
+// Waits for the context's second stream when it goes out of scope, so that
+// no work of a call is left running on it after the call returns or throws.
+struct AuxJoin {
+  gf2_ctx* ctx;
+  bool on = false;
+  hipEvent_t ev = nullptr;
+  ~AuxJoin() {
+    if (on) (void)hipStreamSynchronize(ctx->aux);
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
+// The adaptive loop.  With det_out, Sigma[D,D] is computed into det_out on
+// the context's second stream while the first batch of pairs runs on the
+// main stream; the main stream waits for it before its first read (the
+// energy statistics), so the results equal gf2_sigma_det followed by the
+// plain adaptive call.
+void adaptive_core(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const double* G, const double* Gbar,
+                   int64_t ntau, const double* w, const double* Sigma_det_in, double* det_out, double n_elec,
+                   const gf2_sampling* sampling, gf2_precision prec, double target, int64_t max_pairs,
+                   double* Sigma, double* e_samples, gf2_adaptive_result* res) {
+  const double* Sigma_det = det_out ? det_out : Sigma_det_in;
+  {
     GF2_REQUIRE(split && split->owner == ctx, GF2_E_STATE, "split handle of another context");
     GF2_REQUIRE(B == split->bsrc, GF2_E_STATE, "split handle belongs to a different B");
     GF2_REQUIRE(G && Gbar && w && Sigma_det && Sigma && e_samples && res, GF2_E_ARG, "bad adaptive arguments");
@@ -1331,8 +1355,40 @@ gf2_status gf2_energy_adaptive(gf2_ctx* ctx, const gf2_split_h* split, const voi
     auto* dw = (double*)ctx_buf(ctx, "a_w", (size_t)ntau * 8);
     auto* stats = (double*)ctx_buf(ctx, "a_stats", 4 * 8);
     h2d(ctx, dw, w, (size_t)ntau);
-    launch_trace_prod(Sigma_det, Gbar, n, ntau, tr, ctx->stream);   // Tr(Sigma_det Gbar) per tau
-    GF2_HIP(hipGetLastError());
+    AuxJoin join{ctx};
+    hipEvent_t det_done = nullptr;
+    if (det_out) {
+      if (!ctx->aux) GF2_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+      hipEvent_t ready = nullptr;
+      GF2_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+      GF2_HIP(hipEventRecord(ready, ctx->stream));               // G, Gbar, split in place
+      GF2_HIP(hipStreamWaitEvent(ctx->aux, ready, 0));
+      (void)hipEventDestroy(ready);
+      join.on = true;
+      hipStream_t main = ctx->stream;
+      ctx->stream = ctx->aux;
+      try {
+        run_dd(ctx, split, G, Gbar, ntau, det_out);
+      } catch (...) {
+        ctx->stream = main;
+        throw;
+      }
+      ctx->stream = main;
+      GF2_HIP(hipEventCreateWithFlags(&join.ev, hipEventDisableTiming));
+      det_done = join.ev;
+      GF2_HIP(hipEventRecord(det_done, ctx->aux));
+    }
+    bool have_tr = false;
+    auto ensure_tr = [&] {                // Tr(Sigma_det Gbar) per tau
+      if (have_tr) return;
+      if (det_done) {
+        GF2_HIP(hipStreamWaitEvent(ctx->stream, det_done, 0));
+        det_done = nullptr;
+      }
+      launch_trace_prod(Sigma_det, Gbar, n, ntau, tr, ctx->stream);
+      GF2_HIP(hipGetLastError());
+      have_tr = true;
+    };
     gf2_sampling smp = *sampling;
     auto run = [&](int64_t s0, int64_t cnt, Prec p) {
       smp.s0 = s0;
@@ -1340,6 +1396,7 @@ gf2_status gf2_energy_adaptive(gf2_ctx* ctx, const gf2_split_h* split, const voi
       run_stoch(ctx, split, B, G, Gbar, ntau, &smp, p, sum, e_samples + s0 * ntau);
     };
     auto stat = [&](int64_t pairs, double* h) {
+      ensure_tr();
       launch_energy_stats(tr, dw, ntau, e_samples, pairs, kGM, stats, ctx->stream, true);
       GF2_HIP(hipGetLastError());
       d2h(ctx, h, stats, 3);
@@ -1368,6 +1425,7 @@ gf2_status gf2_energy_adaptive(gf2_ctx* ctx, const gf2_split_h* split, const voi
     // does too).
     auto bf16_ok = [&](int64_t pairs, double se_tot) {
       if (2.0 * bias >= 0.1 * se_tot) return false;
+      ensure_tr();
       std::vector<double> es((size_t)(pairs * ntau)), trh((size_t)ntau);
       d2h(ctx, es.data(), e_samples, es.size());
       d2h(ctx, trh.data(), tr, trh.size());
@@ -1419,6 +1477,7 @@ gf2_status gf2_energy_adaptive(gf2_ctx* ctx, const gf2_split_h* split, const voi
       }
       if (done) break;
     }
+    ensure_tr();
     launch_finalize(Sigma_det, sum, n, ntau, 0.5 / (double)pairs, Sigma, ctx->stream);
     GF2_HIP(hipGetLastError());
     check_finite(ctx, Sigma, (int64_t)mat, "Sigma");
@@ -1429,6 +1488,31 @@ gf2_status gf2_energy_adaptive(gf2_ctx* ctx, const gf2_split_h* split, const voi
     res->precision = wp == Prec::F64 ? GF2_PREC_FP64 : wp == Prec::F32 ? GF2_PREC_FP32
                      : wp == Prec::BF16 ? GF2_PREC_BF16 : GF2_PREC_BF16X3;
     res->bias_probe = bias;
+  }
+}
+
+}  // namespace
+
+gf2_status gf2_energy_adaptive(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const double* G,
+                               const double* Gbar, int64_t ntau, const double* w, const double* Sigma_det,
+                               double n_elec, const gf2_sampling* sampling, gf2_precision prec, double target,
+                               int64_t max_pairs, double* Sigma, double* e_samples, gf2_adaptive_result* res) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(Sigma_det, GF2_E_ARG, "bad adaptive arguments");
+    adaptive_core(ctx, split, B, G, Gbar, ntau, w, Sigma_det, nullptr, n_elec, sampling, prec, target, max_pairs,
+                  Sigma, e_samples, res);
+  });
+}
+
+gf2_status gf2_energy_adaptive_det(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const double* G,
+                                   const double* Gbar, int64_t ntau, const double* w, double n_elec,
+                                   const gf2_sampling* sampling, gf2_precision prec, double target,
+                                   int64_t max_pairs, double* Sigma_det, double* Sigma, double* e_samples,
+                                   gf2_adaptive_result* res) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(Sigma_det && G && Gbar && ntau > 0 && ntau <= 65535, GF2_E_ARG, "bad adaptive arguments");
+    adaptive_core(ctx, split, B, G, Gbar, ntau, w, nullptr, Sigma_det, n_elec, sampling, prec, target, max_pairs,
+                  Sigma, e_samples, res);
   });
 }
 

@@ -142,6 +142,7 @@ struct DevBuf {
 struct gf2_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t aux = nullptr;      // second stream (default priority, non-blocking), made on first use
   std::string err;
   std::vector<DevBuf> pool;       // scratch allocations owned by the context
   int64_t max_units = 0;          // chunk size tuning (0 = automatic)

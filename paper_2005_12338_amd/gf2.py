@@ -107,6 +107,10 @@ _SIGS = {
                                       C.POINTER(C.c_double), C.c_void_p, C.c_double, C.POINTER(Sampling),
                                       C.c_int, C.c_double, C.c_int64, C.c_void_p, C.c_void_p,
                                       C.POINTER(AdaptiveResult)]),
+    "gf2_energy_adaptive_det": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                          C.POINTER(C.c_double), C.c_double, C.POINTER(Sampling), C.c_int,
+                                          C.c_double, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.POINTER(AdaptiveResult)]),
     "gf2_proposal_features": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                         C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
     "gf2_proposal_targets": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
@@ -379,6 +383,27 @@ class Context:
         info = dict(E=r.e_corr, E_per_e=r.e_corr_per_e, stderr=r.stderr_tot, pairs=int(r.pairs),
                     precision=PREC_NAME[int(r.precision)], bias_probe=r.bias_probe)
         return Sigma, es[:r.pairs], info
+
+    def energy_adaptive_det(self, split: Split, B, G, Gb, w: np.ndarray, n_elec: float, target: float,
+                            batch: int = 16, max_pairs: int = 4096, seed: int = 0, prec: str = "auto", p=None,
+                            k: int = 1, classes: int = 0):
+        """energy_adaptive with Sigma[D,D] computed inside, overlapped with the
+        first batch of pairs.  Returns (Sigma, Sigma_det, e_samples[:pairs], dict)."""
+        torch = self.torch
+        ntau, n, _ = G.shape
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        det = torch.empty((ntau, n, n), dtype=torch.float64, device=self.device)
+        Sigma = torch.empty((ntau, n, n), dtype=torch.float64, device=self.device)
+        es = torch.empty((max_pairs, ntau), dtype=torch.float64, device=self.device)
+        smp, keep = self._sampling(batch, seed, 0, p, k, classes)
+        r = AdaptiveResult()
+        self._check(self.lib.gf2_energy_adaptive_det(self.h, split.handle, B.data_ptr(), G.data_ptr(),
+                                                     Gb.data_ptr(), ntau, _dp(w), float(n_elec), C.byref(smp),
+                                                     PREC[prec], float(target), int(max_pairs), det.data_ptr(),
+                                                     Sigma.data_ptr(), es.data_ptr(), C.byref(r)))
+        info = dict(E=r.e_corr, E_per_e=r.e_corr_per_e, stderr=r.stderr_tot, pairs=int(r.pairs),
+                    precision=PREC_NAME[int(r.precision)], bias_probe=r.bias_probe)
+        return Sigma, det, es[:r.pairs], info
 
     # ---------------------------------------------------------------- energy
     def energy(self, Sigma, Gb, w: np.ndarray, n_elec: float, e_samples=None):

@@ -76,3 +76,18 @@ def test_adaptive_reaches_max_pairs_when_the_target_is_out_of_reach(ctx):
     _, es, info = ctx.energy_adaptive(spl, B, G, Gb, w, det, geo.n, 1e-30, batch=3, max_pairs=10,
                                       prec="fp64")
     assert info["pairs"] == 10 and es.shape[0] == 10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "auto"])
+def test_adaptive_with_the_deterministic_block_inside_equals_the_two_calls(ctx, prec):
+    """gf2_energy_adaptive_det overlaps Sigma[D,D] (second stream) with the
+    first batch of pairs; every result equals gf2_sigma_det followed by
+    gf2_energy_adaptive, bit for bit."""
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    pb, geo, B, spl, G, Gb, w, det = _setup(ctx, dtype)
+    kw = dict(batch=4, max_pairs=12, prec=prec)
+    S_a, es_a, info_a = ctx.energy_adaptive(spl, B, G, Gb, w, det, geo.n, 1e-30, **kw)
+    S_b, det_b, es_b, info_b = ctx.energy_adaptive_det(spl, B, G, Gb, w, geo.n, 1e-30, **kw)
+    assert torch.equal(det, det_b)
+    assert torch.equal(S_a, S_b) and torch.equal(es_a, es_b)
+    assert info_a == info_b
