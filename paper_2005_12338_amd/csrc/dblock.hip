@@ -470,20 +470,47 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
 // Sigma[t][i][j] = sum over (Q, a) with S_Q(a) = i of strip[t][Q][a][j] for
 // j >= i; the strips hold only the upper triangle, and Sigma[D,D] is
 // symmetric, so an element below the diagonal takes its mirror's value.
+// One workgroup per (tau, 32 x 32 tile pair (bi, bj), bi <= bj): the upper
+// tile is summed along rows of the strips (coalesced in j) and written, and
+// its transpose goes to the mirror tile through LDS (coalesced too).
 template <int W>
-__global__ void k_dd_gather(const double* strip, int64_t n, int64_t naux, int32_t tau0, int32_t ntb,
-                            const int32_t* col_off, const int32_t* col_q, double* out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)ntb * n * n) return;
-  const int64_t tb = e / (n * n), ij = e % (n * n), i = ij / n, j = ij % n;
-  const int64_t ru = i < j ? i : j, cu = i < j ? j : i;
-  double acc = 0.0;
-  for (int k = col_off[ru]; k < col_off[ru + 1]; ++k) {
-    const int64_t q = col_q[k] >> 5;
-    const int a = col_q[k] & 31;
-    acc += strip[((tb * naux + q) * W + a) * n + cu];
+__global__ __launch_bounds__(256) void k_dd_gather(const double* strip, int64_t n, int64_t naux, int32_t tau0,
+                                                   int64_t nt, const int32_t* col_off, const int32_t* col_q,
+                                                   double* out) {
+  __shared__ double tile[32][33];
+  const int64_t bi = blockIdx.x / nt, bj = blockIdx.x % nt, tb = blockIdx.y;
+  if (bi > bj) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  double* o = out + (int64_t)(tau0 + tb) * n * n;
+  const double* sbase = strip + tb * naux * W * n;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = ty + 8 * u;
+    const int64_t i = bi * 32 + r, j = bj * 32 + tx;
+    double acc = 0.0;
+    if (i < n && j < n && j >= i) {
+      for (int k = col_off[i]; k < col_off[i + 1]; ++k) {
+        const int64_t q = col_q[k] >> 5;
+        const int a = col_q[k] & 31;
+        acc += sbase[(q * W + a) * n + j];
+      }
+    }
+    tile[r][tx] = acc;
   }
-  out[((tau0 + tb) * n + i) * n + j] = acc;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = ty + 8 * u;
+    // upper tile (bi, bj): element (i, j); on the diagonal tile the part
+    // below the diagonal is the transpose of the part above
+    const int64_t i = bi * 32 + r, j = bj * 32 + tx;
+    if (i < n && j < n) o[i * n + j] = (bi < bj || tx >= r) ? tile[r][tx] : tile[tx][r];
+    // mirror tile (bj, bi): element (bj*32 + r, bi*32 + tx) = tile[tx][r]
+    if (bi < bj) {
+      const int64_t i2 = bj * 32 + r, j2 = bi * 32 + tx;
+      if (i2 < n && j2 < n) o[i2 * n + j2] = tile[tx][r];
+    }
+  }
 }
 
 }  // namespace
@@ -504,7 +531,8 @@ bool launch_dd_strips(const double* G, const double* Gb, int64_t n, int64_t naux
   for (int64_t t0 = 0; t0 < ntau; t0 += ntau_batch) {
     const int32_t ntb = (int32_t)std::min<int64_t>(ntau_batch, ntau - t0);
     dim3 grid((unsigned)naux, (unsigned)ntb);
-    const unsigned gb = (unsigned)(((int64_t)ntb * n * n + 255) / 256);
+    const int64_t gnt = (n + 31) / 32;
+    const dim3 ggrid((unsigned)(gnt * gnt), (unsigned)ntb);
     if (rows) {
       if (wmax <= 4)
         hipLaunchKernelGGL((k_dd_rows<4, 128>), grid, dim3(128), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
@@ -518,29 +546,29 @@ bool launch_dd_strips(const double* G, const double* Gb, int64_t n, int64_t naux
       GF2_HIP(hipGetLastError());
       const int W = wmax <= 4 ? 4 : wmax <= 6 ? 6 : 8;
       if (W == 4)
-        hipLaunchKernelGGL((k_dd_gather<4>), dim3(gb), dim3(256), 0, st, strip, n, naux, (int32_t)t0, ntb, col_off,
+        hipLaunchKernelGGL((k_dd_gather<4>), ggrid, dim3(256), 0, st, strip, n, naux, (int32_t)t0, gnt, col_off,
                            col_q, out);
       else if (W == 6)
-        hipLaunchKernelGGL((k_dd_gather<6>), dim3(gb), dim3(256), 0, st, strip, n, naux, (int32_t)t0, ntb, col_off,
+        hipLaunchKernelGGL((k_dd_gather<6>), ggrid, dim3(256), 0, st, strip, n, naux, (int32_t)t0, gnt, col_off,
                            col_q, out);
       else
-        hipLaunchKernelGGL((k_dd_gather<8>), dim3(gb), dim3(256), 0, st, strip, n, naux, (int32_t)t0, ntb, col_off,
+        hipLaunchKernelGGL((k_dd_gather<8>), ggrid, dim3(256), 0, st, strip, n, naux, (int32_t)t0, gnt, col_off,
                            col_q, out);
     } else if (wmax <= 4) {
       hipLaunchKernelGGL((k_dd_strip<4, 256>), grid, dim3(256), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
                          col_q, col_cs, ncs, strip);
-      hipLaunchKernelGGL((k_dd_gather<4>), dim3(gb), dim3(256), 0, st, strip, n, naux, (int32_t)t0, ntb, col_off,
-                         col_q, out);
+      hipLaunchKernelGGL((k_dd_gather<4>), ggrid, dim3(256), 0, st, strip, n, naux, (int32_t)t0, gnt, col_off,
+                           col_q, out);
     } else if (wmax <= 6) {
       hipLaunchKernelGGL((k_dd_strip<6, 256>), grid, dim3(256), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
                          col_q, col_cs, ncs, strip);
-      hipLaunchKernelGGL((k_dd_gather<6>), dim3(gb), dim3(256), 0, st, strip, n, naux, (int32_t)t0, ntb, col_off,
-                         col_q, out);
+      hipLaunchKernelGGL((k_dd_gather<6>), ggrid, dim3(256), 0, st, strip, n, naux, (int32_t)t0, gnt, col_off,
+                           col_q, out);
     } else {
       hipLaunchKernelGGL((k_dd_strip<8, 128>), grid, dim3(256), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
                          col_q, col_cs, ncs, strip);
-      hipLaunchKernelGGL((k_dd_gather<8>), dim3(gb), dim3(256), 0, st, strip, n, naux, (int32_t)t0, ntb, col_off,
-                         col_q, out);
+      hipLaunchKernelGGL((k_dd_gather<8>), ggrid, dim3(256), 0, st, strip, n, naux, (int32_t)t0, gnt, col_off,
+                           col_q, out);
     }
     GF2_HIP(hipGetLastError());
   }
