@@ -5,10 +5,11 @@
 // tridiagonal matrix (the textbook two-phase method, e.g. Golub & Van Loan,
 // "Matrix Computations", sections 8.3).  The transforms are accumulated in a
 // transposed copy Q^T so that every update runs over contiguous memory; the
-// O(n^2)-per-step updates are spread over OpenMP threads in blocks of
-// columns.  Each QL sweep records its plane rotations and then applies them
-// to Q^T one column block per thread, which is the same arithmetic in the
-// same order per element as applying them one at a time.
+// O(n^2)-per-step updates are spread over OpenMP threads.  The QL iteration
+// on the tridiagonal matrix does not depend on the vectors, so its plane
+// rotations are recorded and applied to Q^T afterwards, one block of
+// columns per thread through all sweeps: the same arithmetic in the same
+// order per element as applying each sweep as it is found.
 //
 // gauss_legendre: nodes are the roots of P_n found by Newton's method from
 // the Chebyshev-like guess cos(pi (i + 3/4) / (n + 1/2)); weights
@@ -19,13 +20,15 @@
 #include <numeric>
 #include <vector>
 
+#include <omp.h>
+
 #include "host_numerics.hpp"
 
 namespace {
-constexpr int64_t kColBlock = 64;
-// The per-step updates are O(n^2); beyond a few threads the fork/join cost
-// outweighs the work at the sizes of the hot path.
-constexpr int kThreads = 4;
+constexpr int64_t kColBlock = 32;
+
+// Threads of the O(n^2)-per-step Householder updates.
+int nthreads() { return std::max(1, std::min(16, omp_get_max_threads())); }
 
 // x . y with four interleaved partial sums (vectorises without reassociation
 // flags; a fixed summation order either way).
@@ -42,30 +45,64 @@ inline double dot4(const double* x, const double* y, int64_t m) {
   return (s0 + s1) + (s2 + s3);
 }
 
-// Apply the rotations of one QL sweep, rows i = hi-1 down to lo, to the
-// rows of Q^T, one block of columns per thread.  Rotation i leaves row i+1
-// final and row i as the input of rotation i-1, so the running row stays in
-// registers and every element is read and written once.
-void apply_sweep(double* qt, int64_t n, int64_t lo, int64_t hi, const double* cs, const double* sn) {
-  const int64_t nb = (n + kColBlock - 1) / kColBlock;
-#pragma omp parallel for num_threads(kThreads) schedule(static) if ((hi - lo) * n > 65536)
-  for (int64_t bk = 0; bk < nb; ++bk) {
-    const int64_t k0 = bk * kColBlock, k1 = std::min(n, k0 + kColBlock), kn = k1 - k0;
-    double carry[kColBlock];
-    const double* top = qt + hi * n + k0;
+// The plane rotations of the QL iteration, recorded sweep by sweep: sweep w
+// acts on rows lo[w] .. hi[w] with (c, s) of rotation i = hi-1 .. lo at
+// cs[2 (off[w] + hi-1-i)], cs[2 (off[w] + hi-1-i) + 1].
+struct Sweeps {
+  std::vector<int64_t> lo, hi, off;
+  std::vector<double> cs;
+};
+
+// All sweeps on the columns k0 .. k0+kn-1 of Q^T.  The block is first
+// copied to a contiguous buffer (row stride kn), so consecutive rotations
+// walk consecutive memory; KN > 0 fixes kn at compile time.
+template <int KN>
+void apply_block(double* qt, int64_t n, int64_t k0, int64_t kn_rt, const Sweeps& sw, double* buf) {
+  const int64_t kn = KN > 0 ? KN : kn_rt;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = 0; k < kn; ++k) buf[i * kn + k] = qt[i * n + k0 + k];
+  double carry[KN > 0 ? KN : kColBlock];
+  const int64_t nsw = (int64_t)sw.lo.size();
+  for (int64_t w = 0; w < nsw; ++w) {
+    const int64_t lo = sw.lo[w], hi = sw.hi[w];
+    const double* r = sw.cs.data() + 2 * sw.off[w];
+    const double* top = buf + hi * kn;
     for (int64_t k = 0; k < kn; ++k) carry[k] = top[k];
-    for (int64_t i = hi - 1; i >= lo; --i) {
-      const double s = sn[i], c = cs[i];
-      double* zi = qt + i * n + k0;
-      double* zj = qt + (i + 1) * n + k0;
+    for (int64_t i = hi - 1; i >= lo; --i, r += 2) {
+      const double c = r[0], s = r[1];
+      double* zi = buf + i * kn;
+      double* zj = zi + kn;
       for (int64_t k = 0; k < kn; ++k) {
         const double fz = carry[k], xi = zi[k];
         zj[k] = s * xi + c * fz;
         carry[k] = c * xi - s * fz;
       }
     }
-    double* bot = qt + lo * n + k0;
+    double* bot = buf + lo * kn;
     for (int64_t k = 0; k < kn; ++k) bot[k] = carry[k];
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = 0; k < kn; ++k) qt[i * n + k0 + k] = buf[i * kn + k];
+}
+
+// Apply every recorded sweep, in order, to the rows of Q^T.  Rotations mix
+// rows only, so each block of columns is independent: one thread per block
+// runs all sweeps on its block (which stays in cache), with a single
+// fork/join for the whole iteration.  Within a sweep, rotation i leaves row
+// i+1 final and row i as the input of rotation i-1, so the running row stays
+// in registers and every element is read and written once per sweep.
+void apply_sweeps(double* qt, int64_t n, const Sweeps& sw) {
+  const int64_t nb = (n + kColBlock - 1) / kColBlock;
+  const int64_t nsw = (int64_t)sw.lo.size();
+  std::vector<double> buf((size_t)(nb * kColBlock * n));
+#pragma omp parallel for num_threads(nthreads()) schedule(dynamic, 1) if (nsw * n > 65536)
+  for (int64_t bk = 0; bk < nb; ++bk) {
+    const int64_t k0 = bk * kColBlock, k1 = std::min(n, k0 + kColBlock), kn = k1 - k0;
+    double* b = buf.data() + bk * kColBlock * n;
+    if (kn == kColBlock)
+      apply_block<kColBlock>(qt, n, k0, kColBlock, sw, b);
+    else
+      apply_block<0>(qt, n, k0, kn, sw, b);
   }
 }
 }  // namespace
@@ -94,7 +131,7 @@ void sym_eigen(int64_t n, double* a, double* e_out, double* v_out) {
     const double beta = 2.0 / vn2;
     betas[k] = beta;
     // p = beta * A22 v
-#pragma omp parallel for num_threads(kThreads) schedule(static) if (m > 256)
+#pragma omp parallel for num_threads(nthreads()) schedule(static) if (m > 256)
     for (int64_t i = 0; i < m; ++i) {
       p[i] = beta * dot4(a + (k + 1 + i) * n + (k + 1), vv, m);
     }
@@ -103,7 +140,7 @@ void sym_eigen(int64_t n, double* a, double* e_out, double* v_out) {
     kk *= 0.5 * beta;
     for (int64_t i = 0; i < m; ++i) w[i] = p[i] - kk * vv[i];
     // A22 -= v w^T + w v^T
-#pragma omp parallel for num_threads(kThreads) schedule(static) if (m > 256)
+#pragma omp parallel for num_threads(nthreads()) schedule(static) if (m > 256)
     for (int64_t i = 0; i < m; ++i) {
       double* row = a + (k + 1 + i) * n + (k + 1);
       const double vi = vv[i], wi = w[i];
@@ -128,7 +165,7 @@ void sym_eigen(int64_t n, double* a, double* e_out, double* v_out) {
     const int64_t m = n - k - 1;
     const double* vv = refl.data() + k * n;
     // y = X[k+1.., k+1..] v (rows contiguous), then X -= beta y v^T
-#pragma omp parallel for num_threads(kThreads) schedule(static) if (m > 128)
+#pragma omp parallel for num_threads(nthreads()) schedule(static) if (m > 128)
     for (int64_t i = 0; i < m; ++i) {
       double* row = qt.data() + (k + 1 + i) * n + (k + 1);
       const double bs = beta * dot4(row, vv, m);
@@ -139,9 +176,11 @@ void sym_eigen(int64_t n, double* a, double* e_out, double* v_out) {
   for (int64_t i = 0; i < n; ++i) d[i] = a[i * n + i];
   for (int64_t i = 0; i + 1 < n; ++i) e[i] = a[(i + 1) * n + i];
 
-  // ---- implicit QL on (d, e); rotations act on rows i, i+1 of Q^T
+  // ---- implicit QL on (d, e); the rotations (acting on rows i, i+1 of
+  // Q^T) are recorded and applied afterwards, all sweeps at once
   const double tiny = 2.220446049250313e-16;
   std::vector<double> rc(n), rs(n);
+  Sweeps sw;
   for (int64_t l = 0; l < n; ++l) {
     for (int iter = 0; iter < 200; ++iter) {
       int64_t m = l;
@@ -177,13 +216,23 @@ void sym_eigen(int64_t n, double* a, double* e_out, double* v_out) {
         rs[i] = s;
         ilo = i;
       }
-      apply_sweep(qt.data(), n, ilo, m, rc.data(), rs.data());
+      if (m > ilo) {
+        sw.lo.push_back(ilo);
+        sw.hi.push_back(m);
+        sw.off.push_back((int64_t)sw.cs.size() / 2);
+        for (int64_t i = m - 1; i >= ilo; --i) {
+          sw.cs.push_back(rc[i]);
+          sw.cs.push_back(rs[i]);
+        }
+      }
       if (early) continue;
       d[l] -= pp;
       e[l] = g;
       e[m] = 0.0;
     }
   }
+
+  apply_sweeps(qt.data(), n, sw);
 
   // ---- sort ascending
   std::vector<int64_t> ord(n);
