@@ -45,6 +45,14 @@ inline double dot4(const double* x, const double* y, int64_t m) {
   return (s0 + s1) + (s2 + s3);
 }
 
+// sqrt(x^2 + y^2); the library hypot (which rescales, and is several times
+// slower) only where the plain sum of squares could over- or underflow.
+inline double hyp(double x, double y) {
+  const double s = x * x + y * y;
+  if (s > 1e-290 && s < 1e290) return std::sqrt(s);
+  return std::hypot(x, y);
+}
+
 // The plane rotations of the QL iteration, recorded sweep by sweep: sweep w
 // acts on rows lo[w] .. hi[w] with (c, s) of rotation i = hi-1 .. lo at
 // cs[2 (off[w] + hi-1-i)], cs[2 (off[w] + hi-1-i) + 1].
@@ -190,14 +198,14 @@ void sym_eigen(int64_t n, double* a, double* e_out, double* v_out) {
       }
       if (m == l) break;
       double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-      double r = std::hypot(g, 1.0);
+      double r = hyp(g, 1.0);
       g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
       double s = 1.0, c = 1.0, pp = 0.0;
       bool early = false;
       int64_t ilo = m;                  // rotations recorded for rows ilo .. m-1
       for (int64_t i = m - 1; i >= l; --i) {
         const double f = s * e[i], b = c * e[i];
-        r = std::hypot(f, g);
+        r = hyp(f, g);
         e[i + 1] = r;
         if (r == 0.0) {
           d[i + 1] -= pp;
