@@ -229,6 +229,42 @@ def gemm_reference(args):
     ctx.close()
 
 
+def learned_bench(args):
+    """The learned-proposal workload: 800 dimers (N=1600, N_aux=4800, B in
+    FP32 is 49 GB), 128 tau, eps=1e-4.  The network is trained on the small
+    training chains; pairs are drawn adaptively (AUTO precision, batches of 8)
+    until the 95% bound of the standard error is below the target, with
+    plain +-1 vectors and with the network's stratified class weights."""
+    import torch
+    import chain_inputs as ci
+    from paper_2005_12338_amd import gf2
+    wl = ci.N1600
+    ctx = gf2.Context(0)
+    pb = Problem(ctx, wl)
+    log(f"[bench] workload {wl.name}: N={wl.n} Naux={wl.naux} ntau={wl.ntau} eps={wl.eps}")
+    mlp, t_train, l0, l1 = train_proposal(ctx, wl.eps, wl.beta)
+    log(f"[bench] proposal network trained in {t_train:.2f} s (loss {l0:.4f} -> {l1:.4f})")
+    rows = {}
+    target = args.target_meh * 1e-3
+    learned = dict(mlp=mlp, classes=PROPOSAL_CLASSES)
+    for name, prec, kw in (("fp32_pm1", "fp32", {}), ("bf16_pm1", "bf16", {}), ("auto_pm1", "auto", {}),
+                           ("auto_learned_stratified", "auto", learned),
+                           ("bf16_learned_stratified", "bf16", learned)):
+        pb.time_to_target(prec, target, **kw)                      # warm
+        t_s, info = pb.time_to_target(prec, target, **kw)
+        log(f"[bench] time to {args.target_meh} mEh ({name}): {t_s:.3f} s, {info['pairs']} pairs, "
+            f"E={info['E']:.9f} stderr={info['stderr']:.3e} precision={info['precision']}")
+        rows[name] = dict(s=t_s, **info)
+    print(json.dumps({"metric": f"time to {args.target_meh} mEh stderr in E_corr, N=1600 (learned vs plain)",
+                      "value": rows["auto_learned_stratified"]["s"], "unit": "s", "n_gpus": 1,
+                      "vs_plain_fp32": rows["fp32_pm1"]["s"] / rows["auto_learned_stratified"]["s"],
+                      "higher_is_better": False, "dtype": "bf16", "data": "synthetic",
+                      "config": {"workload": f"{wl.name}: H2-dimer chain, {wl.n_dimer} dimers, N={wl.n}, "
+                                             f"Naux={wl.naux}, beta={wl.beta}, ntau={wl.ntau}, eps={wl.eps}"},
+                      "train_s": t_train, "runs": rows}), flush=True)
+    ctx.close()
+
+
 def batch_bench(args):
     """The uneven-size batch: 96 chains (20..200 dimers), 64 tau, 128 pairs,
     eps = 1e-3.  One pass = B, split, G(tau) for every chain, then all chains'
@@ -359,7 +395,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="n800", choices=["n800", "n200", "tiny", "batch"])
+    ap.add_argument("--workload", default="n800", choices=["n800", "n200", "tiny", "batch", "n1600"])
     ap.add_argument("--batch-count", type=int, default=96, help="chains in the batch workload")
     ap.add_argument("--batch-prec-bf16", action="store_true", help="run the batch in BF16 (default FP32)")
     ap.add_argument("--prec", default="bf16", choices=["bf16", "bf16x3", "fp32", "fp64"])
@@ -384,6 +420,9 @@ def main():
         return
     if args.workload == "batch":
         batch_bench(args)
+        return
+    if args.workload == "n1600":
+        learned_bench(args)
         return
 
     import torch
