@@ -246,6 +246,15 @@ gf2_status gf2_set_profiling(gf2_ctx* ctx, int on);
 gf2_status gf2_profile_read(gf2_ctx* ctx, int32_t cap, char* names, int64_t* launches,
                             double* total_ms, double* flops, double* bytes, int32_t* count);
 
+/* ------------------------------------------------------------ GEMM tiles --
+ * mode 1 (default): in BF16, the single-product product stage of the chain
+ * (and gf2_debug_gemm) runs on 160 x 160 tiles of 16x16x32 MFMAs wherever
+ * that pads an N x N product less than the 128 x 128 tile (N = 400, 800,
+ * ...); mode 0: the 128 x 128 tile everywhere.  Both give the same results
+ * up to the FP32 rounding of the accumulation order.  GF2_E_ARG for other
+ * modes. */
+gf2_status gf2_set_gemm_tiles(gf2_ctx* ctx, int32_t mode);
+
 /* ------------------------------------------------------------ test hook ---
  * The chain's GEMM kernel on its own: C[b] = A[b] B[b]^T for b < batch,
  * square n x n operands (row-major, leading dimension ld = n rounded up to a

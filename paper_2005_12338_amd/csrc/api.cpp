@@ -141,11 +141,19 @@ Prob prob0() {
   p.nseg = 1; p.nA = 1; p.nB = 1;
   return p;
 }
-int tiles_of(const Prob& p, Prec prec, int64_t m, int64_t nc) {
-  const int64_t sm = gemm_tile_m(prec) / p.nA, sn = gemm_tile_n(prec) / p.nB;
+int tiles_of(const Prob& p, Prec prec, int64_t m, int64_t nc, int wide = 0) {
+  const int64_t sm = gemm_tile_m(prec, wide) / p.nA, sn = gemm_tile_n(prec, wide) / p.nB;
   return (int)(((m + sm - 1) / sm) * ((nc + sn - 1) / sn));
 }
-int tiles_of(const Prob& p, Prec prec, int64_t n) { return tiles_of(p, prec, n, n); }
+int tiles_of(const Prob& p, Prec prec, int64_t n, int wide = 0) { return tiles_of(p, prec, n, n, wide); }
+
+// The wide BF16 tile for the chain's single-product stage when it pads an
+// n x n product less than the standard tile (n = 400, 800, ...).
+int wide_for(const gf2_ctx* ctx, Prec prec, int64_t n) {
+  if (prec != Prec::BF16 || !ctx->gemm_wide) return 0;
+  const int64_t w = gemm_tile_m(prec, 1), s = gemm_tile_m(prec, 0);
+  return ((n + w - 1) / w) * w < ((n + s - 1) / s) * s ? 1 : 0;
+}
 
 void run_dd(gf2_ctx* ctx, const gf2_split_h* sp, const double* G, const double* Gb, int64_t ntau,
             double* out);
@@ -182,6 +190,12 @@ void gf2_destroy(gf2_ctx* ctx) {
   }
   free_scratch(ctx);
   delete ctx;
+}
+
+gf2_status gf2_set_gemm_tiles(gf2_ctx* ctx, int32_t mode) {
+  if (!ctx || mode < 0 || mode > 1) return GF2_E_ARG;
+  ctx->gemm_wide = mode;
+  return GF2_OK;
 }
 
 gf2_status gf2_set_stream(gf2_ctx* ctx, void* stream) {
@@ -270,7 +284,7 @@ gf2_status gf2_build_B(gf2_ctx* ctx, int64_t n, int64_t naux, const void* ijA, c
     Unit uh{0, 0, 0, 0};
     auto* units = (Unit*)ctx_buf(ctx, "bunit", sizeof(Unit));
     h2d(ctx, units, &uh, 1);
-    GemmLaunch L{probs, 1, 0, units, 1, InstGeo{nn, naux, kp, kp, 0}, nullptr, 0, 0, nullptr, 0, 0};
+    GemmLaunch L{probs, 1, 0, units, 1, InstGeo{nn, naux, kp, kp, 0}, nullptr, 0, 0, nullptr, 0, 0, 0};
     launch_gemm(Prec::F64, L, tiles_of(pb, Prec::F64, nn, naux), ctx->stream);
     launch_untranspose(tout, nn, naux, kp, B, f64, ctx->stream);
     GF2_HIP(hipGetLastError());
@@ -597,6 +611,7 @@ struct ChainPlan {
   size_t sb = 0, ab = 0;
   int64_t slots = 0, sc = 0, tcnt = 0;
   int mtiles = 0, ftiles = 0;
+  int wide4 = 0;                 // stage s4 (single product) on the wide BF16 tile
   double *mpart = nullptr, *epart = nullptr, *coef = nullptr, *gb64 = nullptr;
   char *wz = nullptr, *jw_l = nullptr, *jw_s = nullptr, *jz_st = nullptr, *jz_sum_t = nullptr, *jblk = nullptr;
   char* sig = nullptr;
@@ -793,7 +808,8 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
   quad.nA = 2; quad.nB = 2;
   c.mtiles = tiles_of(quad, prec, n);
   Prob single = prob0();
-  c.ftiles = tiles_of(single, prec, n);
+  c.wide4 = wide_for(ctx, prec, n);
+  c.ftiles = tiles_of(single, prec, n, c.wide4);
   c.mpart = (double*)S("c_mpart", 4 * c.mtiles * 8);
   c.epart = (double*)S("c_epart", c.ftiles * 8);
   c.coef = (double*)S("c_coef", kMaxAdd * 8);
@@ -902,10 +918,12 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
 
 void chain_stage(gf2_ctx* ctx, const ChainPlan& c, int stage, int64_t ci) {
   const int off = kStageOff[stage], cnt = kStageCnt[stage];
+  const int wide = stage == 3 ? c.wide4 : 0;
   int mt = 0;
-  for (int i = 0; i < cnt; ++i) mt = std::max(mt, tiles_of(c.P[off + i], c.prec, c.n));
+  for (int i = 0; i < cnt; ++i) mt = std::max(mt, tiles_of(c.P[off + i], c.prec, c.n, wide));
   const int nu = (int)c.chunks[ci].second;
   GemmLaunch L = chain_launch(c.dprobs + off, cnt, c.dunits + c.chunks[ci].first, nu, c.n, c.np, c.plane);
+  L.wide = wide;
   static const char* tag[4] = {".s1", ".s2", ".s3", ".s4"};
   const std::string nm = std::string(gemm_name(c.prec)) + tag[stage];
   ProfScope ps(ctx, nm.c_str(), 2.0 * (double)c.n * c.n * c.n * kStageProducts[stage] * nu);
@@ -1122,11 +1140,12 @@ void batch_plan(gf2_ctx* ctx, BatchRun& R, int32_t nitem, const gf2_batch_item* 
       R.segoff.push_back((int64_t)sh.size());
       int64_t item = 0;
       for (const auto& r : runs) {
+        if (stage == 3 && R.plans[r.first].wide4) continue;   // launched on its own (wide tile)
         const int32_t t = itiles[r.first][stage];
         sh.push_back(BatchSeg{item, r.second.first, r.second.second, t, 0});
         item += (int64_t)r.second.second * kStageCnt[stage] * t;
       }
-      R.nseg.push_back((int64_t)runs.size());
+      R.nseg.push_back((int64_t)(sh.size() - R.segoff.back()));
       R.nitems.push_back(item);
     }
   }
@@ -1152,13 +1171,16 @@ void batch_steps(gf2_ctx* ctx, const BatchRun& R, Prec prec, int64_t s0, int64_t
                    R.nitems[k]};
       double fl = 0.0;
       for (const ChainPlan& c : R.plans)
-        if (st < (int64_t)c.chunks.size())
+        if (st < (int64_t)c.chunks.size() && !(stage == 3 && c.wide4))
           fl += 2.0 * (double)c.n * c.n * c.n * kStageProducts[stage] * c.chunks[st].second;
       {
         const std::string nm = std::string(gemm_name(prec)) + tag[stage];
         ProfScope ps(ctx, nm.c_str(), fl);
         launch_gemm(prec, L, R.tiles[stage], ctx->stream);
       }
+      if (stage == 3)   // instances whose single-product stage runs on the wide tile, one launch each
+        for (const ChainPlan& c : R.plans)
+          if (c.wide4 && st < (int64_t)c.chunks.size()) chain_stage(ctx, c, 3, st);
       if (stage == 1)
         for (const ChainPlan& c : R.plans)
           if (st < (int64_t)c.chunks.size()) chain_jk(ctx, c, st);
@@ -1536,8 +1558,9 @@ gf2_status gf2_debug_gemm(gf2_ctx* ctx, gf2_precision prec, int64_t n, int64_t b
     auto* units = (Unit*)ctx_buf(ctx, "dbg_units", uh.size() * sizeof(Unit));
     h2d(ctx, units, uh.data(), uh.size());
     GemmLaunch L = chain_launch(probs, 1, units, (int32_t)batch, n, ld, ld2);
+    L.wide = wide_for(ctx, p, n);      // the tile the chain's single-product stage would use
     ProfScope ps(ctx, "debug_gemm", 2.0 * (double)n * n * n * batch);
-    launch_gemm(p, L, tiles_of(pb, p, n), ctx->stream);
+    launch_gemm(p, L, tiles_of(pb, p, n, L.wide), ctx->stream);
   });
 }
 

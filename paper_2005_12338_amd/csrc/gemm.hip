@@ -12,6 +12,11 @@
 //   FP32   v_mfma_f32_32x32x2_f32     128 x 128 tile, 4 waves
 //   BF16   v_mfma_f32_32x32x16_bf16   128 x 128 tile, 4 waves
 //   BF16X3 three bf16 MFMAs per step (hi*hi + hi*lo + lo*hi)
+//   BF16, wide tile (W = 1, single-product problems):
+//          v_mfma_f32_16x16x32_bf16   160 x 160 tile, 4 waves of 80 x 80;
+//          160 divides N = 800 and 400, where 128 pads by 12%.  Its LDS rows
+//          are unpadded and XOR-swizzled (16-byte chunk c of row r stored at
+//          c ^ (r mod 8)), so two workgroups fit the 160 KB of a CU.
 // Operands are double-buffered through LDS (global -> registers -> LDS).
 // The epilogue writes straight from the accumulators: combinations of the
 // tile's products, row-major or transposed, in accumulator or storage
@@ -21,44 +26,49 @@
 
 #include "gf2_internal.hpp"
 
-// BF16 block tile (the other precisions use fixed tiles).
-#ifndef GF2_BF16_BM
-#define GF2_BF16_BM 128
-#endif
-#ifndef GF2_BF16_BN
-#define GF2_BF16_BN 128
-#endif
-
 namespace {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 // 16-byte vector in the global address space (global_load, not flat_load)
 typedef __attribute__((address_space(1))) const u32x4_t GVec;
 
-template <Prec P> struct Cfg;
+template <Prec P, int W = 0> struct Cfg;
 // BM x BN block tile, 2 x 2 waves, each TM x TN MFMA tiles of MT x MT.
+// SWZ: unpadded XOR-swizzled LDS rows; PF: k tiles in flight in registers
+// (0: none, the operands go straight from global memory to LDS).
 template <> struct Cfg<Prec::F64> {
   using E = double; using Acc = double;
   static constexpr int BM = 64, BN = 64, BK = 16, PAD = 2, PLANES = 1;
   static constexpr int MT = 16, NACC = 4, TM = 2, TN = 2;
+  static constexpr bool SWZ = false; static constexpr int PF = 2;
 };
 template <> struct Cfg<Prec::F32> {
   using E = float; using Acc = float;
   static constexpr int BM = 128, BN = 128, BK = 32, PAD = 4, PLANES = 1;
   static constexpr int MT = 32, NACC = 16, TM = 2, TN = 2;
+  static constexpr bool SWZ = false; static constexpr int PF = 2;
 };
 template <> struct Cfg<Prec::BF16> {
   using E = bf16_t; using Acc = float;
-  static constexpr int BM = GF2_BF16_BM, BN = GF2_BF16_BN, BK = 64, PAD = 8, PLANES = 1;
-  static constexpr int MT = 32, NACC = 16, TM = BM / 64, TN = BN / 64;
+  static constexpr int BM = 128, BN = 128, BK = 64, PAD = 8, PLANES = 1;
+  static constexpr int MT = 32, NACC = 16, TM = 2, TN = 2;
+  static constexpr bool SWZ = false; static constexpr int PF = 2;
 };
 template <> struct Cfg<Prec::BF16X3> {
   using E = bf16_t; using Acc = float;
   static constexpr int BM = 128, BN = 128, BK = 32, PAD = 8, PLANES = 2;
   static constexpr int MT = 32, NACC = 16, TM = 2, TN = 2;
+  static constexpr bool SWZ = false; static constexpr int PF = 2;
+};
+template <> struct Cfg<Prec::BF16, 1> {
+  using E = bf16_t; using Acc = float;
+  static constexpr int BM = 160, BN = 160, BK = 64, PAD = 0, PLANES = 1;
+  static constexpr int MT = 16, NACC = 4, TM = 5, TN = 5;
+  static constexpr bool SWZ = true; static constexpr int PF = 0;   // PF 0: direct global -> LDS loads
 };
 
 constexpr int kThreads = 256;
@@ -156,9 +166,9 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t wg, int64_t total) {
   return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
-template <Prec P>
+template <Prec P, int W = 0>
 struct Smem {
-  using C = Cfg<P>;
+  using C = Cfg<P, W>;
   using E = typename C::E;
   static constexpr int PITCH = C::BK + C::PAD;
   static constexpr int TILE_A = C::PLANES * C::BM * PITCH;
@@ -167,30 +177,31 @@ struct Smem {
 };
 
 // Row (within the 32 x 32 or 16 x 16 MFMA tile) held by accumulator r of a lane.
-template <Prec P>
+template <Prec P, int MT>
 __device__ __forceinline__ int acc_row(int lane, int r) {
   if constexpr (P == Prec::F64) return (lane >> 4) + 4 * r;       // f64 16x16x4
+  else if constexpr (MT == 16) return 4 * (lane >> 4) + r;        // f32 16x16x32 bf16
   else return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);           // 32x32 f32 / bf16
 }
-template <Prec P>
+template <Prec P, int MT>
 __device__ __forceinline__ int acc_col(int lane) {
-  if constexpr (P == Prec::F64) return lane & 15;
+  if constexpr (P == Prec::F64 || MT == 16) return lane & 15;
   else return lane & 31;
 }
 
-template <Prec P, int NA, int NB>
+template <Prec P, int W, int NA, int NB>
 __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, const Unit& u, int tile,
                                           unsigned char* smem, double* red) {
-  using C = Cfg<P>;
+  using C = Cfg<P, W>;
   using E = typename C::E;
   using Acc = typename C::Acc;
   constexpr int BM = C::BM, BN = C::BN, BK = C::BK, PL = C::PLANES;
-  constexpr int PITCH = Smem<P>::PITCH;
+  constexpr int PITCH = Smem<P, W>::PITCH;
   constexpr int VE = 16 / sizeof(E);                      // elements per 16 B vector
   constexpr int VPR = BK / VE;                            // vectors per tile row
   constexpr int AV = BM * VPR * PL / kThreads, BV = BN * VPR * PL / kThreads;
   static_assert(BM * VPR * PL % kThreads == 0 && BN * VPR * PL % kThreads == 0, "tile/threads");
-  constexpr int TILE_A = Smem<P>::TILE_A, TILE_B = Smem<P>::TILE_B;
+  constexpr int TILE_A = Smem<P, W>::TILE_A, TILE_B = Smem<P, W>::TILE_B;
   constexpr int SM = BM / NA, SN = BN / NB;               // output rows / cols per tile
   constexpr int MT = C::MT, NACC = C::NACC;
   constexpr int TM = C::TM, TN = C::TN;                   // MFMA tiles per wave
@@ -201,7 +212,7 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
   E* Bs = As + 2 * TILE_A;             // [2][PL][BN][PITCH]
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform (scalar)
   const int wm = wave >> 1, wn = wave & 1;
 
   const int64_t mrows = L.m, ncols = L.nc, kk = L.k, ld = L.ld;
@@ -221,6 +232,11 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
   auto frag_col_lds = [&](int j) { return (j / FC) * SN + wn * (FC * MT) + (j % FC) * MT; };
   auto frag_row_out = [&](int i) { return wm * (FR * MT) + i * MT; };   // i < FR
   auto frag_col_out = [&](int j) { return wn * (FC * MT) + j * MT; };   // j < FC
+  // element (row, k) of a tile plane in LDS; k a multiple of 8 with SWZ
+  auto lds_at = [&](int row, int k) {
+    if constexpr (C::SWZ) return row * PITCH + ((((k >> 3) ^ (row & 7))) << 3);
+    else return row * PITCH + k;
+  };
 
   // Staging geometry.  Vector i of thread t covers tile row trow + c_i
   // (c_i = (i * RSTEP) % rows) of plane (i * RSTEP) / rows and k offset kv;
@@ -270,9 +286,10 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
       rb[i] = *(const GVec*)(ok ? bbase[i] + toff + k0 : zvec);
     }
   };
+  static_assert(!C::SWZ || RSTEP % 8 == 0, "swizzle: staged rows share row mod 8");
   auto sstore = [&](int buf, const u32x4_t* ra, const u32x4_t* rb) {
-    E* a = As + buf * TILE_A + trow * PITCH + kv;
-    E* b = Bs + buf * TILE_B + trow * PITCH + kv;
+    E* a = As + buf * TILE_A + lds_at(trow, kv);
+    E* b = Bs + buf * TILE_B + lds_at(trow, kv);
 #pragma unroll
     for (int i = 0; i < AV; ++i) {
       const int pl = (i * RSTEP) / BM, c = (i * RSTEP) % BM;
@@ -285,7 +302,8 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
     }
   };
 
-  using AccV = typename std::conditional<P == Prec::F64, f64x4_t, f32x16_t>::type;
+  using AccV = typename std::conditional<P == Prec::F64, f64x4_t,
+                                         typename std::conditional<NACC == 4, f32x4_t, f32x16_t>::type>::type;
   AccV acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -344,6 +362,22 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
             for (int j = 0; j < TN; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i][q], bv[j][q], acc[i][j], 0, 0, 0);
       }
+    } else if constexpr (MT == 16) {
+      // 16x16x32: lane group g = lane/16 owns k in [8g, 8g+8) of each 32-wide k step
+      const int lr = lane & 15, g = lane >> 4;
+#pragma unroll
+      for (int ks = 0; ks < BK / 32; ++ks) {
+        bf16x8_t ah[TM], bh[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) ah[i] = *(const bf16x8_t*)(a + lds_at(frag_row_lds(i) + lr, ks * 32 + g * 8));
+#pragma unroll
+        for (int j = 0; j < TN; ++j) bh[j] = *(const bf16x8_t*)(b + lds_at(frag_col_lds(j) + lr, ks * 32 + g * 8));
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      }
     } else {
       // lane group g = lane/32 owns k in [8g, 8g+8) of each 16-wide k step
       const int lr = lane & 31, g = lane >> 5;
@@ -387,12 +421,94 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
   // Every step issues its loads and stores (tiles past the end load zeros),
   // so the outstanding-load count is the same on every path and each store
   // waits only for the loads of its own tile.
-  u32x4_t ra0[AV], rb0[BV], ra1[AV], rb1[BV];
+  u32x4_t ra0[AV], rb0[BV];
   auto issue = [&](int t, u32x4_t* ra, u32x4_t* rb) {
     if (t < ktiles && t % kps == 0) set_seg(t / kps);
     gload(t, ra, rb);
   };
-  if (ktiles > 0) {
+  if constexpr (C::PF == 0) {
+    // Direct global -> LDS loads (global_load_lds_dwordx4): instruction i of
+    // wave w fills tile rows 8 (4 i + w) .. +7, lane L row 8 (4 i + w) + L/8
+    // at physical chunk L mod 8, i.e. logical chunk (L mod 8) ^ (row mod 8)
+    // of the swizzled layout.  Two stages: tile t+1 streams into LDS while
+    // tile t is computed; one barrier per k tile.
+    static_assert(C::SWZ && PL == 1 && NA == 1 && NB == 1 && BK == 64 && BM % 32 == 0 && BN % 32 == 0,
+                  "direct loads: swizzled single-plane 64-wide k tiles");
+    constexpr int NLA = BM / 32, NLB = BN / 32;
+    const int lrow = lane >> 3, pch = lane & 7;
+    const E* dab[NLA];
+    const E* dbb[NLB];
+    auto dseg = [&](int seg) {
+      const OpRef& ar = pb.a[seg];
+      const OpRef& br = pb.b[seg];
+#pragma unroll
+      for (int i = 0; i < NLA; ++i)
+        dab[i] = (const E*)ar.base + off(ar, u) + (row0 + 8 * (4 * i + wave) + lrow) * ld;
+#pragma unroll
+      for (int i = 0; i < NLB; ++i)
+        dbb[i] = (const E*)br.base + off(br, u) + (col0 + 8 * (4 * i + wave) + lrow) * ld;
+    };
+    int dseg_i = 0, dk = 0;                 // segment and k tile within it of the next load
+    auto dload = [&](int /*t*/) {
+      if (dk == 0) dseg(dseg_i);
+      const int64_t k0 = (int64_t)dk * BK;
+      const int t = dseg_i * kps + dk;
+      E* sa = As + (t & 1) * TILE_A;
+      E* sb = Bs + (t & 1) * TILE_B;
+#pragma unroll
+      for (int i = 0; i < NLA; ++i) {
+        const int r = 8 * (4 * i + wave) + lrow;
+        const int64_t kc = k0 + ((pch ^ (r & 7)) << 3);
+        const bool ok = kc < kk && row0 + r < mrows;
+        const E* src = ok ? dab[i] + kc : zvec;
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                         (__attribute__((address_space(3))) void*)(sa + (4 * i + wave) * 512),
+                                         16, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < NLB; ++i) {
+        const int r = 8 * (4 * i + wave) + lrow;
+        const int64_t kc = k0 + ((pch ^ (r & 7)) << 3);
+        const bool ok = kc < kk && col0 + r < ncols;
+        const E* src = ok ? dbb[i] + kc : zvec;
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                         (__attribute__((address_space(3))) void*)(sb + (4 * i + wave) * 512),
+                                         16, 0, 0);
+      }
+      if (++dk == kps) {
+        dk = 0;
+        ++dseg_i;
+      }
+    };
+    if (ktiles > 0) {
+      dload(0);
+      for (int kt = 0; kt < ktiles; ++kt) {
+        // this lane's loads of tile kt have landed (vmcnt 0: nothing else is
+        // in flight), then every lane's have; every wave is also done with
+        // tile kt-1, whose buffer the next loads overwrite.  A fenced
+        // barrier would add nothing but a wait on all memory traffic.
+        __builtin_amdgcn_s_waitcnt(0x0F70);                      // vmcnt(0)
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        if (kt + 1 < ktiles) dload(kt + 1);
+        compute(kt & 1);
+      }
+      __syncthreads();       // LDS free for the epilogue's reduction slots
+    }
+  } else if constexpr (C::PF == 1) {
+    // one k tile in flight in registers: tile t+1 loads while tile t computes
+    if (ktiles > 0) {
+      issue(0, ra0, rb0);
+      sstore(0, ra0, rb0);
+      __syncthreads();
+      for (int kt = 0; kt < ktiles; ++kt) {
+        issue(kt + 1, ra0, rb0);
+        compute(kt & 1);
+        sstore((kt + 1) & 1, ra0, rb0);
+        __syncthreads();
+      }
+    }
+  } else if (ktiles > 0) {
+    u32x4_t ra1[AV], rb1[BV];
     issue(0, ra0, rb0);
     issue(1, ra1, rb1);
     sstore(0, ra0, rb0);
@@ -429,7 +545,7 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
   const double* hmat = pb.nhad ? (const double*)pb.had_h.base + off(pb.had_h, u) : nullptr;
   double hsum[kMaxHad] = {0.0, 0.0, 0.0, 0.0};
   const int nh = pb.nhad;
-  const int ac = acc_col<P>(lane);
+  const int ac = acc_col<P, MT>(lane);
   // Row-major outputs are written element by element (consecutive lanes hold
   // consecutive columns).  For 32 x 32 tiles, accumulators 4q .. 4q+3 of a
   // lane are four consecutive rows, so transposed outputs are written as one
@@ -449,7 +565,7 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
 #pragma unroll
         for (int e = 0; e < RG; ++e) {
           const int r = q * RG + e;
-          grs[e] = rbase + acc_row<P>(lane, r);
+          grs[e] = rbase + acc_row<P, MT>(lane, r);
 #pragma unroll
           for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -512,19 +628,23 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
   }
 }
 
-template <Prec P, bool MI>
+template <Prec P, int W, bool MI>
 __device__ __forceinline__ void gemm_item(const GemmLaunch& L, int tile, int py, unsigned char* smem,
                                           double* red) {
   const int ui = py / L.nprob, pi = py % L.nprob;
   const Unit u = L.units[ui];
   const Prob& pb = MI ? L.probs[(int64_t)u.inst * L.pstride + pi] : L.probs[pi];
   const InstGeo g = MI ? L.geo[u.inst] : L.g;
-  const int mode = (pb.nA == 2 ? 2 : 0) + (pb.nB == 2 ? 1 : 0);
-  switch (mode) {
-    case 0: gemm_body<P, 1, 1>(g, pb, u, tile, smem, red); break;
-    case 1: gemm_body<P, 1, 2>(g, pb, u, tile, smem, red); break;
-    case 2: gemm_body<P, 2, 1>(g, pb, u, tile, smem, red); break;
-    default: gemm_body<P, 2, 2>(g, pb, u, tile, smem, red); break;
+  if constexpr (W == 1) {
+    gemm_body<P, W, 1, 1>(g, pb, u, tile, smem, red);   // single-product problems only
+  } else {
+    const int mode = (pb.nA == 2 ? 2 : 0) + (pb.nB == 2 ? 1 : 0);
+    switch (mode) {
+      case 0: gemm_body<P, W, 1, 1>(g, pb, u, tile, smem, red); break;
+      case 1: gemm_body<P, W, 1, 2>(g, pb, u, tile, smem, red); break;
+      case 2: gemm_body<P, W, 2, 1>(g, pb, u, tile, smem, red); break;
+      default: gemm_body<P, W, 2, 2>(g, pb, u, tile, smem, red); break;
+    }
   }
 }
 
@@ -554,14 +674,22 @@ __device__ __forceinline__ void decode_item(const GemmLaunch& L, int64_t item, i
 // list of runs); otherwise one instance, items tile-major per (unit, problem).
 // PERSIST: a grid-stride loop over the items, else one item per workgroup
 // (kept loop-free, so nothing is hoisted across items).
-template <Prec P, bool MI, bool PERSIST>
+// W = 1: the wide tile fills exactly half of a CU's LDS, so the epilogue's
+// reduction slots reuse the operand buffers (the main loop ends with a
+// barrier); otherwise they have their own.
+template <Prec P, int W> struct RedSlots {
+  static constexpr int N = W == 1 ? 1 : 4 * kMaxHad;
+};
+
+template <Prec P, int W, bool MI, bool PERSIST>
 __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(GemmLaunch L) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[Smem<P>::BYTES];
-  __shared__ double red[4 * kMaxHad];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[Smem<P, W>::BYTES];
+  __shared__ double red_own[RedSlots<P, W>::N];
+  double* red = W == 1 ? (double*)smem : red_own;
   int tile, py;
   if constexpr (!PERSIST) {
     decode_item<MI>(L, xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x), tile, py);
-    gemm_item<P, MI>(L, tile, py, smem, red);
+    gemm_item<P, W, MI>(L, tile, py, smem, red);
   } else {
     // XCD x = b % 8 takes the contiguous x-th eighth of the items
     // (consecutive items share a (unit, problem)); its workgroups stride
@@ -573,7 +701,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(GemmLaunch L) {
     const int64_t hi = lo + per + (x < rem ? 1 : 0);
     for (int64_t j = lo + (blockIdx.x >> 3); j < hi; j += gridDim.x >> 3) {
       decode_item<MI>(L, j, tile, py);
-      gemm_item<P, MI>(L, tile, py, smem, red);
+      gemm_item<P, W, MI>(L, tile, py, smem, red);
       __syncthreads();                   // LDS of the next item
     }
   }
@@ -581,19 +709,19 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(GemmLaunch L) {
 
 }  // namespace
 
-int gemm_tile_m(Prec p) {
+int gemm_tile_m(Prec p, int wide) {
   switch (p) {
     case Prec::F64: return Cfg<Prec::F64>::BM;
     case Prec::F32: return Cfg<Prec::F32>::BM;
-    case Prec::BF16: return Cfg<Prec::BF16>::BM;
+    case Prec::BF16: return wide ? Cfg<Prec::BF16, 1>::BM : Cfg<Prec::BF16>::BM;
     default: return Cfg<Prec::BF16X3>::BM;
   }
 }
-int gemm_tile_n(Prec p) {
+int gemm_tile_n(Prec p, int wide) {
   switch (p) {
     case Prec::F64: return Cfg<Prec::F64>::BN;
     case Prec::F32: return Cfg<Prec::F32>::BN;
-    case Prec::BF16: return Cfg<Prec::BF16>::BN;
+    case Prec::BF16: return wide ? Cfg<Prec::BF16, 1>::BN : Cfg<Prec::BF16>::BN;
     default: return Cfg<Prec::BF16X3>::BN;
   }
 }
@@ -610,26 +738,33 @@ void launch_gemm(Prec p, const GemmLaunch& Lin, int max_tiles, hipStream_t st) {
   dim3 grid(L.persist > 0 ? (unsigned)(((L.persist + 7) / 8) * 8) : (unsigned)items);
   const bool mi = L.segs != nullptr, pers = L.persist > 0;
   auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(kThreads), 0, st, L); };
+  if (L.wide) {
+    // the wide tile: BF16, one instance, single-product problems
+    if (p != Prec::BF16 || mi) throw Gf2Error{GF2_E_STATE, "wide GEMM tile: BF16 single-instance launches only"};
+    go(gemm_kernel<Prec::BF16, 1, false, false>);
+    GF2_HIP(hipGetLastError());
+    return;
+  }
   switch (p) {
     case Prec::F64:
-      if (!mi) go(gemm_kernel<Prec::F64, false, false>);
-      else if (pers) go(gemm_kernel<Prec::F64, true, true>);
-      else go(gemm_kernel<Prec::F64, true, false>);
+      if (!mi) go(gemm_kernel<Prec::F64, 0, false, false>);
+      else if (pers) go(gemm_kernel<Prec::F64, 0, true, true>);
+      else go(gemm_kernel<Prec::F64, 0, true, false>);
       break;
     case Prec::F32:
-      if (!mi) go(gemm_kernel<Prec::F32, false, false>);
-      else if (pers) go(gemm_kernel<Prec::F32, true, true>);
-      else go(gemm_kernel<Prec::F32, true, false>);
+      if (!mi) go(gemm_kernel<Prec::F32, 0, false, false>);
+      else if (pers) go(gemm_kernel<Prec::F32, 0, true, true>);
+      else go(gemm_kernel<Prec::F32, 0, true, false>);
       break;
     case Prec::BF16:
-      if (!mi) go(gemm_kernel<Prec::BF16, false, false>);
-      else if (pers) go(gemm_kernel<Prec::BF16, true, true>);
-      else go(gemm_kernel<Prec::BF16, true, false>);
+      if (!mi) go(gemm_kernel<Prec::BF16, 0, false, false>);
+      else if (pers) go(gemm_kernel<Prec::BF16, 0, true, true>);
+      else go(gemm_kernel<Prec::BF16, 0, true, false>);
       break;
     case Prec::BF16X3:
-      if (!mi) go(gemm_kernel<Prec::BF16X3, false, false>);
-      else if (pers) go(gemm_kernel<Prec::BF16X3, true, true>);
-      else go(gemm_kernel<Prec::BF16X3, true, false>);
+      if (!mi) go(gemm_kernel<Prec::BF16X3, 0, false, false>);
+      else if (pers) go(gemm_kernel<Prec::BF16X3, 0, true, true>);
+      else go(gemm_kernel<Prec::BF16X3, 0, true, false>);
       break;
   }
   GF2_HIP(hipGetLastError());

@@ -120,6 +120,7 @@ struct GemmLaunch {
   const BatchSeg* segs; // device work list (multi-instance), or null: items are
   int32_t nseg;         // tile + tiles * (unit * nprob + problem)
   int64_t nitems;       // items of the work list
+  int32_t wide;         // BF16 wide tile (single instance, single-product problems)
 };
 
 // Kernel launchers (device code in separate translation units).
@@ -127,10 +128,10 @@ void launch_gemm(Prec p, const GemmLaunch& L, int max_tiles, hipStream_t st);
 // Chain launch: square n x n products stored with leading dimension np.
 inline GemmLaunch chain_launch(const Prob* probs, int nprob, const Unit* units, int nunit, int64_t n,
                                int64_t np, int64_t plane) {
-  return GemmLaunch{probs, nprob, 0, units, nunit, InstGeo{n, n, np, np, plane}, nullptr, 0, 0, nullptr, 0, 0};
+  return GemmLaunch{probs, nprob, 0, units, nunit, InstGeo{n, n, np, np, plane}, nullptr, 0, 0, nullptr, 0, 0, 0};
 }
-int gemm_tile_m(Prec p);     // BM
-int gemm_tile_n(Prec p);     // BN
+int gemm_tile_m(Prec p, int wide = 0);     // BM
+int gemm_tile_n(Prec p, int wide = 0);     // BN
 
 // ---------------------------------------------------------------- context -
 
@@ -146,6 +147,7 @@ struct gf2_ctx {
   std::string err;
   std::vector<DevBuf> pool;       // scratch allocations owned by the context
   int64_t max_units = 0;          // chunk size tuning (0 = automatic)
+  int32_t gemm_wide = 1;          // 1: wide BF16 tile where it pads less; 0: standard tiles only
   // (n, np, precision) of the last chain layout per buffer-tag prefix
   std::map<std::string, std::string> chain_keys;
   // launch shapes chosen by the batch autotuner, per batch signature

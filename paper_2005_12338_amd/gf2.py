@@ -98,6 +98,7 @@ _SIGS = {
     "gf2_rng_words": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int64,
                                 C.POINTER(C.c_uint64)]),
     "gf2_set_profiling": (C.c_int, [C.c_void_p, C.c_int]),
+    "gf2_set_gemm_tiles": (C.c_int, [C.c_void_p, C.c_int32]),
     "gf2_debug_gemm": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
                                  C.c_void_p]),
     "gf2_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -422,6 +423,10 @@ class Context:
         """C[b] = A[b] Bt[b]^T with the chain's GEMM kernel (padded square operands)."""
         self._check(self.lib.gf2_debug_gemm(self.h, PREC[prec], n, batch, A.data_ptr(), Bt.data_ptr(),
                                             Cout.data_ptr()))
+
+    def set_gemm_tiles(self, wide: bool):
+        """wide=True (default): the 160-wide BF16 tile where it pads less."""
+        self._check(self.lib.gf2_set_gemm_tiles(self.h, 1 if wide else 0))
 
     def set_profiling(self, on: bool):
         self._check(self.lib.gf2_set_profiling(self.h, 1 if on else 0))

@@ -90,3 +90,20 @@ def test_batch_rejects_foreign_split(ctx):
     inst[1] = dict(inst[1], B=inst[0]["B"])
     with pytest.raises(gf2.Gf2Error):
         ctx.sigma_batch(inst, prec="fp64")
+
+
+def test_batch_with_importance_and_stratified_items_equals_single_calls(ctx):
+    """Items with their own sampling modes (plain, k=2 importance draws,
+    stratified with 5 classes) in one FP64 batch: each equals its single
+    call bit for bit."""
+    import chain_inputs as ci
+    inst = _instances(ctx, [8, 14, 21], 3, 1e-2, torch.float64, 4)
+    naux = [it["pb"]["geo"].naux for it in inst]
+    inst[1] = dict(inst[1], p=ci.random_weights(naux[1], 3), k=2)
+    inst[2] = dict(inst[2], p=ci.random_weights(naux[2], 4), classes=5)
+    got = ctx.sigma_batch(inst, prec="fp64")
+    ref = [ctx.sigma_tau(it["split"], it["B"], it["G"], it["Gb"], ns=it["ns"], seed=it["seed"], prec="fp64",
+                         p=it.get("p"), k=it.get("k", 1), classes=it.get("classes", 0)) for it in inst]
+    for (S, es), (Sr, esr) in zip(got, ref):
+        assert torch.equal(S, Sr)
+        assert torch.equal(es, esr)

@@ -258,7 +258,8 @@ def test_sigma_stoch_batches_equal_one_call(ctx):
     assert torch.equal(s_all, s_b)
 
 
-@pytest.mark.parametrize("prec,n,batch", [("fp64", 70, 3), ("fp32", 150, 2), ("bf16", 200, 2), ("bf16x3", 130, 2)])
+@pytest.mark.parametrize("prec,n,batch", [("fp64", 70, 3), ("fp32", 150, 2), ("bf16", 200, 2), ("bf16x3", 130, 2),
+                                          ("bf16", 150, 3), ("bf16", 300, 2)])
 def test_gemm_kernel_matches_torch_reference(ctx, prec, n, batch):
     """The chain's GEMM kernel alone, against a plain PyTorch reference of the
     same product (FP64 / FP32 on the CPU)."""
@@ -299,3 +300,23 @@ def test_gemm_kernel_matches_torch_reference(ctx, prec, n, batch):
     err = (got - ref).abs().max().item() / ref.abs().max().item()
     assert err < tol, err
     assert torch.count_nonzero(C.cpu()[:, n:, :]) == 0 and torch.count_nonzero(C.cpu()[:, :, n:]) == 0
+
+
+@pytest.mark.parametrize("n_dimer", [75, 200])
+def test_wide_tile_chain_matches_standard_tiles(ctx, n_dimer):
+    """N = 150 and 400: the single-product stage runs on the 160-wide BF16
+    tile.  Against the same chain on 128-wide tiles only, the results differ
+    by the FP32 accumulation order of that stage alone."""
+    pb = chain(n_dimer, 100.0, 3, 1e-3)
+    B, G, Gb, mu, tau, w = _gpu_inputs(ctx, pb, torch.float32)
+    spl = ctx.split(B, pb["eps"])
+    try:
+        ctx.set_gemm_tiles(False)
+        S0, e0 = ctx.sigma_tau(spl, B, G, Gb, ns=3, seed=4, prec="bf16")
+        ctx.set_gemm_tiles(True)
+        S1, e1 = ctx.sigma_tau(spl, B, G, Gb, ns=3, seed=4, prec="bf16")
+    finally:
+        ctx.set_gemm_tiles(True)
+    assert not torch.equal(e0, e1)                 # the wide tile did run
+    assert rel(S1.cpu().numpy(), S0.cpu().numpy()) < 1e-6
+    assert rel(e1.cpu().numpy(), e0.cpu().numpy()) < 1e-5
