@@ -39,8 +39,13 @@ MFMA_PEAK = {"bf16": 2.5e15, "bf16x3": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12
 # 256 MiB copy in the same runs), recorded with the hash of the kernel source
 # they were taken on: reported only while that source is unchanged.
 GEMM_TRAFFIC = {
-    ("bf16", "n800"): {"bytes_per_launch": (821349.9 * 1.9997 + 658565.7) * 1024.0,
-                       "gemm_src_sha256_16": "6b04e5cd20ddba11",
+    # launch-weighted mean of the two BF16 chain GEMM kernels at N=800
+    # (128-wide tile: 8448 launches of stages s1-s3, FETCH 402379.6 / WRITE
+    # 839264.6 KiB; 160-wide tile: 2816 launches of stage s4, FETCH 945070.2 /
+    # WRITE 143361.7 KiB), FETCH scaled by 1.9997 from a plain copy
+    ("bf16", "n800"): {"bytes_per_launch": ((402379.6 * 1.9997 + 839264.6) * 8448 + (945070.2 * 1.9997 + 143361.7) * 2816)
+                                         / 11264 * 1024.0,
+                       "gemm_src_sha256_16": "7291b473c0b2a35a",
                        "profile": "profiles/chain_n800_bf16.md"},
 }
 
