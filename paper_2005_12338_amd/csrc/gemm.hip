@@ -546,11 +546,27 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
   double hsum[kMaxHad] = {0.0, 0.0, 0.0, 0.0};
   const int nh = pb.nhad;
   const int ac = acc_col<P, MT>(lane);
-  // Row-major outputs are written element by element (consecutive lanes hold
-  // consecutive columns).  For 32 x 32 tiles, accumulators 4q .. 4q+3 of a
-  // lane are four consecutive rows, so transposed outputs are written as one
-  // 4-element vector per lane.
+  // For 32 x 32 tiles, accumulators 4q .. 4q+3 of a lane are four
+  // consecutive rows, so transposed outputs are written as one 4-element
+  // vector per lane.  Row-major outputs hold consecutive columns in
+  // consecutive lanes: in BF16 (128-wide tiles) they are staged through the
+  // LDS operand buffers (free after the main loop) and written out as
+  // 16-byte row vectors; otherwise element by element.
   constexpr int RG = (P == Prec::F64) ? 1 : 4;            // rows packed per transposed store
+  constexpr bool kStageRows = P == Prec::BF16 && W == 0;
+  int soff[kMaxOut];                                       // byte offset of a staged output
+  bool staged = false;
+  if constexpr (kStageRows) {
+    int total = 0;
+    for (int o = 0; o < nout; ++o) {
+      soff[o] = -1;
+      if (pb.out[o].layout == 0) {
+        soff[o] = total;
+        total += SM * SN * (pb.out[o].type == 0 ? 4 : 2);
+      }
+    }
+    staged = total > 0 && total <= Smem<P, W>::BYTES;
+  }
 #pragma unroll
   for (int gi = 0; gi < GI; ++gi)
 #pragma unroll
@@ -586,7 +602,19 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
             for (int t = 0; t < NPROD; ++t) s += (Acc)os.coef[t] * v[e][t];
             sv[e] = s;
           }
-          if (os.layout != 0 && RG == 4 && full) {
+          if (kStageRows && staged && os.layout == 0) {
+            // tile-local (row, column); out-of-range positions are staged
+            // too but never copied out
+            const int lc = (int)(gc - col0);
+#pragma unroll
+            for (int e = 0; e < RG; ++e) {
+              const int lrw = (int)(grs[e] - row0);
+              if (os.type == 0)
+                ((float*)(smem + soff[o]))[lrw * SN + lc] = sv[e];
+              else
+                ((bf16_t*)(smem + soff[o]))[lrw * SN + lc] = f2bf(sv[e]);
+            }
+          } else if (os.layout != 0 && RG == 4 && full) {
             store_out_vec4<P>(os.type, obase[o], gc * ld + grs[0], L.plane, sv);
           } else {
 #pragma unroll
@@ -611,6 +639,29 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
         }
       }
     }
+  if (kStageRows && staged) {
+    __syncthreads();
+    for (int o = 0; o < nout; ++o) {
+      if (pb.out[o].layout != 0) continue;
+      const int es = pb.out[o].type == 0 ? 4 : 2;
+      const int vl = 16 / es;                 // elements per 16-byte vector
+      const int vpr = SN / vl;                // vectors per tile row
+      const unsigned char* src = smem + soff[o];
+      char* dst = (char*)obase[o];
+      for (int idx = tid; idx < SM * vpr; idx += kThreads) {
+        const int r = idx / vpr, c = (idx % vpr) * vl;
+        const int64_t gr = row0 + r, gcc = col0 + c;
+        if (gr >= mrows || gcc >= ncols) continue;
+        const int64_t gi = gr * ld + gcc;
+        if (gcc + vl <= ncols) {
+          *(u32x4_t*)(dst + gi * es) = *(const u32x4_t*)(src + (r * SN + c) * es);
+        } else {
+          for (int e = 0; e < vl && gcc + e < ncols; ++e)
+            for (int bq = 0; bq < es; ++bq) dst[(gi + e) * es + bq] = (char)src[(r * SN + c + e) * es + bq];
+        }
+      }
+    }
+  }
   if (nh) {
     // deterministic block reduction: wave tree, then the four waves in order
     for (int q = 0; q < nh; ++q) {
