@@ -40,12 +40,12 @@ MFMA_PEAK = {"bf16": 2.5e15, "bf16x3": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12
 # they were taken on: reported only while that source is unchanged.
 GEMM_TRAFFIC = {
     # launch-weighted mean of the two BF16 chain GEMM kernels at N=800
-    # (128-wide tile: 8448 launches of stages s1-s3, FETCH 402379.6 / WRITE
-    # 839264.6 KiB; 160-wide tile: 2816 launches of stage s4, FETCH 945070.2 /
-    # WRITE 143361.7 KiB), FETCH scaled by 1.9997 from a plain copy
-    ("bf16", "n800"): {"bytes_per_launch": ((402379.6 * 1.9997 + 839264.6) * 8448 + (945070.2 * 1.9997 + 143361.7) * 2816)
+    # (128-wide tile: 8448 launches of stages s1-s3, FETCH 393739.4 / WRITE
+    # 754652.7 KiB; 160-wide tile: 2816 launches of stage s4, FETCH 944954.3 /
+    # WRITE 143389.2 KiB), FETCH scaled by 1.9997 from a plain copy
+    ("bf16", "n800"): {"bytes_per_launch": ((393739.4 * 1.9997 + 754652.7) * 8448 + (944954.3 * 1.9997 + 143389.2) * 2816)
                                          / 11264 * 1024.0,
-                       "gemm_src_sha256_16": "7291b473c0b2a35a",
+                       "gemm_src_sha256_16": "d0658038cad4d977",
                        "profile": "profiles/chain_n800_bf16.md"},
 }
 
