@@ -227,6 +227,25 @@ gf2_status gf2_energy(gf2_ctx* ctx, int64_t n, int64_t ntau, const double* w,
                       const double* e_samples, int64_t ns, double n_elec,
                       double* E_tot, double* E_per_e, double* stderr_tot);
 
+/* gf2_energy_noalloc: gf2_energy for callers that cannot allocate device
+ * memory -- code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same kernels and arithmetic as gf2_energy, with
+ * every argument on the DEVICE: w [ntau], Sigma and Gbar [ntau][n][n],
+ * e_samples [ns][ntau] or NULL, out [3] = {E_tot, E_tot / n_elec, stderr}.
+ * It allocates nothing and does not synchronise: it only enqueues kernels on
+ * the context's stream.  Its scratch (per-tau traces and result slots) is a
+ * fixed library array of 520 doubles per GPU, resolved by gf2_create and
+ * held until the process ends, so ntau is limited to 512.  Every call on a
+ * GPU shares that array: calls that overlap on one GPU (other streams, other
+ * threads, other contexts) race and must be ordered by the caller.
+ * Errors: GF2_E_ARG (ntau > 512, n_elec <= 0, ns < 2 with e_samples, null
+ * pointers).  Non-finite results are written through, not reported (a check
+ * would need a host synchronisation). */
+gf2_status gf2_energy_noalloc(gf2_ctx* ctx, int64_t n, int64_t ntau, const double* w,
+                              const double* Sigma, const double* Gbar,
+                              const double* e_samples, int64_t ns, double n_elec,
+                              double* out);
+
 /* ------------------------------------------------------------ RNG ---------
  * word(seed, stream, s, q) = mix(seed * 0x9E3779B97F4A7C15
  *                                + ((stream << 62) | (s << 32) | q) + 1),

@@ -172,6 +172,14 @@ gf2_status gf2_create(gf2_ctx** out, int device, void* stream) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return GF2_E_DEVICE;
   if (device < 0 || device >= ndev) return GF2_E_ARG;
+  {
+    // the no-allocation entry point's fixed scratch, resolved once per device
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess) return GF2_E_DEVICE;
+    const gf2_status st = noalloc_attach(device);
+    (void)hipSetDevice(prev);
+    if (st != GF2_OK) return st;
+  }
   gf2_ctx* c = new (std::nothrow) gf2_ctx();
   if (!c) return GF2_E_NOMEM;
   c->device = device;

@@ -123,6 +123,9 @@ struct GemmLaunch {
   int32_t wide;         // BF16 wide tile (single instance, single-product problems)
 };
 
+// Resolves the fixed scratch of gf2_energy_noalloc on `device` (current).
+gf2_status noalloc_attach(int device);
+
 // Kernel launchers (device code in separate translation units).
 void launch_gemm(Prec p, const GemmLaunch& L, int max_tiles, hipStream_t st);
 // Chain launch: square n x n products stored with leading dimension np.

@@ -95,6 +95,8 @@ _SIGS = {
     "gf2_energy": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_double), C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.POINTER(C.c_double),
                              C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "gf2_energy_noalloc": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_int64, C.c_double, C.c_void_p]),
     "gf2_rng_words": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int64,
                                 C.POINTER(C.c_uint64)]),
     "gf2_set_profiling": (C.c_int, [C.c_void_p, C.c_int]),
@@ -418,6 +420,15 @@ class Context:
                                         _ptr(e_samples), ns, float(n_elec), C.byref(e), C.byref(epe),
                                         C.byref(se)))
         return e.value, epe.value, se.value
+
+    def energy_noalloc(self, Sigma, Gb, w_dev, n_elec: float, out, e_samples=None):
+        """gf2_energy_noalloc: every argument on the device; out[3] receives
+        (E_tot, E_per_e, stderr).  Enqueues kernels only (no allocation, no
+        synchronisation)."""
+        ntau, n, _ = Sigma.shape
+        ns = 0 if e_samples is None else e_samples.shape[0]
+        self._check(self.lib.gf2_energy_noalloc(self.h, n, ntau, w_dev.data_ptr(), Sigma.data_ptr(), Gb.data_ptr(),
+                                                _ptr(e_samples), ns, float(n_elec), out.data_ptr()))
 
     def debug_gemm(self, prec: str, n: int, A, Bt, Cout, batch: int = 1):
         """C[b] = A[b] Bt[b]^T with the chain's GEMM kernel (padded square operands)."""
