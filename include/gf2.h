@@ -60,9 +60,19 @@ typedef enum {
   GF2_PREC_FP32 = 1,
   GF2_PREC_BF16 = 2,
   GF2_PREC_BF16X3 = 3,
-  GF2_PREC_AUTO = 4    /* gf2_energy_adaptive only: BF16, switching to
-                          BF16X3 when the measured BF16 rounding of a probe
-                          pair exceeds 0.1x the standard error reached     */
+  GF2_PREC_AUTO = 4,   /* gf2_energy_adaptive only: BF16 with the
+                          two-level correction below, switching to BF16X3
+                          when the correction is not precise enough        */
+  GF2_PREC_BF16C = 5   /* gf2_sigma_tau / gf2_sigma_stoch only: two-level
+                          estimator.  Every pair runs in BF16; the first
+                          k = min(ns, 8) pairs also run in BF16X3, and
+                          Sigma_sum and the per-pair traces are moved by
+                          the mean BF16X3 - BF16 difference of those pairs
+                          (ns/k times their summed difference).  BF16
+                          rounding biases every pair alike (its second-order
+                          terms do not average out over pairs); the
+                          correction removes that bias in expectation and
+                          leaves std(difference)/sqrt(k) of it            */
 } gf2_precision;
 
 /* How the stochastic orbitals are drawn (counter-based SplitMix64, see
@@ -274,13 +284,6 @@ gf2_status gf2_profile_read(gf2_ctx* ctx, int32_t cap, char* names, int64_t* lau
  * modes. */
 gf2_status gf2_set_gemm_tiles(gf2_ctx* ctx, int32_t mode);
 
-/* ------------------------------------------------------------ test hook ---
- * The chain's GEMM kernel on its own: C[b] = A[b] B[b]^T for b < batch,
- * square n x n operands (row-major, leading dimension ld = n rounded up to a
- * multiple of 32, zero padded, device).  prec FP64: double operands and
- * output; FP32: float; BF16: bf16 operands, float output; BF16X3: each
- * operand is two bf16 planes (hi, lo) of ld*ld elements each.  For tests and
- * benchmarks of the kernel itself. */
 /* ------------------------------------------------------------ batch -------
  * Many chains of uneven size in one schedule: every instance's (tau, pair)
  * units go through the same grouped product launches (each unit carries its
@@ -322,14 +325,18 @@ gf2_status gf2_sigma_batch(gf2_ctx* ctx, int32_t nitem, const gf2_batch_item* it
  * pairs - 1 degrees of freedom; 1.80x the estimate at 8 pairs, 1.26x at 32),
  * so a small first batch cannot stop on a lucky low estimate.
  *
- * prec GF2_PREC_AUTO: the batches run in BF16.  Pairs 0 and 1 are also
- * evaluated in BF16X3; the largest differences of their energies,
- * b = max |E_s(BF16) - E_s(BF16X3)|, and of their per-tau traces e_s(tau)
- * estimate the BF16 rounding of a pair.  If 2b >= 0.1 x the standard error
- * reached, or, for some tau, twice the trace difference >= the larger of
- * 0.1 x the standard error of that tau's mean trace and 1e-5 x the trace
- * Tr(Sigma(tau) Gbar(tau)), every pair is recomputed in BF16X3 (same theta)
- * and sampling continues in BF16X3.  batch must then be >= 2.
+ * prec GF2_PREC_AUTO: the two-level estimator.  Pairs 0 .. k-1
+ * (k = min(8, max_pairs)) run in BF16 and in BF16X3, then the batches in
+ * BF16; at the end Sigma and the per-pair traces are moved by the mean
+ * BF16X3 - BF16 difference d of the k probe pairs (scaled to all pairs),
+ * which removes the BF16 rounding bias in expectation.  If twice the
+ * standard error of that mean, std(d_E)/sqrt(k), is >= 0.1 x the standard
+ * error reached, or, for some tau, twice the standard error of the mean
+ * trace difference is >= the larger of 0.1 x the standard error of that
+ * tau's mean trace and 1e-5 x the trace Tr(Sigma(tau) Gbar(tau)), every
+ * pair is recomputed in BF16X3 (same theta) and sampling continues in
+ * BF16X3.  res->precision reports BF16C or BF16X3; res->bias_probe the
+ * |mean d_E| removed.  batch must be >= 2.
  *
  * Inputs as gf2_sigma_stoch; w host [ntau] quadrature weights; Sigma_det
  * device [ntau][n][n] (gf2_sigma_det).  Outputs: Sigma device [ntau][n][n]
@@ -367,6 +374,13 @@ gf2_status gf2_energy_adaptive_det(gf2_ctx* ctx, const gf2_split_h* split, const
                                    double* Sigma_det, double* Sigma, double* e_samples,
                                    gf2_adaptive_result* res);
 
+/* ------------------------------------------------------------ test hook ---
+ * The chain's GEMM kernel on its own: C[b] = A[b] B[b]^T for b < batch,
+ * square n x n operands (row-major, leading dimension ld = n rounded up to a
+ * multiple of 32, zero padded, device).  prec FP64: double operands and
+ * output; FP32: float; BF16: bf16 operands, float output; BF16X3: each
+ * operand is two bf16 planes (hi, lo) of ld*ld elements each.  For tests and
+ * benchmarks of the kernel itself. */
 gf2_status gf2_debug_gemm(gf2_ctx* ctx, gf2_precision prec, int64_t n, int64_t batch,
                           const void* A, const void* Bt, void* C);
 

@@ -24,19 +24,14 @@ void launch_mlp_infer(const gf2_mlp& m, const double* phi, int64_t naux, int bf1
 namespace {
 
 constexpr double kGM = 0.5;   // E = -1/2 int Tr(Sigma Gbar): the MP2 limit fixes it
+constexpr int64_t kLevelProbe = 8;   // pairs run at both levels (BF16 and BF16X3) by BF16C and AUTO
 
 // ------------------------------------------------------------ scratch ----
-struct Scratch {
-  std::map<std::string, DevBuf> bufs;
-};
-std::map<const gf2_ctx*, Scratch>& scratch_table() {
-  static std::map<const gf2_ctx*, Scratch> t;
-  return t;
-}
-
+// Named device buffers owned by the context (grown on demand, never shrunk,
+// freed by gf2_destroy).  The map lives in the context, so contexts used
+// from different host threads share nothing.
 void* ctx_buf(gf2_ctx* ctx, const std::string& tag, size_t bytes, bool zero = false) {
-  auto& s = scratch_table()[ctx];
-  DevBuf& b = s.bufs[tag];
+  DevBuf& b = ctx->bufs[tag];
   if (bytes == 0) bytes = 16;
   if (b.bytes < bytes) {
     if (b.p) {
@@ -48,6 +43,7 @@ void* ctx_buf(gf2_ctx* ctx, const std::string& tag, size_t bytes, bool zero = fa
     hipError_t e = hipMalloc(&b.p, bytes);
     if (e != hipSuccess) {
       b.p = nullptr;
+      (void)hipGetLastError();   // clear the runtime's sticky error: later launch checks must not see it
       throw Gf2Error{GF2_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes for " + tag +
                                       " failed: " + hipGetErrorString(e)};
     }
@@ -58,13 +54,10 @@ void* ctx_buf(gf2_ctx* ctx, const std::string& tag, size_t bytes, bool zero = fa
   return b.p;
 }
 
-void free_scratch(const gf2_ctx* ctx) {
-  auto& t = scratch_table();
-  auto it = t.find(ctx);
-  if (it == t.end()) return;
-  for (auto& kv : it->second.bufs)
+void free_scratch(gf2_ctx* ctx) {
+  for (auto& kv : ctx->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
-  t.erase(it);
+  ctx->bufs.clear();
 }
 
 template <typename T>
@@ -103,8 +96,9 @@ Prec to_prec(gf2_precision p) {
     case GF2_PREC_FP32: return Prec::F32;
     case GF2_PREC_BF16: return Prec::BF16;
     case GF2_PREC_BF16X3: return Prec::BF16X3;
+    default: break;
   }
-  throw Gf2Error{GF2_E_ARG, "unknown precision"};
+  throw Gf2Error{GF2_E_ARG, "precision not available here (AUTO: adaptive calls; BF16C: single-chain calls)"};
 }
 size_t st_elem(Prec p) { return p == Prec::F64 ? 8 : p == Prec::F32 ? 4 : 2; }
 int st_planes(Prec p) { return p == Prec::BF16X3 ? 2 : 1; }
@@ -422,7 +416,10 @@ gf2_status gf2_split(gf2_ctx* ctx, const void* B, gf2_dtype dtype, int64_t n, in
     auto alloc = [&](void** p, size_t bytes) {
       if (bytes == 0) bytes = 16;
       hipError_t e = hipMalloc(p, bytes);
-      if (e != hipSuccess) throw Gf2Error{GF2_E_NOMEM, "split allocation failed"};
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Gf2Error{GF2_E_NOMEM, "split allocation failed"};
+      }
     };
     alloc((void**)&h->w, naux * 4);
     alloc((void**)&h->idx, naux * kWMax * 4);
@@ -781,10 +778,11 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
   c.st_sl = (int64_t)(sb / st_elem(prec));        // elements per storage slot
   c.ac_sl = (int64_t)np2;
   const int64_t st_sl = c.st_sl, ac_sl = c.ac_sl;
+  const OpRef g_op = opref(gst, planes * np2);      // G(tau), G(beta - tau): one matrix per tau
+  const OpRef gb_op = opref(gbst, planes * np2);
 
   // ---- problem tables
   const int64_t vst = planes * np2;                            // one vector
-  const int64_t gstride = planes * np2;                        // one tau of G storage
   std::vector<Prob>& P = c.P;
   P.clear();
   // S1: U = X G (dual A), V = G Y (dual B)
@@ -793,7 +791,7 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
     p.nA = 2;
     p.a[0] = opref(xl, 0, vst);
     p.a[1] = opref(xs, 0, vst);
-    p.b[0] = opref(gst, gstride);
+    p.b[0] = g_op;
     p.nout = 4;
     p.out[0] = outspec(ul_n, st_sl, {1, 0}, 0, 1);
     p.out[1] = outspec(ul_t, st_sl, {1, 0}, 1, 1);
@@ -802,7 +800,7 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
     P.push_back(p);
     Prob q = prob0();
     q.nB = 2;
-    q.a[0] = opref(gst, gstride);
+    q.a[0] = g_op;
     q.b[0] = opref(xl + sb * ns, 0, vst);
     q.b[1] = opref(xs + sb * ns, 0, vst);
     q.nout = 4;
@@ -851,14 +849,14 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
     w.nA = 2;
     w.a[0] = opref(vl_n, 0, 0, st_sl);
     w.a[1] = opref(vs_n, 0, 0, st_sl);
-    w.b[0] = opref(gbst, gstride);
+    w.b[0] = gb_op;
     w.nout = 2;
     w.out[0] = outspec(wz + 0 * ab, 4 * ac_sl, {1, 0}, 0, 0);
     w.out[1] = outspec(wz + 1 * ab, 4 * ac_sl, {0, 1}, 0, 0);
     P.push_back(w);
     Prob z = prob0();
     z.nB = 2;
-    z.a[0] = opref(gbst, gstride);
+    z.a[0] = gb_op;
     z.b[0] = opref(ul_t, 0, 0, st_sl);
     z.b[1] = opref(us_t, 0, 0, st_sl);
     z.nout = 2;
@@ -872,7 +870,7 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
     p.nA = 2;
     p.a[0] = opref(mst + (2 * h) * sb, 0, 0, 4 * st_sl);
     p.a[1] = opref(mst + (2 * h + 1) * sb, 0, 0, 4 * st_sl);
-    p.b[0] = opref(gbst, gstride);
+    p.b[0] = gb_op;
     p.nout = 2;
     p.out[0] = outspec(tq + (2 * h) * sb, 4 * st_sl, {1, 0}, 0, 1);
     p.out[1] = outspec(tq + (2 * h + 1) * sb, 4 * st_sl, {0, 1}, 0, 1);
@@ -976,6 +974,37 @@ void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double*
   GF2_HIP(hipStreamSynchronize(ctx->stream));
 }
 
+// run_stoch at a gf2_precision: BF16C is the two-level estimator -- every
+// pair in BF16, the first k = min(ns, kLevelProbe) pairs also in BF16X3, and
+// Sigma_sum and the per-pair traces moved by the mean BF16X3 - BF16
+// difference of those pairs (ns / k times their summed difference).
+void run_stoch_prec(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double* G, const double* Gbar,
+                    int64_t ntau, const gf2_sampling* smp, gf2_precision prec, double* Sigma_sum,
+                    double* e_samples) {
+  if (prec != GF2_PREC_BF16C) {
+    run_stoch(ctx, sp, B, G, Gbar, ntau, smp, to_prec(prec), Sigma_sum, e_samples);
+    return;
+  }
+  const int64_t ns = smp->ns, k = std::min<int64_t>(ns, kLevelProbe);
+  const size_t mat = (size_t)(ntau * sp->n * sp->n);
+  auto* lo = (double*)ctx_buf(ctx, "l_lo", mat * 8, true);
+  auto* hi = (double*)ctx_buf(ctx, "l_hi", mat * 8, true);
+  auto* ehi = (double*)ctx_buf(ctx, "l_ehi", (size_t)(k * ntau) * 8);
+  auto* elo = e_samples ? e_samples : (double*)ctx_buf(ctx, "l_elo", (size_t)(k * ntau) * 8);
+  gf2_sampling part = *smp;
+  part.ns = k;
+  run_stoch(ctx, sp, B, G, Gbar, ntau, &part, Prec::BF16, lo, elo);
+  run_stoch(ctx, sp, B, G, Gbar, ntau, &part, Prec::BF16X3, hi, ehi);
+  if (ns > k) {
+    part.s0 = smp->s0 + k;
+    part.ns = ns - k;
+    run_stoch(ctx, sp, B, G, Gbar, ntau, &part, Prec::BF16, Sigma_sum, e_samples ? e_samples + k * ntau : nullptr);
+  }
+  launch_level_correct(Sigma_sum, hi, lo, (int64_t)mat, (double)ns / (double)k, ctx->stream);
+  if (e_samples) launch_level_shift(e_samples, ehi, k, ns, ntau, ctx->stream);
+  GF2_HIP(hipGetLastError());
+}
+
 void check_sampling(const gf2_split_h* sp, const gf2_sampling* s) {
   GF2_REQUIRE(s, GF2_E_ARG, "sampling is null");
   GF2_REQUIRE(s->ns >= 1 && s->s0 >= 0 && s->s0 + s->ns <= (1 << 30), GF2_E_ARG, "bad ns / s0");
@@ -1005,7 +1034,7 @@ gf2_status gf2_sigma_stoch(gf2_ctx* ctx, const gf2_split_h* split, const void* B
     GF2_REQUIRE(B == split->bsrc, GF2_E_STATE, "split handle belongs to a different B");
     GF2_REQUIRE(G && Gbar && Sigma_sum && ntau > 0 && ntau <= 4096, GF2_E_ARG, "bad sigma arguments");
     check_sampling(split, sampling);
-    run_stoch(ctx, split, B, G, Gbar, ntau, sampling, to_prec(prec), Sigma_sum, e_samples);
+    run_stoch_prec(ctx, split, B, G, Gbar, ntau, sampling, prec, Sigma_sum, e_samples);
   });
 }
 
@@ -1033,7 +1062,7 @@ gf2_status gf2_sigma_tau(gf2_ctx* ctx, const gf2_split_h* split, const void* B, 
     auto* det = (double*)ctx_buf(ctx, "t_det", bytes);
     auto* sum = (double*)ctx_buf(ctx, "t_sum", bytes, true);
     run_dd(ctx, split, G, Gbar, ntau, det);
-    run_stoch(ctx, split, B, G, Gbar, ntau, sampling, to_prec(prec), sum, e_samples);
+    run_stoch_prec(ctx, split, B, G, Gbar, ntau, sampling, prec, sum, e_samples);
     launch_finalize(det, sum, n, ntau, 0.5 / (double)sampling->ns, Sigma, ctx->stream);
     GF2_HIP(hipGetLastError());
     check_finite(ctx, Sigma, ntau * n * n, "Sigma");
@@ -1433,79 +1462,97 @@ void adaptive_core(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const 
       GF2_HIP(hipStreamSynchronize(ctx->stream));
       GF2_REQUIRE(std::isfinite(h[0]) && std::isfinite(h[2]), GF2_E_NUMERIC, "non-finite energy");
     };
-    // AUTO: pairs 0 and 1 also in BF16X3; their energies and per-tau traces
-    // against the BF16 ones measure the BF16 rounding of a pair.
-    constexpr int kProbe = 2;
-    std::vector<double> e_hi, d_probe;
+    // AUTO (two-level estimator): every pair runs in BF16; the first kp
+    // pairs also run in BF16X3.  Their differences d_q = BF16X3 - BF16 (per
+    // pair energy and per-tau trace) estimate the BF16 rounding bias, which
+    // is removed from the final mean; the correction's own uncertainty is
+    // std(d)/sqrt(kp).
+    const int64_t kp = autop ? std::min<int64_t>(kLevelProbe, max_pairs) : 0;
+    double* psum16 = nullptr;
+    double* psum3 = nullptr;
+    double* eprobe = nullptr;
+    std::vector<double> dE, de;              // per probe pair: energy, and [kp][ntau] traces
     double bias = 0.0;
+    int64_t pairs = 0;
     if (autop) {
-      auto* ssum = (double*)ctx_buf(ctx, "a_probe_sum", mat * 8, true);
-      auto* eprobe = (double*)ctx_buf(ctx, "a_probe_e", (size_t)(kProbe * ntau) * 8);
+      psum16 = (double*)ctx_buf(ctx, "a_probe_lo", mat * 8, true);
+      psum3 = (double*)ctx_buf(ctx, "a_probe_hi", mat * 8, true);
+      eprobe = (double*)ctx_buf(ctx, "a_probe_e", (size_t)(kp * ntau) * 8);
       smp.s0 = 0;
-      smp.ns = kProbe;
-      run_stoch(ctx, split, B, G, Gbar, ntau, &smp, Prec::BF16X3, ssum, eprobe);
-      e_hi.resize((size_t)(kProbe * ntau));
-      d2h(ctx, e_hi.data(), eprobe, e_hi.size());
+      smp.ns = kp;
+      run_stoch(ctx, split, B, G, Gbar, ntau, &smp, Prec::BF16, psum16, e_samples);
+      run_stoch(ctx, split, B, G, Gbar, ntau, &smp, Prec::BF16X3, psum3, eprobe);
+      std::vector<double> lo((size_t)(kp * ntau)), hi((size_t)(kp * ntau));
+      d2h(ctx, lo.data(), e_samples, lo.size());
+      d2h(ctx, hi.data(), eprobe, hi.size());
+      dE.assign((size_t)kp, 0.0);
+      de.assign((size_t)(kp * ntau), 0.0);
+      for (int64_t q = 0; q < kp; ++q)
+        for (int64_t t = 0; t < ntau; ++t) {
+          de[q * ntau + t] = hi[q * ntau + t] - lo[q * ntau + t];
+          dE[q] += -kGM * w[t] * de[q * ntau + t];
+        }
+      double m = 0.0;
+      for (int64_t q = 0; q < kp; ++q) m += dE[q];
+      bias = std::fabs(m / (double)kp);
+      pairs = kp;
     }
-    // BF16 is kept only if the probe's rounding, with a safety factor of 2,
-    // is below 0.1x the standard error of the total, and, for every tau,
-    // below 0.1x the standard error of the mean trace or 1e-5 of the trace
-    // Tr(Sigma(tau) Gbar(tau)) itself (the FP32 path's relative tolerance;
-    // at tau points where the stochastic part vanishes its standard error
-    // does too).
-    auto bf16_ok = [&](int64_t pairs, double se_tot) {
-      if (2.0 * bias >= 0.1 * se_tot) return false;
+    // sample mean and standard error of the mean of x[0..k)
+    auto mean_se = [](const double* x, int64_t k, int64_t stride) {
+      double m = 0.0, v = 0.0;
+      for (int64_t q = 0; q < k; ++q) m += x[q * stride];
+      m /= (double)k;
+      for (int64_t q = 0; q < k; ++q) v += (x[q * stride] - m) * (x[q * stride] - m);
+      return std::make_pair(m, k > 1 ? std::sqrt(v / (double)(k - 1) / (double)k) : INFINITY);
+    };
+    // The corrected BF16 mean is accepted if twice the correction's
+    // uncertainty is below 0.1x the standard error of the total, and, for
+    // every tau, below the larger of 0.1x the standard error of the mean
+    // trace and 1e-5 of the trace Tr(Sigma(tau) Gbar(tau)) itself (the FP32
+    // path's relative tolerance; at tau points where the stochastic part
+    // vanishes its standard error does too).
+    auto bf16_ok = [&](int64_t np_, double se_tot) {
+      if (2.0 * mean_se(dE.data(), kp, 1).second >= 0.1 * se_tot) return false;
       ensure_tr();
-      std::vector<double> es((size_t)(pairs * ntau)), trh((size_t)ntau);
+      std::vector<double> es((size_t)(np_ * ntau)), trh((size_t)ntau);
       d2h(ctx, es.data(), e_samples, es.size());
       d2h(ctx, trh.data(), tr, trh.size());
       for (int64_t t = 0; t < ntau; ++t) {
-        double m = 0.0, v = 0.0;
-        for (int64_t q = 0; q < pairs; ++q) m += es[q * ntau + t];
-        m /= (double)pairs;
-        for (int64_t q = 0; q < pairs; ++q) v += (es[q * ntau + t] - m) * (es[q * ntau + t] - m);
-        const double se_t = std::sqrt(v / (double)(pairs - 1) / (double)pairs);
-        const double bar = std::max(0.1 * se_t, 1e-5 * std::fabs(trh[t] + m));
-        if (2.0 * d_probe[t] >= bar) return false;
+        const auto st_ = mean_se(es.data() + t, np_, ntau);
+        const double bar = std::max(0.1 * st_.second, 1e-5 * std::fabs(trh[t] + st_.first));
+        if (2.0 * mean_se(de.data() + t, kp, ntau).second >= bar) return false;
       }
       return true;
     };
-    int64_t pairs = 0;
     double h[4] = {0, 0, 0, 0};
-    bool probed = false;
     while (true) {
+      if (pairs >= 2) {
+        stat(pairs, h);
+        bool done = stderr_upper(h[2], pairs) < target || pairs >= max_pairs;
+        if (done && autop && wp == Prec::BF16 && !bf16_ok(pairs, h[2])) {
+          // the correction is not precise enough at this error: redo every
+          // pair in BF16X3 (same theta) and go on sampling in BF16X3
+          wp = Prec::BF16X3;
+          GF2_HIP(hipMemsetAsync(sum, 0, mat * 8, ctx->stream));
+          for (int64_t s0 = 0; s0 < pairs; s0 += batch) run(s0, std::min(batch, pairs - s0), wp);
+          stat(pairs, h);
+          done = stderr_upper(h[2], pairs) < target || pairs >= max_pairs;
+        }
+        if (done) break;
+      }
       const int64_t cnt = std::min(batch, max_pairs - pairs);
       if (cnt <= 0) break;
       run(pairs, cnt, wp);
       pairs += cnt;
-      if (autop && !probed && pairs >= kProbe) {
-        std::vector<double> e_lo((size_t)(kProbe * ntau));
-        d2h(ctx, e_lo.data(), e_samples, e_lo.size());
-        d_probe.assign(ntau, 0.0);
-        for (int q = 0; q < kProbe; ++q) {
-          double d = 0.0;
-          for (int64_t t = 0; t < ntau; ++t) {
-            const double dt = e_lo[q * ntau + t] - e_hi[q * ntau + t];
-            d_probe[t] = std::max(d_probe[t], std::fabs(dt));
-            d += w[t] * dt;
-          }
-          bias = std::max(bias, std::fabs(kGM * d));
-        }
-        probed = true;
-      }
-      if (pairs < 2) continue;
+    }
+    if (autop && wp == Prec::BF16) {
+      // Sigma_sum and the samples to the BF16X3 level: sum += lo + (pairs/kp)(hi - lo)
+      launch_level_correct(sum, psum3, psum16, (int64_t)mat, (double)pairs / (double)kp, ctx->stream);
+      launch_level_shift(e_samples, eprobe, kp, pairs, ntau, ctx->stream);
+      GF2_HIP(hipGetLastError());
       stat(pairs, h);
-      bool done = stderr_upper(h[2], pairs) < target || pairs >= max_pairs;
-      if (done && autop && wp == Prec::BF16 && !bf16_ok(pairs, h[2])) {
-        // BF16 rounding is not negligible at this error: redo every pair in
-        // BF16X3 (same theta) and go on sampling in BF16X3
-        wp = Prec::BF16X3;
-        GF2_HIP(hipMemsetAsync(sum, 0, mat * 8, ctx->stream));
-        for (int64_t s0 = 0; s0 < pairs; s0 += batch) run(s0, std::min(batch, pairs - s0), wp);
-        stat(pairs, h);
-        done = stderr_upper(h[2], pairs) < target || pairs >= max_pairs;
-      }
-      if (done) break;
+    } else if (autop) {
+      bias = 0.0;                 // every pair ran in BF16X3: nothing corrected
     }
     ensure_tr();
     launch_finalize(Sigma_det, sum, n, ntau, 0.5 / (double)pairs, Sigma, ctx->stream);
@@ -1516,7 +1563,7 @@ void adaptive_core(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const 
     res->stderr_tot = h[2];
     res->pairs = pairs;
     res->precision = wp == Prec::F64 ? GF2_PREC_FP64 : wp == Prec::F32 ? GF2_PREC_FP32
-                     : wp == Prec::BF16 ? GF2_PREC_BF16 : GF2_PREC_BF16X3;
+                     : wp == Prec::BF16 ? (autop ? GF2_PREC_BF16C : GF2_PREC_BF16) : GF2_PREC_BF16X3;
     res->bias_probe = bias;
   }
 }

@@ -148,7 +148,7 @@ struct gf2_ctx {
   hipStream_t stream = nullptr;
   hipStream_t aux = nullptr;      // second stream (default priority, non-blocking), made on first use
   std::string err;
-  std::vector<DevBuf> pool;       // scratch allocations owned by the context
+  std::map<std::string, DevBuf> bufs;   // named scratch buffers owned by the context
   int64_t max_units = 0;          // chunk size tuning (0 = automatic)
   int32_t gemm_wide = 1;          // 1: wide BF16 tile where it pads less; 0: standard tiles only
   // (n, np, precision) of the last chain layout per buffer-tag prefix

@@ -428,6 +428,28 @@ __global__ void k_finalize(const double* det, const double* sum, int64_t n, int6
   out[e] = det[e] + inv2ns * (s[i * n + j] + s[j * n + i]);
 }
 
+// Two-level correction of the BF16 estimator.  sum += lo + c (hi - lo):
+// the BF16 sum of the probe pairs (lo) joins the rest of the pairs, and c =
+// ns / k times the probe pairs' BF16X3 - BF16 difference moves the total to
+// the BF16X3 level in expectation.
+__global__ void k_level_correct(double* sum, const double* hi, const double* lo, int64_t count, double c) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  sum[e] += lo[e] + c * (hi[e] - lo[e]);
+}
+// shift[t] = (1/k) sum_{q<k} (hi[q][t] - es[q][t]) (fixed order), then every
+// sample row q < ns gets es[q][t] += shift[t].  One block, ntau <= 4096.
+__global__ void k_level_shift(double* es, const double* hi, int64_t k, int64_t ns, int64_t ntau) {
+  __shared__ double shift[4096];
+  for (int64_t t = threadIdx.x; t < ntau; t += blockDim.x) {
+    double d = 0.0;
+    for (int64_t q = 0; q < k; ++q) d += hi[q * ntau + t] - es[q * ntau + t];
+    shift[t] = d / (double)k;
+  }
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < ns * ntau; e += blockDim.x) es[e] += shift[e % ntau];
+}
+
 // ------------------------------------------------------------- energy -----
 // tr[t] = sum_ij Sigma[t]_ij Gbar[t]_ji: one block per tau, fixed-order tree.
 __global__ void k_trace_prod(const double* sig, const double* gb, int64_t n, double* tr) {
@@ -640,6 +662,13 @@ void launch_esamples(const Unit* units, int32_t nunit, const double* part, int64
 void launch_finalize(const double* det, const double* sum, int64_t n, int64_t ntau, double inv2ns,
                      double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(blocks(ntau * n * n)), dim3(256), 0, st, det, sum, n, ntau, inv2ns, out);
+}
+void launch_level_correct(double* sum, const double* hi, const double* lo, int64_t count, double c,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_level_correct, dim3(blocks(count)), dim3(256), 0, st, sum, hi, lo, count, c);
+}
+void launch_level_shift(double* es, const double* hi, int64_t k, int64_t ns, int64_t ntau, hipStream_t st) {
+  hipLaunchKernelGGL(k_level_shift, dim3(1), dim3(256), 0, st, es, hi, k, ns, ntau);
 }
 void launch_trace_prod(const double* sig, const double* gb, int64_t n, int64_t ntau, double* tr,
                        hipStream_t st) {

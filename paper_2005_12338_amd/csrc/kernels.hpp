@@ -47,6 +47,11 @@ void launch_esamples(const Unit* units, int32_t nunit, const double* part, int64
                      int64_t ntau, double* es, hipStream_t st);
 void launch_finalize(const double* det, const double* sum, int64_t n, int64_t ntau, double inv2ns,
                      double* out, hipStream_t st);
+// Two-level (BF16 / BF16X3) correction: sum += lo + c (hi - lo); and the
+// per-tau mean of hi - es over the first k sample rows added to all ns rows.
+void launch_level_correct(double* sum, const double* hi, const double* lo, int64_t count, double c,
+                          hipStream_t st);
+void launch_level_shift(double* es, const double* hi, int64_t k, int64_t ns, int64_t ntau, hipStream_t st);
 void launch_trace_prod(const double* sig, const double* gb, int64_t n, int64_t ntau, double* tr,
                        hipStream_t st);
 void launch_energy_stats(const double* tr, const double* w, int64_t ntau, const double* es, int64_t ns,

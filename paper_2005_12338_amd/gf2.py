@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libgf2.so")
 
 GF2_OK, GF2_E_ARG, GF2_E_DEVICE, GF2_E_NOMEM, GF2_E_NUMERIC, GF2_E_STATE = 0, -1, -2, -3, -4, -5
 GF2_F64, GF2_F32 = 0, 1
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "auto": 4}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "auto": 4, "bf16c": 5}
 PREC_NAME = {v: k for k, v in PREC.items()}
 SAMPLE_RADEMACHER, SAMPLE_IMPORTANCE, SAMPLE_STRATIFIED = 0, 1, 2
 
