@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12                        # B/s
-MFMA_PEAK = {"bf16": 2.5e15, "bf16x3": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}
+MFMA_PEAK = {"bf16": 2.5e15, "bf16c": 2.5e15, "bf16x3": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}
 
 
 # HBM bytes per launch of the chain GEMM from two rocprofv3 PMC passes
@@ -405,7 +405,7 @@ def main():
     ap.add_argument("--workload", default="n800", choices=["n800", "n200", "tiny", "batch", "n1600"])
     ap.add_argument("--batch-count", type=int, default=96, help="chains in the batch workload")
     ap.add_argument("--batch-prec-bf16", action="store_true", help="run the batch in BF16 (default FP32)")
-    ap.add_argument("--prec", default="bf16", choices=["bf16", "bf16x3", "fp32", "fp64"])
+    ap.add_argument("--prec", default="bf16c", choices=["bf16c", "bf16", "bf16x3", "fp32", "fp64"])
     ap.add_argument("--ns", type=int, default=0, help="pairs per step (default: the workload's)")
     ap.add_argument("--gemm-reference", action="store_true",
                     help="only compare the chain GEMM kernel with torch.bmm on the same shapes")
@@ -467,7 +467,8 @@ def main():
     ctx.set_profiling(False)
     ms_step = (t1 - t0) * 1000.0 / args.steps
     log(f"[bench] {args.steps} steps: {ms_step:.1f} ms/step, E={e:.9f} Eh stderr={se_:.3e} Eh")
-    gname = {"bf16": "gemm_bf16", "bf16x3": "gemm_bf16x3", "fp32": "gemm_f32", "fp64": "gemm_f64"}[args.prec]
+    gname = {"bf16": "gemm_bf16", "bf16c": "gemm_bf16", "bf16x3": "gemm_bf16x3", "fp32": "gemm_f32",
+             "fp64": "gemm_f64"}[args.prec]
     gk = dict(launches=0, ms=0.0, flops=0.0, bytes=0.0)
     for k, v in prof.items():                      # the GEMM kernel over all chain stages
         if k == gname or k.startswith(gname + "."):

@@ -276,12 +276,17 @@ gf2_status gf2_profile_read(gf2_ctx* ctx, int32_t cap, char* names, int64_t* lau
                             double* total_ms, double* flops, double* bytes, int32_t* count);
 
 /* ------------------------------------------------------------ GEMM tiles --
- * mode 1 (default): in BF16, the single-product product stage of the chain
- * (and gf2_debug_gemm) runs on 160 x 160 tiles of 16x16x32 MFMAs wherever
- * that pads an N x N product less than the 128 x 128 tile (N = 400, 800,
- * ...); mode 0: the 128 x 128 tile everywhere.  Both give the same results
- * up to the FP32 rounding of the accumulation order.  GF2_E_ARG for other
- * modes. */
+ * Tile choice of the BF16 chain products where a 160-wide tile pads an
+ * N x N product less than the 128 x 128 tile (N = 400, 800, ...):
+ * mode 2 (default): the deep-K stage (exchange and cross terms) on 160 x 160
+ *   tiles of 16x16x32 MFMAs with 64-wide k tiles, and the dual-A product
+ *   launches (U and V^T, W and Z^T, T) on 320 x 160 tiles (two 160 x 160
+ *   products sharing the B tile) with 32-wide k tiles, both fed by direct
+ *   global -> LDS loads;
+ * mode 1: only the deep-K stage on the 160 tile (and gf2_debug_gemm);
+ * mode 0: the 128 x 128 tile everywhere.
+ * All modes give the same results up to the FP32 rounding of the
+ * accumulation order.  GF2_E_ARG for other modes. */
 gf2_status gf2_set_gemm_tiles(gf2_ctx* ctx, int32_t mode);
 
 /* ------------------------------------------------------------ batch -------

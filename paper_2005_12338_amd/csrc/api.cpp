@@ -133,6 +133,7 @@ Prob prob0() {
   Prob p;
   std::memset(&p, 0, sizeof(p));
   p.nseg = 1; p.nA = 1; p.nB = 1;
+  p.had_slot_stride = 1;
   return p;
 }
 int tiles_of(const Prob& p, Prec prec, int64_t m, int64_t nc, int wide = 0) {
@@ -195,7 +196,7 @@ void gf2_destroy(gf2_ctx* ctx) {
 }
 
 gf2_status gf2_set_gemm_tiles(gf2_ctx* ctx, int32_t mode) {
-  if (!ctx || mode < 0 || mode > 1) return GF2_E_ARG;
+  if (!ctx || mode < 0 || mode > 2) return GF2_E_ARG;
   ctx->gemm_wide = mode;
   return GF2_OK;
 }
@@ -616,7 +617,7 @@ struct ChainPlan {
   size_t sb = 0, ab = 0;
   int64_t slots = 0, sc = 0, tcnt = 0;
   int mtiles = 0, ftiles = 0;
-  int wide4 = 0;                 // stage s4 (single product) on the wide BF16 tile
+  int wideg[4] = {0, 0, 0, 0};    // per launch group: 0 the standard tile, else a 160-wide BF16 tile
   double *mpart = nullptr, *epart = nullptr, *coef = nullptr, *gb64 = nullptr;
   char *wz = nullptr, *jw_l = nullptr, *jw_s = nullptr, *jz_st = nullptr, *jz_sum_t = nullptr, *jblk = nullptr;
   char* sig = nullptr;
@@ -629,13 +630,18 @@ struct ChainPlan {
   std::vector<std::pair<int32_t, int32_t>> trange;   // tau range of each chunk
   double* Sigma_sum = nullptr;
   double* e_samples = nullptr;
+  char* mst = nullptr;           // the four M matrices per slot (storage format)
 };
 
-// The four product stages of one chunk: (first problem, problems, products per unit).
-constexpr int kStageOff[4] = {0, 2, 5, 7};
-constexpr int kStageCnt[4] = {2, 3, 2, 1};
-constexpr int kStageProducts[4] = {4, 8, 4, 8};
-constexpr int kProbsPerPlan = 8;
+// The product launches of one chunk (first problem, problems, products per
+// unit): s1 {U, V^T}, s2 {M_xL, M_xS, W, Z^T}, s3 {T, T}, s4; every problem
+// of s1-s3 is a dual-A product.
+constexpr int kGroups = 4;
+constexpr int kStageOff[kGroups] = {0, 2, 6, 8};
+constexpr int kStageCnt[kGroups] = {2, 4, 2, 1};
+constexpr int kStageProducts[kGroups] = {4, 8, 4, 8};
+constexpr int kProbsPerPlan = 9;
+const char* const kGroupTag[kGroups] = {".s1", ".s2", ".s3", ".s4"};
 
 const char* gemm_name(Prec prec) {
   return prec == Prec::F64 ? "gemm_f64" : prec == Prec::F32 ? "gemm_f32"
@@ -798,53 +804,64 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
     p.out[2] = outspec(us_n, st_sl, {0, 1}, 0, 1);
     p.out[3] = outspec(us_t, st_sl, {0, 1}, 1, 1);
     P.push_back(p);
+    // V_c = G Y_c as its transpose Y_c G (G and Y_c symmetric): a dual-A
+    // product whose tile holds V_L^T and V_S^T at the same positions
     Prob q = prob0();
-    q.nB = 2;
-    q.a[0] = g_op;
-    q.b[0] = opref(xl + sb * ns, 0, vst);
-    q.b[1] = opref(xs + sb * ns, 0, vst);
+    q.nA = 2;
+    q.a[0] = opref(xl + sb * ns, 0, vst);
+    q.a[1] = opref(xs + sb * ns, 0, vst);
+    q.b[0] = g_op;
     q.nout = 4;
-    q.out[0] = outspec(vl_n, st_sl, {1, 0}, 0, 1);
-    q.out[1] = outspec(vs_n, st_sl, {0, 1}, 0, 1);
-    q.out[2] = outspec(vs_t, st_sl, {0, 1}, 1, 1);
-    q.out[3] = outspec(vsum_t, st_sl, {1, 1}, 1, 1);
+    q.out[0] = outspec(vl_n, st_sl, {1, 0}, 1, 1);
+    q.out[1] = outspec(vs_n, st_sl, {0, 1}, 1, 1);
+    q.out[2] = outspec(vs_t, st_sl, {0, 1}, 0, 1);
+    q.out[3] = outspec(vsum_t, st_sl, {1, 1}, 0, 1);
     P.push_back(q);
   }
-  Prob quad = prob0();
-  quad.nA = 2; quad.nB = 2;
-  c.mtiles = tiles_of(quad, prec, n);
+  if (wide_for(ctx, prec, n)) {
+    // 160-wide tiles where they pad n less: the deep-K stage s4 always, the
+    // dual-A launches (s1, s2, s3) in the default mode 2
+    c.wideg[3] = 1;
+    if (ctx->gemm_wide >= 2) c.wideg[0] = c.wideg[1] = c.wideg[2] = 3;
+  }
+  Prob dual = prob0();
+  dual.nA = 2;
+  c.mtiles = tiles_of(dual, prec, n, c.wideg[2]);
   Prob single = prob0();
-  c.wide4 = wide_for(ctx, prec, n);
-  c.ftiles = tiles_of(single, prec, n, c.wide4);
+  c.ftiles = tiles_of(single, prec, n, c.wideg[3]);
   c.mpart = (double*)S("c_mpart", 4 * c.mtiles * 8);
   c.epart = (double*)S("c_epart", c.ftiles * 8);
-  c.coef = (double*)S("c_coef", kMaxAdd * 8);
-  // S2: M quad, W = V Gb (dual A), Z = Gb U (dual B)
-  {
+  c.coef = (double*)S("c_coef", kCoefStride * 8);
+  c.mst = mst;
+  // Matrices of the exchange term, -sum over the nine (T_xy, M_zw) pairs of
+  // S_xi x S_eta, grouped into four products whose factors each come from
+  // one dual-A tile:
+  //   T_SS (M_LL + M_SL) + (T_SL + T_SS)(M_LS + M_SS) + T_LS M_SL + (T_LL + T_LS) M_SS.
+  // mst[x] = M_x (x = LL, LS, SL, SS; row-major, the A operands of s3 and
+  // the direct terms); mct[x] = the x-th B factor above, negated and
+  // transposed; tq[x] = the x-th A factor.
+  // S2: M_xL = U_x Y_L and M_xS = U_x Y_S (dual-A over x), W = V Gb (dual-A),
+  // Z = Gb U as Z^T = U^T Gb (dual-A)
+  for (int y = 0; y < 2; ++y) {
     Prob p = prob0();
-    p.nA = 2; p.nB = 2;
+    p.nA = 2;
     p.a[0] = opref(ul_n, 0, 0, st_sl);
     p.a[1] = opref(us_n, 0, 0, st_sl);
-    p.b[0] = opref(xl + sb * ns, 0, vst);
-    p.b[1] = opref(xs + sb * ns, 0, vst);
-    p.nout = 8;
-    for (int x = 0; x < 4; ++x) {
-      p.out[x] = outspec(mst + x * sb, 4 * st_sl, {0, 0, 0, 0}, 0, 1);
-      p.out[x].coef[x] = 1.0f;
+    p.b[0] = opref((y == 0 ? xl : xs) + sb * ns, 0, vst);
+    p.nout = 4;
+    const int lx = y == 0 ? 0 : 1, sx = y == 0 ? 2 : 3;      // M_Ly and M_Sy in mst order
+    p.out[0] = outspec(mst + lx * sb, 4 * st_sl, {1, 0}, 0, 1);
+    p.out[1] = outspec(mst + sx * sb, 4 * st_sl, {0, 1}, 0, 1);
+    if (y == 0) {
+      p.out[2] = outspec(mct + 0 * sb, 4 * st_sl, {-1, -1}, 1, 1);     // -(M_LL + M_SL)^T
+      p.out[3] = outspec(mct + 2 * sb, 4 * st_sl, {0, -1}, 1, 1);      // -M_SL^T
+    } else {
+      p.out[2] = outspec(mct + 1 * sb, 4 * st_sl, {-1, -1}, 1, 1);     // -(M_LS + M_SS)^T
+      p.out[3] = outspec(mct + 3 * sb, 4 * st_sl, {0, -1}, 1, 1);      // -M_SS^T
     }
-    p.out[4] = outspec(mct + 0 * sb, 4 * st_sl, {0, 0, 0, -1}, 1, 1);
-    p.out[5] = outspec(mct + 1 * sb, 4 * st_sl, {0, 0, -1, -1}, 1, 1);
-    p.out[6] = outspec(mct + 2 * sb, 4 * st_sl, {0, -1, 0, -1}, 1, 1);
-    p.out[7] = outspec(mct + 3 * sb, 4 * st_sl, {-1, -1, -1, -1}, 1, 1);
-    p.nhad = 4;
-    p.had_h = opref(c.gb64, np2);
-    for (int x = 0; x < 4; ++x) {
-      for (int y = 0; y < 4; ++y) p.had_coef[x][y] = 0.0f;
-      p.had_coef[x][x] = 1.0f;
-    }
-    p.had_part = c.mpart;
-    p.had_ntiles = c.mtiles;
     P.push_back(p);
+  }
+  {
     Prob w = prob0();
     w.nA = 2;
     w.a[0] = opref(vl_n, 0, 0, st_sl);
@@ -854,30 +871,42 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
     w.out[0] = outspec(wz + 0 * ab, 4 * ac_sl, {1, 0}, 0, 0);
     w.out[1] = outspec(wz + 1 * ab, 4 * ac_sl, {0, 1}, 0, 0);
     P.push_back(w);
+    // Z_b = Gbar U_b as its transpose U_b^T Gbar (Gbar symmetric): dual-A
     Prob z = prob0();
-    z.nB = 2;
-    z.a[0] = gb_op;
-    z.b[0] = opref(ul_t, 0, 0, st_sl);
-    z.b[1] = opref(us_t, 0, 0, st_sl);
+    z.nA = 2;
+    z.a[0] = opref(ul_t, 0, 0, st_sl);
+    z.a[1] = opref(us_t, 0, 0, st_sl);
+    z.b[0] = gb_op;
     z.nout = 2;
-    z.out[0] = outspec(wz + 2 * ab, 4 * ac_sl, {1, 0}, 0, 0);
-    z.out[1] = outspec(wz + 3 * ab, 4 * ac_sl, {0, 1}, 0, 0);
+    z.out[0] = outspec(wz + 2 * ab, 4 * ac_sl, {1, 0}, 1, 0);
+    z.out[1] = outspec(wz + 3 * ab, 4 * ac_sl, {0, 1}, 1, 0);
     P.push_back(z);
   }
-  // S3: T_xy = M_xy Gb
+  // S3: T = M Gb for the pairs (M_SS, M_SL) and (M_LS, M_LL), writing the A
+  // factors of the exchange term and the traces Tr(T_x) (the diagonal of the
+  // FP32 products) into mpart[slot][x][tile]
   for (int h = 0; h < 2; ++h) {
     Prob p = prob0();
     p.nA = 2;
-    p.a[0] = opref(mst + (2 * h) * sb, 0, 0, 4 * st_sl);
-    p.a[1] = opref(mst + (2 * h + 1) * sb, 0, 0, 4 * st_sl);
+    const int a0 = h == 0 ? 3 : 1, a1 = h == 0 ? 2 : 0;       // (SS, SL) and (LS, LL)
+    p.a[0] = opref(mst + a0 * sb, 0, 0, 4 * st_sl);
+    p.a[1] = opref(mst + a1 * sb, 0, 0, 4 * st_sl);
     p.b[0] = gb_op;
     p.nout = 2;
-    p.out[0] = outspec(tq + (2 * h) * sb, 4 * st_sl, {1, 0}, 0, 1);
-    p.out[1] = outspec(tq + (2 * h + 1) * sb, 4 * st_sl, {0, 1}, 0, 1);
+    p.out[0] = outspec(tq + (2 * h) * sb, 4 * st_sl, {1, 0}, 0, 1);       // T_SS, T_LS
+    p.out[1] = outspec(tq + (2 * h + 1) * sb, 4 * st_sl, {1, 1}, 0, 1);   // T_SL + T_SS, T_LL + T_LS
+    p.nhad = 2;
+    p.had_diag = 1;
+    p.had_coef[0][0] = 0.0f; p.had_coef[0][1] = 1.0f;                     // Tr(T_a1)
+    p.had_coef[1][0] = 1.0f; p.had_coef[1][1] = 0.0f;                     // Tr(T_a0)
+    p.had_part = c.mpart + (int64_t)std::min(a0, a1) * c.mtiles;         // h slots a1, a0 (a1 < a0)
+    p.had_ntiles = c.mtiles;
+    p.had_slot_stride = 4;
     P.push_back(p);
   }
-  // S4: exchange + cross terms as one K-concatenated product, direct term
-  // and the energy trace in the epilogue
+  // S4: exchange + cross terms as one K-concatenated product, the trace of
+  // that product in the epilogue (the direct terms 2 Tr(T) M join in the
+  // accumulation)
   {
     Prob p = prob0();
     p.nseg = 8;
@@ -889,9 +918,6 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
     p.a[5] = opref(jw_s, 0, 0, st_sl);   p.b[5] = opref(vsum_t, 0, 0, st_sl);
     p.a[6] = opref(ul_n, 0, 0, st_sl);   p.b[6] = opref(jz_st, 0, 0, st_sl);
     p.a[7] = opref(us_n, 0, 0, st_sl);   p.b[7] = opref(jz_sum_t, 0, 0, st_sl);
-    p.nadd = 4;
-    for (int x = 0; x < 4; ++x) p.add[x] = opref(mst + x * sb, 0, 0, 4 * st_sl);
-    p.add_coef = c.coef;
     p.nout = 1;
     p.out[0] = outspec(sig, ac_sl, {1}, 0, 0);
     p.nhad = 1;
@@ -899,8 +925,12 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
     p.had_coef[0][0] = 1.0f;
     p.had_part = c.epart;
     p.had_ntiles = c.ftiles;
+    p.had_slot_stride = 1;
     P.push_back(p);
   }
+  for (int g = 0; g < kGroups; ++g)
+    for (int j = 0; j < kStageCnt[g]; ++j)
+      GF2_REQUIRE(gemm_wide_supports(c.wideg[g], P[kStageOff[g] + j]), GF2_E_STATE, "product problem not supported by its tile");
   c.dprobs = (Prob*)ctx_buf(ctx, pfx + "c_probs", P.size() * sizeof(Prob));
   h2d(ctx, c.dprobs, P.data(), P.size());
 
@@ -924,14 +954,13 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
 
 void chain_stage(gf2_ctx* ctx, const ChainPlan& c, int stage, int64_t ci) {
   const int off = kStageOff[stage], cnt = kStageCnt[stage];
-  const int wide = stage == 3 ? c.wide4 : 0;
+  const int wide = c.wideg[stage];
   int mt = 0;
   for (int i = 0; i < cnt; ++i) mt = std::max(mt, tiles_of(c.P[off + i], c.prec, c.n, wide));
   const int nu = (int)c.chunks[ci].second;
   GemmLaunch L = chain_launch(c.dprobs + off, cnt, c.dunits + c.chunks[ci].first, nu, c.n, c.np, c.plane);
   L.wide = wide;
-  static const char* tag[4] = {".s1", ".s2", ".s3", ".s4"};
-  const std::string nm = std::string(gemm_name(c.prec)) + tag[stage];
+  const std::string nm = std::string(gemm_name(c.prec)) + kGroupTag[stage] + (wide ? "@160" : "");
   ProfScope ps(ctx, nm.c_str(), 2.0 * (double)c.n * c.n * c.n * kStageProducts[stage] * nu);
   launch_gemm(c.prec, L, mt, ctx->stream);
 }
@@ -940,7 +969,6 @@ void chain_jk(gf2_ctx* ctx, const ChainPlan& c, int64_t ci) {
   const gf2_split_h* sp = c.sp;
   const int nu = (int)c.chunks[ci].second;
   ProfScope ps(ctx, "jk");
-  launch_trace_coef(c.mpart, c.mtiles, (int32_t)c.slots, c.coef, ctx->stream);
   launch_jk_blocks(c.accf64, c.wz, 4 * c.ac_sl, c.ac_sl, c.np, c.naux, nu, sp->w, sp->idx,
                    c.accf64 ? (const void*)sp->blk : (const void*)sp->blk32, c.jblk, ctx->stream);
   launch_jk_scatter(c.accf64, c.jblk, c.naux, nu, sp->npat, sp->pat_ij, sp->pat_off, sp->pat_q, c.np, c.prec,
@@ -951,11 +979,12 @@ void chain_acc(gf2_ctx* ctx, const ChainPlan& c, int64_t ci) {
   const Unit* du = c.dunits + c.chunks[ci].first;
   const int nu = (int)c.chunks[ci].second;
   const int64_t n = c.n;
+  launch_trace_coef(c.mpart, c.mtiles, (int32_t)c.slots, c.coef, ctx->stream);
   ProfScope ps(ctx, "accumulate", 0.0,
                (double)nu * n * n * (c.accf64 ? 8 : 4) + 2.0 * (c.trange[ci].second - c.trange[ci].first) * n * n * 8);
   launch_accumulate(du, nu, c.sig, c.accf64, c.ac_sl, n, c.np, c.Sigma_sum, c.trange[ci].first,
-                    c.trange[ci].second, ctx->stream);
-  if (c.e_samples) launch_esamples(du, nu, c.epart, c.ftiles, 0, c.ntau, c.e_samples, ctx->stream);
+                    c.trange[ci].second, c.mst, c.prec, 4 * c.st_sl, c.st_sl, c.plane, c.coef, ctx->stream);
+  if (c.e_samples) launch_esamples(du, nu, c.epart, c.ftiles, 0, c.ntau, c.e_samples, c.coef, ctx->stream);
 }
 
 void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double* G, const double* Gbar,
@@ -1109,9 +1138,9 @@ struct BatchRun {
   InstGeo* dgeo = nullptr;         // [ninst]
   Unit* dunits = nullptr;          // all steps' merged unit lists
   std::vector<std::pair<int64_t, int64_t>> steps;   // (offset, count) into dunits
-  int tiles[4] = {0, 0, 0, 0};     // per stage, max over instances
+  int tiles[kGroups] = {0, 0, 0, 0};      // per launch group, max over instances
   BatchSeg* dsegs = nullptr;       // work lists of all (step, stage)
-  std::vector<int64_t> segoff, nseg, nitems;         // per step * 4 + stage
+  std::vector<int64_t> segoff, nseg, nitems;         // per step * kGroups + group
   int64_t nsteps = 0;
   int32_t persist = 0;
 };
@@ -1130,7 +1159,7 @@ void batch_plan(gf2_ctx* ctx, BatchRun& R, int32_t nitem, const gf2_batch_item* 
     const ChainPlan& c = R.plans[i];
     for (int j = 0; j < kProbsPerPlan; ++j) ph[(size_t)i * kProbsPerPlan + j] = c.P[j];
     gh[i] = InstGeo{c.n, c.n, c.np, c.np, c.plane};
-    for (int st = 0; st < 4; ++st)
+    for (int st = 0; st < kGroups; ++st)
       for (int j = 0; j < kStageCnt[st]; ++j)
         R.tiles[st] = std::max(R.tiles[st], tiles_of(c.P[kStageOff[st] + j], prec, c.n));
   }
@@ -1145,9 +1174,9 @@ void batch_plan(gf2_ctx* ctx, BatchRun& R, int32_t nitem, const gf2_batch_item* 
   R.nsteps = 0;
   for (const ChainPlan& c : R.plans) R.nsteps = std::max<int64_t>(R.nsteps, (int64_t)c.chunks.size());
   // per instance and stage: tiles of its largest problem of the stage
-  std::vector<std::array<int32_t, 4>> itiles(nitem);
+  std::vector<std::array<int32_t, kGroups>> itiles(nitem);
   for (int32_t i = 0; i < nitem; ++i)
-    for (int st = 0; st < 4; ++st) {
+    for (int st = 0; st < kGroups; ++st) {
       int32_t t = 0;
       for (int j = 0; j < kStageCnt[st]; ++j) t = std::max(t, tiles_of(R.plans[i].P[kStageOff[st] + j], prec, R.plans[i].n));
       itiles[i][st] = t;
@@ -1173,11 +1202,11 @@ void batch_plan(gf2_ctx* ctx, BatchRun& R, int32_t nitem, const gf2_batch_item* 
       runs.push_back({i, {u0, (int32_t)c.chunks[st].second}});
     }
     R.steps.push_back({off0, (int64_t)uh.size() - off0});
-    for (int stage = 0; stage < 4; ++stage) {
+    for (int stage = 0; stage < kGroups; ++stage) {
       R.segoff.push_back((int64_t)sh.size());
       int64_t item = 0;
       for (const auto& r : runs) {
-        if (stage == 3 && R.plans[r.first].wide4) continue;   // launched on its own (wide tile)
+        if (R.plans[r.first].wideg[stage]) continue;   // launched on its own (wide tile)
         const int32_t t = itiles[r.first][stage];
         sh.push_back(BatchSeg{item, r.second.first, r.second.second, t, 0});
         item += (int64_t)r.second.second * kStageCnt[stage] * t;
@@ -1196,28 +1225,27 @@ void batch_plan(gf2_ctx* ctx, BatchRun& R, int32_t nitem, const gf2_batch_item* 
 // Launch steps [s0, s1) of the batch (kernels only: no allocation, copy or
 // fill, so the sequence can be recorded into a graph).
 void batch_steps(gf2_ctx* ctx, const BatchRun& R, Prec prec, int64_t s0, int64_t s1) {
-  static const char* tag[4] = {".s1", ".s2", ".s3", ".s4"};
   GF2_REQUIRE(0 <= s0 && s0 <= s1 && s1 <= R.nsteps && R.nsteps == (int64_t)R.steps.size(), GF2_E_STATE,
               "batch step range out of bounds");
   for (int64_t st = s0; st < s1; ++st) {
     const int nu = (int)R.steps[st].second;
-    for (int stage = 0; stage < 4; ++stage) {
-      const int64_t k = st * 4 + stage;
+    for (int stage = 0; stage < kGroups; ++stage) {
+      const int64_t k = st * kGroups + stage;
       GemmLaunch L{R.dprobs + kStageOff[stage], kStageCnt[stage], kProbsPerPlan, R.dunits + R.steps[st].first, nu,
                    InstGeo{0, 0, 0, 0, 0}, R.dgeo, 0, R.persist, R.dsegs + R.segoff[k], (int32_t)R.nseg[k],
                    R.nitems[k]};
       double fl = 0.0;
       for (const ChainPlan& c : R.plans)
-        if (st < (int64_t)c.chunks.size() && !(stage == 3 && c.wide4))
+        if (st < (int64_t)c.chunks.size() && !c.wideg[stage])
           fl += 2.0 * (double)c.n * c.n * c.n * kStageProducts[stage] * c.chunks[st].second;
       {
-        const std::string nm = std::string(gemm_name(prec)) + tag[stage];
+        const std::string nm = std::string(gemm_name(prec)) + kGroupTag[stage];
         ProfScope ps(ctx, nm.c_str(), fl);
         launch_gemm(prec, L, R.tiles[stage], ctx->stream);
       }
-      if (stage == 3)   // instances whose single-product stage runs on the wide tile, one launch each
-        for (const ChainPlan& c : R.plans)
-          if (c.wide4 && st < (int64_t)c.chunks.size()) chain_stage(ctx, c, 3, st);
+      // instances whose launch group runs on a wide tile, one launch each
+      for (const ChainPlan& c : R.plans)
+        if (c.wideg[stage] && st < (int64_t)c.chunks.size()) chain_stage(ctx, c, stage, st);
       if (stage == 1)
         for (const ChainPlan& c : R.plans)
           if (st < (int64_t)c.chunks.size()) chain_jk(ctx, c, st);

@@ -69,6 +69,25 @@ template <> struct Cfg<Prec::BF16, 1> {
   static constexpr int BM = 160, BN = 160, BK = 64, PAD = 0, PLANES = 1;
   static constexpr int MT = 16, NACC = 4, TM = 5, TN = 5;
   static constexpr bool SWZ = true; static constexpr int PF = 0;   // PF 0: direct global -> LDS loads
+  static constexpr int STAGES = 2;
+};
+// 160-wide tiles with 32-wide k tiles (half the LDS per stage, so three
+// stages fit two workgroups per CU): single products (W = 2), and dual-A
+// products (W = 3: A_0 rows in [0, 160), A_1 rows in [160, 320), both times
+// the same B tile; every wave owns the same 80 x 80 positions of both).
+template <> struct Cfg<Prec::BF16, 2> {
+  using E = bf16_t; using Acc = float;
+  static constexpr int BM = 160, BN = 160, BK = 32, PAD = 0, PLANES = 1;
+  static constexpr int MT = 16, NACC = 4, TM = 5, TN = 5;
+  static constexpr bool SWZ = true; static constexpr int PF = 0;
+  static constexpr int STAGES = 3;
+};
+template <> struct Cfg<Prec::BF16, 3> {
+  using E = bf16_t; using Acc = float;
+  static constexpr int BM = 320, BN = 160, BK = 32, PAD = 0, PLANES = 1;
+  static constexpr int MT = 16, NACC = 4, TM = 10, TN = 5;
+  static constexpr bool SWZ = true; static constexpr int PF = 0;
+  static constexpr int STAGES = 3;
 };
 
 constexpr int kThreads = 256;
@@ -153,6 +172,11 @@ __device__ __forceinline__ void store_out_vec4(int type, void* base, int64_t i, 
   }
 }
 
+// Wait until at most N vector-memory operations of this wave are outstanding.
+template <int N> __device__ __forceinline__ void waitcnt_vm() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
 // Sixteen zero bytes: the source of every out-of-range operand vector.
 __device__ __attribute__((aligned(16))) const u32x4_t kZeroVec = {0u, 0u, 0u, 0u};
 
@@ -166,14 +190,29 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t wg, int64_t total) {
   return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
+// Direct global -> LDS loads: one instruction fills 1 KB per wave, i.e.
+// 1024 / (2 BK) rows; a workgroup round covers four times that many, and
+// tiles are padded (in LDS only) to whole rounds.
+template <int BK> constexpr int direct_rows() { return 8 * 64 / BK; }
+template <int R, int BK> constexpr int direct_pad(int rows) {
+  return (rows + 4 * direct_rows<BK>() - 1) / (4 * direct_rows<BK>()) * (4 * direct_rows<BK>());
+}
+template <Prec P, int W> struct Stages { static constexpr int N = 2; };
+template <> struct Stages<Prec::BF16, 1> { static constexpr int N = Cfg<Prec::BF16, 1>::STAGES; };
+template <> struct Stages<Prec::BF16, 2> { static constexpr int N = Cfg<Prec::BF16, 2>::STAGES; };
+template <> struct Stages<Prec::BF16, 3> { static constexpr int N = Cfg<Prec::BF16, 3>::STAGES; };
+
 template <Prec P, int W = 0>
 struct Smem {
   using C = Cfg<P, W>;
   using E = typename C::E;
   static constexpr int PITCH = C::BK + C::PAD;
-  static constexpr int TILE_A = C::PLANES * C::BM * PITCH;
-  static constexpr int TILE_B = C::PLANES * C::BN * PITCH;
-  static constexpr int BYTES = 2 * (TILE_A + TILE_B) * (int)sizeof(E);
+  static constexpr int ROWS_A = C::PF == 0 ? direct_pad<0, C::BK>(C::BM) : C::BM;
+  static constexpr int ROWS_B = C::PF == 0 ? direct_pad<0, C::BK>(C::BN) : C::BN;
+  static constexpr int TILE_A = C::PLANES * ROWS_A * PITCH;
+  static constexpr int TILE_B = C::PLANES * ROWS_B * PITCH;
+  static constexpr int STAGES = Stages<P, W>::N;
+  static constexpr int BYTES = STAGES * (TILE_A + TILE_B) * (int)sizeof(E);
 };
 
 // Row (within the 32 x 32 or 16 x 16 MFMA tile) held by accumulator r of a lane.
@@ -189,6 +228,241 @@ __device__ __forceinline__ int acc_col(int lane) {
   else return lane & 31;
 }
 
+// LDS byte address of a pointer into a __shared__ array.
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+// Fragments of one 32-wide k step of the 160-wide tiles: TN = 5 B fragments
+// at bbase + j * STEP and TM = 5 (or 10: two products) A fragments at abase
+// + (i / FR) * PROD + (i % FR) * STEP, read back to back with one wait at
+// the end of the same asm block.
+template <int TM, int FR, int PROD, int STEP>
+__device__ __forceinline__ void lds_frags(bf16x8_t* ah, bf16x8_t* bh, uint32_t abase, uint32_t bbase) {
+  static_assert(TM == 5 || TM == 10, "fragment count");
+  static_assert((TM / FR - 1) * PROD + (FR - 1) * STEP < 65536 && 4 * STEP < 65536, "ds offsets");
+  if constexpr (TM == 5) {
+    asm volatile(
+        "ds_read_b128 %0, %10 offset:%c12\n\t"
+        "ds_read_b128 %1, %10 offset:%c13\n\t"
+        "ds_read_b128 %2, %10 offset:%c14\n\t"
+        "ds_read_b128 %3, %10 offset:%c15\n\t"
+        "ds_read_b128 %4, %10 offset:%c16\n\t"
+        "ds_read_b128 %5, %11 offset:%c12\n\t"
+        "ds_read_b128 %6, %11 offset:%c13\n\t"
+        "ds_read_b128 %7, %11 offset:%c14\n\t"
+        "ds_read_b128 %8, %11 offset:%c15\n\t"
+        "ds_read_b128 %9, %11 offset:%c16\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(ah[0]), "=&v"(ah[1]), "=&v"(ah[2]), "=&v"(ah[3]), "=&v"(ah[4]),
+          "=&v"(bh[0]), "=&v"(bh[1]), "=&v"(bh[2]), "=&v"(bh[3]), "=&v"(bh[4])
+        : "v"(abase), "v"(bbase), "n"(0), "n"(STEP), "n"(2 * STEP), "n"(3 * STEP), "n"(4 * STEP)
+        : "memory");
+  } else {
+    asm volatile(
+        "ds_read_b128 %0, %15 offset:%c17\n\t"
+        "ds_read_b128 %1, %15 offset:%c18\n\t"
+        "ds_read_b128 %2, %15 offset:%c19\n\t"
+        "ds_read_b128 %3, %15 offset:%c20\n\t"
+        "ds_read_b128 %4, %15 offset:%c21\n\t"
+        "ds_read_b128 %5, %15 offset:%c22\n\t"
+        "ds_read_b128 %6, %15 offset:%c23\n\t"
+        "ds_read_b128 %7, %15 offset:%c24\n\t"
+        "ds_read_b128 %8, %15 offset:%c25\n\t"
+        "ds_read_b128 %9, %15 offset:%c26\n\t"
+        "ds_read_b128 %10, %16 offset:%c17\n\t"
+        "ds_read_b128 %11, %16 offset:%c18\n\t"
+        "ds_read_b128 %12, %16 offset:%c19\n\t"
+        "ds_read_b128 %13, %16 offset:%c20\n\t"
+        "ds_read_b128 %14, %16 offset:%c21\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(ah[0]), "=&v"(ah[1]), "=&v"(ah[2]), "=&v"(ah[3]), "=&v"(ah[4]),
+          "=&v"(ah[5]), "=&v"(ah[6]), "=&v"(ah[7]), "=&v"(ah[8]), "=&v"(ah[9]),
+          "=&v"(bh[0]), "=&v"(bh[1]), "=&v"(bh[2]), "=&v"(bh[3]), "=&v"(bh[4])
+        : "v"(abase), "v"(bbase), "n"(0), "n"(STEP), "n"(2 * STEP), "n"(3 * STEP), "n"(4 * STEP),
+          "n"(PROD), "n"(PROD + STEP), "n"(PROD + 2 * STEP), "n"(PROD + 3 * STEP), "n"(PROD + 4 * STEP)
+        : "memory");
+  }
+}
+
+// Epilogue of the 160-wide BF16 tiles (16x16 MFMA fragments; each wave
+// owns 80 x 80 positions of every product of the tile).
+//  1. Trace partials (against a matrix, or of the diagonal) from the
+//     registers, reduced in a fixed order into had_part.
+//  2. Each output in turn is staged through the LDS operand buffers (free
+//     after the main loop) in its own orientation -- row-major, or
+//     transposed -- and copied out as 16-byte vectors along its rows.  FP32
+//     outputs that do not fit are staged in two halves of the tile rows.
+// Problems on these tiles carry no addends.
+__device__ __forceinline__ uint16_t bf16_bits(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
+template <Prec P, int W, int NA, typename AccT>
+__device__ __forceinline__ void wide_epilogue(const InstGeo& L, const Prob& pb, const Unit& u, int tile, int64_t row0,
+                                              int64_t col0, unsigned char* smem, double* red, AccT& acc) {
+  using C = Cfg<P, W>;
+  constexpr int SM = C::BM / NA, SN = C::BN;
+  constexpr int FR = C::TM / NA, FC = C::TN;
+  constexpr int HALF_R = SM / 2, HALF_C = SN / 2;
+  static_assert(P == Prec::BF16 && C::MT == 16 && C::NACC == 4 && SM == SN, "wide epilogue: BF16 16x16 square tiles");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t mrows = L.m, ncols = L.nc, ld = L.ld;
+  const int g4 = 4 * (lane >> 4), lc0 = lane & 15;
+  // tile-local row / column of accumulator (gi, gj, r) of this lane
+  auto lrow = [&](int gi, int r) { return wm * HALF_R + gi * 16 + g4 + r; };
+  auto lcol = [&](int gj) { return wn * HALF_C + gj * 16 + lc0; };
+
+  // 1. trace partials
+  const int nh = pb.nhad;
+  if (nh) {
+    const bool hdiag = pb.had_diag != 0;
+    const double* hmat = hdiag ? nullptr : (const double*)pb.had_h.base + off(pb.had_h, u);
+    double hs0 = 0.0, hs1 = 0.0, hs2 = 0.0, hs3 = 0.0;
+    float hc[kMaxHad][NA];
+#pragma unroll
+    for (int q = 0; q < kMaxHad; ++q)
+#pragma unroll
+      for (int a = 0; a < NA; ++a) hc[q][a] = q < nh ? pb.had_coef[q][a] : 0.0f;
+    auto add = [&](int gi, int gj, int r, double hv) {
+      double s[kMaxHad];
+#pragma unroll
+      for (int q = 0; q < kMaxHad; ++q) {
+        s[q] = 0.0;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) s[q] += (double)hc[q][a] * (double)acc[a * FR + gi][gj][r];
+      }
+      hs0 += s[0] * hv; hs1 += s[1] * hv; hs2 += s[2] * hv; hs3 += s[3] * hv;
+    };
+    if (hdiag) {
+      // the diagonal lies in tiles with row0 == col0, on the waves with wm == wn
+      if (row0 == col0 && wm == wn) {
+#pragma unroll
+        for (int gi = 0; gi < FR; ++gi)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            // fragment row gi holds tile rows lrow(gi, r); its diagonal element is in column fragment gi
+            if (lrow(gi, r) != lcol(gi) || row0 + lrow(gi, r) >= mrows) continue;
+            add(gi, gi, r, 1.0);
+          }
+      }
+    } else {
+#pragma unroll
+      for (int gi = 0; gi < FR; ++gi)
+#pragma unroll
+        for (int gj = 0; gj < FC; ++gj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t gr = row0 + lrow(gi, r), gc = col0 + lcol(gj);
+            if (gr >= mrows || gc >= ncols) continue;
+            add(gi, gj, r, hmat[gr * ld + gc]);
+          }
+    }
+    const double hsv[kMaxHad] = {hs0, hs1, hs2, hs3};
+#pragma unroll
+    for (int q = 0; q < kMaxHad; ++q) {
+      if (q >= nh) break;
+      double sq = hsv[q];
+      for (int d = 32; d > 0; d >>= 1) sq += __shfl_down(sq, d, 64);
+      if (lane == 0) red[wave * kMaxHad + q] = sq;
+    }
+    __syncthreads();
+    if (tid < nh) {
+      double sq = red[0 * kMaxHad + tid] + red[1 * kMaxHad + tid];
+      sq += red[2 * kMaxHad + tid];
+      sq += red[3 * kMaxHad + tid];
+      pb.had_part[((int64_t)u.slot * pb.had_slot_stride + tid) * pb.had_ntiles + tile] = sq;
+    }
+  }
+
+  // 2. outputs, staged
+  constexpr int CAP = Smem<P, W>::BYTES;
+  for (int o = 0; o < pb.nout; ++o) {
+    const OutSpec& os = pb.out[o];
+    const int es = os.type == 0 ? 4 : 2;              // bytes per element
+    const int vl = 16 / es;                            // elements per 16-byte vector
+    char* dst = (char*)os.base + off(os, u) * (int64_t)es;
+    float cf[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) cf[a] = os.coef[a];
+    const bool tr = os.layout != 0;
+    // staged region: tile rows [h RS, (h+1) RS); pitch padded by 16 bytes
+    const int pr = SN + vl, pt_full = SM + vl, pt_half = HALF_R + vl;
+    const bool halves = (tr ? SN * pt_full : SM * pr) * es > CAP;
+    const int rs = halves ? HALF_R : SM;
+    const int pt = halves ? pt_half : pt_full;
+    // single-product wide tiles write row-major FP32 outputs only (the
+    // deep-K stage's; the host checks), which keeps their epilogue within
+    // two workgroups' registers
+    const int kind = (tr ? 2 : 0) + (es == 4 ? 1 : 0);
+    if (NA == 1 && kind != 1) continue;
+    for (int h = 0; h < (halves ? 2 : 1); ++h) {
+      __syncthreads();                               // LDS free (main loop, traces, last copy-out)
+      if (!halves || wm == h) {
+        auto val = [&](int gi, int gj, int r) {
+          float x = 0.0f;
+#pragma unroll
+          for (int a = 0; a < NA; ++a) x += cf[a] * acc[a * FR + gi][gj][r];
+          return x;
+        };
+        const int hr = h * rs;
+        if (NA == 2 && kind == 0) {  // row-major BF16
+#pragma unroll
+          for (int gi = 0; gi < FR; ++gi)
+#pragma unroll
+            for (int gj = 0; gj < FC; ++gj)
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                ((uint16_t*)smem)[(lrow(gi, r) - hr) * pr + lcol(gj)] = bf16_bits(val(gi, gj, r));
+        } else if (kind == 1) {      // row-major FP32
+#pragma unroll
+          for (int gi = 0; gi < FR; ++gi)
+#pragma unroll
+            for (int gj = 0; gj < FC; ++gj)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) ((float*)smem)[(lrow(gi, r) - hr) * pr + lcol(gj)] = val(gi, gj, r);
+        } else if (NA == 2 && kind == 2) {   // transposed BF16: four consecutive tile rows = four elements of an output row
+#pragma unroll
+          for (int gi = 0; gi < FR; ++gi)
+#pragma unroll
+            for (int gj = 0; gj < FC; ++gj) {
+              const uint32_t lo = (uint32_t)bf16_bits(val(gi, gj, 0)) | ((uint32_t)bf16_bits(val(gi, gj, 1)) << 16);
+              const uint32_t hi = (uint32_t)bf16_bits(val(gi, gj, 2)) | ((uint32_t)bf16_bits(val(gi, gj, 3)) << 16);
+              *(uint2*)((uint16_t*)smem + lcol(gj) * pt + lrow(gi, 0) - hr) = make_uint2(lo, hi);
+            }
+        } else if (NA == 2) {        // transposed FP32
+#pragma unroll
+          for (int gi = 0; gi < FR; ++gi)
+#pragma unroll
+            for (int gj = 0; gj < FC; ++gj)
+              *(float4*)((float*)smem + lcol(gj) * pt + lrow(gi, 0) - hr) =
+                  make_float4(val(gi, gj, 0), val(gi, gj, 1), val(gi, gj, 2), val(gi, gj, 3));
+        }
+      }
+      __syncthreads();
+      // copy-out: output rows of the staged region as 16-byte vectors
+      const int orows = tr ? SN : rs, ocols = tr ? rs : SN;
+      const int64_t grow0 = tr ? col0 : row0 + h * rs, gcol0 = tr ? row0 + h * rs : col0;
+      const int64_t grows = tr ? ncols : mrows, gcols = tr ? mrows : ncols;
+      const int opitch = tr ? pt : pr;
+      const int vpr = ocols / vl;
+      for (int idx = tid; idx < orows * vpr; idx += kThreads) {
+        const int rr = idx / vpr, cc = (idx % vpr) * vl;
+        const int64_t gr = grow0 + rr, gc = gcol0 + cc;
+        if (gr >= grows || gc >= gcols) continue;
+        const unsigned char* src = smem + ((int64_t)rr * opitch + cc) * es;
+        char* d = dst + (gr * ld + gc) * es;
+        if (gc + vl <= gcols) {
+          *(u32x4_t*)d = *(const u32x4_t*)src;
+        } else {
+          for (int e = 0; e < vl && gc + e < gcols; ++e)
+            for (int bq = 0; bq < es; ++bq) d[e * es + bq] = (char)src[e * es + bq];
+        }
+      }
+    }
+  }
+}
+
 template <Prec P, int W, int NA, int NB>
 __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, const Unit& u, int tile,
                                           unsigned char* smem, double* red) {
@@ -200,7 +474,7 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
   constexpr int VE = 16 / sizeof(E);                      // elements per 16 B vector
   constexpr int VPR = BK / VE;                            // vectors per tile row
   constexpr int AV = BM * VPR * PL / kThreads, BV = BN * VPR * PL / kThreads;
-  static_assert(BM * VPR * PL % kThreads == 0 && BN * VPR * PL % kThreads == 0, "tile/threads");
+  static_assert(C::PF == 0 || (BM * VPR * PL % kThreads == 0 && BN * VPR * PL % kThreads == 0), "tile/threads");
   constexpr int TILE_A = Smem<P, W>::TILE_A, TILE_B = Smem<P, W>::TILE_B;
   constexpr int SM = BM / NA, SN = BN / NB;               // output rows / cols per tile
   constexpr int MT = C::MT, NACC = C::NACC;
@@ -208,8 +482,8 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
   constexpr int FR = TM / NA, FC = TN / NB;               // ... per product
   static_assert(TM % NA == 0 && TN % NB == 0 && FR * MT * 2 == SM && FC * MT * 2 == SN, "wave tiling");
 
-  E* As = (E*)smem;                    // [2][PL][BM][PITCH]
-  E* Bs = As + 2 * TILE_A;             // [2][PL][BN][PITCH]
+  E* As = (E*)smem;                    // [STAGES][PL][rows][PITCH]
+  E* Bs = As + Smem<P, W>::STAGES * TILE_A;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform (scalar)
@@ -233,8 +507,12 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
   auto frag_row_out = [&](int i) { return wm * (FR * MT) + i * MT; };   // i < FR
   auto frag_col_out = [&](int j) { return wn * (FC * MT) + j * MT; };   // j < FC
   // element (row, k) of a tile plane in LDS; k a multiple of 8 with SWZ
+  // 16-byte chunk c of row r sits at chunk c ^ swz(r): 128-byte rows (BK 64)
+  // rotate by r mod 8, 64-byte rows (BK 32) by (r / 4) mod 4, so that the 16
+  // rows one MFMA fragment read touches fall in distinct banks
+  auto swz = [&](int row) { return BK == 64 ? (row & 7) : ((row >> 2) & 3); };
   auto lds_at = [&](int row, int k) {
-    if constexpr (C::SWZ) return row * PITCH + ((((k >> 3) ^ (row & 7))) << 3);
+    if constexpr (C::SWZ) return row * PITCH + ((((k >> 3) ^ swz(row))) << 3);
     else return row * PITCH + k;
   };
 
@@ -243,7 +521,8 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
   // everything but trow and kv is uniform over the workgroup, so each load
   // is a uniform base plus one per-thread offset.
   constexpr int RSTEP = kThreads / VPR;
-  static_assert(BM % RSTEP == 0 && BN % RSTEP == 0 && SM % RSTEP == 0 && SN % RSTEP == 0, "staging rows");
+  static_assert(C::PF == 0 || (BM % RSTEP == 0 && BN % RSTEP == 0 && SM % RSTEP == 0 && SN % RSTEP == 0),
+                "staging rows");
   const int trow = tid / VPR;
   const int kv = (tid % VPR) * VE;
   const int64_t toff = (int64_t)trow * ld + kv;
@@ -368,10 +647,24 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
 #pragma unroll
       for (int ks = 0; ks < BK / 32; ++ks) {
         bf16x8_t ah[TM], bh[TN];
+        if constexpr (C::PF == 0 && (TM == 5 || TM == 10) && TN == 5) {
+          // Direct-load tiles: the fragments are read by one asm block (all
+          // reads, then one wait in the same block).  Through ordinary loads
+          // the compiler cannot tell these reads from the direct loads still
+          // filling another stage of the ring, and waits for those first.
+          // Fragment rows differ by multiples of 16 rows, which leaves the
+          // swizzle unchanged, so one base address and immediate offsets
+          // cover each operand.
+          constexpr int RB = PITCH * (int)sizeof(E);                  // bytes per LDS row
+          const uint32_t abase = lds_addr(a + lds_at(frag_row_lds(0) + lr, ks * 32 + g * 8));
+          const uint32_t bbase = lds_addr(b + lds_at(frag_col_lds(0) + lr, ks * 32 + g * 8));
+          lds_frags<TM, FR, SM * RB, 16 * RB>(ah, bh, abase, bbase);
+        } else {
 #pragma unroll
-        for (int i = 0; i < TM; ++i) ah[i] = *(const bf16x8_t*)(a + lds_at(frag_row_lds(i) + lr, ks * 32 + g * 8));
+          for (int j = 0; j < TN; ++j) bh[j] = *(const bf16x8_t*)(b + lds_at(frag_col_lds(j) + lr, ks * 32 + g * 8));
 #pragma unroll
-        for (int j = 0; j < TN; ++j) bh[j] = *(const bf16x8_t*)(b + lds_at(frag_col_lds(j) + lr, ks * 32 + g * 8));
+          for (int i = 0; i < TM; ++i) ah[i] = *(const bf16x8_t*)(a + lds_at(frag_row_lds(i) + lr, ks * 32 + g * 8));
+        }
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -428,38 +721,48 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
   };
   if constexpr (C::PF == 0) {
     // Direct global -> LDS loads (global_load_lds_dwordx4): instruction i of
-    // wave w fills tile rows 8 (4 i + w) .. +7, lane L row 8 (4 i + w) + L/8
-    // at physical chunk L mod 8, i.e. logical chunk (L mod 8) ^ (row mod 8)
-    // of the swizzled layout.  Two stages: tile t+1 streams into LDS while
-    // tile t is computed; one barrier per k tile.
-    static_assert(C::SWZ && PL == 1 && NA == 1 && NB == 1 && BK == 64 && BM % 32 == 0 && BN % 32 == 0,
-                  "direct loads: swizzled single-plane 64-wide k tiles");
-    constexpr int NLA = BM / 32, NLB = BN / 32;
-    const int lrow = lane >> 3, pch = lane & 7;
+    // wave w fills the RPI tile rows RPI (4 i + w) .. +RPI-1 (1 KB), lane L
+    // row RPI (4 i + w) + L / CPR at physical chunk L mod CPR, i.e. logical
+    // chunk (L mod CPR) ^ swz(row) of the swizzled layout.  Rows past the
+    // tile (LDS padding) load zeros.  STAGES-deep ring: tile t+STAGES-1
+    // streams in while tile t is computed; one barrier per k tile.  Every
+    // wave issues the same loads per tile, so the wait for tile t is
+    // "at most (STAGES-2) tiles of loads outstanding".
+    constexpr int STG = Smem<P, W>::STAGES;
+    constexpr int RPI = direct_rows<BK>(), CPR = BK / 8;
+    constexpr int NLA = Smem<P, W>::ROWS_A / (4 * RPI), NLB = Smem<P, W>::ROWS_B / (4 * RPI);
+    static_assert(C::SWZ && PL == 1 && NB == 1 && (NA == 1 || W == 3),
+                  "direct loads: swizzled single-plane tiles, single products or dual-A (one K segment)");
+    static_assert(SM % RPI == 0 && STG >= 2 && (STG - 2) * (NLA + NLB) < 64, "direct-load geometry");
+    const int lrow = lane / CPR, pch = lane % CPR;
     const E* dab[NLA];
     const E* dbb[NLB];
     auto dseg = [&](int seg) {
-      const OpRef& ar = pb.a[seg];
       const OpRef& br = pb.b[seg];
 #pragma unroll
-      for (int i = 0; i < NLA; ++i)
-        dab[i] = (const E*)ar.base + off(ar, u) + (row0 + 8 * (4 * i + wave) + lrow) * ld;
+      for (int i = 0; i < NLA; ++i) {
+        const int r = RPI * (4 * i + wave) + lrow;
+        const int sel = NA == 2 ? (r < SM ? 0 : 1) : seg;
+        const OpRef& ar = pb.a[sel];
+        const int rr = NA == 2 ? r % SM : r;
+        dab[i] = (const E*)ar.base + off(ar, u) + (row0 + rr) * ld;
+      }
 #pragma unroll
       for (int i = 0; i < NLB; ++i)
-        dbb[i] = (const E*)br.base + off(br, u) + (col0 + 8 * (4 * i + wave) + lrow) * ld;
+        dbb[i] = (const E*)br.base + off(br, u) + (col0 + RPI * (4 * i + wave) + lrow) * ld;
     };
     int dseg_i = 0, dk = 0;                 // segment and k tile within it of the next load
-    auto dload = [&](int /*t*/) {
+    auto dload = [&](int t) {
       if (dk == 0) dseg(dseg_i);
       const int64_t k0 = (int64_t)dk * BK;
-      const int t = dseg_i * kps + dk;
-      E* sa = As + (t & 1) * TILE_A;
-      E* sb = Bs + (t & 1) * TILE_B;
+      E* sa = As + (t % STG) * TILE_A;
+      E* sb = Bs + (t % STG) * TILE_B;
 #pragma unroll
       for (int i = 0; i < NLA; ++i) {
-        const int r = 8 * (4 * i + wave) + lrow;
-        const int64_t kc = k0 + ((pch ^ (r & 7)) << 3);
-        const bool ok = kc < kk && row0 + r < mrows;
+        const int r = RPI * (4 * i + wave) + lrow;
+        const int rr = NA == 2 ? r % SM : r;
+        const int64_t kc = k0 + ((pch ^ swz(r)) << 3);
+        const bool ok = r < BM && kc < kk && row0 + rr < mrows;
         const E* src = ok ? dab[i] + kc : zvec;
         __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
                                          (__attribute__((address_space(3))) void*)(sa + (4 * i + wave) * 512),
@@ -467,9 +770,9 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
       }
 #pragma unroll
       for (int i = 0; i < NLB; ++i) {
-        const int r = 8 * (4 * i + wave) + lrow;
-        const int64_t kc = k0 + ((pch ^ (r & 7)) << 3);
-        const bool ok = kc < kk && col0 + r < ncols;
+        const int r = RPI * (4 * i + wave) + lrow;
+        const int64_t kc = k0 + ((pch ^ swz(r)) << 3);
+        const bool ok = r < BN && kc < kk && col0 + r < ncols;
         const E* src = ok ? dbb[i] + kc : zvec;
         __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
                                          (__attribute__((address_space(3))) void*)(sb + (4 * i + wave) * 512),
@@ -481,16 +784,19 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
       }
     };
     if (ktiles > 0) {
-      dload(0);
+#pragma unroll
+      for (int t = 0; t < STG - 1; ++t)
+        if (t < ktiles) dload(t);
       for (int kt = 0; kt < ktiles; ++kt) {
-        // this lane's loads of tile kt have landed (vmcnt 0: nothing else is
-        // in flight), then every lane's have; every wave is also done with
-        // tile kt-1, whose buffer the next loads overwrite.  A fenced
-        // barrier would add nothing but a wait on all memory traffic.
-        __builtin_amdgcn_s_waitcnt(0x0F70);                      // vmcnt(0)
+        // this lane's loads of tile kt have landed (the only ones that may
+        // still be outstanding belong to the STG-2 tiles after it), then
+        // every lane's have; every wave is also done with tile kt-1, whose
+        // buffer the next loads overwrite
+        if (kt + STG - 2 < ktiles) waitcnt_vm<(STG - 2) * (NLA + NLB)>();
+        else waitcnt_vm<0>();
         asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-        if (kt + 1 < ktiles) dload(kt + 1);
-        compute(kt & 1);
+        if (kt + STG - 1 < ktiles) dload(kt + STG - 1);
+        compute(kt % STG);
       }
       __syncthreads();       // LDS free for the epilogue's reduction slots
     }
@@ -526,13 +832,21 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
     }
   }
 
+  if constexpr (W != 0) {
+    wide_epilogue<P, W, NA>(L, pb, u, tile, row0, col0, smem, red, acc);
+    return;
+  }
   // -------- epilogue straight from the accumulators
   constexpr int NPROD = NA * NB;
   constexpr int GI = FR;                      // distinct row positions
   constexpr int GJ = FC;                      // distinct column positions
   Acc addc[kMaxAdd];
   const void* addp[kMaxAdd];
-  const int nadd = pb.nadd;
+  // dual-A wide tiles carry no addends and no Hadamard partials against a
+  // matrix (their problems have none; diagonal traces they do carry):
+  // compiled out, which keeps the tile in registers
+  constexpr bool kExtras = W != 3;
+  const int nadd = kExtras ? pb.nadd : 0;
   for (int x = 0; x < nadd; ++x) {
     addc[x] = (Acc)pb.add_coef[(int64_t)u.slot * kMaxAdd + x];
     addp[x] = (const char*)pb.add[x].base + off(pb.add[x], u) * (int64_t)sizeof(E);
@@ -542,9 +856,10 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
   for (int o = 0; o < nout; ++o)
     obase[o] = (char*)pb.out[o].base +
                off(pb.out[o], u) * (int64_t)(pb.out[o].type == 0 ? sizeof(Acc) : sizeof(E));
-  const double* hmat = pb.nhad ? (const double*)pb.had_h.base + off(pb.had_h, u) : nullptr;
+  const bool hdiag = pb.had_diag != 0;      // traces of the products (H = I): no matrix read
+  const double* hmat = pb.nhad && !hdiag ? (const double*)pb.had_h.base + off(pb.had_h, u) : nullptr;
   double hsum[kMaxHad] = {0.0, 0.0, 0.0, 0.0};
-  const int nh = pb.nhad;
+  const int nh = (kExtras || hdiag) ? pb.nhad : 0;
   const int ac = acc_col<P, MT>(lane);
   // For 32 x 32 tiles, accumulators 4q .. 4q+3 of a lane are four
   // consecutive rows, so transposed outputs are written as one 4-element
@@ -628,7 +943,14 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
 #pragma unroll
           for (int e = 0; e < RG; ++e) {
             if (grs[e] >= mrows) continue;
-            const double h = hmat[grs[e] * ld + gc];
+            double h;
+            if (hdiag) {
+              if (grs[e] != gc) continue;
+              h = 1.0;
+            } else {
+              if constexpr (!kExtras) continue;
+              h = hmat[grs[e] * ld + gc];
+            }
             for (int hq = 0; hq < nh; ++hq) {
               double s = 0.0;
 #pragma unroll
@@ -674,7 +996,7 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
       double s = red[0 * kMaxHad + tid] + red[1 * kMaxHad + tid];
       s += red[2 * kMaxHad + tid];
       s += red[3 * kMaxHad + tid];
-      pb.had_part[((int64_t)u.slot * nh + tid) * pb.had_ntiles + tile] = s;
+      pb.had_part[((int64_t)u.slot * pb.had_slot_stride + tid) * pb.had_ntiles + tile] = s;
     }
   }
 }
@@ -686,8 +1008,10 @@ __device__ __forceinline__ void gemm_item(const GemmLaunch& L, int tile, int py,
   const Unit u = L.units[ui];
   const Prob& pb = MI ? L.probs[(int64_t)u.inst * L.pstride + pi] : L.probs[pi];
   const InstGeo g = MI ? L.geo[u.inst] : L.g;
-  if constexpr (W == 1) {
+  if constexpr (W == 1 || W == 2) {
     gemm_body<P, W, 1, 1>(g, pb, u, tile, smem, red);   // single-product problems only
+  } else if constexpr (W == 3) {
+    gemm_body<P, W, 2, 1>(g, pb, u, tile, smem, red);   // dual-A problems only
   } else {
     const int mode = (pb.nA == 2 ? 2 : 0) + (pb.nB == 2 ? 1 : 0);
     switch (mode) {
@@ -732,8 +1056,13 @@ template <Prec P, int W> struct RedSlots {
   static constexpr int N = W == 1 ? 1 : 4 * kMaxHad;
 };
 
+// Workgroups per CU the register budget is sized for: the dual-A wide tile
+// keeps 200 accumulator registers live through its staged epilogue and
+// takes a whole CU's register file; the others fit two.
+template <int W> struct MinBlocks { static constexpr int N = W == 3 ? 1 : 2; };
+
 template <Prec P, int W, bool MI, bool PERSIST>
-__global__ __launch_bounds__(kThreads, 2) void gemm_kernel(GemmLaunch L) {
+__global__ __launch_bounds__(kThreads, MinBlocks<W>::N) void gemm_kernel(GemmLaunch L) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[Smem<P, W>::BYTES];
   __shared__ double red_own[RedSlots<P, W>::N];
   double* red = W == 1 ? (double*)smem : red_own;
@@ -764,7 +1093,8 @@ int gemm_tile_m(Prec p, int wide) {
   switch (p) {
     case Prec::F64: return Cfg<Prec::F64>::BM;
     case Prec::F32: return Cfg<Prec::F32>::BM;
-    case Prec::BF16: return wide ? Cfg<Prec::BF16, 1>::BM : Cfg<Prec::BF16>::BM;
+    case Prec::BF16: return wide == 1 ? Cfg<Prec::BF16, 1>::BM : wide == 2 ? Cfg<Prec::BF16, 2>::BM
+                            : wide == 3 ? Cfg<Prec::BF16, 3>::BM : Cfg<Prec::BF16>::BM;
     default: return Cfg<Prec::BF16X3>::BM;
   }
 }
@@ -772,9 +1102,21 @@ int gemm_tile_n(Prec p, int wide) {
   switch (p) {
     case Prec::F64: return Cfg<Prec::F64>::BN;
     case Prec::F32: return Cfg<Prec::F32>::BN;
-    case Prec::BF16: return wide ? Cfg<Prec::BF16, 1>::BN : Cfg<Prec::BF16>::BN;
+    case Prec::BF16: return wide == 1 ? Cfg<Prec::BF16, 1>::BN : wide == 2 ? Cfg<Prec::BF16, 2>::BN
+                            : wide == 3 ? Cfg<Prec::BF16, 3>::BN : Cfg<Prec::BF16>::BN;
     default: return Cfg<Prec::BF16X3>::BN;
   }
+}
+
+bool gemm_wide_supports(int wide, const Prob& pb) {
+  if (wide == 3) return pb.nA == 2 && pb.nB == 1 && pb.nseg == 1 && pb.nadd == 0 && (pb.nhad == 0 || pb.had_diag);
+  if (wide == 1 || wide == 2) {
+    if (pb.nA != 1 || pb.nB != 1 || pb.nadd != 0) return false;
+    for (int o = 0; o < pb.nout; ++o)
+      if (pb.out[o].type != 0 || pb.out[o].layout != 0) return false;
+    return true;
+  }
+  return true;
 }
 
 void launch_gemm(Prec p, const GemmLaunch& Lin, int max_tiles, hipStream_t st) {
@@ -790,9 +1132,13 @@ void launch_gemm(Prec p, const GemmLaunch& Lin, int max_tiles, hipStream_t st) {
   const bool mi = L.segs != nullptr, pers = L.persist > 0;
   auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(kThreads), 0, st, L); };
   if (L.wide) {
-    // the wide tile: BF16, one instance, single-product problems
+    // the 160-wide tiles: BF16, one instance; W 1 and 2 single-product
+    // problems, W 3 dual-A problems
     if (p != Prec::BF16 || mi) throw Gf2Error{GF2_E_STATE, "wide GEMM tile: BF16 single-instance launches only"};
-    go(gemm_kernel<Prec::BF16, 1, false, false>);
+    if (L.wide == 1) go(gemm_kernel<Prec::BF16, 1, false, false>);
+    else if (L.wide == 2) go(gemm_kernel<Prec::BF16, 2, false, false>);
+    else if (L.wide == 3) go(gemm_kernel<Prec::BF16, 3, false, false>);
+    else throw Gf2Error{GF2_E_STATE, "unknown GEMM tile"};
     GF2_HIP(hipGetLastError());
     return;
   }

@@ -69,12 +69,17 @@ struct Prob {
   OpRef a[kMaxSeg];
   OpRef b[kMaxSeg];
   OutSpec out[kMaxOut];
-  // Hadamard partial sums: part[(slot*nhad + h)*ntiles + tile] =
+  // Hadamard partial sums: part[(slot*had_slot_stride + h)*ntiles + tile] =
   //   sum over the tile of (sum_ab had_coef[h][ab] P_ab)_ij * H_ij.
+  // had_diag: H is the identity (traces of the product combinations; had_h
+  // unused).  Partials of slot s go to had_part[(s * had_slot_stride + h) *
+  // had_ntiles + tile].
   OpRef had_h;              // FP64 np x np
   float had_coef[kMaxHad][4];
   double* had_part;
   int64_t had_ntiles;
+  int32_t had_diag;
+  int32_t had_slot_stride;
   // Addends (nA = nB = 1 only): P += sum_x add_coef[slot][x] * Add_x (storage
   // format, row-major).
   OpRef add[kMaxAdd];
@@ -133,6 +138,10 @@ inline GemmLaunch chain_launch(const Prob* probs, int nprob, const Unit* units, 
                                int64_t np, int64_t plane) {
   return GemmLaunch{probs, nprob, 0, units, nunit, InstGeo{n, n, np, np, plane}, nullptr, 0, 0, nullptr, 0, 0, 0};
 }
+// Whether a problem fits the epilogue of wide tile `wide` (1 and 2: single
+// products with row-major FP32 outputs; 3: dual-A products without addends
+// or matrix Hadamard partials).
+bool gemm_wide_supports(int wide, const Prob& pb);
 int gemm_tile_m(Prec p, int wide = 0);     // BM
 int gemm_tile_n(Prec p, int wide = 0);     // BN
 
@@ -150,7 +159,7 @@ struct gf2_ctx {
   std::string err;
   std::map<std::string, DevBuf> bufs;   // named scratch buffers owned by the context
   int64_t max_units = 0;          // chunk size tuning (0 = automatic)
-  int32_t gemm_wide = 1;          // 1: wide BF16 tile where it pads less; 0: standard tiles only
+  int32_t gemm_wide = 2;          // BF16 tiles where 160 pads less than 128: 2 all stages, 1 s4 only, 0 none
   // (n, np, precision) of the last chain layout per buffer-tag prefix
   std::map<std::string, std::string> chain_keys;
   // launch shapes chosen by the batch autotuner, per batch signature

@@ -34,6 +34,15 @@ __device__ __forceinline__ void put_st(void* base, int64_t i, int64_t plane, Pre
     } break;
   }
 }
+// Read element i of a padded matrix in storage format `p` (hi + lo planes for BF16X3).
+__device__ __forceinline__ double get_st(const void* base, int64_t i, int64_t plane, Prec p) {
+  switch (p) {
+    case Prec::F64: return ((const double*)base)[i];
+    case Prec::F32: return (double)((const float*)base)[i];
+    case Prec::BF16: return (double)bf2f(((const bf16_t*)base)[i]);
+    default: return (double)bf2f(((const bf16_t*)base)[i]) + (double)bf2f(((const bf16_t*)base)[i + plane]);
+  }
+}
 __device__ __forceinline__ double get_acc(const void* base, int64_t i, bool f64) {
   return f64 ? ((const double*)base)[i] : (double)((const float*)base)[i];
 }
@@ -384,19 +393,23 @@ __global__ __launch_bounds__(256) void k_trace_coef(const double* part, int64_t 
   if ((threadIdx.x & 63) == 0) c[h] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double* o = coef + (int64_t)slot * kMaxAdd;
+    double* o = coef + (int64_t)slot * kCoefStride;
     o[0] = 2.0 * c[3];
     o[1] = 2.0 * (c[2] + c[3]);
     o[2] = 2.0 * (c[1] + c[3]);
     o[3] = 2.0 * (c[0] + c[1] + c[2] + c[3]);
+    for (int h = 0; h < 4; ++h) o[4 + h] = c[h];       // Tr(T_h) = Tr(M_h Gbar)
   }
 }
 
-// Sigma_sum[tau] += sum of the chunk's Sigma_s in unit order; e_s(tau) from
-// the per-tile partials.  One thread per (tau-group, i, j).
+// Sigma_sum[tau] += sum of the chunk's Sigma_s in unit order, each the
+// product stage's output plus its direct terms sum_x coef_x M_x (M_x the
+// slot's four M matrices in storage format, coef from k_trace_coef).  One
+// thread per (tau-group, i, j).
 __global__ void k_accumulate(const Unit* units, int32_t nunit, const void* sig, int f64,
                              int64_t sig_st_slot, int64_t n, int64_t np, double* sum,
-                             int32_t tau_lo, int32_t tau_hi) {
+                             int32_t tau_lo, int32_t tau_hi, const void* mst, Prec prec,
+                             int64_t m_st_slot, int64_t m_st_m, int64_t plane, const double* coef) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t ntau = tau_hi - tau_lo;
   if (e >= ntau * n * n) return;
@@ -405,18 +418,29 @@ __global__ void k_accumulate(const Unit* units, int32_t nunit, const void* sig, 
   double acc = sum[(int64_t)t * n * n + ij];
   for (int u = 0; u < nunit; ++u) {
     if (units[u].tau != t) continue;
-    acc += get_acc(sig, (int64_t)units[u].slot * sig_st_slot + i * np + j, f64);
+    const int64_t slot = units[u].slot;
+    double v = get_acc(sig, slot * sig_st_slot + i * np + j, f64);
+    const double* cf = coef + slot * kCoefStride;
+    for (int x = 0; x < 4; ++x) v += cf[x] * get_st(mst, slot * m_st_slot + x * m_st_m + i * np + j, plane, prec);
+    acc += v;
   }
   sum[(int64_t)t * n * n + ij] = acc;
 }
 
-// e_s(tau) of every unit from its per-tile partials: one wave per unit.
+// e_s(tau) of every unit: its per-tile partials of Tr(product part Gbar)
+// plus the direct terms' sum_x coef_x Tr(M_x Gbar).  One wave per unit.
 __global__ __launch_bounds__(256) void k_esamples(const Unit* units, int32_t nunit, const double* part,
-                                                  int64_t ntiles, int64_t s0, int64_t ntau, double* es) {
+                                                  int64_t ntiles, int64_t s0, int64_t ntau, double* es,
+                                                  const double* coef) {
   const int u = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (u >= nunit) return;                        // whole wave leaves together
   const double s = wave_sum_fixed(part + (int64_t)units[u].slot * ntiles, ntiles);
-  if ((threadIdx.x & 63) == 0) es[((int64_t)units[u].s - s0) * ntau + units[u].tau] = s;
+  if ((threadIdx.x & 63) == 0) {
+    const double* cf = coef + (int64_t)units[u].slot * kCoefStride;
+    double d = 0.0;
+    for (int x = 0; x < 4; ++x) d += cf[x] * cf[4 + x];
+    es[((int64_t)units[u].s - s0) * ntau + units[u].tau] = s + d;
+  }
 }
 
 __global__ void k_finalize(const double* det, const double* sum, int64_t n, int64_t ntau,
@@ -649,15 +673,17 @@ void launch_trace_coef(const double* part, int64_t ntiles, int32_t nslot, double
   hipLaunchKernelGGL(k_trace_coef, dim3((unsigned)nslot), dim3(256), 0, st, part, ntiles, nslot, coef);
 }
 void launch_accumulate(const Unit* units, int32_t nunit, const void* sig, bool f64, int64_t sig_st_slot,
-                       int64_t n, int64_t np, double* sum, int32_t tau_lo, int32_t tau_hi, hipStream_t st) {
+                       int64_t n, int64_t np, double* sum, int32_t tau_lo, int32_t tau_hi, const void* mst,
+                       Prec prec, int64_t m_st_slot, int64_t m_st_m, int64_t plane, const double* coef,
+                       hipStream_t st) {
   int64_t total = (int64_t)(tau_hi - tau_lo) * n * n;
   hipLaunchKernelGGL(k_accumulate, dim3(blocks(total)), dim3(256), 0, st, units, nunit, sig, (int)f64,
-                     sig_st_slot, n, np, sum, tau_lo, tau_hi);
+                     sig_st_slot, n, np, sum, tau_lo, tau_hi, mst, prec, m_st_slot, m_st_m, plane, coef);
 }
 void launch_esamples(const Unit* units, int32_t nunit, const double* part, int64_t ntiles, int64_t s0,
-                     int64_t ntau, double* es, hipStream_t st) {
+                     int64_t ntau, double* es, const double* coef, hipStream_t st) {
   hipLaunchKernelGGL(k_esamples, dim3((unsigned)((nunit + 3) / 4)), dim3(256), 0, st, units, nunit, part, ntiles, s0,
-                     ntau, es);
+                     ntau, es, coef);
 }
 void launch_finalize(const double* det, const double* sum, int64_t n, int64_t ntau, double inv2ns,
                      double* out, hipStream_t st) {

@@ -40,11 +40,15 @@ void launch_jk_scatter(bool f64, const void* jblk, int64_t naux, int32_t nslot, 
                        Prec prec, int64_t plane, void* jw_l, void* jw_s, void* jz_st, void* jz_sum_t,
                        int64_t out_st_slot, hipStream_t st);
 void launch_trace_coef(const double* part, int64_t ntiles, int32_t nslot, double* coef, hipStream_t st);
+// Per-slot direct-term record written by launch_trace_coef: coef[0..3] for
+// M_LL, M_LS, M_SL, M_SS, then Tr(T_h) for h = 0..3.
+constexpr int kCoefStride = 8;
 void launch_accumulate(const Unit* units, int32_t nunit, const void* sig, bool f64, int64_t sig_st_slot,
-                       int64_t n, int64_t np, double* sum, int32_t tau_lo, int32_t tau_hi,
+                       int64_t n, int64_t np, double* sum, int32_t tau_lo, int32_t tau_hi, const void* mst,
+                       Prec prec, int64_t m_st_slot, int64_t m_st_m, int64_t plane, const double* coef,
                        hipStream_t st);
 void launch_esamples(const Unit* units, int32_t nunit, const double* part, int64_t ntiles, int64_t s0,
-                     int64_t ntau, double* es, hipStream_t st);
+                     int64_t ntau, double* es, const double* coef, hipStream_t st);
 void launch_finalize(const double* det, const double* sum, int64_t n, int64_t ntau, double inv2ns,
                      double* out, hipStream_t st);
 // Two-level (BF16 / BF16X3) correction: sum += lo + c (hi - lo); and the

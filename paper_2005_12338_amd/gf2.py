@@ -435,9 +435,12 @@ class Context:
         self._check(self.lib.gf2_debug_gemm(self.h, PREC[prec], n, batch, A.data_ptr(), Bt.data_ptr(),
                                             Cout.data_ptr()))
 
-    def set_gemm_tiles(self, wide: bool):
-        """wide=True (default): the 160-wide BF16 tile where it pads less."""
-        self._check(self.lib.gf2_set_gemm_tiles(self.h, 1 if wide else 0))
+    def set_gemm_tiles(self, mode):
+        """BF16 tile choice where 160 pads less than 128: 2 (default, or True)
+        the 160-wide tiles on every product launch, 1 on the deep-K stage only,
+        0 (or False) the 128-wide tile everywhere."""
+        m = (2 if mode else 0) if isinstance(mode, bool) else int(mode)
+        self._check(self.lib.gf2_set_gemm_tiles(self.h, m))
 
     def set_profiling(self, on: bool):
         self._check(self.lib.gf2_set_profiling(self.h, 1 if on else 0))

@@ -304,19 +304,38 @@ def test_gemm_kernel_matches_torch_reference(ctx, prec, n, batch):
 
 @pytest.mark.parametrize("n_dimer", [75, 200])
 def test_wide_tile_chain_matches_standard_tiles(ctx, n_dimer):
-    """N = 150 and 400: the single-product stage runs on the 160-wide BF16
-    tile.  Against the same chain on 128-wide tiles only, the results differ
-    by the FP32 accumulation order of that stage alone."""
+    """N = 150 and 400, where the 160-wide BF16 tiles pad less than 128.
+    Mode 1 (deep-K stage only on the wide tile) against mode 0 (128 tiles
+    only): the deep-K stage writes FP32, so the two differ by its FP32
+    accumulation order alone.  Mode 2 (every launch on the wide tiles) also
+    reorders products whose outputs are stored in BF16, so single roundings
+    can flip: against the FP32 path it stays at the BF16 level, as mode 0
+    does."""
     pb = chain(n_dimer, 100.0, 3, 1e-3)
     B, G, Gb, mu, tau, w = _gpu_inputs(ctx, pb, torch.float32)
     spl = ctx.split(B, pb["eps"])
+    out, ran = {}, {}
     try:
-        ctx.set_gemm_tiles(False)
-        S0, e0 = ctx.sigma_tau(spl, B, G, Gb, ns=3, seed=4, prec="bf16")
-        ctx.set_gemm_tiles(True)
-        S1, e1 = ctx.sigma_tau(spl, B, G, Gb, ns=3, seed=4, prec="bf16")
+        for mode in (0, 1, 2):
+            ctx.set_gemm_tiles(mode)
+            ctx.set_profiling(True)
+            ctx.profile_read()
+            out[mode] = ctx.sigma_tau(spl, B, G, Gb, ns=3, seed=4, prec="bf16")
+            ran[mode] = sorted(k for k in ctx.profile_read() if k.endswith("@160"))
     finally:
-        ctx.set_gemm_tiles(True)
-    assert not torch.equal(e0, e1)                 # the wide tile did run
+        ctx.set_profiling(False)
+        ctx.set_gemm_tiles(2)
+    assert ran[0] == [] and ran[1] == ["gemm_bf16.s4@160"]
+    assert ran[2] == ["gemm_bf16.s1@160", "gemm_bf16.s2@160", "gemm_bf16.s3@160", "gemm_bf16.s4@160"]
+    S32, e32 = ctx.sigma_tau(spl, B, G, Gb, ns=3, seed=4, prec="fp32")
+    (S0, e0), (S1, e1), (S2, e2) = out[0], out[1], out[2]
+    assert not torch.equal(e0, e1)
     assert rel(S1.cpu().numpy(), S0.cpu().numpy()) < 1e-6
     assert rel(e1.cpu().numpy(), e0.cpu().numpy()) < 1e-5
+    err0 = rel(S0.cpu().numpy(), S32.cpu().numpy())
+    err2 = rel(S2.cpu().numpy(), S32.cpu().numpy())
+    ee0 = rel(e0.cpu().numpy(), e32.cpu().numpy())
+    ee2 = rel(e2.cpu().numpy(), e32.cpu().numpy())
+    print(f"n_dimer {n_dimer}: BF16 vs FP32: Sigma rel {err0:.2e} (128 tiles) {err2:.2e} (wide); "
+          f"e_s rel {ee0:.2e} {ee2:.2e}")
+    assert err2 < 2.0 * err0 + 1e-7 and ee2 < 2.0 * ee0 + 1e-6
