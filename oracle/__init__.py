@@ -19,4 +19,5 @@ Modules
   selfenergy  eq:sigma (brute force and bilinear form), eq:sigma_2 estimator
   energy      Galitskii-Migdal energy (eq:corr) and statistics
   proposal    importance proposal over the auxiliary index (project form)
+  variants    control-variate and double-sum forms of the eq:sigma_2 average
 """

@@ -288,25 +288,26 @@ __global__ void k_pad_convert(const double* g, int64_t n, int64_t np, int64_t nt
 // ------------------------------------------------------------- JK ---------
 // For every (slot, m in 0..3, Q): J = 2 Tr(k W_SS) k - k W_SS k with W the
 // m-th matrix of the slot (accumulator format, row-major padded).  One wave
-// per (slot, m, Q); lanes walk the w x w block elements.
-template <typename T>
+// per (slot, m, Q); lanes walk the w x w block elements (w <= WB).  Waves
+// share nothing: each keeps its blocks in its own LDS slice, ordered by a
+// wave-level fence (LDS operations of one wave complete in order).
+template <typename T, int WB>
 __global__ __launch_bounds__(256) void k_jk_blocks(const void* wbase, int64_t w_st_slot,
                                                     int64_t w_st_m, int64_t np, int64_t naux,
                                                     int32_t nslot, const int32_t* wq,
                                                     const int32_t* idx, const T* blk, T* jout) {
-  __shared__ T sk[4][kWMax * kWMax];
-  __shared__ T sw[4][kWMax * kWMax];
-  __shared__ T st[4][kWMax * kWMax];
+  __shared__ T sk[4][WB * WB];
+  __shared__ T sw[4][WB * WB];
+  __shared__ T st[4][WB * WB];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t task = (int64_t)blockIdx.x * 4 + wv;
   const int64_t total = (int64_t)nslot * 4 * naux;
-  const bool active = task < total;               // every wave reaches the barriers
-  const int64_t tk = active ? task : 0;
-  const int64_t q = tk % naux;
-  const int64_t m = (tk / naux) % 4;
-  const int64_t slot = tk / (naux * 4);
-  const int w = active ? wq[q] : 0;
-  T* out = jout + tk * kWMax * kWMax;
+  if (task >= total) return;                      // whole wave leaves together
+  const int64_t q = task % naux;
+  const int64_t m = (task / naux) % 4;
+  const int64_t slot = task / (naux * 4);
+  const int w = wq[q];
+  T* out = jout + task * kWMax * kWMax;
   const T* W = (const T*)wbase + slot * w_st_slot + m * w_st_m;
   const int32_t* s = idx + q * kWMax;
   const int ww = w * w;
@@ -315,7 +316,8 @@ __global__ __launch_bounds__(256) void k_jk_blocks(const void* wbase, int64_t w_
     sk[wv][e] = blk[q * kWMax * kWMax + a * kWMax + c];
     sw[wv][e] = W[(int64_t)s[a] * np + s[c]];
   }
-  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
   // t = Tr(k W) = sum_ab k_ab W_ba
   T tr = 0;
   for (int e = lane; e < ww; e += 64) {
@@ -329,7 +331,8 @@ __global__ __launch_bounds__(256) void k_jk_blocks(const void* wbase, int64_t w_
     for (int x = 0; x < w; ++x) acc += sk[wv][a * w + x] * sw[wv][x * w + c];
     st[wv][e] = acc;
   }
-  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
   for (int e = lane; e < ww; e += 64) {
     int a = e / w, c = e % w;
     T acc = 0;
@@ -405,26 +408,51 @@ __global__ __launch_bounds__(256) void k_trace_coef(const double* part, int64_t 
 // Sigma_sum[tau] += sum of the chunk's Sigma_s in unit order, each the
 // product stage's output plus its direct terms sum_x coef_x M_x (M_x the
 // slot's four M matrices in storage format, coef from k_trace_coef).  One
-// thread per (tau-group, i, j).
+// thread per (tau-group, i, four consecutive j): the padded rows (np a
+// multiple of 32) give aligned 4-element vectors.
 __global__ void k_accumulate(const Unit* units, int32_t nunit, const void* sig, int f64,
                              int64_t sig_st_slot, int64_t n, int64_t np, double* sum,
                              int32_t tau_lo, int32_t tau_hi, const void* mst, Prec prec,
                              int64_t m_st_slot, int64_t m_st_m, int64_t plane, const double* coef) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t ntau = tau_hi - tau_lo;
-  if (e >= ntau * n * n) return;
-  int32_t t = tau_lo + (int32_t)(e / (n * n));
-  int64_t ij = e % (n * n), i = ij / n, j = ij % n;
-  double acc = sum[(int64_t)t * n * n + ij];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ntau = tau_hi - tau_lo, nq = np / 4;
+  if (e >= ntau * n * nq) return;
+  const int32_t t = tau_lo + (int32_t)(e / (n * nq));
+  const int64_t r = e % (n * nq), i = r / nq, j0 = 4 * (r % nq);
+  if (j0 >= n) return;
+  const int nj = (int)(n - j0 < 4 ? n - j0 : 4);
+  double* srow = sum + (int64_t)t * n * n + i * n + j0;
+  double acc[4];
+  for (int k = 0; k < nj; ++k) acc[k] = srow[k];
+  for (int k = nj; k < 4; ++k) acc[k] = 0.0;
   for (int u = 0; u < nunit; ++u) {
     if (units[u].tau != t) continue;
     const int64_t slot = units[u].slot;
-    double v = get_acc(sig, slot * sig_st_slot + i * np + j, f64);
+    const int64_t o = i * np + j0;
+    double v[4];
+    if (f64) {
+      const double* p = (const double*)sig + slot * sig_st_slot + o;
+      for (int k = 0; k < 4; ++k) v[k] = p[k];
+    } else {
+      const float4 x = *(const float4*)((const float*)sig + slot * sig_st_slot + o);
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    }
     const double* cf = coef + slot * kCoefStride;
-    for (int x = 0; x < 4; ++x) v += cf[x] * get_st(mst, slot * m_st_slot + x * m_st_m + i * np + j, plane, prec);
-    acc += v;
+    for (int x = 0; x < 4; ++x) {
+      const int64_t mo = slot * m_st_slot + x * m_st_m + o;
+      if (prec == Prec::BF16) {
+        const uint2 h = *(const uint2*)((const bf16_t*)mst + mo);
+        v[0] += cf[x] * (double)bf2f((bf16_t)(h.x & 0xffffu));
+        v[1] += cf[x] * (double)bf2f((bf16_t)(h.x >> 16));
+        v[2] += cf[x] * (double)bf2f((bf16_t)(h.y & 0xffffu));
+        v[3] += cf[x] * (double)bf2f((bf16_t)(h.y >> 16));
+      } else {
+        for (int k = 0; k < 4; ++k) v[k] += cf[x] * get_st(mst, mo + k, plane, prec);
+      }
+    }
+    for (int k = 0; k < 4; ++k) acc[k] += v[k];
   }
-  sum[(int64_t)t * n * n + ij] = acc;
+  for (int k = 0; k < nj; ++k) srow[k] = acc[k];
 }
 
 // e_s(tau) of every unit: its per-tile partials of Tr(product part Gbar)
@@ -642,17 +670,31 @@ void launch_pad_convert(const double* g, int64_t n, int64_t np, int64_t ntau, Pr
   hipLaunchKernelGGL(k_pad_convert, dim3(blocks(ntau * np * np)), dim3(256), 0, st, g, n, np, ntau,
                      prec, stbuf, plane, mstride, f64pad);
 }
+template <typename T>
+void jk_blocks_launch(int32_t wmax, dim3 grid, hipStream_t st, const void* wbase, int64_t w_st_slot, int64_t w_st_m,
+                      int64_t np, int64_t naux, int32_t nslot, const int32_t* wq, const int32_t* idx, const T* blk,
+                      T* jout) {
+  if (wmax <= 8)
+    hipLaunchKernelGGL((k_jk_blocks<T, 8>), grid, dim3(256), 0, st, wbase, w_st_slot, w_st_m, np, naux, nslot, wq,
+                       idx, blk, jout);
+  else if (wmax <= 16)
+    hipLaunchKernelGGL((k_jk_blocks<T, 16>), grid, dim3(256), 0, st, wbase, w_st_slot, w_st_m, np, naux, nslot, wq,
+                       idx, blk, jout);
+  else
+    hipLaunchKernelGGL((k_jk_blocks<T, kWMax>), grid, dim3(256), 0, st, wbase, w_st_slot, w_st_m, np, naux, nslot,
+                       wq, idx, blk, jout);
+}
 void launch_jk_blocks(bool f64, const void* wbase, int64_t w_st_slot, int64_t w_st_m, int64_t np,
-                      int64_t naux, int32_t nslot, const int32_t* wq, const int32_t* idx,
+                      int64_t naux, int32_t nslot, int32_t wmax, const int32_t* wq, const int32_t* idx,
                       const void* blk, void* jout, hipStream_t st) {
   int64_t tasks = (int64_t)nslot * 4 * naux;
   dim3 grid((unsigned)((tasks + 3) / 4));
   if (f64)
-    hipLaunchKernelGGL((k_jk_blocks<double>), grid, dim3(256), 0, st, wbase, w_st_slot, w_st_m, np,
-                       naux, nslot, wq, idx, (const double*)blk, (double*)jout);
+    jk_blocks_launch<double>(wmax, grid, st, wbase, w_st_slot, w_st_m, np, naux, nslot, wq, idx, (const double*)blk,
+                             (double*)jout);
   else
-    hipLaunchKernelGGL((k_jk_blocks<float>), grid, dim3(256), 0, st, wbase, w_st_slot, w_st_m, np,
-                       naux, nslot, wq, idx, (const float*)blk, (float*)jout);
+    jk_blocks_launch<float>(wmax, grid, st, wbase, w_st_slot, w_st_m, np, naux, nslot, wq, idx, (const float*)blk,
+                            (float*)jout);
 }
 void launch_jk_scatter(bool f64, const void* jblk, int64_t naux, int32_t nslot, int64_t npat,
                        const int32_t* pat_ij, const int32_t* pat_off, const int32_t* pat_q, int64_t np,
@@ -676,7 +718,7 @@ void launch_accumulate(const Unit* units, int32_t nunit, const void* sig, bool f
                        int64_t n, int64_t np, double* sum, int32_t tau_lo, int32_t tau_hi, const void* mst,
                        Prec prec, int64_t m_st_slot, int64_t m_st_m, int64_t plane, const double* coef,
                        hipStream_t st) {
-  int64_t total = (int64_t)(tau_hi - tau_lo) * n * n;
+  int64_t total = (int64_t)(tau_hi - tau_lo) * n * (np / 4);
   hipLaunchKernelGGL(k_accumulate, dim3(blocks(total)), dim3(256), 0, st, units, nunit, sig, (int)f64,
                      sig_st_slot, n, np, sum, tau_lo, tau_hi, mst, prec, m_st_slot, m_st_m, plane, coef);
 }
