@@ -224,6 +224,44 @@ gf2_status gf2_sigma_finalize(gf2_ctx* ctx, int64_t n, int64_t ntau,
                               const double* Sigma_det, const double* Sigma_sum,
                               int64_t ns_total, double* Sigma);
 
+/* ------------------------------------------------------------ estimator variants
+ * Two other readings of the averages <>_theta <>_theta' of eq:sigma_2, with
+ * the inputs, outputs and errors of gf2_sigma_stoch (Sigma_sum is ADDED to,
+ * unsymmetrised; finish with gf2_sigma_finalize and gf2_sigma_det):
+ *
+ * gf2_sigma_stoch_cv: the control-variate form.  E[R (x) R] = v and
+ *   E[R^L (x) R^L] = D give, per pair, Sigma_s = chain(R_xi, R_eta) -
+ *   chain(R^L_xi, R^L_eta) with chain(a, b) = 2 Tr(T) M - T M, M = a G b,
+ *   T = M Gbar (eq:sigma with one bilinear vertex each): 8 N x N products
+ *   per (tau, pair) instead of 24; unbiased, but the D (x) S cross terms are
+ *   sampled.  The difference cancels: use FP32 or FP64 (BF16 rounding of the
+ *   two chains is not small next to their difference).  e_samples
+ *   [ns][ntau].
+ *
+ * gf2_sigma_stoch_double: the double average over every combination of a
+ *   first-set vector i and a second-set vector j (i, j < ns <= 256): ns^2
+ *   pair estimates from 2 ns vectors, each as in gf2_sigma_stoch, added into
+ *   Sigma_sum; e_samples [ns * ns][ntau], row i ns + j.  Finish with
+ *   gf2_sigma_finalize(..., ns_total = ns * ns, ...) and gf2_energy_double.
+ *
+ * gf2_energy_double: E_tot as gf2_energy (w host [ntau]; Sigma, Gbar,
+ *   e_samples device), and the standard error of the double average to
+ *   first order (Hoeffding): sqrt(Var_i(r_i)/ns + Var_j(c_j)/ns), r_i and
+ *   c_j the row and column means of the per-combination energies.
+ *   GF2_E_ARG unless 2 <= ns <= 256 and ntau <= 512; GF2_E_NUMERIC. */
+gf2_status gf2_sigma_stoch_cv(gf2_ctx* ctx, const gf2_split_h* split, const void* B,
+                              const double* G, const double* Gbar, int64_t ntau,
+                              const gf2_sampling* sampling, gf2_precision prec,
+                              double* Sigma_sum, double* e_samples);
+gf2_status gf2_sigma_stoch_double(gf2_ctx* ctx, const gf2_split_h* split, const void* B,
+                                  const double* G, const double* Gbar, int64_t ntau,
+                                  const gf2_sampling* sampling, gf2_precision prec,
+                                  double* Sigma_sum, double* e_samples);
+gf2_status gf2_energy_double(gf2_ctx* ctx, int64_t n, int64_t ntau, const double* w,
+                             const double* Sigma, const double* Gbar,
+                             const double* e_samples, int64_t ns, double n_elec,
+                             double* E_tot, double* E_per_e, double* stderr_tot);
+
 /* ------------------------------------------------------------ energy (a10)
  * E_tot = -(1/2) sum_t w_t Tr(Sigma(tau_t) Gbar(tau_t)) in FP64 (eq:corr;
  * the -1/2 makes the beta -> infinity limit the closed-shell MP2 energy).

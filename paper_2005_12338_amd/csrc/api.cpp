@@ -114,10 +114,13 @@ void check_finite(gf2_ctx* ctx, const double* x, int64_t count, const char* what
   if (h) throw Gf2Error{GF2_E_NUMERIC, std::to_string(h) + " non-finite values in " + what};
 }
 
-OpRef opref(const void* base, int64_t st_tau = 0, int64_t st_s = 0, int64_t st_slot = 0) {
+OpRef opref(const void* base, int64_t st_tau = 0, int64_t st_s = 0, int64_t st_slot = 0, int64_t st_s2 = 0) {
   OpRef r;
-  r.base = base; r.st_tau = st_tau; r.st_s = st_s; r.st_slot = st_slot;
+  r.base = base; r.st_tau = st_tau; r.st_s = st_s; r.st_slot = st_slot; r.st_s2 = st_s2;
   return r;
+}
+Unit mk_unit(int64_t tau, int64_t s, int64_t slot, int64_t s2, int64_t row) {
+  return Unit{(int32_t)tau, (int32_t)s, (int32_t)slot, 0, (int32_t)s2, (int32_t)row};
 }
 OutSpec outspec(void* base, int64_t st_slot, std::initializer_list<float> coef, int layout, int type,
                 int64_t st_tau = 0) {
@@ -553,7 +556,7 @@ gf2_status gf2_green_tau(gf2_ctx* ctx, int64_t n, const double* F, const double*
     auto* probs = (Prob*)ctx_buf(ctx, "g_prob", sizeof(Prob));
     h2d(ctx, probs, &pb, 1);
     std::vector<Unit> uh(ntau);
-    for (int64_t t = 0; t < ntau; ++t) uh[t] = Unit{(int32_t)t, 0, 0, 0};
+    for (int64_t t = 0; t < ntau; ++t) uh[t] = mk_unit(t, 0, 0, 0, 0);
     auto* units = (Unit*)ctx_buf(ctx, "g_units", (size_t)ntau * sizeof(Unit));
     h2d(ctx, units, uh.data(), uh.size());
     GemmLaunch L = chain_launch(probs, 1, units, (int32_t)ntau, n, np, 0);
@@ -631,6 +634,12 @@ struct ChainPlan {
   double* Sigma_sum = nullptr;
   double* e_samples = nullptr;
   char* mst = nullptr;           // the four M matrices per slot (storage format)
+  // estimator: 0 the paired L/S-resolved form, 1 the control-variate form,
+  // 2 the double average over every (first-set, second-set) combination
+  int variant = 0;
+  int64_t npairs = 0;            // pairs of the unit list (ns, or ns^2 for the double average)
+  int ngroups = 0;               // product launches per chunk and their problems
+  int goff[4] = {0, 0, 0, 0}, gcnt[4] = {0, 0, 0, 0}, gprod[4] = {0, 0, 0, 0};
 };
 
 // The product launches of one chunk (first problem, problems, products per
@@ -661,9 +670,11 @@ int64_t auto_slots(int64_t n, Prec prec) {
 // tables and unit lists of one instance.  sc / tcnt > 0 force the chunk shape.
 void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_split_h* sp, const void* B,
                 const double* G, const double* Gbar, int64_t ntau, const gf2_sampling* smp, Prec prec,
-                double* Sigma_sum, double* e_samples, int64_t force_sc = 0, int64_t force_tcnt = 0) {
+                double* Sigma_sum, double* e_samples, int64_t force_sc = 0, int64_t force_tcnt = 0,
+                int variant = 0) {
   c.sp = sp;
   c.prec = prec;
+  c.variant = variant;
   c.n = sp->n;
   c.np = sp->np;
   c.np2 = c.np * c.np;
@@ -686,9 +697,11 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
   // ---- chunking: units (tau, s), s outer so that every Sigma_sum[tau]
   // receives its pairs in increasing s; several pairs per tau in a chunk, so
   // each Sigma_sum[tau] is read and written once per chunk for all of them.
+  const int64_t npairs = variant == 2 ? ns * ns : ns;
+  c.npairs = npairs;
   int64_t slots = ctx->max_units > 0 ? ctx->max_units : auto_slots(n, prec);
-  slots = std::min<int64_t>(slots, ntau * ns);
-  c.sc = force_sc > 0 ? std::min(force_sc, ns) : std::min<int64_t>(ns, std::min<int64_t>(8, slots));
+  slots = std::min<int64_t>(slots, ntau * npairs);
+  c.sc = force_sc > 0 ? std::min(force_sc, npairs) : std::min<int64_t>(npairs, std::min<int64_t>(8, slots));
   c.tcnt = force_tcnt > 0 ? std::min(force_tcnt, ntau) : std::max<int64_t>(1, std::min<int64_t>(ntau, slots / c.sc));
   c.slots = slots = c.sc * c.tcnt;
 
@@ -791,146 +804,232 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
   const int64_t vst = planes * np2;                            // one vector
   std::vector<Prob>& P = c.P;
   P.clear();
-  // S1: U = X G (dual A), V = G Y (dual B)
-  {
-    Prob p = prob0();
-    p.nA = 2;
-    p.a[0] = opref(xl, 0, vst);
-    p.a[1] = opref(xs, 0, vst);
-    p.b[0] = g_op;
-    p.nout = 4;
-    p.out[0] = outspec(ul_n, st_sl, {1, 0}, 0, 1);
-    p.out[1] = outspec(ul_t, st_sl, {1, 0}, 1, 1);
-    p.out[2] = outspec(us_n, st_sl, {0, 1}, 0, 1);
-    p.out[3] = outspec(us_t, st_sl, {0, 1}, 1, 1);
-    P.push_back(p);
-    // V_c = G Y_c as its transpose Y_c G (G and Y_c symmetric): a dual-A
-    // product whose tile holds V_L^T and V_S^T at the same positions
-    Prob q = prob0();
-    q.nA = 2;
-    q.a[0] = opref(xl + sb * ns, 0, vst);
-    q.a[1] = opref(xs + sb * ns, 0, vst);
-    q.b[0] = g_op;
-    q.nout = 4;
-    q.out[0] = outspec(vl_n, st_sl, {1, 0}, 1, 1);
-    q.out[1] = outspec(vs_n, st_sl, {0, 1}, 1, 1);
-    q.out[2] = outspec(vs_t, st_sl, {0, 1}, 0, 1);
-    q.out[3] = outspec(vsum_t, st_sl, {1, 1}, 0, 1);
-    P.push_back(q);
-  }
-  if (wide_for(ctx, prec, n)) {
-    // 160-wide tiles where they pad n less: the deep-K stage s4 always, the
-    // dual-A launches (s1, s2, s3) in the default mode 2
-    c.wideg[3] = 1;
-    if (ctx->gemm_wide >= 2) c.wideg[0] = c.wideg[1] = c.wideg[2] = 3;
-  }
-  Prob dual = prob0();
-  dual.nA = 2;
-  c.mtiles = tiles_of(dual, prec, n, c.wideg[2]);
-  Prob single = prob0();
-  c.ftiles = tiles_of(single, prec, n, c.wideg[3]);
-  c.mpart = (double*)S("c_mpart", 4 * c.mtiles * 8);
-  c.epart = (double*)S("c_epart", c.ftiles * 8);
-  c.coef = (double*)S("c_coef", kCoefStride * 8);
-  c.mst = mst;
-  // Matrices of the exchange term, -sum over the nine (T_xy, M_zw) pairs of
-  // S_xi x S_eta, grouped into four products whose factors each come from
-  // one dual-A tile:
-  //   T_SS (M_LL + M_SL) + (T_SL + T_SS)(M_LS + M_SS) + T_LS M_SL + (T_LL + T_LS) M_SS.
-  // mst[x] = M_x (x = LL, LS, SL, SS; row-major, the A operands of s3 and
-  // the direct terms); mct[x] = the x-th B factor above, negated and
-  // transposed; tq[x] = the x-th A factor.
-  // S2: M_xL = U_x Y_L and M_xS = U_x Y_S (dual-A over x), W = V Gb (dual-A),
-  // Z = Gb U as Z^T = U^T Gb (dual-A)
-  for (int y = 0; y < 2; ++y) {
-    Prob p = prob0();
-    p.nA = 2;
-    p.a[0] = opref(ul_n, 0, 0, st_sl);
-    p.a[1] = opref(us_n, 0, 0, st_sl);
-    p.b[0] = opref((y == 0 ? xl : xs) + sb * ns, 0, vst);
-    p.nout = 4;
-    const int lx = y == 0 ? 0 : 1, sx = y == 0 ? 2 : 3;      // M_Ly and M_Sy in mst order
-    p.out[0] = outspec(mst + lx * sb, 4 * st_sl, {1, 0}, 0, 1);
-    p.out[1] = outspec(mst + sx * sb, 4 * st_sl, {0, 1}, 0, 1);
-    if (y == 0) {
-      p.out[2] = outspec(mct + 0 * sb, 4 * st_sl, {-1, -1}, 1, 1);     // -(M_LL + M_SL)^T
-      p.out[3] = outspec(mct + 2 * sb, 4 * st_sl, {0, -1}, 1, 1);      // -M_SL^T
-    } else {
-      p.out[2] = outspec(mct + 1 * sb, 4 * st_sl, {-1, -1}, 1, 1);     // -(M_LS + M_SS)^T
-      p.out[3] = outspec(mct + 3 * sb, 4 * st_sl, {0, -1}, 1, 1);      // -M_SS^T
+  if (variant == 1) {
+    // Control-variate form: chain(R_xi, R_eta) - chain(R^L_xi, R^L_eta) per
+    // pair, chain(a, b) = 2 Tr(T) M - T M with M = a G b and T = M Gbar.
+    // Full vectors R = R^L + R^S next to the large parts.
+    char* xt = CB("c_xt", sb * nvec);
+    launch_vec_sum(xl, xs, xt, nvec * mstride, prec, plane, mstride, st);
+    c.wideg[0] = c.wideg[1] = c.wideg[2] = c.wideg[3] = 0;
+    if (wide_for(ctx, prec, n)) {
+      c.wideg[3] = 1;
+      if (ctx->gemm_wide >= 2) c.wideg[0] = c.wideg[2] = 3;
     }
-    P.push_back(p);
-  }
-  {
-    Prob w = prob0();
-    w.nA = 2;
-    w.a[0] = opref(vl_n, 0, 0, st_sl);
-    w.a[1] = opref(vs_n, 0, 0, st_sl);
-    w.b[0] = gb_op;
-    w.nout = 2;
-    w.out[0] = outspec(wz + 0 * ab, 4 * ac_sl, {1, 0}, 0, 0);
-    w.out[1] = outspec(wz + 1 * ab, 4 * ac_sl, {0, 1}, 0, 0);
-    P.push_back(w);
-    // Z_b = Gbar U_b as its transpose U_b^T Gbar (Gbar symmetric): dual-A
-    Prob z = prob0();
-    z.nA = 2;
-    z.a[0] = opref(ul_t, 0, 0, st_sl);
-    z.a[1] = opref(us_t, 0, 0, st_sl);
-    z.b[0] = gb_op;
-    z.nout = 2;
-    z.out[0] = outspec(wz + 2 * ab, 4 * ac_sl, {1, 0}, 1, 0);
-    z.out[1] = outspec(wz + 3 * ab, 4 * ac_sl, {0, 1}, 1, 0);
-    P.push_back(z);
-  }
-  // S3: T = M Gb for the pairs (M_SS, M_SL) and (M_LS, M_LL), writing the A
-  // factors of the exchange term and the traces Tr(T_x) (the diagonal of the
-  // FP32 products) into mpart[slot][x][tile]
-  for (int h = 0; h < 2; ++h) {
-    Prob p = prob0();
-    p.nA = 2;
-    const int a0 = h == 0 ? 3 : 1, a1 = h == 0 ? 2 : 0;       // (SS, SL) and (LS, LL)
-    p.a[0] = opref(mst + a0 * sb, 0, 0, 4 * st_sl);
-    p.a[1] = opref(mst + a1 * sb, 0, 0, 4 * st_sl);
-    p.b[0] = gb_op;
-    p.nout = 2;
-    p.out[0] = outspec(tq + (2 * h) * sb, 4 * st_sl, {1, 0}, 0, 1);       // T_SS, T_LS
-    p.out[1] = outspec(tq + (2 * h + 1) * sb, 4 * st_sl, {1, 1}, 0, 1);   // T_SL + T_SS, T_LL + T_LS
-    p.nhad = 2;
-    p.had_diag = 1;
-    p.had_coef[0][0] = 0.0f; p.had_coef[0][1] = 1.0f;                     // Tr(T_a1)
-    p.had_coef[1][0] = 1.0f; p.had_coef[1][1] = 0.0f;                     // Tr(T_a0)
-    p.had_part = c.mpart + (int64_t)std::min(a0, a1) * c.mtiles;         // h slots a1, a0 (a1 < a0)
-    p.had_ntiles = c.mtiles;
-    p.had_slot_stride = 4;
-    P.push_back(p);
-  }
-  // S4: exchange + cross terms as one K-concatenated product, the trace of
-  // that product in the epilogue (the direct terms 2 Tr(T) M join in the
-  // accumulation)
-  {
-    Prob p = prob0();
-    p.nseg = 8;
-    for (int x = 0; x < 4; ++x) {
-      p.a[x] = opref(tq + x * sb, 0, 0, 4 * st_sl);
-      p.b[x] = opref(mct + x * sb, 0, 0, 4 * st_sl);
+    Prob dual = prob0();
+    dual.nA = 2;
+    c.mtiles = tiles_of(dual, prec, n, c.wideg[2]);
+    Prob single = prob0();
+    c.ftiles = tiles_of(single, prec, n, c.wideg[3]);
+    c.mpart = (double*)S("c_mpart", 4 * c.mtiles * 8);
+    c.epart = (double*)S("c_epart", c.ftiles * 8);
+    c.coef = (double*)S("c_coef", kCoefStride * 8);
+    c.mst = mst;
+    // s1: U_t = R_xi G, U_L = R^L_xi G (dual-A)
+    {
+      Prob p = prob0();
+      p.nA = 2;
+      p.a[0] = opref(xt, 0, vst);
+      p.a[1] = opref(xl, 0, vst);
+      p.b[0] = g_op;
+      p.nout = 2;
+      p.out[0] = outspec(ul_n, st_sl, {1, 0}, 0, 1);
+      p.out[1] = outspec(us_n, st_sl, {0, 1}, 0, 1);
+      P.push_back(p);
     }
-    p.a[4] = opref(jw_l, 0, 0, st_sl);   p.b[4] = opref(vs_t, 0, 0, st_sl);
-    p.a[5] = opref(jw_s, 0, 0, st_sl);   p.b[5] = opref(vsum_t, 0, 0, st_sl);
-    p.a[6] = opref(ul_n, 0, 0, st_sl);   p.b[6] = opref(jz_st, 0, 0, st_sl);
-    p.a[7] = opref(us_n, 0, 0, st_sl);   p.b[7] = opref(jz_sum_t, 0, 0, st_sl);
-    p.nout = 1;
-    p.out[0] = outspec(sig, ac_sl, {1}, 0, 0);
-    p.nhad = 1;
-    p.had_h = opref(c.gb64, np2);
-    p.had_coef[0][0] = 1.0f;
-    p.had_part = c.epart;
-    p.had_ntiles = c.ftiles;
-    p.had_slot_stride = 1;
-    P.push_back(p);
+    // s2: M_t = U_t R_eta, M_L = U_L R^L_eta, and -M_t^T, +M_L^T for the exchange
+    for (int h = 0; h < 2; ++h) {
+      Prob p = prob0();
+      p.a[0] = opref(h == 0 ? ul_n : us_n, 0, 0, st_sl);
+      p.b[0] = opref((h == 0 ? xt : xl) + sb * ns, 0, 0, 0, vst);
+      p.nout = 2;
+      p.out[0] = outspec(mst + h * sb, 4 * st_sl, {1}, 0, 1);
+      p.out[1] = outspec(mct + h * sb, 4 * st_sl, {h == 0 ? -1.0f : 1.0f}, 1, 1);
+      P.push_back(p);
+    }
+    // s3: T = M Gbar for (M_t, M_L) with their traces into mpart[slot][0..1]
+    {
+      Prob p = prob0();
+      p.nA = 2;
+      p.a[0] = opref(mst + 0 * sb, 0, 0, 4 * st_sl);
+      p.a[1] = opref(mst + 1 * sb, 0, 0, 4 * st_sl);
+      p.b[0] = gb_op;
+      p.nout = 2;
+      p.out[0] = outspec(tq + 0 * sb, 4 * st_sl, {1, 0}, 0, 1);
+      p.out[1] = outspec(tq + 1 * sb, 4 * st_sl, {0, 1}, 0, 1);
+      p.nhad = 2;
+      p.had_diag = 1;
+      p.had_coef[0][0] = 1.0f; p.had_coef[0][1] = 0.0f;
+      p.had_coef[1][0] = 0.0f; p.had_coef[1][1] = 1.0f;
+      p.had_part = c.mpart;
+      p.had_ntiles = c.mtiles;
+      p.had_slot_stride = 4;
+      P.push_back(p);
+    }
+    // s4: -T_t M_t + T_L M_L (the direct terms join in the accumulation)
+    {
+      Prob p = prob0();
+      p.nseg = 2;
+      for (int x = 0; x < 2; ++x) {
+        p.a[x] = opref(tq + x * sb, 0, 0, 4 * st_sl);
+        p.b[x] = opref(mct + x * sb, 0, 0, 4 * st_sl);
+      }
+      p.nout = 1;
+      p.out[0] = outspec(sig, ac_sl, {1}, 0, 0);
+      p.nhad = 1;
+      p.had_h = opref(c.gb64, np2);
+      p.had_coef[0][0] = 1.0f;
+      p.had_part = c.epart;
+      p.had_ntiles = c.ftiles;
+      p.had_slot_stride = 1;
+      P.push_back(p);
+    }
+    c.ngroups = 4;
+    const int go[4] = {0, 1, 3, 4}, gc[4] = {1, 2, 1, 1}, gp[4] = {2, 2, 2, 2};
+    for (int g = 0; g < 4; ++g) { c.goff[g] = go[g]; c.gcnt[g] = gc[g]; c.gprod[g] = gp[g]; }
+  } else {
+    // S1: U = X G (dual A), V = G Y (dual B)
+    {
+      Prob p = prob0();
+      p.nA = 2;
+      p.a[0] = opref(xl, 0, vst);
+      p.a[1] = opref(xs, 0, vst);
+      p.b[0] = g_op;
+      p.nout = 4;
+      p.out[0] = outspec(ul_n, st_sl, {1, 0}, 0, 1);
+      p.out[1] = outspec(ul_t, st_sl, {1, 0}, 1, 1);
+      p.out[2] = outspec(us_n, st_sl, {0, 1}, 0, 1);
+      p.out[3] = outspec(us_t, st_sl, {0, 1}, 1, 1);
+      P.push_back(p);
+      // V_c = G Y_c as its transpose Y_c G (G and Y_c symmetric): a dual-A
+      // product whose tile holds V_L^T and V_S^T at the same positions
+      Prob q = prob0();
+      q.nA = 2;
+      q.a[0] = opref(xl + sb * ns, 0, 0, 0, vst);
+      q.a[1] = opref(xs + sb * ns, 0, 0, 0, vst);
+      q.b[0] = g_op;
+      q.nout = 4;
+      q.out[0] = outspec(vl_n, st_sl, {1, 0}, 1, 1);
+      q.out[1] = outspec(vs_n, st_sl, {0, 1}, 1, 1);
+      q.out[2] = outspec(vs_t, st_sl, {0, 1}, 0, 1);
+      q.out[3] = outspec(vsum_t, st_sl, {1, 1}, 0, 1);
+      P.push_back(q);
+    }
+    if (wide_for(ctx, prec, n)) {
+      // 160-wide tiles where they pad n less: the deep-K stage s4 always, the
+      // dual-A launches (s1, s2, s3) in the default mode 2
+      c.wideg[3] = 1;
+      if (ctx->gemm_wide >= 2) c.wideg[0] = c.wideg[1] = c.wideg[2] = 3;
+    }
+    Prob dual = prob0();
+    dual.nA = 2;
+    c.mtiles = tiles_of(dual, prec, n, c.wideg[2]);
+    Prob single = prob0();
+    c.ftiles = tiles_of(single, prec, n, c.wideg[3]);
+    c.mpart = (double*)S("c_mpart", 4 * c.mtiles * 8);
+    c.epart = (double*)S("c_epart", c.ftiles * 8);
+    c.coef = (double*)S("c_coef", kCoefStride * 8);
+    c.mst = mst;
+    // Matrices of the exchange term, -sum over the nine (T_xy, M_zw) pairs of
+    // S_xi x S_eta, grouped into four products whose factors each come from
+    // one dual-A tile:
+    //   T_SS (M_LL + M_SL) + (T_SL + T_SS)(M_LS + M_SS) + T_LS M_SL + (T_LL + T_LS) M_SS.
+    // mst[x] = M_x (x = LL, LS, SL, SS; row-major, the A operands of s3 and
+    // the direct terms); mct[x] = the x-th B factor above, negated and
+    // transposed; tq[x] = the x-th A factor.
+    // S2: M_xL = U_x Y_L and M_xS = U_x Y_S (dual-A over x), W = V Gb (dual-A),
+    // Z = Gb U as Z^T = U^T Gb (dual-A)
+    for (int y = 0; y < 2; ++y) {
+      Prob p = prob0();
+      p.nA = 2;
+      p.a[0] = opref(ul_n, 0, 0, st_sl);
+      p.a[1] = opref(us_n, 0, 0, st_sl);
+      p.b[0] = opref((y == 0 ? xl : xs) + sb * ns, 0, 0, 0, vst);
+      p.nout = 4;
+      const int lx = y == 0 ? 0 : 1, sx = y == 0 ? 2 : 3;      // M_Ly and M_Sy in mst order
+      p.out[0] = outspec(mst + lx * sb, 4 * st_sl, {1, 0}, 0, 1);
+      p.out[1] = outspec(mst + sx * sb, 4 * st_sl, {0, 1}, 0, 1);
+      if (y == 0) {
+        p.out[2] = outspec(mct + 0 * sb, 4 * st_sl, {-1, -1}, 1, 1);     // -(M_LL + M_SL)^T
+        p.out[3] = outspec(mct + 2 * sb, 4 * st_sl, {0, -1}, 1, 1);      // -M_SL^T
+      } else {
+        p.out[2] = outspec(mct + 1 * sb, 4 * st_sl, {-1, -1}, 1, 1);     // -(M_LS + M_SS)^T
+        p.out[3] = outspec(mct + 3 * sb, 4 * st_sl, {0, -1}, 1, 1);      // -M_SS^T
+      }
+      P.push_back(p);
+    }
+    {
+      Prob w = prob0();
+      w.nA = 2;
+      w.a[0] = opref(vl_n, 0, 0, st_sl);
+      w.a[1] = opref(vs_n, 0, 0, st_sl);
+      w.b[0] = gb_op;
+      w.nout = 2;
+      w.out[0] = outspec(wz + 0 * ab, 4 * ac_sl, {1, 0}, 0, 0);
+      w.out[1] = outspec(wz + 1 * ab, 4 * ac_sl, {0, 1}, 0, 0);
+      P.push_back(w);
+      // Z_b = Gbar U_b as its transpose U_b^T Gbar (Gbar symmetric): dual-A
+      Prob z = prob0();
+      z.nA = 2;
+      z.a[0] = opref(ul_t, 0, 0, st_sl);
+      z.a[1] = opref(us_t, 0, 0, st_sl);
+      z.b[0] = gb_op;
+      z.nout = 2;
+      z.out[0] = outspec(wz + 2 * ab, 4 * ac_sl, {1, 0}, 1, 0);
+      z.out[1] = outspec(wz + 3 * ab, 4 * ac_sl, {0, 1}, 1, 0);
+      P.push_back(z);
+    }
+    // S3: T = M Gb for the pairs (M_SS, M_SL) and (M_LS, M_LL), writing the A
+    // factors of the exchange term and the traces Tr(T_x) (the diagonal of the
+    // FP32 products) into mpart[slot][x][tile]
+    for (int h = 0; h < 2; ++h) {
+      Prob p = prob0();
+      p.nA = 2;
+      const int a0 = h == 0 ? 3 : 1, a1 = h == 0 ? 2 : 0;       // (SS, SL) and (LS, LL)
+      p.a[0] = opref(mst + a0 * sb, 0, 0, 4 * st_sl);
+      p.a[1] = opref(mst + a1 * sb, 0, 0, 4 * st_sl);
+      p.b[0] = gb_op;
+      p.nout = 2;
+      p.out[0] = outspec(tq + (2 * h) * sb, 4 * st_sl, {1, 0}, 0, 1);       // T_SS, T_LS
+      p.out[1] = outspec(tq + (2 * h + 1) * sb, 4 * st_sl, {1, 1}, 0, 1);   // T_SL + T_SS, T_LL + T_LS
+      p.nhad = 2;
+      p.had_diag = 1;
+      p.had_coef[0][0] = 0.0f; p.had_coef[0][1] = 1.0f;                     // Tr(T_a1)
+      p.had_coef[1][0] = 1.0f; p.had_coef[1][1] = 0.0f;                     // Tr(T_a0)
+      p.had_part = c.mpart + (int64_t)std::min(a0, a1) * c.mtiles;         // h slots a1, a0 (a1 < a0)
+      p.had_ntiles = c.mtiles;
+      p.had_slot_stride = 4;
+      P.push_back(p);
+    }
+    // S4: exchange + cross terms as one K-concatenated product, the trace of
+    // that product in the epilogue (the direct terms 2 Tr(T) M join in the
+    // accumulation)
+    {
+      Prob p = prob0();
+      p.nseg = 8;
+      for (int x = 0; x < 4; ++x) {
+        p.a[x] = opref(tq + x * sb, 0, 0, 4 * st_sl);
+        p.b[x] = opref(mct + x * sb, 0, 0, 4 * st_sl);
+      }
+      p.a[4] = opref(jw_l, 0, 0, st_sl);   p.b[4] = opref(vs_t, 0, 0, st_sl);
+      p.a[5] = opref(jw_s, 0, 0, st_sl);   p.b[5] = opref(vsum_t, 0, 0, st_sl);
+      p.a[6] = opref(ul_n, 0, 0, st_sl);   p.b[6] = opref(jz_st, 0, 0, st_sl);
+      p.a[7] = opref(us_n, 0, 0, st_sl);   p.b[7] = opref(jz_sum_t, 0, 0, st_sl);
+      p.nout = 1;
+      p.out[0] = outspec(sig, ac_sl, {1}, 0, 0);
+      p.nhad = 1;
+      p.had_h = opref(c.gb64, np2);
+      p.had_coef[0][0] = 1.0f;
+      p.had_part = c.epart;
+      p.had_ntiles = c.ftiles;
+      p.had_slot_stride = 1;
+      P.push_back(p);
+    }
+    c.ngroups = kGroups;
+    for (int g = 0; g < kGroups; ++g) { c.goff[g] = kStageOff[g]; c.gcnt[g] = kStageCnt[g]; c.gprod[g] = kStageProducts[g]; }
   }
-  for (int g = 0; g < kGroups; ++g)
-    for (int j = 0; j < kStageCnt[g]; ++j)
-      GF2_REQUIRE(gemm_wide_supports(c.wideg[g], P[kStageOff[g] + j]), GF2_E_STATE, "product problem not supported by its tile");
+  for (int g = 0; g < c.ngroups; ++g)
+    for (int j = 0; j < c.gcnt[g]; ++j)
+      GF2_REQUIRE(gemm_wide_supports(c.wideg[g], P[c.goff[g] + j]), GF2_E_STATE, "product problem not supported by its tile");
   c.dprobs = (Prob*)ctx_buf(ctx, pfx + "c_probs", P.size() * sizeof(Prob));
   h2d(ctx, c.dprobs, P.data(), P.size());
 
@@ -938,13 +1037,17 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
   c.uall.clear();
   c.chunks.clear();
   c.trange.clear();
-  for (int64_t sbk = 0; sbk < ns; sbk += c.sc)
+  for (int64_t sbk = 0; sbk < npairs; sbk += c.sc)
     for (int64_t tb = 0; tb < ntau; tb += c.tcnt) {
       const int64_t off0 = (int64_t)c.uall.size();
       int32_t slot = 0;
-      const int64_t t1 = std::min(ntau, tb + c.tcnt), s1 = std::min(ns, sbk + c.sc);
+      const int64_t t1 = std::min(ntau, tb + c.tcnt), s1 = std::min(npairs, sbk + c.sc);
       for (int64_t t = tb; t < t1; ++t)
-        for (int64_t s = sbk; s < s1; ++s) c.uall.push_back(Unit{(int32_t)t, (int32_t)s, slot++, 0});
+        for (int64_t p = sbk; p < s1; ++p) {
+          // pair p: vectors (p, p), or (p / ns, p mod ns) for the double average
+          const int64_t a = variant == 2 ? p / ns : p, b2 = variant == 2 ? p % ns : p;
+          c.uall.push_back(mk_unit(t, a, slot++, b2, p));
+        }
       c.chunks.push_back({off0, (int64_t)c.uall.size() - off0});
       c.trange.push_back({(int32_t)tb, (int32_t)t1});
     }
@@ -953,7 +1056,7 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
 }
 
 void chain_stage(gf2_ctx* ctx, const ChainPlan& c, int stage, int64_t ci) {
-  const int off = kStageOff[stage], cnt = kStageCnt[stage];
+  const int off = c.goff[stage], cnt = c.gcnt[stage];
   const int wide = c.wideg[stage];
   int mt = 0;
   for (int i = 0; i < cnt; ++i) mt = std::max(mt, tiles_of(c.P[off + i], c.prec, c.n, wide));
@@ -961,16 +1064,19 @@ void chain_stage(gf2_ctx* ctx, const ChainPlan& c, int stage, int64_t ci) {
   GemmLaunch L = chain_launch(c.dprobs + off, cnt, c.dunits + c.chunks[ci].first, nu, c.n, c.np, c.plane);
   L.wide = wide;
   const std::string nm = std::string(gemm_name(c.prec)) + kGroupTag[stage] + (wide ? "@160" : "");
-  ProfScope ps(ctx, nm.c_str(), 2.0 * (double)c.n * c.n * c.n * kStageProducts[stage] * nu);
+  ProfScope ps(ctx, nm.c_str(), 2.0 * (double)c.n * c.n * c.n * c.gprod[stage] * nu);
   launch_gemm(c.prec, L, mt, ctx->stream);
 }
 
 void chain_jk(gf2_ctx* ctx, const ChainPlan& c, int64_t ci) {
   const gf2_split_h* sp = c.sp;
   const int nu = (int)c.chunks[ci].second;
-  ProfScope ps(ctx, "jk");
-  launch_jk_blocks(c.accf64, c.wz, 4 * c.ac_sl, c.ac_sl, c.np, c.naux, nu, sp->w, sp->idx,
-                   c.accf64 ? (const void*)sp->blk : (const void*)sp->blk32, c.jblk, ctx->stream);
+  {
+    ProfScope ps(ctx, "jk_blocks");
+    launch_jk_blocks(c.accf64, c.wz, 4 * c.ac_sl, c.ac_sl, c.np, c.naux, nu, sp->wmax, sp->w, sp->idx,
+                     c.accf64 ? (const void*)sp->blk : (const void*)sp->blk32, c.jblk, ctx->stream);
+  }
+  ProfScope ps(ctx, "jk_scatter");
   launch_jk_scatter(c.accf64, c.jblk, c.naux, nu, sp->npat, sp->pat_ij, sp->pat_off, sp->pat_q, c.np, c.prec,
                     c.plane, c.jw_l, c.jw_s, c.jz_st, c.jz_sum_t, c.st_sl, ctx->stream);
 }
@@ -979,7 +1085,7 @@ void chain_acc(gf2_ctx* ctx, const ChainPlan& c, int64_t ci) {
   const Unit* du = c.dunits + c.chunks[ci].first;
   const int nu = (int)c.chunks[ci].second;
   const int64_t n = c.n;
-  launch_trace_coef(c.mpart, c.mtiles, (int32_t)c.slots, c.coef, ctx->stream);
+  launch_trace_coef(c.mpart, c.mtiles, (int32_t)c.slots, c.coef, c.variant == 1 ? 1 : 0, ctx->stream);
   ProfScope ps(ctx, "accumulate", 0.0,
                (double)nu * n * n * (c.accf64 ? 8 : 4) + 2.0 * (c.trange[ci].second - c.trange[ci].first) * n * n * 8);
   launch_accumulate(du, nu, c.sig, c.accf64, c.ac_sl, n, c.np, c.Sigma_sum, c.trange[ci].first,
@@ -988,15 +1094,15 @@ void chain_acc(gf2_ctx* ctx, const ChainPlan& c, int64_t ci) {
 }
 
 void run_stoch(gf2_ctx* ctx, const gf2_split_h* sp, const void* B, const double* G, const double* Gbar,
-               int64_t ntau, const gf2_sampling* smp, Prec prec, double* Sigma_sum, double* e_samples) {
+               int64_t ntau, const gf2_sampling* smp, Prec prec, double* Sigma_sum, double* e_samples,
+               int variant = 0) {
   ChainPlan c;
-  plan_chain(ctx, c, "", sp, B, G, Gbar, ntau, smp, prec, Sigma_sum, e_samples);
+  plan_chain(ctx, c, "", sp, B, G, Gbar, ntau, smp, prec, Sigma_sum, e_samples, 0, 0, variant);
   for (size_t ci = 0; ci < c.chunks.size(); ++ci) {
-    chain_stage(ctx, c, 0, (int64_t)ci);
-    chain_stage(ctx, c, 1, (int64_t)ci);
-    chain_jk(ctx, c, (int64_t)ci);
-    chain_stage(ctx, c, 2, (int64_t)ci);
-    chain_stage(ctx, c, 3, (int64_t)ci);
+    for (int g = 0; g < c.ngroups; ++g) {
+      chain_stage(ctx, c, g, (int64_t)ci);
+      if (g == 1 && c.variant != 1) chain_jk(ctx, c, (int64_t)ci);   // the control-variate form has no J/K
+    }
     chain_acc(ctx, c, (int64_t)ci);
     GF2_HIP(hipGetLastError());
   }
@@ -1064,6 +1170,54 @@ gf2_status gf2_sigma_stoch(gf2_ctx* ctx, const gf2_split_h* split, const void* B
     GF2_REQUIRE(G && Gbar && Sigma_sum && ntau > 0 && ntau <= 4096, GF2_E_ARG, "bad sigma arguments");
     check_sampling(split, sampling);
     run_stoch_prec(ctx, split, B, G, Gbar, ntau, sampling, prec, Sigma_sum, e_samples);
+  });
+}
+
+gf2_status gf2_sigma_stoch_cv(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const double* G,
+                              const double* Gbar, int64_t ntau, const gf2_sampling* sampling, gf2_precision prec,
+                              double* Sigma_sum, double* e_samples) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(split && split->owner == ctx, GF2_E_STATE, "split handle of another context");
+    GF2_REQUIRE(B == split->bsrc, GF2_E_STATE, "split handle belongs to a different B");
+    GF2_REQUIRE(G && Gbar && Sigma_sum && ntau > 0 && ntau <= 4096, GF2_E_ARG, "bad sigma arguments");
+    check_sampling(split, sampling);
+    run_stoch(ctx, split, B, G, Gbar, ntau, sampling, to_prec(prec), Sigma_sum, e_samples, 1);
+  });
+}
+
+gf2_status gf2_sigma_stoch_double(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const double* G,
+                                  const double* Gbar, int64_t ntau, const gf2_sampling* sampling,
+                                  gf2_precision prec, double* Sigma_sum, double* e_samples) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(split && split->owner == ctx, GF2_E_STATE, "split handle of another context");
+    GF2_REQUIRE(B == split->bsrc, GF2_E_STATE, "split handle belongs to a different B");
+    GF2_REQUIRE(G && Gbar && Sigma_sum && ntau > 0 && ntau <= 4096, GF2_E_ARG, "bad sigma arguments");
+    check_sampling(split, sampling);
+    GF2_REQUIRE(sampling->ns <= 256, GF2_E_ARG, "the double average takes at most 256 vectors per set");
+    run_stoch(ctx, split, B, G, Gbar, ntau, sampling, to_prec(prec), Sigma_sum, e_samples, 2);
+  });
+}
+
+gf2_status gf2_energy_double(gf2_ctx* ctx, int64_t n, int64_t ntau, const double* w, const double* Sigma,
+                             const double* Gbar, const double* e_samples, int64_t ns, double n_elec, double* E_tot,
+                             double* E_per_e, double* stderr_tot) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(n > 0 && ntau > 0 && ntau <= 512 && w && Sigma && Gbar && e_samples, GF2_E_ARG,
+                "bad energy arguments");
+    GF2_REQUIRE(n_elec > 0 && ns >= 2 && ns <= 256, GF2_E_ARG, "n_elec > 0 and 2 <= ns <= 256");
+    auto* tr = (double*)ctx_buf(ctx, "e_tr", (size_t)ntau * 8);
+    auto* dw = (double*)ctx_buf(ctx, "e_w", (size_t)ntau * 8);
+    auto* res = (double*)ctx_buf(ctx, "e_res", 4 * 8);
+    h2d(ctx, dw, w, (size_t)ntau);
+    launch_trace_prod(Sigma, Gbar, n, ntau, tr, ctx->stream);
+    launch_double_stats(tr, dw, ntau, e_samples, ns, kGM, res, ctx->stream);
+    GF2_HIP(hipGetLastError());
+    double h[4];
+    d2h(ctx, h, res, 3);
+    GF2_REQUIRE(std::isfinite(h[0]) && std::isfinite(h[2]), GF2_E_NUMERIC, "non-finite energy");
+    if (E_tot) *E_tot = h[0];
+    if (E_per_e) *E_per_e = h[0] / n_elec;
+    if (stderr_tot) *stderr_tot = h[2];
   });
 }
 
@@ -1637,7 +1791,7 @@ gf2_status gf2_debug_gemm(gf2_ctx* ctx, gf2_precision prec, int64_t n, int64_t b
     auto* probs = (Prob*)ctx_buf(ctx, "dbg_prob", sizeof(Prob));
     h2d(ctx, probs, &pb, 1);
     std::vector<Unit> uh(batch);
-    for (int64_t b = 0; b < batch; ++b) uh[b] = Unit{0, (int32_t)b, 0, 0};
+    for (int64_t b = 0; b < batch; ++b) uh[b] = mk_unit(0, b, 0, b, b);
     auto* units = (Unit*)ctx_buf(ctx, "dbg_units", uh.size() * sizeof(Unit));
     h2d(ctx, units, uh.data(), uh.size());
     GemmLaunch L = chain_launch(probs, 1, units, (int32_t)batch, n, ld, ld2);

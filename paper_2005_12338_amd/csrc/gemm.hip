@@ -101,7 +101,7 @@ __device__ __forceinline__ bf16_t f2bf(float f) {
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
 __device__ __forceinline__ int64_t off(const OpRef& r, const Unit& u) {
-  return (int64_t)u.tau * r.st_tau + (int64_t)u.s * r.st_s + (int64_t)u.slot * r.st_slot;
+  return (int64_t)u.tau * r.st_tau + (int64_t)u.s * r.st_s + (int64_t)u.s2 * r.st_s2 + (int64_t)u.slot * r.st_slot;
 }
 __device__ __forceinline__ int64_t off(const OutSpec& r, const Unit& u) {
   return (int64_t)u.tau * r.st_tau + (int64_t)u.s * r.st_s + (int64_t)u.slot * r.st_slot;

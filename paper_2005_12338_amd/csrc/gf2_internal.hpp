@@ -39,10 +39,12 @@ enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2, BF16X3 = 3 };
 // np x np with np = pad_dim(n), zero outside [0,n) x [0,n).
 inline int64_t pad_dim(int64_t n) { return (n + 31) / 32 * 32; }
 
-// Address of an operand for one (tau, sample, slot) unit, in elements.
+// Address of an operand for one (tau, sample, slot) unit, in elements:
+// base + tau st_tau + s st_s + s2 st_s2 + slot st_slot (s indexes the
+// first set of stochastic vectors, s2 the second).
 struct OpRef {
   const void* base;
-  int64_t st_tau, st_s, st_slot;
+  int64_t st_tau, st_s, st_slot, st_s2;
 };
 
 // One output of a GEMM tile: a combination of the nA x nB products written
@@ -86,8 +88,11 @@ struct Prob {
   const double* add_coef;   // [slot][kMaxAdd]
 };
 
+// One (tau, pair) unit: s and s2 index the first- and second-set vectors
+// of the pair (equal for the paired estimator), row its per-pair sample row.
 struct Unit {
   int32_t tau, s, slot, inst;   // inst: instance of a multi-instance launch (0 otherwise)
+  int32_t s2, row;
 };
 
 // Geometry of one instance of a launch.

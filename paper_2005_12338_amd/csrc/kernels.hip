@@ -389,7 +389,7 @@ __device__ __forceinline__ double wave_sum_fixed(const double* p, int64_t cnt) {
 // Direct-term coefficients of a slot from its Hadamard-trace partials: one
 // workgroup per slot, one wave per trace.
 __global__ __launch_bounds__(256) void k_trace_coef(const double* part, int64_t ntiles, int32_t nslot,
-                                                    double* coef) {
+                                                    double* coef, int mode) {
   __shared__ double c[4];
   const int slot = blockIdx.x, h = threadIdx.x >> 6;
   const double s = wave_sum_fixed(part + ((int64_t)slot * 4 + h) * ntiles, ntiles);
@@ -397,11 +397,21 @@ __global__ __launch_bounds__(256) void k_trace_coef(const double* part, int64_t 
   __syncthreads();
   if (threadIdx.x == 0) {
     double* o = coef + (int64_t)slot * kCoefStride;
-    o[0] = 2.0 * c[3];
-    o[1] = 2.0 * (c[2] + c[3]);
-    o[2] = 2.0 * (c[1] + c[3]);
-    o[3] = 2.0 * (c[0] + c[1] + c[2] + c[3]);
-    for (int h = 0; h < 4; ++h) o[4 + h] = c[h];       // Tr(T_h) = Tr(M_h Gbar)
+    if (mode == 0) {
+      o[0] = 2.0 * c[3];
+      o[1] = 2.0 * (c[2] + c[3]);
+      o[2] = 2.0 * (c[1] + c[3]);
+      o[3] = 2.0 * (c[0] + c[1] + c[2] + c[3]);
+      for (int h = 0; h < 4; ++h) o[4 + h] = c[h];       // Tr(T_h) = Tr(M_h Gbar)
+    } else {
+      // control-variate form: direct terms 2 Tr(T_t) M_t - 2 Tr(T_L) M_L
+      o[0] = 2.0 * c[0];
+      o[1] = -2.0 * c[1];
+      o[2] = o[3] = 0.0;
+      o[4] = c[0];
+      o[5] = c[1];
+      o[6] = o[7] = 0.0;
+    }
   }
 }
 
@@ -439,6 +449,7 @@ __global__ void k_accumulate(const Unit* units, int32_t nunit, const void* sig, 
     }
     const double* cf = coef + slot * kCoefStride;
     for (int x = 0; x < 4; ++x) {
+      if (cf[x] == 0.0) continue;                     // matrices a form does not use are never read
       const int64_t mo = slot * m_st_slot + x * m_st_m + o;
       if (prec == Prec::BF16) {
         const uint2 h = *(const uint2*)((const bf16_t*)mst + mo);
@@ -467,7 +478,7 @@ __global__ __launch_bounds__(256) void k_esamples(const Unit* units, int32_t nun
     const double* cf = coef + (int64_t)units[u].slot * kCoefStride;
     double d = 0.0;
     for (int x = 0; x < 4; ++x) d += cf[x] * cf[4 + x];
-    es[((int64_t)units[u].s - s0) * ntau + units[u].tau] = s + d;
+    es[((int64_t)units[u].row - s0) * ntau + units[u].tau] = s + d;
   }
 }
 
@@ -500,6 +511,54 @@ __global__ void k_level_shift(double* es, const double* hi, int64_t k, int64_t n
   }
   __syncthreads();
   for (int64_t e = threadIdx.x; e < ns * ntau; e += blockDim.x) es[e] += shift[e % ntau];
+}
+
+// Energy of the double average: out[0] = -gm sum_t w_t tr[t] (tr from the
+// final Sigma), out[2] = its first-order U-statistic standard error
+// sqrt(Var_i(r_i)/ns + Var_j(c_j)/ns) with r_i, c_j the row and column means
+// of the per-combination energies E_ij = -gm sum_t w_t es[i ns + j][t].
+// One block; ns <= 256; fixed summation orders.
+__global__ void k_double_stats(const double* tr, const double* w, int64_t ntau, const double* es, int64_t ns,
+                               double gm, double* out) {
+  __shared__ double rm[256], cm[256];
+  for (int64_t k = threadIdx.x; k < 2 * ns; k += blockDim.x) {
+    const int64_t a = k % ns;
+    const bool row = k < ns;
+    double acc = 0.0;
+    for (int64_t b = 0; b < ns; ++b) {
+      const double* e = es + (row ? a * ns + b : b * ns + a) * ntau;
+      double v = 0.0;
+      for (int64_t t = 0; t < ntau; ++t) v += w[t] * e[t];
+      acc += -gm * v;
+    }
+    (row ? rm : cm)[a] = acc / (double)ns;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double e = 0.0;
+    for (int64_t t = 0; t < ntau; ++t) e += w[t] * tr[t];
+    double mr = 0.0, mc = 0.0;
+    for (int64_t a = 0; a < ns; ++a) { mr += rm[a]; mc += cm[a]; }
+    mr /= (double)ns;
+    mc /= (double)ns;
+    double vr = 0.0, vc = 0.0;
+    for (int64_t a = 0; a < ns; ++a) { vr += (rm[a] - mr) * (rm[a] - mr); vc += (cm[a] - mc) * (cm[a] - mc); }
+    vr /= (double)(ns - 1);
+    vc /= (double)(ns - 1);
+    out[0] = -gm * e;
+    out[1] = 0.0;
+    out[2] = sqrt(vr / (double)ns + vc / (double)ns);
+  }
+}
+
+// xt = xl + xs element by element (storage format; count elements of the
+// hi plane, each matrix of mstride elements also carrying its lo plane).
+__global__ void k_vec_sum(const void* xl, const void* xs, void* xt, int64_t count, Prec prec, int64_t plane,
+                          int64_t mstride) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  if (prec == Prec::BF16X3 && (e % mstride) >= plane) return;   // lo planes: written with their hi element
+  put_st(xt, e, plane, prec, get_st(xl, e, plane, prec) + get_st(xs, e, plane, prec));
 }
 
 // ------------------------------------------------------------- energy -----
@@ -711,8 +770,17 @@ void launch_jk_scatter(bool f64, const void* jblk, int64_t naux, int32_t nslot, 
                        npat, pat_ij, pat_off, pat_q, np, prec, plane, jw_l, jw_s, jz_st, jz_sum_t,
                        out_st_slot);
 }
-void launch_trace_coef(const double* part, int64_t ntiles, int32_t nslot, double* coef, hipStream_t st) {
-  hipLaunchKernelGGL(k_trace_coef, dim3((unsigned)nslot), dim3(256), 0, st, part, ntiles, nslot, coef);
+void launch_trace_coef(const double* part, int64_t ntiles, int32_t nslot, double* coef, int mode,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_trace_coef, dim3((unsigned)nslot), dim3(256), 0, st, part, ntiles, nslot, coef, mode);
+}
+void launch_double_stats(const double* tr, const double* w, int64_t ntau, const double* es, int64_t ns, double gm,
+                         double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_double_stats, dim3(1), dim3(256), 0, st, tr, w, ntau, es, ns, gm, out);
+}
+void launch_vec_sum(const void* xl, const void* xs, void* xt, int64_t count, Prec prec, int64_t plane,
+                    int64_t mstride, hipStream_t st) {
+  hipLaunchKernelGGL(k_vec_sum, dim3(blocks(count)), dim3(256), 0, st, xl, xs, xt, count, prec, plane, mstride);
 }
 void launch_accumulate(const Unit* units, int32_t nunit, const void* sig, bool f64, int64_t sig_st_slot,
                        int64_t n, int64_t np, double* sum, int32_t tau_lo, int32_t tau_hi, const void* mst,

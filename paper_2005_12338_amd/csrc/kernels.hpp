@@ -33,13 +33,21 @@ void launch_unpad_sym(const double* p, int64_t n, int64_t np, int64_t ntau, doub
 void launch_pad_convert(const double* g, int64_t n, int64_t np, int64_t ntau, Prec prec, void* stbuf,
                         int64_t plane, int64_t mstride, double* f64pad, hipStream_t st);
 void launch_jk_blocks(bool f64, const void* wbase, int64_t w_st_slot, int64_t w_st_m, int64_t np,
-                      int64_t naux, int32_t nslot, const int32_t* wq, const int32_t* idx,
+                      int64_t naux, int32_t nslot, int32_t wmax, const int32_t* wq, const int32_t* idx,
                       const void* blk, void* jout, hipStream_t st);
 void launch_jk_scatter(bool f64, const void* jblk, int64_t naux, int32_t nslot, int64_t npat,
                        const int32_t* pat_ij, const int32_t* pat_off, const int32_t* pat_q, int64_t np,
                        Prec prec, int64_t plane, void* jw_l, void* jw_s, void* jz_st, void* jz_sum_t,
                        int64_t out_st_slot, hipStream_t st);
-void launch_trace_coef(const double* part, int64_t ntiles, int32_t nslot, double* coef, hipStream_t st);
+// mode 0: the L/S-resolved direct-term coefficients; 1: the control-variate form's.
+void launch_trace_coef(const double* part, int64_t ntiles, int32_t nslot, double* coef, int mode,
+                       hipStream_t st);
+// E and the U-statistic standard error of the double average (ns <= 256).
+void launch_double_stats(const double* tr, const double* w, int64_t ntau, const double* es, int64_t ns, double gm,
+                         double* out, hipStream_t st);
+// xt = xl + xs for count storage elements (matrices of mstride elements).
+void launch_vec_sum(const void* xl, const void* xs, void* xt, int64_t count, Prec prec, int64_t plane,
+                    int64_t mstride, hipStream_t st);
 // Per-slot direct-term record written by launch_trace_coef: coef[0..3] for
 // M_LL, M_LS, M_SL, M_SS, then Tr(T_h) for h = 0..3.
 constexpr int kCoefStride = 8;

@@ -90,6 +90,13 @@ _SIGS = {
     "gf2_sigma_det": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "gf2_sigma_stoch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                   C.POINTER(Sampling), C.c_int, C.c_void_p, C.c_void_p]),
+    "gf2_sigma_stoch_cv": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                     C.POINTER(Sampling), C.c_int, C.c_void_p, C.c_void_p]),
+    "gf2_sigma_stoch_double": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                         C.POINTER(Sampling), C.c_int, C.c_void_p, C.c_void_p]),
+    "gf2_energy_double": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_double), C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "gf2_sigma_finalize": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
                                      C.c_void_p]),
     "gf2_energy": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_double), C.c_void_p,
@@ -339,6 +346,34 @@ class Context:
         self._check(self.lib.gf2_sigma_stoch(self.h, split.handle, B.data_ptr(), G.data_ptr(),
                                              Gb.data_ptr(), ntau, C.byref(smp), PREC[prec],
                                              Sigma_sum.data_ptr(), _ptr(e_samples)))
+
+    def sigma_stoch_cv(self, split: Split, B, G, Gb, Sigma_sum, ns: int, seed: int = 0, prec: str = "fp32",
+                       s0: int = 0, e_samples=None):
+        """Control-variate form: adds sum_s [chain(R, R') - chain(R^L, R'^L)]."""
+        ntau = G.shape[0]
+        smp, keep = self._sampling(ns, seed, s0)
+        self._check(self.lib.gf2_sigma_stoch_cv(self.h, split.handle, B.data_ptr(), G.data_ptr(), Gb.data_ptr(),
+                                                ntau, C.byref(smp), PREC[prec], Sigma_sum.data_ptr(),
+                                                _ptr(e_samples)))
+
+    def sigma_stoch_double(self, split: Split, B, G, Gb, Sigma_sum, ns: int, seed: int = 0, prec: str = "fp32",
+                           s0: int = 0, e_samples=None):
+        """Double average: adds the pair estimate of every (i, j) < ns combination;
+        e_samples [ns*ns][ntau], row i*ns + j."""
+        ntau = G.shape[0]
+        smp, keep = self._sampling(ns, seed, s0)
+        self._check(self.lib.gf2_sigma_stoch_double(self.h, split.handle, B.data_ptr(), G.data_ptr(),
+                                                    Gb.data_ptr(), ntau, C.byref(smp), PREC[prec],
+                                                    Sigma_sum.data_ptr(), _ptr(e_samples)))
+
+    def energy_double(self, Sigma, Gb, w: np.ndarray, n_elec: float, e_samples, ns: int):
+        ntau, n, _ = Sigma.shape
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        e, epe, se = C.c_double(), C.c_double(), C.c_double()
+        self._check(self.lib.gf2_energy_double(self.h, n, ntau, _dp(w), Sigma.data_ptr(), Gb.data_ptr(),
+                                               e_samples.data_ptr(), int(ns), float(n_elec), C.byref(e),
+                                               C.byref(epe), C.byref(se)))
+        return e.value, epe.value, se.value
 
     def sigma_finalize(self, Sigma_det, Sigma_sum, ns_total: int):
         out = self.torch.empty_like(Sigma_det)
