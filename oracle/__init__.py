@@ -20,4 +20,5 @@ Modules
   energy      Galitskii-Migdal energy (eq:corr) and statistics
   proposal    importance proposal over the auxiliary index (project form)
   variants    control-variate and double-sum forms of the eq:sigma_2 average
+  scf         Matsubara transforms, Dyson, mu tuning, RI Fock build (Section III)
 """
