@@ -40,13 +40,14 @@ MFMA_PEAK = {"bf16": 2.5e15, "bf16c": 2.5e15, "bf16x3": 2.5e15, "fp32": 157.3e12
 # they were taken on: reported only while that source is unchanged.
 GEMM_TRAFFIC = {
     # launch-weighted mean of the two BF16 chain GEMM kernels at N=800
-    # (128-wide tile: 8448 launches of stages s1-s3, FETCH 393739.4 / WRITE
-    # 754652.7 KiB; 160-wide tile: 2816 launches of stage s4, FETCH 944954.3 /
-    # WRITE 143389.2 KiB), FETCH scaled by 1.9997 from a plain copy
-    ("bf16", "n800"): {"bytes_per_launch": ((393739.4 * 1.9997 + 754652.7) * 8448 + (944954.3 * 1.9997 + 143389.2) * 2816)
-                                         / 11264 * 1024.0,
-                       "gemm_src_sha256_16": "d0658038cad4d977",
-                       "profile": "profiles/chain_n800_bf16.md"},
+    # (dual-A 320x160 tile: 132 launches of stages s1-s3, FETCH 270502.2 /
+    # WRITE 544790.3 KiB; 160x160 tile: 44 launches of stage s4, FETCH
+    # 737054.7 / WRITE 116377.9 KiB), FETCH scaled by 1.9987 and WRITE by
+    # 0.9997 from a plain copy
+    ("bf16c", "n800"): {"bytes_per_launch": ((270502.2 * 1.9987 + 544790.3 * 0.9997) * 132
+                                          + (737054.7 * 1.9987 + 116377.9 * 0.9997) * 44) / 176 * 1024.0,
+                        "gemm_src_sha256_16": "3673d727129be642",
+                        "profile": "profiles/chain_n800_bf16.md"},
 }
 
 
@@ -336,6 +337,64 @@ def batch_bench(args):
     ctx.close()
 
 
+def variants_bench(args):
+    """Variance x cost of the estimator forms on one workload: the paired
+    L/S-resolved form (24 products per pair), the control-variate form (8),
+    and the double average over every combination of two vector sets.  For
+    each: seconds for the pairs, standard error reached, and the cost of one
+    standard error of `target`: t * (se / target)^2 (the error falls as
+    1/sqrt(cost) for each form)."""
+    import torch
+    from paper_2005_12338_amd import gf2
+    wl = workload(args.workload)
+    ctx = gf2.Context(0)
+    pb = Problem(ctx, wl)
+    B, spl, G, Gb, det = pb.setup()
+    w = pb.w
+    rows = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    ns = args.ns or 64
+    target = 1e-7
+
+    def paired(prec, cv=False):
+        acc = torch.zeros_like(det)
+        es = torch.empty((ns, wl.ntau), dtype=torch.float64, device="cuda")
+        (ctx.sigma_stoch_cv if cv else ctx.sigma_stoch)(spl, B, G, Gb, acc, ns=ns, seed=wl.seed, prec=prec,
+                                                         e_samples=es)
+        sig = ctx.sigma_finalize(det, acc, ns)
+        return ctx.energy(sig, Gb, w, wl.n_elec, es)
+
+    nd = max(2, int(round(math.sqrt(ns))))
+
+    def double(prec):
+        acc = torch.zeros_like(det)
+        es = torch.empty((nd * nd, wl.ntau), dtype=torch.float64, device="cuda")
+        ctx.sigma_stoch_double(spl, B, G, Gb, acc, ns=nd, seed=wl.seed, prec=prec, e_samples=es)
+        sig = ctx.sigma_finalize(det, acc, nd * nd)
+        return ctx.energy_double(sig, Gb, w, wl.n_elec, es, nd)
+
+    for name, fn, units in (("paired_fp32", lambda: paired("fp32"), ns),
+                            ("paired_bf16c", lambda: paired("bf16c"), ns),
+                            ("control_variate_fp32", lambda: paired("fp32", cv=True), ns),
+                            ("double_fp32", lambda: double("fp32"), nd * nd)):
+        t, (e, epe, se_) = timed(fn)
+        rows[name] = {"s": t, "pairs": units, "E": e, "stderr": se_,
+                      "s_for_stderr_1e-7": t * (se_ / target) ** 2}
+        log(f"[bench] {name:22s} {units:5d} pairs {t:8.3f} s  E={e:.9f} stderr={se_:.3e}  "
+            f"cost of stderr 1e-7: {t * (se_ / target) ** 2:9.2f} s")
+    print(json.dumps({"metric": "estimator forms: variance x cost", "workload": wl.name, "rows": rows}), flush=True)
+    spl.free()
+    ctx.close()
+
+
 def cpu_baseline(wl, pairs):
     """The oracle (FP64 NumPy, as it stands) timed on a bounded sample of the
     same workload and extrapolated to a time-to-target estimate (s)."""
@@ -407,6 +466,8 @@ def main():
     ap.add_argument("--batch-prec-bf16", action="store_true", help="run the batch in BF16 (default FP32)")
     ap.add_argument("--prec", default="bf16c", choices=["bf16c", "bf16", "bf16x3", "fp32", "fp64"])
     ap.add_argument("--ns", type=int, default=0, help="pairs per step (default: the workload's)")
+    ap.add_argument("--variants", action="store_true",
+                    help="only compare the estimator forms (paired, control-variate, double average)")
     ap.add_argument("--gemm-reference", action="store_true",
                     help="only compare the chain GEMM kernel with torch.bmm on the same shapes")
     ap.add_argument("--target-meh", type=float, default=1.0)
@@ -424,6 +485,9 @@ def main():
 
     if args.gemm_reference:
         gemm_reference(args)
+        return
+    if args.variants:
+        variants_bench(args)
         return
     if args.workload == "batch":
         batch_bench(args)
