@@ -294,6 +294,64 @@ gf2_status gf2_energy_noalloc(gf2_ctx* ctx, int64_t n, int64_t ntau, const doubl
                               const double* e_samples, int64_t ns, double n_elec,
                               double* out);
 
+/* ------------------------------------------------------------ SCF (f1)
+ * The steps on either side of the self-energy that make GF2 self-consistent
+ * (Section III).  Common arguments: F and S host [n][n] (S NULL = the
+ * identity; S must be positive definite), beta > 0, tau and w host [ntau]
+ * (the quadrature of the self-energy's tau grid, tau in [0, beta]), Sigma
+ * device [ntau][n][n] FP64 (e.g. from gf2_sigma_finalize), nw >= 1 odd
+ * Matsubara frequencies w_k = (2k + 1) pi / beta, k < nw.
+ *
+ * Numerics (the paper leaves them open; these are the readings):
+ *   Sigma(i w_k) = sum_t w_t e^{i w_k tau_t} Sigma(tau_t)      (eq:GFT)
+ *   G(i w_k) = [(mu + i w_k) S - F - Sigma(i w_k)]^{-1}       (eq:dyson, eq:G0)
+ *   G(tau) = G0(tau) + (2/beta) sum_{k<nw} Re[e^{-i w_k tau} (G - G0)(i w_k)]
+ *                                                             (eq:Ginverse)
+ * with G0 the non-interacting function of the same (F, S, mu), whose tau
+ * form is closed.  The work runs in the orthonormal eigenbasis of (F, S)
+ * (there G0(i w) is diagonal), frequency chunk by chunk: the quadrature and
+ * the back-transform as FP64 kernels, the per-frequency inversion as
+ * blocked complex Gauss-Jordan on FP64 MFMAs without pivoting (the Dyson
+ * matrix is complex symmetric with a positive definite imaginary part for a
+ * causal self-energy).  A vanishing or non-finite pivot: GF2_E_NUMERIC.
+ *
+ * gf2_dyson: G(tau_t), Gbar = G(beta - tau_t) (device [ntau][n][n]) and
+ *   G(beta-) (device [n][n]) at the given mu; any output may be NULL (not
+ *   all).  Symmetrised ((X + X^T) / 2) like gf2_green_tau.  Synchronous.
+ * gf2_electron_count: *n_e = N_e(mu) = -2 sum_ij G_ij(beta-) S_ij (host).
+ * gf2_tune_mu: the mu in [mu_lo, mu_hi] with N_e(mu) = n_elec at fixed
+ *   Sigma (N_e grows with mu): regula falsi (Illinois) to |N_e - n_elec| <=
+ *   1e-11 max(1, n_elec) or a bracket of 1e-15 relative.  *mu_out, and
+ *   *n_e (may be NULL) the count reached.  GF2_E_ARG if the bracket does not
+ *   contain the root.
+ * gf2_fock: eq:F with the RI factors of eq:vKQKQ, F = h + J[P] - K[P]/2,
+ *   J_ij = sum_Q B^Q_ij Tr(B^Q P), K = sum_Q B^Q P B^Q, P = -2 G(beta-).
+ *   B device [naux][n][n] (dtype), h host [n][n], Gbeta device [n][n];
+ *   F_out host [n][n].  FP64 throughout.
+ * gf2_scf_step: one update of the loop around the self-energy: mu tuned
+ *   to n_elec (gf2_tune_mu), G, Gbar, G(beta-) at that mu (gf2_dyson), and
+ *   the new Fock matrix (gf2_fock).  Outputs as above; *mu_out host. */
+gf2_status gf2_dyson(gf2_ctx* ctx, int64_t n, const double* F, const double* S, double mu,
+                     double beta, int64_t ntau, const double* tau, const double* w,
+                     const double* Sigma, int64_t nw, double* G, double* Gbar,
+                     double* Gbeta);
+gf2_status gf2_electron_count(gf2_ctx* ctx, int64_t n, const double* F, const double* S,
+                              double mu, double beta, int64_t ntau, const double* tau,
+                              const double* w, const double* Sigma, int64_t nw,
+                              double* n_e);
+gf2_status gf2_tune_mu(gf2_ctx* ctx, int64_t n, const double* F, const double* S,
+                       double beta, int64_t ntau, const double* tau, const double* w,
+                       const double* Sigma, int64_t nw, double n_elec, double mu_lo,
+                       double mu_hi, double* mu_out, double* n_e);
+gf2_status gf2_fock(gf2_ctx* ctx, int64_t n, int64_t naux, const void* B, gf2_dtype dtype,
+                    const double* h, const double* Gbeta, double* F_out);
+gf2_status gf2_scf_step(gf2_ctx* ctx, int64_t n, int64_t naux, const void* B,
+                        gf2_dtype dtype, const double* h, const double* F, const double* S,
+                        double beta, int64_t ntau, const double* tau, const double* w,
+                        const double* Sigma, int64_t nw, double n_elec, double mu_lo,
+                        double mu_hi, double* mu_out, double* G, double* Gbar,
+                        double* Gbeta, double* F_out);
+
 /* ------------------------------------------------------------ RNG ---------
  * word(seed, stream, s, q) = mix(seed * 0x9E3779B97F4A7C15
  *                                + ((stream << 62) | (s << 32) | q) + 1),

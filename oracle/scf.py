@@ -46,24 +46,33 @@ def matsubara(beta: float, nw: int) -> np.ndarray:
 def tau_to_iw(x_tau: np.ndarray, tau: np.ndarray, w: np.ndarray, omegas: np.ndarray) -> np.ndarray:
     """eq:GFT by the tau quadrature: X(i w_n) = sum_t w_t e^{i w_n tau_t} X(tau_t)."""
     ph = np.exp(1j * omegas[:, None] * tau[None, :]) * w[None, :]          # [nw][ntau]
-    return np.einsum("nt,tij->nij", ph, x_tau)
+    nt, n, m = x_tau.shape
+    x = x_tau.reshape(nt, n * m)
+    return (ph.real @ x + 1j * (ph.imag @ x)).reshape(-1, n, m)
 
 
 def g0_iw(f: np.ndarray, s: np.ndarray, mu: float, omegas: np.ndarray) -> np.ndarray:
     """eq:G0: [(mu + i w) S - F]^{-1} per frequency."""
-    return np.array([np.linalg.inv((mu + 1j * wn) * s - f) for wn in omegas])
+    out = np.empty((len(omegas),) + f.shape, dtype=np.complex128)
+    for k, wn in enumerate(omegas):
+        out[k] = np.linalg.inv((mu + 1j * wn) * s - f)
+    return out
 
 
 def dyson(f: np.ndarray, s: np.ndarray, mu: float, sigma_iw: np.ndarray, omegas: np.ndarray) -> np.ndarray:
     """eq:dyson: G(i w) = [G0(i w)^{-1} - Sigma(i w)]^{-1}."""
-    return np.array([np.linalg.inv((mu + 1j * wn) * s - f - sg) for wn, sg in zip(omegas, sigma_iw)])
+    out = np.empty((len(omegas),) + f.shape, dtype=np.complex128)
+    for k, (wn, sg) in enumerate(zip(omegas, sigma_iw)):
+        out[k] = np.linalg.inv((mu + 1j * wn) * s - f - sg)
+    return out
 
 
 def iw_to_tau(diff_iw: np.ndarray, omegas: np.ndarray, beta: float, tau: np.ndarray) -> np.ndarray:
     """eq:Ginverse for a difference that decays at high frequency:
     (2/beta) sum_n Re[e^{-i w_n tau} X(i w_n)] for each tau (tau in [0, beta])."""
     ph = np.exp(-1j * np.outer(np.atleast_1d(tau), omegas))                 # [ntau][nw]
-    return (2.0 / beta) * np.real(np.einsum("tn,nij->tij", ph, diff_iw))
+    nw, n, m = diff_iw.shape
+    return (2.0 / beta) * np.real(ph @ diff_iw.reshape(nw, n * m)).reshape(-1, n, m)
 
 
 def green_tau_dyson(f, s, mu, beta, sigma_iw, omegas, tau):

@@ -153,6 +153,48 @@ int wide_for(const gf2_ctx* ctx, Prec prec, int64_t n) {
   return ((n + w - 1) / w) * w < ((n + s - 1) / s) * s ? 1 : 0;
 }
 
+// Orthonormal eigenbasis of (F, S) on the host in FP64: F C = S C diag(eps)
+// with C^T S C = I (S = null: the identity), eps ascending; c[i * n + k] is
+// the i-th component of orbital k.  Through S^{-1/2} from S's eigenvectors.
+void orbitals_fs(int64_t n, const double* F, const double* S, std::vector<double>& eps, std::vector<double>& c) {
+  eps.assign((size_t)n, 0.0);
+  c.assign((size_t)(n * n), 0.0);
+  if (!S) {
+    std::vector<double> a(F, F + n * n);
+    sym_eigen(n, a.data(), eps.data(), c.data());
+    return;
+  }
+  std::vector<double> a(S, S + n * n), se(n), su((size_t)(n * n));
+  sym_eigen(n, a.data(), se.data(), su.data());
+  GF2_REQUIRE(se[0] > 0, GF2_E_ARG, "S is not positive definite");
+  std::vector<double> x((size_t)(n * n)), fx((size_t)(n * n)), xfx((size_t)(n * n)), y((size_t)(n * n));
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int64_t k = 0; k < n; ++k) s += su[i * n + k] * su[j * n + k] / std::sqrt(se[k]);
+      x[i * n + j] = s;
+    }
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int64_t k = 0; k < n; ++k) s += F[i * n + k] * x[k * n + j];
+      fx[i * n + j] = s;
+    }
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int64_t k = 0; k < n; ++k) s += x[i * n + k] * fx[k * n + j];
+      xfx[i * n + j] = s;
+    }
+  sym_eigen(n, xfx.data(), eps.data(), y.data());
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int64_t k = 0; k < n; ++k) s += x[i * n + k] * y[k * n + j];
+      c[i * n + j] = s;
+    }
+}
+
 void run_dd(gf2_ctx* ctx, const gf2_split_h* sp, const double* G, const double* Gb, int64_t ntau,
             double* out);
 
@@ -492,41 +534,8 @@ gf2_status gf2_green_tau(gf2_ctx* ctx, int64_t n, const double* F, const double*
     GF2_REQUIRE(n_occ < n, GF2_E_ARG, "n_occ must be < n");
     for (int64_t t = 0; t < ntau; ++t)
       GF2_REQUIRE(tau[t] >= 0 && tau[t] <= beta, GF2_E_ARG, "tau outside [0, beta]");
-    std::vector<double> eps(n), c((size_t)(n * n));
-    if (!S) {
-      std::vector<double> a(F, F + n * n);
-      sym_eigen(n, a.data(), eps.data(), c.data());
-    } else {
-      std::vector<double> a(S, S + n * n), se(n), su((size_t)(n * n));
-      sym_eigen(n, a.data(), se.data(), su.data());
-      GF2_REQUIRE(se[0] > 0, GF2_E_ARG, "S is not positive definite");
-      std::vector<double> x((size_t)(n * n)), fx((size_t)(n * n)), xfx((size_t)(n * n)), y((size_t)(n * n));
-      for (int64_t i = 0; i < n; ++i)
-        for (int64_t j = 0; j < n; ++j) {
-          double s = 0.0;
-          for (int64_t k = 0; k < n; ++k) s += su[i * n + k] * su[j * n + k] / std::sqrt(se[k]);
-          x[i * n + j] = s;
-        }
-      for (int64_t i = 0; i < n; ++i)
-        for (int64_t j = 0; j < n; ++j) {
-          double s = 0.0;
-          for (int64_t k = 0; k < n; ++k) s += F[i * n + k] * x[k * n + j];
-          fx[i * n + j] = s;
-        }
-      for (int64_t i = 0; i < n; ++i)
-        for (int64_t j = 0; j < n; ++j) {
-          double s = 0.0;
-          for (int64_t k = 0; k < n; ++k) s += x[i * n + k] * fx[k * n + j];
-          xfx[i * n + j] = s;
-        }
-      sym_eigen(n, xfx.data(), eps.data(), y.data());
-      for (int64_t i = 0; i < n; ++i)
-        for (int64_t j = 0; j < n; ++j) {
-          double s = 0.0;
-          for (int64_t k = 0; k < n; ++k) s += x[i * n + k] * y[k * n + j];
-          c[i * n + j] = s;
-        }
-    }
+    std::vector<double> eps, c;
+    orbitals_fs(n, F, S, eps, c);
     if (n_occ > 0) mu = 0.5 * (eps[n_occ - 1] + eps[n_occ]);
     if (mu_out) *mu_out = mu;
     GF2_REQUIRE(std::isfinite(mu), GF2_E_ARG, "mu is not finite");
@@ -1951,6 +1960,397 @@ gf2_status gf2_proposal_infer(gf2_ctx* ctx, const gf2_mlp* mlp, const double* ph
     launch_mlp_infer(*mlp, phi, naux, bf16, alpha, z, p, ctx->stream);
     GF2_HIP(hipGetLastError());
     GF2_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+
+// ------------------------------------------------------------ SCF --------
+// The steps on either side of Sigma(tau) that make GF2 self-consistent
+// (Section III), in the orthonormal eigenbasis of (F, S).
+namespace {
+
+struct ScfGrid {
+  int64_t n = 0, np = 0, ntau = 0, nw = 0, nc = 0, ncp = 0, nchunk = 0, nto = 0, ntop = 0;
+  double beta = 0.0;
+  std::vector<double> eps, c, tau;
+  double* sig = nullptr;     // Sigma~(tau) [ntau][np][np]
+  double* ph = nullptr;      // [nchunk][ntau][ncp][2]: w_t (cos, sin)(w_f tau_t)
+  double* cs = nullptr;      // [nchunk][ntop][ncp][2]: (cos, sin)(w_f tau_o), tau_ntau = beta
+  double* om = nullptr;      // [nchunk][ncp]
+  double* a = nullptr;       // [nc][2][np][np]
+  double* colbuf = nullptr;  // [nc][2][np][32]
+  double* pbuf = nullptr;    // [nc][2][32][32]
+  double* tr = nullptr;      // [nchunk * nc]
+  double* shift = nullptr;   // [np]
+  int* err = nullptr;
+};
+
+constexpr size_t kScfChunkBytes = size_t(1) << 31;   // Dyson matrices of one frequency chunk
+
+// Upload C (padded) and C^T, transform Sigma(tau) to Sigma~ = C^T Sigma C on
+// the FP64 MFMA GEMM, and tabulate the phases of both transforms.
+void scf_prepare(gf2_ctx* ctx, ScfGrid& g, int64_t n, const double* F, const double* S, double beta, int64_t ntau,
+                 const double* tau, const double* w, const double* Sigma, int64_t nw, bool need_back) {
+  GF2_REQUIRE(n > 0 && F && tau && w && Sigma && ntau > 0 && nw > 0, GF2_E_ARG, "bad Dyson arguments");
+  GF2_REQUIRE(beta > 0 && std::isfinite(beta), GF2_E_ARG, "beta must be positive");
+  for (int64_t t = 0; t < ntau; ++t)
+    GF2_REQUIRE(tau[t] >= 0 && tau[t] <= beta, GF2_E_ARG, "tau outside [0, beta]");
+  orbitals_fs(n, F, S, g.eps, g.c);
+  g.n = n;
+  g.np = pad_dim(n);
+  g.ntau = ntau;
+  g.nw = nw;
+  g.beta = beta;
+  g.tau.assign(tau, tau + ntau);
+  const int64_t np = g.np, np2 = np * np, fg = scf_freq_group(), og = scf_time_group();
+  g.nc = std::max<int64_t>(1, std::min<int64_t>({nw, 4096, (int64_t)(kScfChunkBytes / (size_t)(16 * np2))}));
+  g.ncp = (g.nc + fg - 1) / fg * fg;
+  g.nchunk = (nw + g.nc - 1) / g.nc;
+  g.nto = ntau + 1;
+  g.ntop = (g.nto + og - 1) / og * og;
+  // eigenvectors, padded, and their transpose
+  std::vector<double> cp((size_t)np2, 0.0), ctp((size_t)np2, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = 0; k < n; ++k) {
+      cp[i * np + k] = g.c[i * n + k];
+      ctp[k * np + i] = g.c[i * n + k];
+    }
+  auto* dcp = (double*)ctx_buf(ctx, "scf_cp", (size_t)np2 * 8);
+  auto* dct = (double*)ctx_buf(ctx, "scf_ct", (size_t)np2 * 8);
+  h2d(ctx, dcp, cp.data(), cp.size());
+  h2d(ctx, dct, ctp.data(), ctp.size());
+  // Sigma~ = C^T Sigma C: Y = C^T Sigma (A = C^T, B = Sigma, Sigma symmetric),
+  // then Sigma~ = Y C (A = Y, B = C^T).  The GEMM writes only the n x n part
+  // of its outputs: their padding is cleared first, since Y is read again as
+  // an operand over the padded length and Sigma~ in full by the quadrature.
+  auto* spad = (double*)ctx_buf(ctx, "scf_spad", (size_t)(ntau * np2) * 8);
+  auto* y = (double*)ctx_buf(ctx, "scf_y", (size_t)(ntau * np2) * 8, true);
+  g.sig = (double*)ctx_buf(ctx, "scf_sig", (size_t)(ntau * np2) * 8, true);
+  launch_pad_convert(Sigma, n, np, ntau, Prec::F64, spad, 0, np2, nullptr, ctx->stream);
+  GF2_HIP(hipGetLastError());
+  Prob pb[2];
+  pb[0] = prob0();
+  pb[0].a[0] = opref(dct);
+  pb[0].b[0] = opref(spad, np2);
+  pb[0].nout = 1;
+  pb[0].out[0] = outspec(y, 0, {1.0f}, 0, 0, np2);
+  pb[1] = prob0();
+  pb[1].a[0] = opref(y, np2);
+  pb[1].b[0] = opref(dct);
+  pb[1].nout = 1;
+  pb[1].out[0] = outspec(g.sig, 0, {1.0f}, 0, 0, np2);
+  auto* probs = (Prob*)ctx_buf(ctx, "scf_prob", 2 * sizeof(Prob));
+  h2d(ctx, probs, pb, 2);
+  std::vector<Unit> uh((size_t)ntau);
+  for (int64_t t = 0; t < ntau; ++t) uh[t] = mk_unit(t, 0, 0, 0, 0);
+  auto* units = (Unit*)ctx_buf(ctx, "scf_units", (size_t)ntau * sizeof(Unit));
+  h2d(ctx, units, uh.data(), uh.size());
+  {
+    ProfScope ps(ctx, "scf_mo", 4.0 * (double)ntau * (double)n * n * n);
+    for (int k = 0; k < 2; ++k) {
+      GemmLaunch L = chain_launch(probs + k, 1, units, (int32_t)ntau, n, np, 0);
+      launch_gemm(Prec::F64, L, tiles_of(pb[k], Prec::F64, n), ctx->stream);
+    }
+  }
+  GF2_HIP(hipGetLastError());
+  // phase tables (host, FP64): w_f = (2f + 1) pi / beta
+  std::vector<double> ph((size_t)(g.nchunk * ntau * g.ncp * 2), 0.0), om((size_t)(g.nchunk * g.ncp), 0.0);
+  std::vector<double> cs(need_back ? (size_t)(g.nchunk * g.ntop * g.ncp * 2) : 0, 0.0);
+#pragma omp parallel for schedule(static)
+  for (int64_t ch = 0; ch < g.nchunk; ++ch)
+    for (int64_t f = 0; f < g.nc; ++f) {
+      const int64_t fg_ = ch * g.nc + f;
+      if (fg_ >= nw) break;
+      const double wf = (2.0 * (double)fg_ + 1.0) * M_PI / beta;
+      om[ch * g.ncp + f] = wf;
+      for (int64_t t = 0; t < ntau; ++t) {
+        const double x = wf * tau[t];
+        double* p = &ph[((ch * ntau + t) * g.ncp + f) * 2];
+        p[0] = w[t] * std::cos(x);
+        p[1] = w[t] * std::sin(x);
+      }
+      if (need_back)
+        for (int64_t o = 0; o < g.nto; ++o) {
+          const double x = wf * (o < ntau ? tau[o] : beta);
+          double* p = &cs[((ch * g.ntop + o) * g.ncp + f) * 2];
+          p[0] = std::cos(x);
+          p[1] = std::sin(x);
+        }
+    }
+  g.ph = (double*)ctx_buf(ctx, "scf_ph", ph.size() * 8);
+  g.om = (double*)ctx_buf(ctx, "scf_om", om.size() * 8);
+  h2d(ctx, g.ph, ph.data(), ph.size());
+  h2d(ctx, g.om, om.data(), om.size());
+  if (need_back) {
+    g.cs = (double*)ctx_buf(ctx, "scf_cs", cs.size() * 8);
+    h2d(ctx, g.cs, cs.data(), cs.size());
+  }
+  const int64_t nb = scf_panel();
+  g.a = (double*)ctx_buf(ctx, "scf_a", (size_t)(g.nc * 2 * np2) * 8);
+  g.colbuf = (double*)ctx_buf(ctx, "scf_col", (size_t)(g.nc * 2 * np * nb) * 8);
+  g.pbuf = (double*)ctx_buf(ctx, "scf_piv", (size_t)(g.nc * 2 * nb * nb) * 8);
+  g.tr = (double*)ctx_buf(ctx, "scf_tr", (size_t)(g.nchunk * g.nc) * 8);
+  g.shift = (double*)ctx_buf(ctx, "scf_shift", (size_t)np * 8);
+  g.err = (int*)ctx_buf(ctx, "scf_err", sizeof(int), true);
+  GF2_HIP(hipStreamSynchronize(ctx->stream));
+}
+
+// Dyson matrices of frequency chunk ch at chemical potential mu (shift
+// already uploaded), inverted in place; returns the chunk's frequency count.
+int64_t scf_chunk(gf2_ctx* ctx, const ScfGrid& g, int64_t ch) {
+  const int64_t cnt = std::min(g.nc, g.nw - ch * g.nc);
+  const double np = (double)g.np;
+  {
+    ProfScope ps(ctx, "scf_sig_iw", 4.0 * (double)cnt * (double)g.ntau * np * np);
+    launch_sig_iw(g.sig, g.ntau, g.np, g.n, g.ph + ch * g.ntau * g.ncp * 2, (int32_t)cnt, (int32_t)g.ncp, g.shift,
+                  g.om + ch * g.ncp, g.a, ctx->stream);
+  }
+  {
+    ProfScope ps(ctx, "scf_invert", 8.0 * (double)cnt * np * np * np);
+    launch_gj_invert(g.a, (int32_t)cnt, g.np, g.colbuf, g.pbuf, g.err, ctx->stream);
+  }
+  GF2_HIP(hipGetLastError());
+  return cnt;
+}
+
+void scf_set_mu(gf2_ctx* ctx, const ScfGrid& g, double mu) {
+  std::vector<double> sh((size_t)g.np, 0.0);
+  for (int64_t i = 0; i < g.n; ++i) sh[i] = mu - g.eps[i];
+  h2d(ctx, g.shift, sh.data(), sh.size());
+}
+
+void scf_check(gf2_ctx* ctx, const ScfGrid& g) {
+  int e = 0;
+  d2h(ctx, &e, g.err, 1);
+  if (e) throw Gf2Error{GF2_E_NUMERIC, "Dyson matrix with a vanishing or non-finite pivot"};
+}
+
+// N_e(mu) = -2 Tr G~(beta-) = 2 sum_i f_i + (4 / beta) sum_w sum_i Re D_ii(i w).
+double scf_count(gf2_ctx* ctx, const ScfGrid& g, double mu) {
+  scf_set_mu(ctx, g, mu);
+  for (int64_t ch = 0; ch < g.nchunk; ++ch) {
+    const int64_t cnt = scf_chunk(ctx, g, ch);
+    launch_iw_diag(g.a, (int32_t)cnt, g.np, g.n, g.shift, g.om + ch * g.ncp, g.tr + ch * g.nc, ctx->stream);
+  }
+  GF2_HIP(hipGetLastError());
+  std::vector<double> tr((size_t)g.nw);
+  d2h(ctx, tr.data(), g.tr, tr.size());
+  scf_check(ctx, g);
+  double s = 0.0;
+  for (double v : tr) s += v;
+  double fsum = 0.0;
+  for (int64_t i = 0; i < g.n; ++i) fsum += std::exp(-softplus(g.beta * (g.eps[i] - mu)));
+  return 2.0 * fsum + 4.0 / g.beta * s;
+}
+
+// Regula falsi with the Illinois modification on N_e(mu) - n_elec (N_e grows
+// with mu) inside [lo, hi].
+double scf_tune(gf2_ctx* ctx, const ScfGrid& g, double n_elec, double lo, double hi, double* ne_out) {
+  GF2_REQUIRE(lo < hi && std::isfinite(lo) && std::isfinite(hi), GF2_E_ARG, "bad mu bracket");
+  double flo = scf_count(ctx, g, lo) - n_elec, fhi = scf_count(ctx, g, hi) - n_elec;
+  GF2_REQUIRE(flo <= 0.0 && fhi >= 0.0, GF2_E_ARG, "the mu bracket does not contain N_e = n_elec");
+  const double tol_n = 1e-11 * std::max(1.0, std::fabs(n_elec));
+  double m = flo == 0.0 ? lo : hi, fm = flo == 0.0 ? flo : fhi;
+  int side = 0;
+  for (int it = 0; it < 200 && std::fabs(fm) > tol_n; ++it) {
+    if (hi - lo <= 1e-15 * std::max(1.0, std::fabs(lo) + std::fabs(hi))) break;
+    m = (lo * fhi - hi * flo) / (fhi - flo);
+    if (!(m > lo && m < hi)) m = 0.5 * (lo + hi);
+    fm = scf_count(ctx, g, m) - n_elec;
+    if (fm < 0.0) {
+      lo = m;
+      flo = fm;
+      if (side == -1) fhi *= 0.5;
+      side = -1;
+    } else {
+      hi = m;
+      fhi = fm;
+      if (side == 1) flo *= 0.5;
+      side = 1;
+    }
+  }
+  if (ne_out) *ne_out = fm + n_elec;
+  return m;
+}
+
+// G(tau), G(beta - tau) and G(beta-) at mu: the back-transform sums over all
+// chunks, G~ in the eigenbasis, then G = C G~ C^T on the FP64 MFMA GEMM.
+void scf_dyson(gf2_ctx* ctx, const ScfGrid& g, double mu, double* G, double* Gbar, double* Gbeta) {
+  const int64_t np = g.np, np2 = np * np, nt = g.ntau, nmo = 2 * nt + 1;
+  scf_set_mu(ctx, g, mu);
+  auto* pc = (double*)ctx_buf(ctx, "scf_pc", (size_t)(g.nto * np2) * 8, true);
+  auto* ps = (double*)ctx_buf(ctx, "scf_ps", (size_t)(g.nto * np2) * 8, true);
+  for (int64_t ch = 0; ch < g.nchunk; ++ch) {
+    const int64_t cnt = scf_chunk(ctx, g, ch);
+    ProfScope pr(ctx, "scf_back", 4.0 * (double)cnt * (double)g.nto * (double)np2);
+    launch_iw_back(g.a, (int32_t)cnt, np, g.n, g.shift, g.om + ch * g.ncp, g.cs + ch * g.ntop * g.ncp * 2,
+                   (int32_t)g.nto, (int32_t)g.ncp, pc, ps, ctx->stream);
+  }
+  GF2_HIP(hipGetLastError());
+  scf_check(ctx, g);
+  std::vector<double> emu((size_t)g.n);
+  for (int64_t i = 0; i < g.n; ++i) emu[i] = g.eps[i] - mu;
+  auto* demu = (double*)ctx_buf(ctx, "scf_emu", (size_t)g.n * 8);
+  auto* dtau = (double*)ctx_buf(ctx, "scf_tau", (size_t)nt * 8);
+  h2d(ctx, demu, emu.data(), emu.size());
+  h2d(ctx, dtau, g.tau.data(), g.tau.size());
+  auto* mo = (double*)ctx_buf(ctx, "scf_mo", (size_t)(nmo * np2) * 8);
+  auto* y = (double*)ctx_buf(ctx, "scf_y2", (size_t)(nmo * np2) * 8, true);
+  auto* out = (double*)ctx_buf(ctx, "scf_out", (size_t)(nmo * np2) * 8);
+  launch_g_mo(pc, ps, np, g.n, nt, dtau, demu, g.beta, mo, ctx->stream);
+  GF2_HIP(hipGetLastError());
+  // G = C G~ C^T: Y = C G~ (A = C, B = G~, symmetric), then G = Y C^T (A = Y,
+  // B = C); Y's padding is cleared (read as an operand over the padded length)
+  const double* dcp = (const double*)ctx_buf(ctx, "scf_cp", (size_t)np2 * 8);
+  Prob pb[2];
+  pb[0] = prob0();
+  pb[0].a[0] = opref(dcp);
+  pb[0].b[0] = opref(mo, np2);
+  pb[0].nout = 1;
+  pb[0].out[0] = outspec(y, 0, {1.0f}, 0, 0, np2);
+  pb[1] = prob0();
+  pb[1].a[0] = opref(y, np2);
+  pb[1].b[0] = opref(dcp);
+  pb[1].nout = 1;
+  pb[1].out[0] = outspec(out, 0, {1.0f}, 0, 0, np2);
+  auto* probs = (Prob*)ctx_buf(ctx, "scf_prob2", 2 * sizeof(Prob));
+  h2d(ctx, probs, pb, 2);
+  std::vector<Unit> uh((size_t)nmo);
+  for (int64_t t = 0; t < nmo; ++t) uh[t] = mk_unit(t, 0, 0, 0, 0);
+  auto* units = (Unit*)ctx_buf(ctx, "scf_units2", (size_t)nmo * sizeof(Unit));
+  h2d(ctx, units, uh.data(), uh.size());
+  {
+    ProfScope ps2(ctx, "scf_ao", 4.0 * (double)nmo * (double)g.n * g.n * g.n);
+    for (int k = 0; k < 2; ++k) {
+      GemmLaunch L = chain_launch(probs + k, 1, units, (int32_t)nmo, g.n, np, 0);
+      launch_gemm(Prec::F64, L, tiles_of(pb[k], Prec::F64, g.n), ctx->stream);
+    }
+  }
+  if (G) launch_unpad_sym(out, g.n, np, nt, 1.0, G, ctx->stream);
+  if (Gbar) launch_unpad_sym(out + nt * np2, g.n, np, nt, 1.0, Gbar, ctx->stream);
+  if (Gbeta) launch_unpad_sym(out + 2 * nt * np2, g.n, np, 1, 1.0, Gbeta, ctx->stream);
+  GF2_HIP(hipGetLastError());
+  GF2_HIP(hipStreamSynchronize(ctx->stream));
+}
+
+// F = h + J[P] - K[P]/2 with P = -2 G(beta-): J from c_Q = Tr(B^Q P), K as
+// sums over groups of 8 auxiliary indices of (B^Q P) B^Q on the FP64 GEMM.
+void scf_fock(gf2_ctx* ctx, int64_t n, int64_t naux, const void* B, gf2_dtype dtype, const double* h,
+              const double* Gbeta, double* Fout) {
+  GF2_REQUIRE(n > 0 && naux > 0 && B && h && Gbeta && Fout, GF2_E_ARG, "bad Fock arguments");
+  GF2_REQUIRE(dtype == GF2_F64 || dtype == GF2_F32, GF2_E_ARG, "bad dtype");
+  const bool f64 = dtype == GF2_F64;
+  const int64_t np = pad_dim(n), np2 = np * np, nn = n * n;
+  auto* p = (double*)ctx_buf(ctx, "fk_p", (size_t)nn * 8);
+  auto* ppad = (double*)ctx_buf(ctx, "fk_ppad", (size_t)np2 * 8);
+  auto* cq = (double*)ctx_buf(ctx, "fk_c", (size_t)naux * 8);
+  auto* dh = (double*)ctx_buf(ctx, "fk_h", (size_t)nn * 8);
+  auto* df = (double*)ctx_buf(ctx, "fk_f", (size_t)nn * 8);
+  h2d(ctx, dh, h, (size_t)nn);
+  launch_density(Gbeta, nn, p, ctx->stream);
+  launch_pad_convert(p, n, np, 1, Prec::F64, ppad, 0, np2, nullptr, ctx->stream);
+  launch_bq_dot(B, f64, n, naux, p, cq, ctx->stream);
+  GF2_HIP(hipGetLastError());
+  constexpr int64_t kSeg = kMaxSeg;
+  const int64_t qc = std::min<int64_t>((naux + kSeg - 1) / kSeg * kSeg,
+                                       std::max<int64_t>(kSeg, ((int64_t)1 << 30) / (16 * np2) / kSeg * kSeg));
+  const int64_t nchunk = (naux + qc - 1) / qc, ngc = qc / kSeg, ng = nchunk * ngc;
+  auto* bq = (double*)ctx_buf(ctx, "fk_bq", (size_t)(qc * np2) * 8);
+  auto* x = (double*)ctx_buf(ctx, "fk_x", (size_t)(qc * np2) * 8, true);
+  auto* kp = (double*)ctx_buf(ctx, "fk_kp", (size_t)(ng * np2) * 8, true);
+  Prob pb[2];
+  pb[0] = prob0();          // X^Q = B^Q P  (A = B^Q, B = P, symmetric)
+  pb[0].a[0] = opref(bq, np2);
+  pb[0].b[0] = opref(ppad);
+  pb[0].nout = 1;
+  pb[0].out[0] = outspec(x, 0, {1.0f}, 0, 0, np2);
+  pb[1] = prob0();          // sum over a group of 8 of X^Q B^Q (B^Q symmetric)
+  pb[1].nseg = (int32_t)kSeg;
+  for (int s_ = 0; s_ < kSeg; ++s_) {
+    pb[1].a[s_] = opref(x + s_ * np2, kSeg * np2);
+    pb[1].b[s_] = opref(bq + s_ * np2, kSeg * np2);
+  }
+  pb[1].nout = 1;
+  auto* probs = (Prob*)ctx_buf(ctx, "fk_prob", 2 * nchunk * sizeof(Prob));
+  std::vector<Prob> ph((size_t)(2 * nchunk));
+  for (int64_t ch = 0; ch < nchunk; ++ch) {
+    ph[2 * ch] = pb[0];
+    ph[2 * ch + 1] = pb[1];
+    ph[2 * ch + 1].out[0] = outspec(kp + ch * ngc * np2, 0, {1.0f}, 0, 0, np2);
+  }
+  h2d(ctx, probs, ph.data(), ph.size());
+  std::vector<Unit> uh((size_t)qc);
+  for (int64_t t = 0; t < qc; ++t) uh[t] = mk_unit(t, 0, 0, 0, 0);
+  auto* units = (Unit*)ctx_buf(ctx, "fk_units", (size_t)qc * sizeof(Unit));
+  h2d(ctx, units, uh.data(), uh.size());
+  {
+    ProfScope ps(ctx, "fock_k", 4.0 * (double)naux * (double)n * n * n);
+    for (int64_t ch = 0; ch < nchunk; ++ch) {
+      launch_pad_bq(B, f64, n, naux, np, ch * qc, qc, bq, ctx->stream);
+      GemmLaunch L0 = chain_launch(probs + 2 * ch, 1, units, (int32_t)qc, n, np, 0);
+      launch_gemm(Prec::F64, L0, tiles_of(pb[0], Prec::F64, n), ctx->stream);
+      GemmLaunch L1 = chain_launch(probs + 2 * ch + 1, 1, units, (int32_t)ngc, n, np, 0);
+      launch_gemm(Prec::F64, L1, tiles_of(pb[1], Prec::F64, n), ctx->stream);
+    }
+  }
+  launch_fock_final(B, f64, n, naux, cq, dh, kp, ng, np, df, ctx->stream);
+  GF2_HIP(hipGetLastError());
+  d2h(ctx, Fout, df, (size_t)nn);
+}
+
+}  // namespace
+
+gf2_status gf2_dyson(gf2_ctx* ctx, int64_t n, const double* F, const double* S, double mu, double beta,
+                     int64_t ntau, const double* tau, const double* w, const double* Sigma, int64_t nw, double* G,
+                     double* Gbar, double* Gbeta) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(G || Gbar || Gbeta, GF2_E_ARG, "no output requested");
+    GF2_REQUIRE(std::isfinite(mu), GF2_E_ARG, "mu is not finite");
+    ScfGrid g;
+    scf_prepare(ctx, g, n, F, S, beta, ntau, tau, w, Sigma, nw, true);
+    scf_dyson(ctx, g, mu, G, Gbar, Gbeta);
+  });
+}
+
+gf2_status gf2_electron_count(gf2_ctx* ctx, int64_t n, const double* F, const double* S, double mu, double beta,
+                              int64_t ntau, const double* tau, const double* w, const double* Sigma, int64_t nw,
+                              double* n_e) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(n_e && std::isfinite(mu), GF2_E_ARG, "bad electron-count arguments");
+    ScfGrid g;
+    scf_prepare(ctx, g, n, F, S, beta, ntau, tau, w, Sigma, nw, false);
+    *n_e = scf_count(ctx, g, mu);
+  });
+}
+
+gf2_status gf2_tune_mu(gf2_ctx* ctx, int64_t n, const double* F, const double* S, double beta, int64_t ntau,
+                       const double* tau, const double* w, const double* Sigma, int64_t nw, double n_elec,
+                       double mu_lo, double mu_hi, double* mu_out, double* n_e) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(mu_out, GF2_E_ARG, "mu_out is null");
+    ScfGrid g;
+    scf_prepare(ctx, g, n, F, S, beta, ntau, tau, w, Sigma, nw, false);
+    *mu_out = scf_tune(ctx, g, n_elec, mu_lo, mu_hi, n_e);
+  });
+}
+
+gf2_status gf2_fock(gf2_ctx* ctx, int64_t n, int64_t naux, const void* B, gf2_dtype dtype, const double* h,
+                    const double* Gbeta, double* F_out) {
+  return guarded(ctx, [&] { scf_fock(ctx, n, naux, B, dtype, h, Gbeta, F_out); });
+}
+
+gf2_status gf2_scf_step(gf2_ctx* ctx, int64_t n, int64_t naux, const void* B, gf2_dtype dtype, const double* h,
+                        const double* F, const double* S, double beta, int64_t ntau, const double* tau,
+                        const double* w, const double* Sigma, int64_t nw, double n_elec, double mu_lo, double mu_hi,
+                        double* mu_out, double* G, double* Gbar, double* Gbeta, double* F_out) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(mu_out && G && Gbar && Gbeta && F_out, GF2_E_ARG, "bad SCF-step outputs");
+    ScfGrid g;
+    scf_prepare(ctx, g, n, F, S, beta, ntau, tau, w, Sigma, nw, true);
+    const double mu = scf_tune(ctx, g, n_elec, mu_lo, mu_hi, nullptr);
+    scf_dyson(ctx, g, mu, G, Gbar, Gbeta);
+    scf_fock(ctx, n, naux, B, dtype, h, Gbeta, F_out);
+    *mu_out = mu;
   });
 }
 

@@ -87,6 +87,27 @@ bool launch_dd_strips(const double* G, const double* Gb, int64_t n, int64_t naux
                       const int32_t* col_q, const int32_t* col_cs, int32_t ncs, double* strip,
                       int64_t ntau_batch, double* out, hipStream_t st);
 
+// Self-consistent GF2 steps (scf.hip).  Frequencies per chunk are padded to
+// a multiple of scf_freq_group(), output times to scf_time_group().
+int scf_freq_group();
+int scf_time_group();
+int scf_panel();
+void launch_sig_iw(const double* sig, int64_t ntau, int64_t np, int64_t n, const double* ph, int32_t nc, int32_t ncp,
+                   const double* shift, const double* om, double* a, hipStream_t st);
+void launch_gj_invert(double* a, int32_t nmat, int64_t np, double* colbuf, double* pbuf, int* err, hipStream_t st);
+void launch_iw_back(const double* a, int32_t nc, int64_t np, int64_t n, const double* shift, const double* om,
+                    const double* cs, int32_t nto, int32_t ncp, double* pc, double* ps, hipStream_t st);
+void launch_iw_diag(const double* a, int32_t nc, int64_t np, int64_t n, const double* shift, const double* om,
+                    double* tr, hipStream_t st);
+void launch_g_mo(const double* pc, const double* ps, int64_t np, int64_t n, int64_t ntau, const double* tau,
+                 const double* emu, double beta, double* out, hipStream_t st);
+void launch_pad_bq(const void* b, bool f64, int64_t n, int64_t naux, int64_t np, int64_t q0, int64_t qc, double* out,
+                   hipStream_t st);
+void launch_bq_dot(const void* b, bool f64, int64_t n, int64_t naux, const double* p, double* c, hipStream_t st);
+void launch_fock_final(const void* b, bool f64, int64_t n, int64_t naux, const double* c, const double* h,
+                       const double* kp, int64_t ng, int64_t np, double* f, hipStream_t st);
+void launch_density(const double* gbeta, int64_t nn, double* p, hipStream_t st);
+
 struct gf2_mlp;
 int mlp_nparam();
 void launch_features(const void* b, bool f64, int64_t n, int64_t naux, double thr, const double* x,

@@ -1,0 +1,509 @@
+// Kernels of the self-consistent GF2 steps on either side of the self-energy
+// (Section III): the tau -> i w quadrature of eq:GFT, the per-frequency Dyson
+// inversion of eq:dyson, and the back-transform of eq:Ginverse with the
+// non-interacting G0 of eq:G0 subtracted, plus the RI Fock build of eq:F.
+//
+// Everything runs in the orthonormal eigenbasis of (F, S) (C^T S C = I,
+// C^T F C = diag(eps)): there G0(i w) is diagonal, the Dyson matrix is
+//   A(i w) = diag(mu + i w - eps) - Sigma~(i w),  Sigma~ = C^T Sigma C,
+// and N_e = -2 Tr G~(beta-).  Matrices are padded to np (a multiple of 32)
+// with the identity on the padded diagonal, so the padded inverse is the
+// inverse plus the identity block.  Complex matrices are planar: the real
+// np x np plane, then the imaginary one.
+//
+// The inversion is blocked Gauss-Jordan without pivoting over 32-wide panels.
+// A(i w) is complex symmetric with imaginary part w I - Im Sigma~(i w), which
+// is positive definite for a self-energy with a positive spectral function
+// (Im Sigma(i w) <= 0 for w > 0), so every leading block is invertible and
+// elimination without pivoting is stable; a vanishing or non-finite pivot
+// sets an error word that the host turns into GF2_E_NUMERIC.
+#include "kernels.hpp"
+
+namespace {
+
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kNB = 32;    // Gauss-Jordan panel width
+constexpr int kTW = 64;    // output tile width of the panel kernels
+constexpr int kFG = 16;    // frequencies per thread in the forward transform
+constexpr int kOG = 16;    // output times per thread in the back-transform
+
+// Blocks that share an element tile land on one XCD (blockIdx % 8 picks
+// the XCD), one after the other: the tile's input stays in that XCD's L2.
+__device__ __forceinline__ void xcd_split(unsigned b, int ng, int64_t& tile, int& g) {
+  const unsigned xcd = b & 7u, r = b >> 3;
+  g = (int)(r % (unsigned)ng);
+  tile = (int64_t)(r / (unsigned)ng) * 8 + xcd;
+}
+
+// A(i w_f) for the frequencies of one chunk from Sigma~(tau_t) (padded,
+// [ntau][np][np]): Sigma~(i w_f) = sum_t ph[t][f] Sigma~(tau_t) with
+// ph[t][f] = w_t (cos, sin)(w_f tau_t).  shift[i] = mu - eps_i.
+__global__ __launch_bounds__(256) void k_sig_iw(const double* __restrict__ sig, int64_t ntau, int64_t np,
+                                                 int64_t n, const double* __restrict__ ph, int32_t nc, int32_t ncp,
+                                                 const double* __restrict__ shift, const double* __restrict__ om,
+                                                 double* __restrict__ a) {
+  int64_t tile;
+  int g;
+  xcd_split(blockIdx.x, ncp / kFG, tile, g);
+  const int64_t np2 = np * np;
+  const int64_t e = tile * 256 + threadIdx.x;
+  if (e >= np2) return;
+  const int f0 = g * kFG;
+  double sr[kFG], si[kFG];
+#pragma unroll
+  for (int f = 0; f < kFG; ++f) sr[f] = si[f] = 0.0;
+  for (int64_t t = 0; t < ntau; ++t) {
+    const double x = sig[t * np2 + e];
+    const double* p = ph + (t * ncp + f0) * 2;
+#pragma unroll
+    for (int f = 0; f < kFG; ++f) {
+      sr[f] = fma(p[2 * f], x, sr[f]);
+      si[f] = fma(p[2 * f + 1], x, si[f]);
+    }
+  }
+  const int64_t i = e / np, j = e - i * np;
+#pragma unroll
+  for (int f = 0; f < kFG; ++f) {
+    const int fi = f0 + f;
+    if (fi >= nc) break;
+    double re = -sr[f], im = -si[f];
+    if (i == j) {
+      if (i < n) {
+        re += shift[i];
+        im += om[fi];
+      } else {
+        re = 1.0;
+        im = 0.0;
+      }
+    }
+    a[(int64_t)(2 * fi) * np2 + e] = re;
+    a[(int64_t)(2 * fi + 1) * np2 + e] = im;
+  }
+}
+
+__device__ __forceinline__ void cmul(double ar, double ai, double br, double bi, double& cr, double& ci) {
+  cr = ar * br - ai * bi;
+  ci = ar * bi + ai * br;
+}
+
+// Gauss-Jordan, panel k0 (columns K = [k0, k0 + 32)), first half: every
+// block inverts the diagonal block P = A_KK^{-1} in LDS, copies rows
+// [64 ct, 64 ct + 64) of the column panel A_{:,K} to colbuf, and replaces
+// its 64 columns j (outside K) of the row panel by P A_Kj.  Block ct = 0
+// also stores P.  Grid (column tiles, matrices).
+__global__ __launch_bounds__(256) void k_gj_panel(double* a, int64_t np, int64_t k0, double* colbuf,
+                                                  double* pbuf, int* err) {
+  __shared__ double dr[kNB][kNB + 1], di[kNB][kNB + 1];
+  __shared__ double rr[kNB][kTW + 1], ri[kNB][kTW + 1];
+  __shared__ double fr[kNB], fi[kNB];
+  const int tid = threadIdx.x, ct = blockIdx.x;
+  const int64_t mat = blockIdx.y, np2 = np * np;
+  double* ar = a + mat * 2 * np2;
+  double* ai = ar + np2;
+  const int64_t j0 = (int64_t)ct * kTW;
+  for (int x = tid; x < kNB * kNB; x += 256) {
+    const int r = x / kNB, c = x % kNB;
+    dr[r][c] = ar[(k0 + r) * np + k0 + c];
+    di[r][c] = ai[(k0 + r) * np + k0 + c];
+  }
+  for (int x = tid; x < kNB * kTW; x += 256) {
+    const int r = x / kTW, c = x % kTW;
+    const int64_t j = j0 + c;
+    rr[r][c] = j < np ? ar[(k0 + r) * np + j] : 0.0;
+    ri[r][c] = j < np ? ai[(k0 + r) * np + j] : 0.0;
+  }
+  double* cbr = colbuf + mat * 2 * np * kNB;
+  double* cbi = cbr + np * kNB;
+  for (int x = tid; x < kTW * kNB; x += 256) {
+    const int r = x / kNB, c = x % kNB;
+    const int64_t i = j0 + r;
+    if (i < np) {
+      cbr[i * kNB + c] = ar[i * np + k0 + c];
+      cbi[i * kNB + c] = ai[i * np + k0 + c];
+    }
+  }
+  __syncthreads();
+  // in-place Gauss-Jordan inverse of the 32 x 32 diagonal block
+  for (int p = 0; p < kNB; ++p) {
+    if (tid < kNB) {
+      fr[tid] = dr[tid][p];
+      fi[tid] = di[tid][p];
+    }
+    __syncthreads();
+    const double pr = fr[p], pi = fi[p];
+    const double den = pr * pr + pi * pi;
+    if (tid == 0 && ct == 0 && !(den >= 1e-280 && den <= 1e280)) atomicOr(err, 1);
+    const double vr = pr / den, vi = -pi / den;   // 1 / pivot
+    if (tid < kNB) {
+      if (tid == p) {
+        dr[p][tid] = vr;
+        di[p][tid] = vi;
+      } else {
+        double xr, xi;
+        cmul(dr[p][tid], di[p][tid], vr, vi, xr, xi);
+        dr[p][tid] = xr;
+        di[p][tid] = xi;
+      }
+    }
+    __syncthreads();
+    for (int x = tid; x < kNB * kNB; x += 256) {
+      const int r = x / kNB, c = x % kNB;
+      if (r == p) continue;
+      double xr, xi;
+      if (c == p) {
+        cmul(fr[r], fi[r], vr, vi, xr, xi);
+        dr[r][c] = -xr;
+        di[r][c] = -xi;
+      } else {
+        cmul(fr[r], fi[r], dr[p][c], di[p][c], xr, xi);
+        dr[r][c] -= xr;
+        di[r][c] -= xi;
+      }
+    }
+    __syncthreads();
+  }
+  if (ct == 0) {
+    double* pr_ = pbuf + mat * 2 * kNB * kNB;
+    for (int x = tid; x < kNB * kNB; x += 256) {
+      const int r = x / kNB, c = x % kNB;
+      pr_[x] = dr[r][c];
+      pr_[kNB * kNB + x] = di[r][c];
+    }
+  }
+  // row panel: R_Kj = P A_Kj for the tile's columns outside K
+  const int c = tid % kTW, rg = tid / kTW;   // 4 groups of 8 rows
+  const int64_t j = j0 + c;
+  if (j >= np || (j >= k0 && j < k0 + kNB)) return;
+#pragma unroll
+  for (int q = 0; q < kNB / 4; ++q) {
+    const int r = rg * (kNB / 4) + q;
+    double sr = 0.0, si = 0.0;
+#pragma unroll 8
+    for (int l = 0; l < kNB; ++l) {
+      const double xr = dr[r][l], xi = di[r][l], yr = rr[l][c], yi = ri[l][c];
+      sr = fma(xr, yr, fma(-xi, yi, sr));
+      si = fma(xr, yi, fma(xi, yr, si));
+    }
+    ar[(k0 + r) * np + j] = sr;
+    ai[(k0 + r) * np + j] = si;
+  }
+}
+
+// Second half: every 64 x 64 tile outside the panel rows takes
+//   A_ij <- (j in K ? 0 : A_ij) - sum_k C_ik R'_kj
+// with C the column panel saved by the first half and R' the new row panel
+// (P on the K columns), on FP64 MFMAs (complex product as four real ones);
+// the (K, K) block takes P.  Grid (column tiles, row tiles, matrices).
+__global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_t k0, const double* colbuf,
+                                                   const double* pbuf) {
+  __shared__ double cs[2][kTW][kNB + 1];
+  __shared__ double rs[2][kNB][kTW + 1];
+  const int tid = threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * kTW, i0 = (int64_t)blockIdx.y * kTW, mat = blockIdx.z;
+  const int64_t np2 = np * np;
+  double* ar = a + mat * 2 * np2;
+  double* ai = ar + np2;
+  const double* cbr = colbuf + mat * 2 * np * kNB;
+  const double* cbi = cbr + np * kNB;
+  const double* pr_ = pbuf + mat * 2 * kNB * kNB;
+  const double* pi_ = pr_ + kNB * kNB;
+  for (int x = tid; x < kTW * kNB; x += 256) {
+    const int r = x / kNB, c = x % kNB;
+    const int64_t i = i0 + r;
+    cs[0][r][c] = i < np ? cbr[i * kNB + c] : 0.0;
+    cs[1][r][c] = i < np ? cbi[i * kNB + c] : 0.0;
+  }
+  for (int x = tid; x < kNB * kTW; x += 256) {
+    const int r = x / kTW, c = x % kTW;
+    const int64_t j = j0 + c;
+    double vr = 0.0, vi = 0.0;
+    if (j < np) {
+      if (j >= k0 && j < k0 + kNB) {
+        vr = pr_[r * kNB + (j - k0)];
+        vi = pi_[r * kNB + (j - k0)];
+      } else {
+        vr = ar[(k0 + r) * np + j];
+        vi = ai[(k0 + r) * np + j];
+      }
+    }
+    rs[0][r][c] = vr;
+    rs[1][r][c] = vi;
+  }
+  __syncthreads();
+  const int lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+  const int lr = lane & 15, lg = lane >> 4;
+  f64x4_t accr[2][2], acci[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) accr[bi][bj][r] = acci[bi][bj][r] = 0.0;
+#pragma unroll
+  for (int ks = 0; ks < kNB / 4; ++ks) {
+    double xr[2], xi[2], yr[2], yi[2], yn[2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      xr[bi] = cs[0][32 * wr + 16 * bi + lr][4 * ks + lg];
+      xi[bi] = cs[1][32 * wr + 16 * bi + lr][4 * ks + lg];
+    }
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      yr[bj] = rs[0][4 * ks + lg][32 * wc + 16 * bj + lr];
+      yi[bj] = rs[1][4 * ks + lg][32 * wc + 16 * bj + lr];
+      yn[bj] = -yi[bj];
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        accr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[bi], yr[bj], accr[bi][bj], 0, 0, 0);
+        accr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi[bi], yn[bj], accr[bi][bj], 0, 0, 0);
+        acci[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[bi], yi[bj], acci[bi][bj], 0, 0, 0);
+        acci[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi[bi], yr[bj], acci[bi][bj], 0, 0, 0);
+      }
+  }
+  // accumulator r of a lane holds row (lane / 16) + 4 r, column lane % 16
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = i0 + 32 * wr + 16 * bi + lg + 4 * r;
+        const int64_t gj = j0 + 32 * wc + 16 * bj + lr;
+        if (gi >= np || gj >= np) continue;
+        const bool ki = gi >= k0 && gi < k0 + kNB, kj = gj >= k0 && gj < k0 + kNB;
+        const int64_t o = gi * np + gj;
+        if (ki) {
+          if (kj) {
+            ar[o] = pr_[(gi - k0) * kNB + (gj - k0)];
+            ai[o] = pi_[(gi - k0) * kNB + (gj - k0)];
+          }
+          continue;
+        }
+        const double br = kj ? 0.0 : ar[o], bim = kj ? 0.0 : ai[o];
+        ar[o] = br - accr[bi][bj][r];
+        ai[o] = bim - acci[bi][bj][r];
+      }
+}
+
+// D(i w_f) = A^{-1} - G0~(i w_f) (G0~ = diag 1 / (mu - eps_i + i w_f), zero
+// on the padding) accumulated into the back-transform sums
+//   pc[o] += sum_f cs[o][f].cos Re D_f,  ps[o] += sum_f cs[o][f].sin Im D_f.
+__global__ __launch_bounds__(256) void k_iw_back(const double* __restrict__ a, int32_t nc, int64_t np, int64_t n,
+                                                  const double* __restrict__ shift, const double* __restrict__ om,
+                                                  const double* __restrict__ cs, int32_t nto, int32_t ncp,
+                                                  double* __restrict__ pc, double* __restrict__ ps) {
+  int64_t tile;
+  int g;
+  xcd_split(blockIdx.x, (nto + kOG - 1) / kOG, tile, g);
+  const int64_t np2 = np * np;
+  const int64_t e = tile * 256 + threadIdx.x;
+  if (e >= np2) return;
+  const int64_t i = e / np, j = e - i * np;
+  const bool dg = i == j && i < n, pad = i == j && i >= n;
+  const double s = dg ? shift[i] : 0.0;
+  const int o0 = g * kOG;
+  double qc[kOG], qs[kOG];
+#pragma unroll
+  for (int o = 0; o < kOG; ++o) qc[o] = qs[o] = 0.0;
+  for (int f = 0; f < nc; ++f) {
+    double dr = a[(int64_t)(2 * f) * np2 + e], di = a[(int64_t)(2 * f + 1) * np2 + e];
+    if (dg) {
+      const double wf = om[f], den = s * s + wf * wf;
+      dr -= s / den;
+      di += wf / den;
+    } else if (pad) {
+      dr -= 1.0;
+    }
+    const double* p = cs + ((int64_t)o0 * ncp + f) * 2;
+#pragma unroll
+    for (int o = 0; o < kOG; ++o) {
+      qc[o] = fma(p[(int64_t)o * ncp * 2], dr, qc[o]);
+      qs[o] = fma(p[(int64_t)o * ncp * 2 + 1], di, qs[o]);
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < kOG; ++o) {
+    if (o0 + o >= nto) break;
+    pc[(int64_t)(o0 + o) * np2 + e] += qc[o];
+    ps[(int64_t)(o0 + o) * np2 + e] += qs[o];
+  }
+}
+
+// tr[f] = sum_{i < n} Re D_ii(i w_f): one block per matrix, a fixed
+// reduction order.
+__global__ __launch_bounds__(256) void k_iw_diag(const double* a, int64_t np, int64_t n, const double* shift,
+                                                 const double* om, double* tr) {
+  __shared__ double red[256];
+  const int64_t f = blockIdx.x, np2 = np * np;
+  const double* ar = a + f * 2 * np2;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double sh = shift[i], wf = om[f];
+    s += ar[i * np + i] - sh / (sh * sh + wf * wf);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tr[f] = red[0];
+}
+
+__device__ __forceinline__ double softplus_d(double x) { return fmax(x, 0.0) + log1p(exp(-fabs(x))); }
+
+// G~ in the eigenbasis from the back-transform sums: for output time o
+//   G~(tau_o)      = G0~(tau_o)      + (2/beta) (pc + ps)
+//   G~(beta-tau_o) = G0~(beta-tau_o) - (2/beta) (pc - ps)
+// with G0~ = -diag((1-f) e^{-e tau}) and -diag(f e^{e tau}) (e = eps - mu).
+// out: [ntau] G, then [ntau] Gbar, then G(beta-) (o = ntau is tau = beta).
+__global__ void k_g_mo(const double* pc, const double* ps, int64_t np, int64_t n, int64_t ntau,
+                       const double* tau, const double* emu, double beta, double* out) {
+  const int64_t np2 = np * np;
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= (ntau + 1) * np2) return;
+  const int64_t o = x / np2, e = x - o * np2, i = e / np, j = e - i * np;
+  const double c = 2.0 / beta, vc = pc[x], vs = ps[x];
+  if (o == ntau) {
+    double v = c * (vc + vs);
+    if (i == j && i < n) v -= exp(-softplus_d(beta * emu[i]));
+    out[2 * ntau * np2 + e] = v;
+    return;
+  }
+  double g = c * (vc + vs), gb = -c * (vc - vs);
+  if (i == j && i < n) {
+    const double et = emu[i], t = tau[o];
+    g -= exp(-et * t - softplus_d(-beta * et));
+    gb -= exp(et * t - softplus_d(beta * et));
+  }
+  out[o * np2 + e] = g;
+  out[(ntau + o) * np2 + e] = gb;
+}
+
+// ----------------------------------------------------------------- Fock --
+
+// Padded FP64 copies of B^Q for Q in [q0, q0 + qc) (zero for Q >= naux).
+__global__ void k_pad_bq(const void* b, int f64, int64_t n, int64_t naux, int64_t np, int64_t q0, int64_t qc,
+                         double* out) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= qc * np * np) return;
+  const int64_t q = x / (np * np), e = x - q * np * np, i = e / np, j = e - i * np;
+  double v = 0.0;
+  if (i < n && j < n && q0 + q < naux) {
+    const int64_t s = ((q0 + q) * n + i) * n + j;
+    v = f64 ? ((const double*)b)[s] : (double)((const float*)b)[s];
+  }
+  out[x] = v;
+}
+
+// c_Q = Tr(B^Q P) = sum_ij B^Q_ij P_ij, one block per Q.
+__global__ __launch_bounds__(256) void k_bq_dot(const void* b, int f64, int64_t n, const double* p, double* c) {
+  __shared__ double red[256];
+  const int64_t q = blockIdx.x, nn = n * n;
+  double s = 0.0;
+  if (f64) {
+    const double* bq = (const double*)b + q * nn;
+    for (int64_t e = threadIdx.x; e < nn; e += 256) s = fma(bq[e], p[e], s);
+  } else {
+    const float* bq = (const float*)b + q * nn;
+    for (int64_t e = threadIdx.x; e < nn; e += 256) s = fma((double)bq[e], p[e], s);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) c[q] = red[0];
+}
+
+// F = h + J - K/2 with J_ij = sum_Q c_Q B^Q_ij and K the sum of the padded
+// partial products kp[g] (ng of them).
+__global__ void k_fock_final(const void* b, int f64, int64_t n, int64_t naux, const double* c, const double* h,
+                             const double* kp, int64_t ng, int64_t np, double* f) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nn = n * n;
+  if (e >= nn) return;
+  double jv = 0.0;
+  if (f64) {
+    const double* bb = (const double*)b;
+    for (int64_t q = 0; q < naux; ++q) jv = fma(c[q], bb[q * nn + e], jv);
+  } else {
+    const float* bb = (const float*)b;
+    for (int64_t q = 0; q < naux; ++q) jv = fma(c[q], (double)bb[q * nn + e], jv);
+  }
+  const int64_t i = e / n, j = e - i * n;
+  double kv = 0.0;
+  for (int64_t g = 0; g < ng; ++g) kv += kp[g * np * np + i * np + j];
+  f[e] = h[e] + jv - 0.5 * kv;
+}
+
+// P = -2 G(beta-) (n x n).
+__global__ void k_density(const double* gbeta, int64_t nn, double* p) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nn) p[e] = -2.0 * gbeta[e];
+}
+
+inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+int scf_freq_group() { return kFG; }
+int scf_time_group() { return kOG; }
+int scf_panel() { return kNB; }
+
+void launch_sig_iw(const double* sig, int64_t ntau, int64_t np, int64_t n, const double* ph, int32_t nc, int32_t ncp,
+                   const double* shift, const double* om, double* a, hipStream_t st) {
+  const int64_t tiles = (np * np + 255) / 256;
+  const unsigned grid = (unsigned)(((tiles + 7) / 8) * 8 * (ncp / kFG));
+  hipLaunchKernelGGL(k_sig_iw, dim3(grid), dim3(256), 0, st, sig, ntau, np, n, ph, nc, ncp, shift, om, a);
+}
+
+void launch_gj_invert(double* a, int32_t nmat, int64_t np, double* colbuf, double* pbuf, int* err, hipStream_t st) {
+  const unsigned tiles = (unsigned)((np + kTW - 1) / kTW);
+  for (int64_t k0 = 0; k0 < np; k0 += kNB) {
+    hipLaunchKernelGGL(k_gj_panel, dim3(tiles, (unsigned)nmat), dim3(256), 0, st, a, np, k0, colbuf, pbuf, err);
+    hipLaunchKernelGGL(k_gj_update, dim3(tiles, tiles, (unsigned)nmat), dim3(256), 0, st, a, np, k0,
+                       (const double*)colbuf, (const double*)pbuf);
+  }
+}
+
+void launch_iw_back(const double* a, int32_t nc, int64_t np, int64_t n, const double* shift, const double* om,
+                    const double* cs, int32_t nto, int32_t ncp, double* pc, double* ps, hipStream_t st) {
+  const int64_t tiles = (np * np + 255) / 256;
+  const unsigned grid = (unsigned)(((tiles + 7) / 8) * 8 * ((nto + kOG - 1) / kOG));
+  hipLaunchKernelGGL(k_iw_back, dim3(grid), dim3(256), 0, st, a, nc, np, n, shift, om, cs, nto, ncp, pc, ps);
+}
+
+void launch_iw_diag(const double* a, int32_t nc, int64_t np, int64_t n, const double* shift, const double* om,
+                    double* tr, hipStream_t st) {
+  hipLaunchKernelGGL(k_iw_diag, dim3((unsigned)nc), dim3(256), 0, st, a, np, n, shift, om, tr);
+}
+
+void launch_g_mo(const double* pc, const double* ps, int64_t np, int64_t n, int64_t ntau, const double* tau,
+                 const double* emu, double beta, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_g_mo, dim3(nblk((ntau + 1) * np * np)), dim3(256), 0, st, pc, ps, np, n, ntau, tau, emu, beta,
+                     out);
+}
+
+void launch_pad_bq(const void* b, bool f64, int64_t n, int64_t naux, int64_t np, int64_t q0, int64_t qc, double* out,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_pad_bq, dim3(nblk(qc * np * np)), dim3(256), 0, st, b, (int)f64, n, naux, np, q0, qc, out);
+}
+
+void launch_bq_dot(const void* b, bool f64, int64_t n, int64_t naux, const double* p, double* c, hipStream_t st) {
+  hipLaunchKernelGGL(k_bq_dot, dim3((unsigned)naux), dim3(256), 0, st, b, (int)f64, n, p, c);
+}
+
+void launch_fock_final(const void* b, bool f64, int64_t n, int64_t naux, const double* c, const double* h,
+                       const double* kp, int64_t ng, int64_t np, double* f, hipStream_t st) {
+  hipLaunchKernelGGL(k_fock_final, dim3(nblk(n * n)), dim3(256), 0, st, b, (int)f64, n, naux, c, h, kp, ng, np, f);
+}
+
+void launch_density(const double* gbeta, int64_t nn, double* p, hipStream_t st) {
+  hipLaunchKernelGGL(k_density, dim3(nblk(nn)), dim3(256), 0, st, gbeta, nn, p);
+}

@@ -121,6 +121,16 @@ _SIGS = {
                                           C.POINTER(C.c_double), C.c_double, C.POINTER(Sampling), C.c_int,
                                           C.c_double, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.POINTER(AdaptiveResult)]),
+    "gf2_dyson": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double, C.c_double, C.c_int64, C.POINTER(C.c_double),
+                            C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gf2_electron_count": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double, C.c_double, C.c_int64,
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.POINTER(C.c_double)]),
+    "gf2_tune_mu": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                              C.c_void_p, C.c_int64, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "gf2_fock": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_void_p, C.POINTER(C.c_double)]),
+    "gf2_scf_step": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                               C.c_double, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_double, C.c_double,
+                               C.c_double, C.POINTER(C.c_double), C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "gf2_proposal_features": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                         C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
     "gf2_proposal_targets": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
@@ -161,6 +171,16 @@ def load() -> C.CDLL:
         f.argtypes = args
     _lib = lib
     return lib
+
+
+def _dtype(t) -> int:
+    """GF2_F64 / GF2_F32 of a torch tensor (raises for anything else)."""
+    import torch
+    if t.dtype == torch.float64:
+        return GF2_F64
+    if t.dtype == torch.float32:
+        return GF2_F32
+    raise TypeError(f"B must be float64 or float32, not {t.dtype}")
 
 
 def _dp(a: np.ndarray):
@@ -300,6 +320,68 @@ class Context:
                                            tau.shape[0], _dp(tau), G.data_ptr(), Gb.data_ptr(),
                                            C.byref(mu_out)))
         return G, Gb, mu_out.value
+
+    # ---------------------------------------------------------------- SCF
+    @staticmethod
+    def _f64(a):
+        return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+    def dyson(self, F, S, mu, beta, tau, w, Sigma, nw):
+        """G(tau), G(beta - tau) [ntau][n][n] and G(beta-) [n][n] of the Dyson G
+        at mu (gf2_dyson)."""
+        torch = self.torch
+        F, S, tau, w = self._f64(F), self._f64(S), self._f64(tau), self._f64(w)
+        n, ntau = F.shape[0], tau.shape[0]
+        G = torch.empty((ntau, n, n), dtype=torch.float64, device=self.device)
+        Gb = torch.empty_like(G)
+        Gbeta = torch.empty((n, n), dtype=torch.float64, device=self.device)
+        self._check(self.lib.gf2_dyson(self.h, n, _dp(F), None if S is None else _dp(S), float(mu), float(beta),
+                                       ntau, _dp(tau), _dp(w), Sigma.data_ptr(), int(nw), G.data_ptr(),
+                                       Gb.data_ptr(), Gbeta.data_ptr()))
+        return G, Gb, Gbeta
+
+    def electron_count(self, F, S, mu, beta, tau, w, Sigma, nw) -> float:
+        F, S, tau, w = self._f64(F), self._f64(S), self._f64(tau), self._f64(w)
+        out = C.c_double(0)
+        self._check(self.lib.gf2_electron_count(self.h, F.shape[0], _dp(F), None if S is None else _dp(S),
+                                                float(mu), float(beta), tau.shape[0], _dp(tau), _dp(w),
+                                                Sigma.data_ptr(), int(nw), C.byref(out)))
+        return out.value
+
+    def tune_mu(self, F, S, beta, tau, w, Sigma, nw, n_elec, lo, hi):
+        """(mu, N_e reached) with N_e(mu) = n_elec in [lo, hi] (gf2_tune_mu)."""
+        F, S, tau, w = self._f64(F), self._f64(S), self._f64(tau), self._f64(w)
+        mu, ne = C.c_double(0), C.c_double(0)
+        self._check(self.lib.gf2_tune_mu(self.h, F.shape[0], _dp(F), None if S is None else _dp(S), float(beta),
+                                         tau.shape[0], _dp(tau), _dp(w), Sigma.data_ptr(), int(nw),
+                                         float(n_elec), float(lo), float(hi), C.byref(mu), C.byref(ne)))
+        return mu.value, ne.value
+
+    def fock(self, B, h, Gbeta):
+        """eq:F on the RI factors, P = -2 G(beta-) (gf2_fock); host [n][n]."""
+        h = self._f64(h)
+        n, naux = h.shape[0], B.shape[0]
+        out = np.empty((n, n))
+        self._check(self.lib.gf2_fock(self.h, n, naux, B.data_ptr(), _dtype(B), _dp(h), Gbeta.data_ptr(),
+                                      _dp(out)))
+        return out
+
+    def scf_step(self, B, h, F, S, beta, tau, w, Sigma, nw, n_elec, lo, hi):
+        """One update around the self-energy (gf2_scf_step): returns
+        (mu, G, Gbar, G(beta-), new F)."""
+        torch = self.torch
+        h, F, S, tau, w = self._f64(h), self._f64(F), self._f64(S), self._f64(tau), self._f64(w)
+        n, ntau = F.shape[0], tau.shape[0]
+        G = torch.empty((ntau, n, n), dtype=torch.float64, device=self.device)
+        Gb = torch.empty_like(G)
+        Gbeta = torch.empty((n, n), dtype=torch.float64, device=self.device)
+        Fo = np.empty((n, n))
+        mu = C.c_double(0)
+        self._check(self.lib.gf2_scf_step(self.h, n, B.shape[0], B.data_ptr(), _dtype(B), _dp(h), _dp(F),
+                                          None if S is None else _dp(S), float(beta), ntau, _dp(tau), _dp(w),
+                                          Sigma.data_ptr(), int(nw), float(n_elec), float(lo), float(hi),
+                                          C.byref(mu), G.data_ptr(), Gb.data_ptr(), Gbeta.data_ptr(), _dp(Fo)))
+        return mu.value, G, Gb, Gbeta, Fo
 
     # ---------------------------------------------------------------- Sigma
     @staticmethod
