@@ -145,6 +145,15 @@ def training_dimer_counts() -> List[int]:
 # Seeded random operands for tests of the general (non-synthetic) paths.
 # ---------------------------------------------------------------------------
 
+def aux_metric(xq: np.ndarray, alpha: float = 0.5, shift: float = 0.5) -> np.ndarray:
+    """A synthetic Coulomb metric of the auxiliary centres: V_AB =
+    exp(-alpha (x_A - x_B)^2) + shift delta_AB (symmetric positive definite:
+    a Gaussian kernel matrix plus a positive diagonal)."""
+    xq = np.asarray(xq, dtype=np.float64)
+    d = xq[:, None] - xq[None, :]
+    return np.exp(-alpha * d * d) + shift * np.eye(xq.shape[0])
+
+
 def random_symmetric(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
     r = np.random.default_rng(seed).standard_normal((n, n))
     return scale * 0.5 * (r + r.T)

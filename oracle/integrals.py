@@ -2,7 +2,9 @@
 
 eq:K_ijQ defines K^Q_ij = sum_A (ij|A) V^{-1/2}_{AQ}, so that the 4-index
 integrals factor as v_ijkl = sum_Q K^Q_ij K^Q_kl (eq:vKQKQ).  The synthetic
-stand-in supplies K directly from a Gaussian model of the chain (V = I).
+stand-in supplies K directly from a Gaussian model of the chain (V = I), or,
+for the screened front end (eq:V_ijA, then the second eq:K_ijQ), the same
+Gaussian model as (ij|A) with a Gaussian metric V.
 """
 from __future__ import annotations
 
@@ -37,6 +39,21 @@ def b_from_three_index(ija: np.ndarray, v: np.ndarray | None) -> np.ndarray:
         return np.array(ija, dtype=np.float64, copy=True)
     vis = inverse_sqrt_spd(v)
     return np.einsum("aij,aq->qij", ija, vis, optimize=True)
+
+
+def screen_three_index(ija: np.ndarray, eps_prime: float) -> np.ndarray:
+    """eq:V_ijA: (ij|A)^L keeps (ij|A) where |(ij|A)| >= (eps' / N) M_j, with
+    M_j the largest |(ij|A)| over i and A for that j, and is zero elsewhere.
+    ija is [N_aux][N][N] (A, i, j); N is the basis size."""
+    ija = np.asarray(ija, dtype=np.float64)
+    n = ija.shape[1]
+    out = np.zeros_like(ija)
+    for j in range(n):
+        col = ija[:, :, j]
+        m_j = float(np.max(np.abs(col)))
+        thr = eps_prime / n * m_j
+        out[:, :, j] = np.where(np.abs(col) >= thr, col, 0.0)
+    return out
 
 
 def four_index(b: np.ndarray) -> np.ndarray:
