@@ -395,6 +395,119 @@ def variants_bench(args):
     ctx.close()
 
 
+def scf_bench(args):
+    """The steps around the self-energy on a paper-sized grid: an H500-shaped
+    chain (N=500, N_aux=1500), beta=50, 300 tau points and 20000 Matsubara
+    frequencies (the paper's grid).  Sigma(tau) comes from the hot path (BF16C,
+    --ns pairs, eps=1e-3); then one SCF update (mu tuned to N_e = N, Dyson,
+    Fock) is timed with the per-kernel profile."""
+    import torch
+    import chain_inputs as ci
+    from paper_2005_12338_amd import gf2
+    nd, beta, ntau, nw, ns, eps = 250, 50.0, 300, args.nw or 20000, args.ns or 64, 1e-3
+    geo = ci.chain_geometry(nd)
+    F = ci.fock_tight_binding(geo.x)
+    tau, w = gf2.gf2_tau_grid(beta, ntau)
+    ctx = gf2.Context(0)
+    B = ctx.build_B(geo.n, geo.naux, geom=geo, dtype=torch.float32)
+    spl = ctx.split(B, eps)
+    G, Gb, mu = ctx.green_tau(F, tau, beta, n_occ=geo.n // 2)
+    det = ctx.sigma_det(spl, G, Gb)
+    acc = torch.zeros_like(det)
+    ctx.sigma_stoch(spl, B, G, Gb, acc, ns=ns, seed=0, prec="bf16c")
+    Sig = ctx.sigma_finalize(det, acc, ns)
+    _, gb0, _ = ctx.green_tau(F, np.zeros(1), beta, n_occ=geo.n // 2)
+    h = 2.0 * F - ctx.fock(B, F, gb0[0].contiguous())
+    n_e = float(geo.n)
+    log(f"[bench] scf: N={geo.n} Naux={geo.naux} beta={beta} ntau={ntau} nw={nw}, Sigma from {ns} BF16C pairs")
+    out = {"metric": "one SCF update around Sigma (mu tuning, Dyson, Fock)", "workload": f"H{geo.n} chain",
+           "n": geo.n, "naux": geo.naux, "beta": beta, "ntau": ntau, "nw": nw}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_ev = ctx.electron_count(F, None, mu, beta, tau, w, Sig, nw)
+    torch.cuda.synchronize()
+    t_count = time.perf_counter() - t0
+    ctx.set_profiling(True)
+    ctx.profile_read()
+    t0 = time.perf_counter()
+    mu1, G1, Gb1, Gbeta1, F1 = ctx.scf_step(B, h, F, None, beta, tau, w, Sig, nw, n_e, mu - 0.2, mu + 0.2)
+    torch.cuda.synchronize()
+    t_step = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.set_profiling(False)
+    evals = None
+    rows = {}
+    for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"]):
+        rate = v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 and v["flops"] else 0.0
+        rows[k] = {"launches": v["launches"], "ms": v["ms"], "tflops": rate}
+        log(f"[bench]   {k:12s} launches={v['launches']:6d} total={v['ms']:9.2f} ms  {rate:7.2f} TFLOP/s")
+    inv = prof.get("scf_invert")
+    nchunk = rows.get("scf_back", {}).get("launches", 0)
+    if inv and nchunk:
+        evals = inv["launches"] // nchunk
+    ne1 = -2.0 * float(torch.trace(Gbeta1))
+    log(f"[bench] N_e(mu0) = {n_ev:.12f} in {t_count:.2f} s; SCF update {t_step:.2f} s: mu {mu:.9f} -> {mu1:.12f}, "
+        f"N_e = {ne1:.12f}, Dyson evaluations {evals}")
+    out.update({"s_electron_count": t_count, "s_scf_update": t_step, "mu_in": mu, "mu_out": mu1, "n_e_out": ne1,
+                "dyson_evaluations": evals, "kernels": rows,
+                "invert_fp64_frac": (rows["scf_invert"]["tflops"] / 78.6) if "scf_invert" in rows else None})
+    print(json.dumps(out), flush=True)
+    spl.free()
+    ctx.close()
+
+
+def scf_bias(args):
+    """E_corr per electron of the self-consistent loop with stochastic
+    Sigma against 1/N_s (the Results' bias study): an H80-shaped chain
+    (N=80), beta=50, 128 tau, 4000 frequencies, eps=1e-2, 8 updates from the
+    tight-binding start, 4 seeds per N_s; the deterministic RI loop
+    (eps=1e-12: every element above 1e-12 of the largest in the exact block,
+    the rest, below 1e-12, dropped) as the reference."""
+    import torch
+    import chain_inputs as ci
+    from paper_2005_12338_amd import gf2
+    nd, beta, ntau, nw, n_it = 40, 50.0, 128, 4000, 8
+    geo = ci.chain_geometry(nd)
+    F0 = ci.fock_tight_binding(geo.x)
+    tau, w = gf2.gf2_tau_grid(beta, ntau)
+    ctx = gf2.Context(0)
+    B = ctx.build_B(geo.n, geo.naux, geom=geo, dtype=torch.float64)
+    _, gb0, mu0 = ctx.green_tau(F0, np.zeros(1), beta, n_occ=geo.n // 2)
+    h = 2.0 * F0 - ctx.fock(B, F0, gb0[0].contiguous())
+
+    def loop(eps, ns, seed):
+        spl = ctx.split(B, eps)
+        F, mu = F0.copy(), mu0
+        G, Gb, _ = ctx.green_tau(F, tau, beta, mu=mu)
+        hist = []
+        for it in range(n_it):
+            det = ctx.sigma_det(spl, G, Gb)
+            acc = torch.zeros_like(det)
+            if ns:
+                ctx.sigma_stoch(spl, B, G, Gb, acc, ns=ns, seed=seed * 1000 + it, prec="fp64")
+            Sig = ctx.sigma_finalize(det, acc, max(ns, 1))
+            e, epe, _ = ctx.energy(Sig, Gb, w, float(geo.n))
+            hist.append(epe)
+            mu, G, Gb, Gbeta, F = ctx.scf_step(B, h, F, None, beta, tau, w, Sig, nw, float(geo.n),
+                                               mu - 0.3, mu + 0.3)
+        spl.free()
+        return hist
+
+    t0 = time.perf_counter()
+    ref = loop(1e-12, 0, 0)
+    log(f"[bench] deterministic RI loop: E/N_e per update {['%.8f' % x for x in ref]}")
+    rows = {"deterministic": ref}
+    for ns in (8, 16, 32, 64, 128):
+        finals = [loop(1e-2, ns, seed)[-1] for seed in range(4)]
+        m, sd = float(np.mean(finals)), float(np.std(finals, ddof=1) / 2.0)
+        rows[f"ns_{ns}"] = {"mean": m, "stderr": sd, "samples": finals}
+        log(f"[bench] N_s={ns:4d}: E/N_e = {m:.8f} +- {sd:.2e}  (deterministic {ref[-1]:.8f}, "
+            f"diff {m - ref[-1]:+.2e})")
+    print(json.dumps({"metric": "self-consistent E_corr per electron vs 1/N_s", "workload": f"H{geo.n} chain",
+                      "rows": rows, "s": time.perf_counter() - t0}), flush=True)
+    ctx.close()
+
+
 def cpu_baseline(wl, pairs):
     """The oracle (FP64 NumPy, as it stands) timed on a bounded sample of the
     same workload and extrapolated to a time-to-target estimate (s)."""
@@ -461,11 +574,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="n800", choices=["n800", "n200", "tiny", "batch", "n1600"])
+    ap.add_argument("--workload", default="n800", choices=["n800", "n200", "tiny", "batch", "n1600", "scf", "scf-bias"])
     ap.add_argument("--batch-count", type=int, default=96, help="chains in the batch workload")
     ap.add_argument("--batch-prec-bf16", action="store_true", help="run the batch in BF16 (default FP32)")
     ap.add_argument("--prec", default="bf16c", choices=["bf16c", "bf16", "bf16x3", "fp32", "fp64"])
     ap.add_argument("--ns", type=int, default=0, help="pairs per step (default: the workload's)")
+    ap.add_argument("--nw", type=int, default=0, help="Matsubara frequencies of the scf workload")
     ap.add_argument("--variants", action="store_true",
                     help="only compare the estimator forms (paired, control-variate, double average)")
     ap.add_argument("--gemm-reference", action="store_true",
@@ -491,6 +605,12 @@ def main():
         return
     if args.workload == "batch":
         batch_bench(args)
+        return
+    if args.workload == "scf":
+        scf_bench(args)
+        return
+    if args.workload == "scf-bias":
+        scf_bias(args)
         return
     if args.workload == "n1600":
         learned_bench(args)

@@ -145,6 +145,17 @@ def training_dimer_counts() -> List[int]:
 # Seeded random operands for tests of the general (non-synthetic) paths.
 # ---------------------------------------------------------------------------
 
+def gaussian_three_index(geo: "ChainGeometry") -> np.ndarray:
+    """Raw three-index integrals (ij|A) [N_aux][N][N] of the chain: the same
+    Gaussian model as the synthetic factors, amp exp(-a (x_i - x_j)^2)
+    exp(-c (x_A - (x_i + x_j)/2)^2), as a host array for both sides."""
+    x, xq = geo.x, geo.xq
+    d = x[:, None] - x[None, :]
+    m = 0.5 * (x[:, None] + x[None, :])
+    bond = geo.amp * np.exp(-geo.a * d * d)
+    return np.stack([bond * np.exp(-geo.c * (xq[q] - m) ** 2) for q in range(xq.shape[0])])
+
+
 def aux_metric(xq: np.ndarray, alpha: float = 0.5, shift: float = 0.5) -> np.ndarray:
     """A synthetic Coulomb metric of the auxiliary centres: V_AB =
     exp(-alpha (x_A - x_B)^2) + shift delta_AB (symmetric positive definite:

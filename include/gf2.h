@@ -158,6 +158,26 @@ gf2_status gf2_build_B(gf2_ctx* ctx, int64_t n, int64_t naux, const void* ijA,
 gf2_status gf2_split(gf2_ctx* ctx, const void* B, gf2_dtype dtype, int64_t n,
                      int64_t naux, double eps, gf2_split_h** out,
                      int64_t* nnzL, int64_t* wmax);
+
+/* gf2_screen_ijA: eq:V_ijA.  (ij|A)^L = (ij|A) where |(ij|A)| >= (eps' / n)
+ *   M_j, M_j = max over i and A of |(ij|A)| for orbital j (inclusive), and 0
+ *   elsewhere.  ijA and out device [naux][n][n] (A, i, j) of dtype `dtype`
+ *   (may alias: the screen is elementwise after the column maxima); the
+ *   comparison is made in FP64.  *nnz (host, may be NULL) = kept elements.
+ *   Errors: GF2_E_ARG (eps' < 0, sizes, dtype).
+ * gf2_split_large: the split of the screened front end.  The large part is
+ *   taken from KL, the factors of the screened integrals (gf2_build_B of
+ *   gf2_screen_ijA's output: the second eq:K_ijQ), through eq:K_L on KL
+ *   itself (|KL| >= eps max|KL|); R = sum_Q theta_Q B^Q still uses the full
+ *   B, and R^S = R - R^L.  KL device, same shape and dtype as B, unchanged
+ *   while the handle is used.  gf2_split is the case KL = B.  Sampling with
+ *   such a split supports +-1, stratified and importance vectors; the
+ *   proposal features (gf2_proposal_features) need a split of B itself. */
+gf2_status gf2_screen_ijA(gf2_ctx* ctx, int64_t n, int64_t naux, const void* ijA,
+                          gf2_dtype dtype, double eps_prime, void* out, int64_t* nnz);
+gf2_status gf2_split_large(gf2_ctx* ctx, const void* B, const void* KL, gf2_dtype dtype,
+                           int64_t n, int64_t naux, double eps, gf2_split_h** out,
+                           int64_t* nnzL, int64_t* wmax);
 void gf2_split_free(gf2_split_h* h);
 /* Copy the split description to host arrays: support widths w[naux],
  * supports idx[naux][32] (unused slots -1) and blocks blk[naux][32][32]
@@ -320,10 +340,12 @@ gf2_status gf2_energy_noalloc(gf2_ctx* ctx, int64_t n, int64_t ntau, const doubl
  *   all).  Symmetrised ((X + X^T) / 2) like gf2_green_tau.  Synchronous.
  * gf2_electron_count: *n_e = N_e(mu) = -2 sum_ij G_ij(beta-) S_ij (host).
  * gf2_tune_mu: the mu in [mu_lo, mu_hi] with N_e(mu) = n_elec at fixed
- *   Sigma (N_e grows with mu): regula falsi (Illinois) to |N_e - n_elec| <=
- *   1e-11 max(1, n_elec) or a bracket of 1e-15 relative.  *mu_out, and
- *   *n_e (may be NULL) the count reached.  GF2_E_ARG if the bracket does not
- *   contain the root.
+ *   Sigma (N_e grows with mu): Newton steps from the middle of the bracket,
+ *   with dN_e/dmu from the same inverses (dG/dmu = -G^2), bisection where a
+ *   step leaves the narrowed bracket, to |N_e - n_elec| <= 1e-11
+ *   max(1, n_elec) or a bracket of 1e-15 relative.  *mu_out, and *n_e (may
+ *   be NULL) the count reached.  GF2_E_ARG if the bracket does not contain
+ *   the root.
  * gf2_fock: eq:F with the RI factors of eq:vKQKQ, F = h + J[P] - K[P]/2,
  *   J_ij = sum_Q B^Q_ij Tr(B^Q P), K = sum_Q B^Q P B^Q, P = -2 G(beta-).
  *   B device [naux][n][n] (dtype), h host [n][n], Gbeta device [n][n];

@@ -341,28 +341,32 @@ gf2_status gf2_build_B(gf2_ctx* ctx, int64_t n, int64_t naux, const void* ijA, c
 }
 
 // ------------------------------------------------------------ split -------
-gf2_status gf2_split(gf2_ctx* ctx, const void* B, gf2_dtype dtype, int64_t n, int64_t naux, double eps,
-                     gf2_split_h** out, int64_t* nnzL, int64_t* wmax) {
+namespace {
+// eq:K_L on the large-part source L (B itself, or K^L of screened integrals):
+// supports, dense blocks and the deterministic-block lists of the elements
+// with |L| >= eps max|L|.
+gf2_status split_impl(gf2_ctx* ctx, const void* B, const void* L, gf2_dtype dtype, int64_t n, int64_t naux,
+                      double eps, gf2_split_h** out, int64_t* nnzL, int64_t* wmax) {
   gf2_split_h* h = nullptr;
   gf2_status st = guarded(ctx, [&] {
-    GF2_REQUIRE(out && B && n > 0 && naux > 0 && eps >= 0.0 && std::isfinite(eps), GF2_E_ARG,
+    GF2_REQUIRE(out && B && L && n > 0 && naux > 0 && eps >= 0.0 && std::isfinite(eps), GF2_E_ARG,
                 "bad split arguments");
     GF2_REQUIRE(n <= 32768 && naux < (1 << 21), GF2_E_ARG, "n or naux too large");
     const bool f64 = dtype == GF2_F64;
     const int64_t total = naux * n * n;
     const int nblk = 1024;
     auto* part = (double*)ctx_buf(ctx, "split_part", nblk * 8);
-    launch_maxabs(B, f64, total, part, nblk, ctx->stream);
+    launch_maxabs(L, f64, total, part, nblk, ctx->stream);
     GF2_HIP(hipGetLastError());
     std::vector<double> ph(nblk);
     d2h(ctx, ph.data(), part, nblk);
     double kmax = 0.0;
     for (double v : ph) kmax = std::max(kmax, v);
-    GF2_REQUIRE(std::isfinite(kmax), GF2_E_NUMERIC, "non-finite value in B");
+    GF2_REQUIRE(std::isfinite(kmax), GF2_E_NUMERIC, L == B ? "non-finite value in B" : "non-finite value in K^L");
     const double thr = eps * kmax;
     auto* flags = (uint8_t*)ctx_buf(ctx, "split_flags", (size_t)(naux * n));
     auto* cnt = (unsigned long long*)ctx_buf(ctx, "split_cnt", 8, true);
-    launch_rowflags(B, f64, n, naux, thr, flags, cnt, ctx->stream);
+    launch_rowflags(L, f64, n, naux, thr, flags, cnt, ctx->stream);
     GF2_HIP(hipGetLastError());
     std::vector<uint8_t> fh((size_t)(naux * n));
     unsigned long long nnz = 0;
@@ -370,7 +374,7 @@ gf2_status gf2_split(gf2_ctx* ctx, const void* B, gf2_dtype dtype, int64_t n, in
     d2h(ctx, &nnz, cnt, 1);
 
     h = new gf2_split_h();
-    h->owner = ctx; h->bsrc = B; h->dtype = dtype; h->n = n; h->naux = naux; h->np = pad_dim(n);
+    h->owner = ctx; h->bsrc = B; h->lsrc = L == B ? nullptr : L; h->dtype = dtype; h->n = n; h->naux = naux; h->np = pad_dim(n);
     h->eps = eps; h->kmax = kmax; h->thresh = thr; h->nnz = (int64_t)nnz;
     std::vector<int32_t> w(naux, 0), idx((size_t)naux * kWMax, -1);
     int32_t wm = 0;
@@ -490,7 +494,7 @@ gf2_status gf2_split(gf2_ctx* ctx, const void* B, gf2_dtype dtype, int64_t n, in
     if (!pq.empty()) h2d(ctx, h->pat_q, pq.data(), pq.size());
     h2d(ctx, h->row_off, toff.data(), toff.size());
     if (!tq.empty()) h2d(ctx, h->row_q, tq.data(), tq.size());
-    launch_extract_blocks(B, f64, n, naux, thr, h->w, h->idx, h->blk, h->blk32, ctx->stream);
+    launch_extract_blocks(L, f64, n, naux, thr, h->w, h->idx, h->blk, h->blk32, ctx->stream);
     GF2_HIP(hipGetLastError());
     GF2_HIP(hipStreamSynchronize(ctx->stream));
     *out = h;
@@ -504,6 +508,22 @@ gf2_status gf2_split(gf2_ctx* ctx, const void* B, gf2_dtype dtype, int64_t n, in
   return st;
 }
 
+}  // namespace
+
+gf2_status gf2_split(gf2_ctx* ctx, const void* B, gf2_dtype dtype, int64_t n, int64_t naux, double eps,
+                     gf2_split_h** out, int64_t* nnzL, int64_t* wmax) {
+  return split_impl(ctx, B, B, dtype, n, naux, eps, out, nnzL, wmax);
+}
+
+gf2_status gf2_split_large(gf2_ctx* ctx, const void* B, const void* KL, gf2_dtype dtype, int64_t n,
+                           int64_t naux, double eps, gf2_split_h** out, int64_t* nnzL, int64_t* wmax) {
+  if (!KL) {
+    if (ctx) ctx->err = "KL is null";
+    return GF2_E_ARG;
+  }
+  return split_impl(ctx, B, KL, dtype, n, naux, eps, out, nnzL, wmax);
+}
+
 void gf2_split_free(gf2_split_h* h) {
   if (!h) return;
   void* ps[] = {h->w, h->idx, h->blk, h->blk32, h->pat_ij, h->pat_off, h->pat_q, h->row_off, h->row_q,
@@ -511,6 +531,22 @@ void gf2_split_free(gf2_split_h* h) {
   for (void* p : ps)
     if (p) (void)hipFree(p);
   delete h;
+}
+
+gf2_status gf2_screen_ijA(gf2_ctx* ctx, int64_t n, int64_t naux, const void* ijA, gf2_dtype dtype,
+                          double eps_prime, void* out, int64_t* nnz) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(n > 0 && naux > 0 && ijA && out, GF2_E_ARG, "bad screening arguments");
+    GF2_REQUIRE(dtype == GF2_F64 || dtype == GF2_F32, GF2_E_ARG, "bad dtype");
+    GF2_REQUIRE(eps_prime >= 0.0 && std::isfinite(eps_prime), GF2_E_ARG, "eps' must be finite and >= 0");
+    auto* mb = (unsigned long long*)ctx_buf(ctx, "scr_max", (size_t)n * 8, true);
+    auto* kept = (unsigned long long*)ctx_buf(ctx, "scr_cnt", 8, true);
+    launch_screen_ija(ijA, dtype == GF2_F64, n, naux, eps_prime / (double)n, mb, out, kept, ctx->stream);
+    GF2_HIP(hipGetLastError());
+    unsigned long long k = 0;
+    d2h(ctx, &k, kept, 1);
+    if (nnz) *nnz = (int64_t)k;
+  });
 }
 
 gf2_status gf2_split_export(gf2_ctx* ctx, const gf2_split_h* h, int32_t* w, int32_t* idx, double* blk,
@@ -739,7 +775,8 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
     auto* theta = (int8_t*)ctx_buf(ctx, pfx + "c_theta", (size_t)(nvec * naux));
     ProfScope ps(ctx, "rbuild", 4.0 * (double)nvec * naux * n * n, (double)naux * n * n * (bf64 ? 8 : 4));
     launch_theta(smp->seed, ns, s0, naux, theta, st);
-    launch_rbuild(B, bf64, n, naux, sp->thresh, theta, nvec, prec, xl, xs, np, plane, mstride, st);
+    launch_rbuild(B, bf64, n, naux, sp->thresh, theta, nvec, prec, xl, xs, np, plane, mstride, st, nullptr,
+                  sp->lsrc);
   } else if (smp->mode == GF2_SAMPLE_STRATIFIED) {
     // class probabilities and their CDF, sequential FP64 sums
     const int32_t nc = smp->k;
@@ -762,7 +799,7 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
     h2d(ctx, dcdf, cdf.data(), cdf.size());
     ProfScope ps(ctx, "rbuild", 4.0 * (double)nvec * naux * n * n, (double)naux * n * n * (bf64 ? 8 : 4));
     launch_theta_strat(smp->seed, ns, s0, naux, nc, dcdf, dpi, theta, vsc, st);
-    launch_rbuild(B, bf64, n, naux, sp->thresh, theta, nvec, prec, xl, xs, np, plane, mstride, st, vsc);
+    launch_rbuild(B, bf64, n, naux, sp->thresh, theta, nvec, prec, xl, xs, np, plane, mstride, st, vsc, sp->lsrc);
   } else {
     std::vector<double> cdf(naux);
     double acc = 0.0;
@@ -778,7 +815,8 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
     h2d(ctx, dcdf, cdf.data(), cdf.size());
     h2d(ctx, dp, smp->p, (size_t)naux);
     launch_draws(smp->seed, ns, s0, smp->k, dcdf, naux, dp, dq, dw, st);
-    launch_rimportance(B, bf64, n, sp->thresh, dq, dw, smp->k, nvec, prec, xl, xs, np, plane, mstride, st);
+    launch_rimportance(B, bf64, n, sp->thresh, dq, dw, smp->k, nvec, prec, xl, xs, np, plane, mstride, st,
+                       sp->lsrc);
   }
   GF2_HIP(hipGetLastError());
 
@@ -1980,7 +2018,7 @@ struct ScfGrid {
   double* a = nullptr;       // [nc][2][np][np]
   double* colbuf = nullptr;  // [nc][2][np][32]
   double* pbuf = nullptr;    // [nc][2][32][32]
-  double* tr = nullptr;      // [nchunk * nc]
+  double* tr = nullptr;      // [nchunk * nc][2]: trace of D and its mu-derivative
   double* shift = nullptr;   // [np]
   int* err = nullptr;
 };
@@ -2089,7 +2127,7 @@ void scf_prepare(gf2_ctx* ctx, ScfGrid& g, int64_t n, const double* F, const dou
   g.a = (double*)ctx_buf(ctx, "scf_a", (size_t)(g.nc * 2 * np2) * 8);
   g.colbuf = (double*)ctx_buf(ctx, "scf_col", (size_t)(g.nc * 2 * np * nb) * 8);
   g.pbuf = (double*)ctx_buf(ctx, "scf_piv", (size_t)(g.nc * 2 * nb * nb) * 8);
-  g.tr = (double*)ctx_buf(ctx, "scf_tr", (size_t)(g.nchunk * g.nc) * 8);
+  g.tr = (double*)ctx_buf(ctx, "scf_tr", (size_t)(g.nchunk * g.nc * 2) * 8);
   g.shift = (double*)ctx_buf(ctx, "scf_shift", (size_t)np * 8);
   g.err = (int*)ctx_buf(ctx, "scf_err", sizeof(int), true);
   GF2_HIP(hipStreamSynchronize(ctx->stream));
@@ -2125,50 +2163,55 @@ void scf_check(gf2_ctx* ctx, const ScfGrid& g) {
   if (e) throw Gf2Error{GF2_E_NUMERIC, "Dyson matrix with a vanishing or non-finite pivot"};
 }
 
-// N_e(mu) = -2 Tr G~(beta-) = 2 sum_i f_i + (4 / beta) sum_w sum_i Re D_ii(i w).
-double scf_count(gf2_ctx* ctx, const ScfGrid& g, double mu) {
+// N_e(mu) = -2 Tr G~(beta-) = 2 sum_i f_i + (4 / beta) sum_w sum_i Re D_ii(i w),
+// and dN_e/dmu = 2 beta sum_i f_i (1 - f_i) + (4 / beta) sum_w [sum_i Re G0~_ii^2
+// - sum_ij Re G_ij^2] (dG/dmu = -G^2).
+std::pair<double, double> scf_count(gf2_ctx* ctx, const ScfGrid& g, double mu) {
   scf_set_mu(ctx, g, mu);
   for (int64_t ch = 0; ch < g.nchunk; ++ch) {
     const int64_t cnt = scf_chunk(ctx, g, ch);
-    launch_iw_diag(g.a, (int32_t)cnt, g.np, g.n, g.shift, g.om + ch * g.ncp, g.tr + ch * g.nc, ctx->stream);
+    launch_iw_diag(g.a, (int32_t)cnt, g.np, g.n, g.shift, g.om + ch * g.ncp, g.tr + ch * g.nc * 2, ctx->stream);
   }
   GF2_HIP(hipGetLastError());
-  std::vector<double> tr((size_t)g.nw);
+  std::vector<double> tr((size_t)(2 * g.nw));
   d2h(ctx, tr.data(), g.tr, tr.size());
   scf_check(ctx, g);
-  double s = 0.0;
-  for (double v : tr) s += v;
-  double fsum = 0.0;
-  for (int64_t i = 0; i < g.n; ++i) fsum += std::exp(-softplus(g.beta * (g.eps[i] - mu)));
-  return 2.0 * fsum + 4.0 / g.beta * s;
+  double s = 0.0, d = 0.0;
+  for (int64_t k = 0; k < g.nw; ++k) {
+    s += tr[2 * k];
+    d += tr[2 * k + 1];
+  }
+  double fsum = 0.0, fder = 0.0;
+  for (int64_t i = 0; i < g.n; ++i) {
+    const double f = std::exp(-softplus(g.beta * (g.eps[i] - mu)));
+    fsum += f;
+    fder += f * (1.0 - f);
+  }
+  return {2.0 * fsum + 4.0 / g.beta * s, 2.0 * g.beta * fder + 4.0 / g.beta * d};
 }
 
-// Regula falsi with the Illinois modification on N_e(mu) - n_elec (N_e grows
-// with mu) inside [lo, hi].
+// Newton on N_e(mu) - n_elec (N_e grows with mu) from the middle of [lo, hi],
+// the bracket narrowed by every evaluation and a bisection wherever the
+// Newton step leaves it.
 double scf_tune(gf2_ctx* ctx, const ScfGrid& g, double n_elec, double lo, double hi, double* ne_out) {
   GF2_REQUIRE(lo < hi && std::isfinite(lo) && std::isfinite(hi), GF2_E_ARG, "bad mu bracket");
-  double flo = scf_count(ctx, g, lo) - n_elec, fhi = scf_count(ctx, g, hi) - n_elec;
-  GF2_REQUIRE(flo <= 0.0 && fhi >= 0.0, GF2_E_ARG, "the mu bracket does not contain N_e = n_elec");
   const double tol_n = 1e-11 * std::max(1.0, std::fabs(n_elec));
-  double m = flo == 0.0 ? lo : hi, fm = flo == 0.0 ? flo : fhi;
-  int side = 0;
-  for (int it = 0; it < 200 && std::fabs(fm) > tol_n; ++it) {
+  const double lo0 = lo, hi0 = hi;
+  double m = 0.5 * (lo + hi), fm = 0.0;
+  for (int it = 0; it < 200; ++it) {
+    const auto nd = scf_count(ctx, g, m);
+    fm = nd.first - n_elec;
+    if (std::fabs(fm) <= tol_n) break;
+    if (fm < 0.0) lo = m; else hi = m;
     if (hi - lo <= 1e-15 * std::max(1.0, std::fabs(lo) + std::fabs(hi))) break;
-    m = (lo * fhi - hi * flo) / (fhi - flo);
-    if (!(m > lo && m < hi)) m = 0.5 * (lo + hi);
-    fm = scf_count(ctx, g, m) - n_elec;
-    if (fm < 0.0) {
-      lo = m;
-      flo = fm;
-      if (side == -1) fhi *= 0.5;
-      side = -1;
-    } else {
-      hi = m;
-      fhi = fm;
-      if (side == 1) flo *= 0.5;
-      side = 1;
-    }
+    double next = nd.second > 0.0 && std::isfinite(nd.second) ? m - fm / nd.second : lo - 1.0;
+    if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
+    m = next;
   }
+  if (std::fabs(fm) > tol_n)
+    GF2_REQUIRE(!(fm < 0.0 && hi0 - m <= 1e-12 * std::max(1.0, std::fabs(hi0))) &&
+                    !(fm > 0.0 && m - lo0 <= 1e-12 * std::max(1.0, std::fabs(lo0))),
+                GF2_E_ARG, "the mu bracket does not contain N_e = n_elec");
   if (ne_out) *ne_out = fm + n_elec;
   return m;
 }
@@ -2319,7 +2362,7 @@ gf2_status gf2_electron_count(gf2_ctx* ctx, int64_t n, const double* F, const do
     GF2_REQUIRE(n_e && std::isfinite(mu), GF2_E_ARG, "bad electron-count arguments");
     ScfGrid g;
     scf_prepare(ctx, g, n, F, S, beta, ntau, tau, w, Sigma, nw, false);
-    *n_e = scf_count(ctx, g, mu);
+    *n_e = scf_count(ctx, g, mu).first;
   });
 }
 

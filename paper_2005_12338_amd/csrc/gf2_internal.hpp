@@ -195,6 +195,9 @@ struct ProfScope {
 struct gf2_split_h {
   gf2_ctx* owner = nullptr;
   const void* bsrc = nullptr;
+  // The tensor whose elements at or above `thresh` form the large part
+  // (null: B itself).  R^L takes those elements, R^S = R - R^L.
+  const void* lsrc = nullptr;
   gf2_dtype dtype = GF2_F64;
   int64_t n = 0, naux = 0, np = 0;
   double eps = 0.0, kmax = 0.0, thresh = 0.0;

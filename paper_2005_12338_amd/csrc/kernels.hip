@@ -181,7 +181,7 @@ __global__ void k_extract_blocks(const void* b, int f64, int64_t n, int64_t naux
 // to padded storage.  One thread per (i, j) and RV vectors; theta staged in
 // LDS per chunk of Q.
 template <int RV, typename T>
-__global__ __launch_bounds__(256) void k_rbuild(const void* b, int f64, int64_t n, int64_t naux,
+__global__ __launch_bounds__(256) void k_rbuild(const void* b, const void* lsrc, int f64, int64_t n, int64_t naux,
                                                  double thr, const int8_t* theta, int64_t nvec,
                                                  int64_t v0, Prec prec, void* xl, void* xs,
                                                  int64_t np, int64_t plane, int64_t mstride,
@@ -205,10 +205,13 @@ __global__ __launch_bounds__(256) void k_rbuild(const void* b, int f64, int64_t 
     if (ok) {
       const int qe = (int)((naux - q0) < QC ? (naux - q0) : QC);
       for (int qq = 0; qq < qe; ++qq) {
-        T x = f64 ? (T)((const double*)b)[(q0 + qq) * n * n + ij]
-                  : (T)((const float*)b)[(q0 + qq) * n * n + ij];
-        T sx = fabs((double)x) >= thr ? (T)0 : x;
-        T lx = x - sx;
+        const int64_t at = (q0 + qq) * n * n + ij;
+        T x = f64 ? (T)((const double*)b)[at] : (T)((const float*)b)[at];
+        // large part: the source element where it passes the threshold
+        // (the source is B itself unless the split has its own)
+        T y = !lsrc ? x : f64 ? (T)((const double*)lsrc)[at] : (T)((const float*)lsrc)[at];
+        T lx = fabs((double)y) >= thr ? y : (T)0;
+        T sx = x - lx;
 #pragma unroll
         for (int r = 0; r < RV; ++r) {
           al[r] += th[r][qq] * lx;
@@ -231,7 +234,7 @@ __global__ __launch_bounds__(256) void k_rbuild(const void* b, int f64, int64_t 
 }
 
 // Importance vectors: X = sum_j wgt_j B_{Q_j} split into L and S parts.
-__global__ void k_rimportance(const void* b, int f64, int64_t n, double thr, const int32_t* q,
+__global__ void k_rimportance(const void* b, const void* lsrc, int f64, int64_t n, double thr, const int32_t* q,
                               const double* wgt, int32_t k, int64_t nvec, Prec prec, void* xl,
                               void* xs, int64_t np, int64_t plane, int64_t mstride) {
   const int64_t ij = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -240,10 +243,11 @@ __global__ void k_rimportance(const void* b, int f64, int64_t n, double thr, con
   double al = 0.0, as = 0.0;
   for (int j = 0; j < k; ++j) {
     int64_t qq = q[v * k + j];
-    double x = get_acc(b, qq * n * n + ij, f64);
-    double sx = fabs(x) >= thr ? 0.0 : x;
-    al += wgt[v * k + j] * (x - sx);
-    as += wgt[v * k + j] * sx;
+    const double x = get_acc(b, qq * n * n + ij, f64);
+    const double y = lsrc ? get_acc(lsrc, qq * n * n + ij, f64) : x;
+    const double lx = fabs(y) >= thr ? y : 0.0;
+    al += wgt[v * k + j] * lx;
+    as += wgt[v * k + j] * (x - lx);
   }
   const int64_t i = ij / n, jj = ij % n;
   int64_t o = v * mstride + i * np + jj;
@@ -694,14 +698,14 @@ void launch_extract_blocks(const void* b, bool f64, int64_t n, int64_t naux, dou
 }
 void launch_rbuild(const void* b, bool f64, int64_t n, int64_t naux, double thr, const int8_t* theta,
                    int64_t nvec, Prec prec, void* xl, void* xs, int64_t np, int64_t plane,
-                   int64_t mstride, hipStream_t st, const double* vscale) {
+                   int64_t mstride, hipStream_t st, const double* vscale, const void* lsrc) {
   constexpr int RV = 8;
   dim3 grid(blocks(n * n), (unsigned)((nvec + RV - 1) / RV));
   if (prec == Prec::F64)
-    hipLaunchKernelGGL((k_rbuild<RV, double>), grid, dim3(256), 0, st, b, (int)f64, n, naux, thr,
+    hipLaunchKernelGGL((k_rbuild<RV, double>), grid, dim3(256), 0, st, b, lsrc, (int)f64, n, naux, thr,
                        theta, nvec, (int64_t)0, prec, xl, xs, np, plane, mstride, vscale);
   else
-    hipLaunchKernelGGL((k_rbuild<RV, float>), grid, dim3(256), 0, st, b, (int)f64, n, naux, thr,
+    hipLaunchKernelGGL((k_rbuild<RV, float>), grid, dim3(256), 0, st, b, lsrc, (int)f64, n, naux, thr,
                        theta, nvec, (int64_t)0, prec, xl, xs, np, plane, mstride, vscale);
 }
 void launch_theta_strat(uint64_t seed, int64_t ns, int64_t s0, int64_t naux, int32_t nclass, const double* cdf,
@@ -711,9 +715,9 @@ void launch_theta_strat(uint64_t seed, int64_t ns, int64_t s0, int64_t naux, int
 }
 void launch_rimportance(const void* b, bool f64, int64_t n, double thr, const int32_t* q,
                         const double* w, int32_t k, int64_t nvec, Prec prec, void* xl, void* xs,
-                        int64_t np, int64_t plane, int64_t mstride, hipStream_t st) {
+                        int64_t np, int64_t plane, int64_t mstride, hipStream_t st, const void* lsrc) {
   dim3 grid(blocks(n * n), (unsigned)nvec);
-  hipLaunchKernelGGL(k_rimportance, grid, dim3(256), 0, st, b, (int)f64, n, thr, q, w, k, nvec, prec,
+  hipLaunchKernelGGL(k_rimportance, grid, dim3(256), 0, st, b, lsrc, (int)f64, n, thr, q, w, k, nvec, prec,
                      xl, xs, np, plane, mstride);
 }
 void launch_scale_cols(const double* c, const double* lw, int64_t n, int64_t np, int64_t ntau,

@@ -20,12 +20,12 @@ void launch_extract_blocks(const void* b, bool f64, int64_t n, int64_t naux, dou
                            hipStream_t st);
 void launch_rbuild(const void* b, bool f64, int64_t n, int64_t naux, double thr, const int8_t* theta,
                    int64_t nvec, Prec prec, void* xl, void* xs, int64_t np, int64_t plane,
-                   int64_t mstride, hipStream_t st, const double* vscale = nullptr);
+                   int64_t mstride, hipStream_t st, const double* vscale = nullptr, const void* lsrc = nullptr);
 void launch_theta_strat(uint64_t seed, int64_t ns, int64_t s0, int64_t naux, int32_t nclass, const double* cdf,
                         const double* pi, int8_t* theta, double* vscale, hipStream_t st);
 void launch_rimportance(const void* b, bool f64, int64_t n, double thr, const int32_t* q,
                         const double* w, int32_t k, int64_t nvec, Prec prec, void* xl, void* xs,
-                        int64_t np, int64_t plane, int64_t mstride, hipStream_t st);
+                        int64_t np, int64_t plane, int64_t mstride, hipStream_t st, const void* lsrc = nullptr);
 void launch_scale_cols(const double* c, const double* lw, int64_t n, int64_t np, int64_t ntau,
                        double* out, hipStream_t st);
 void launch_unpad_sym(const double* p, int64_t n, int64_t np, int64_t ntau, double sign, double* out,
@@ -86,6 +86,10 @@ bool launch_dd_strips(const double* G, const double* Gb, int64_t n, int64_t naux
                       const int32_t* wq, const int32_t* idx, const double* blk, const int32_t* col_off,
                       const int32_t* col_q, const int32_t* col_cs, int32_t ncs, double* strip,
                       int64_t ntau_batch, double* out, hipStream_t st);
+
+// eq:V_ijA screening (front.hip); mbits [n] and kept must be zeroed.
+void launch_screen_ija(const void* x, bool f64, int64_t n, int64_t naux, double eps_over_n,
+                       unsigned long long* mbits, void* out, unsigned long long* kept, hipStream_t st);
 
 // Self-consistent GF2 steps (scf.hip).  Frequencies per chunk are padded to
 // a multiple of scf_freq_group(), output times to scf_time_group().

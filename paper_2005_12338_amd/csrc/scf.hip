@@ -333,25 +333,42 @@ __global__ __launch_bounds__(256) void k_iw_back(const double* __restrict__ a, i
   }
 }
 
-// tr[f] = sum_{i < n} Re D_ii(i w_f): one block per matrix, a fixed
-// reduction order.
+// Per matrix f of a chunk: tr[2f] = sum_{i<n} Re D_ii(i w_f) and tr[2f + 1] =
+// sum_{i<n} Re G0~_ii^2 - sum_{i,j<n} Re G_ij^2, the derivative of tr[2f]
+// with respect to mu (dG/dmu = -G^2, G complex symmetric).  One block per
+// matrix, a fixed reduction order.
 __global__ __launch_bounds__(256) void k_iw_diag(const double* a, int64_t np, int64_t n, const double* shift,
                                                  const double* om, double* tr) {
-  __shared__ double red[256];
+  __shared__ double red[2][256];
   const int64_t f = blockIdx.x, np2 = np * np;
   const double* ar = a + f * 2 * np2;
-  double s = 0.0;
+  const double* ai = ar + np2;
+  const double wf = om[f];
+  double s = 0.0, d = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 256) {
-    const double sh = shift[i], wf = om[f];
-    s += ar[i * np + i] - sh / (sh * sh + wf * wf);
+    const double sh = shift[i], den = sh * sh + wf * wf;
+    s += ar[i * np + i] - sh / den;
+    d += (sh * sh - wf * wf) / (den * den);
   }
-  red[threadIdx.x] = s;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = threadIdx.x; j < n; j += 256) {
+      const double gr = ar[i * np + j], gi = ai[i * np + j];
+      d -= gr * gr - gi * gi;
+    }
+  red[0][threadIdx.x] = s;
+  red[1][threadIdx.x] = d;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    if ((int)threadIdx.x < h) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + h];
+      red[1][threadIdx.x] += red[1][threadIdx.x + h];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) tr[f] = red[0];
+  if (threadIdx.x == 0) {
+    tr[2 * f] = red[0][0];
+    tr[2 * f + 1] = red[1][0];
+  }
 }
 
 __device__ __forceinline__ double softplus_d(double x) { return fmax(x, 0.0) + log1p(exp(-fabs(x))); }

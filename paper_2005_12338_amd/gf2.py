@@ -121,6 +121,10 @@ _SIGS = {
                                           C.POINTER(C.c_double), C.c_double, C.POINTER(Sampling), C.c_int,
                                           C.c_double, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.POINTER(AdaptiveResult)]),
+    "gf2_screen_ijA": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int, C.c_double, C.c_void_p,
+                                 C.POINTER(C.c_int64)]),
+    "gf2_split_large": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_double,
+                                  C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "gf2_dyson": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double, C.c_double, C.c_int64, C.POINTER(C.c_double),
                             C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gf2_electron_count": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double, C.c_double, C.c_int64,
@@ -213,6 +217,7 @@ class Split:
     b_ptr: int
     dtype: int
     ctx: "Context"
+    large: object = None      # the tensor the large part is read from (kept alive with the handle)
 
     def free(self):
         if self.handle:
@@ -301,6 +306,27 @@ class Context:
         self._check(self.lib.gf2_split(self.h, B.data_ptr(), dt, n, naux, float(eps), C.byref(h),
                                        C.byref(nnz), C.byref(wmax)))
         return Split(h, n, naux, nnz.value, wmax.value, B.data_ptr(), dt, self)
+
+    def screen_ijA(self, ijA, eps_prime: float):
+        """eq:V_ijA on device (ij|A) [naux][n][n]: (screened copy, kept count)."""
+        naux, n, _ = ijA.shape
+        out = self.torch.empty_like(ijA)
+        nnz = C.c_int64()
+        self._check(self.lib.gf2_screen_ijA(self.h, n, naux, ijA.data_ptr(), _dtype(ijA), float(eps_prime),
+                                            out.data_ptr(), C.byref(nnz)))
+        return out, nnz.value
+
+    def split_large(self, B, KL, eps: float) -> Split:
+        """The split whose large part comes from KL (screened front end)."""
+        naux, n, _ = B.shape
+        if KL.shape != B.shape or KL.dtype != B.dtype:
+            raise ValueError("KL must match B in shape and dtype")
+        h = C.c_void_p()
+        nnz = C.c_int64()
+        wmax = C.c_int64()
+        self._check(self.lib.gf2_split_large(self.h, B.data_ptr(), KL.data_ptr(), _dtype(B), n, naux, float(eps),
+                                             C.byref(h), C.byref(nnz), C.byref(wmax)))
+        return Split(h, n, naux, nnz.value, wmax.value, B.data_ptr(), _dtype(B), self, KL)
 
     # ---------------------------------------------------------------- G
     def green_tau(self, F: np.ndarray, tau: np.ndarray, beta: float, mu: float = 0.0, n_occ: int = 0,
