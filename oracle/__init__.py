@@ -21,4 +21,5 @@ Modules
   proposal    importance proposal over the auxiliary index (project form)
   variants    control-variate and double-sum forms of the eq:sigma_2 average
   scf         Matsubara transforms, Dyson, mu tuning, RI Fock build (Section III)
+  qp          quasiparticle energies: Pade continuation of the orbital self-energy
 """
