@@ -353,6 +353,21 @@ gf2_status gf2_energy_noalloc(gf2_ctx* ctx, int64_t n, int64_t ntau, const doubl
  * gf2_scf_step: one update of the loop around the self-energy: mu tuned
  *   to n_elec (gf2_tune_mu), G, Gbar, G(beta-) at that mu (gf2_dyson), and
  *   the new Fock matrix (gf2_fock).  Outputs as above; *mu_out host. */
+/* gf2_qp_energies: quasiparticle energies in the diagonal approximation
+ *   (the Conclusions' excited-state direction; the method is this library's
+ *   reading).  For every orbital k of (F, S): the orbital self-energy
+ *   s_k(i w_f) = c_k^T Sigma(i w_f) c_k on the first n_pade Matsubara
+ *   frequencies (the quadrature above), its n_pade-point Pade continuation
+ *   (Thiele continued fraction, Vidberg-Serene recursion), and the fixed
+ *   point of E = eps_k + Re s_k(E - mu + i eta) from E = eps_k, stopped at
+ *   |dE| <= 1e-13 or after max_iter steps.  E host [n] (ascending eps
+ *   order); converged host [n] (1 where the tolerance was met) or NULL.
+ *   Errors: GF2_E_ARG (n_pade outside [1, 4096], max_iter < 1),
+ *   GF2_E_NUMERIC (a non-finite energy). */
+gf2_status gf2_qp_energies(gf2_ctx* ctx, int64_t n, const double* F, const double* S,
+                           double mu, double beta, int64_t ntau, const double* tau,
+                           const double* w, const double* Sigma, int32_t n_pade, double eta,
+                           int32_t max_iter, double* E, int32_t* converged);
 gf2_status gf2_dyson(gf2_ctx* ctx, int64_t n, const double* F, const double* S, double mu,
                      double beta, int64_t ntau, const double* tau, const double* w,
                      const double* Sigma, int64_t nw, double* G, double* Gbar,

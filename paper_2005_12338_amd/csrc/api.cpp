@@ -2028,7 +2028,8 @@ constexpr size_t kScfChunkBytes = size_t(1) << 31;   // Dyson matrices of one fr
 // Upload C (padded) and C^T, transform Sigma(tau) to Sigma~ = C^T Sigma C on
 // the FP64 MFMA GEMM, and tabulate the phases of both transforms.
 void scf_prepare(gf2_ctx* ctx, ScfGrid& g, int64_t n, const double* F, const double* S, double beta, int64_t ntau,
-                 const double* tau, const double* w, const double* Sigma, int64_t nw, bool need_back) {
+                 const double* tau, const double* w, const double* Sigma, int64_t nw, bool need_back,
+                 bool dyson = true) {
   GF2_REQUIRE(n > 0 && F && tau && w && Sigma && ntau > 0 && nw > 0, GF2_E_ARG, "bad Dyson arguments");
   GF2_REQUIRE(beta > 0 && std::isfinite(beta), GF2_E_ARG, "beta must be positive");
   for (int64_t t = 0; t < ntau; ++t)
@@ -2041,7 +2042,9 @@ void scf_prepare(gf2_ctx* ctx, ScfGrid& g, int64_t n, const double* F, const dou
   g.beta = beta;
   g.tau.assign(tau, tau + ntau);
   const int64_t np = g.np, np2 = np * np, fg = scf_freq_group(), og = scf_time_group();
-  g.nc = std::max<int64_t>(1, std::min<int64_t>({nw, 4096, (int64_t)(kScfChunkBytes / (size_t)(16 * np2))}));
+  // one chunk of all nw frequencies when no Dyson matrices are formed
+  g.nc = dyson ? std::max<int64_t>(1, std::min<int64_t>({nw, 4096, (int64_t)(kScfChunkBytes / (size_t)(16 * np2))}))
+               : nw;
   g.ncp = (g.nc + fg - 1) / fg * fg;
   g.nchunk = (nw + g.nc - 1) / g.nc;
   g.nto = ntau + 1;
@@ -2122,6 +2125,10 @@ void scf_prepare(gf2_ctx* ctx, ScfGrid& g, int64_t n, const double* F, const dou
   if (need_back) {
     g.cs = (double*)ctx_buf(ctx, "scf_cs", cs.size() * 8);
     h2d(ctx, g.cs, cs.data(), cs.size());
+  }
+  if (!dyson) {
+    GF2_HIP(hipStreamSynchronize(ctx->stream));
+    return;
   }
   const int64_t nb = scf_panel();
   g.a = (double*)ctx_buf(ctx, "scf_a", (size_t)(g.nc * 2 * np2) * 8);
@@ -2374,6 +2381,34 @@ gf2_status gf2_tune_mu(gf2_ctx* ctx, int64_t n, const double* F, const double* S
     ScfGrid g;
     scf_prepare(ctx, g, n, F, S, beta, ntau, tau, w, Sigma, nw, false);
     *mu_out = scf_tune(ctx, g, n_elec, mu_lo, mu_hi, n_e);
+  });
+}
+
+gf2_status gf2_qp_energies(gf2_ctx* ctx, int64_t n, const double* F, const double* S, double mu, double beta,
+                           int64_t ntau, const double* tau, const double* w, const double* Sigma, int32_t n_pade,
+                           double eta, int32_t max_iter, double* E, int32_t* converged) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(E && n_pade >= 1 && n_pade <= 4096 && max_iter >= 1 && std::isfinite(mu) && std::isfinite(eta),
+                GF2_E_ARG, "bad quasiparticle arguments");
+    ScfGrid g;
+    scf_prepare(ctx, g, n, F, S, beta, ntau, tau, w, Sigma, n_pade, false, false);
+    auto* deps = (double*)ctx_buf(ctx, "qp_eps", (size_t)n * 8);
+    auto* work = ctx_buf(ctx, "qp_work", (size_t)(n * 2 * n_pade) * 16);
+    auto* de = (double*)ctx_buf(ctx, "qp_e", (size_t)n * 8);
+    auto* dc = (int32_t*)ctx_buf(ctx, "qp_conv", (size_t)n * 4);
+    h2d(ctx, deps, g.eps.data(), g.eps.size());
+    {
+      ProfScope ps(ctx, "qp");
+      launch_qp(g.sig, ntau, g.np, n, g.ph, n_pade, (int32_t)g.ncp, g.om, deps, mu, eta, max_iter, work, de, dc,
+                ctx->stream);
+    }
+    GF2_HIP(hipGetLastError());
+    std::vector<int32_t> ch((size_t)n);
+    d2h(ctx, E, de, (size_t)n);
+    d2h(ctx, ch.data(), dc, ch.size());
+    if (converged) std::copy(ch.begin(), ch.end(), converged);
+    for (int64_t k = 0; k < n; ++k)
+      GF2_REQUIRE(std::isfinite(E[k]), GF2_E_NUMERIC, "non-finite quasiparticle energy");
   });
 }
 

@@ -111,6 +111,10 @@ void launch_bq_dot(const void* b, bool f64, int64_t n, int64_t naux, const doubl
 void launch_fock_final(const void* b, bool f64, int64_t n, int64_t naux, const double* c, const double* h,
                        const double* kp, int64_t ng, int64_t np, double* f, hipStream_t st);
 void launch_density(const double* gbeta, int64_t nn, double* p, hipStream_t st);
+// Quasiparticle energies: work holds 2 m complex (32 bytes) per orbital.
+void launch_qp(const double* sig, int64_t ntau, int64_t np, int64_t n, const double* ph, int32_t m, int32_t ncp,
+               const double* om, const double* eps, double mu, double eta, int32_t iters, void* work, double* e_out,
+               int32_t* conv, hipStream_t st);
 
 struct gf2_mlp;
 int mlp_nparam();

@@ -401,6 +401,79 @@ __global__ void k_g_mo(const double* pc, const double* ps, int64_t np, int64_t n
   out[(ntau + o) * np2 + e] = gb;
 }
 
+// ------------------------------------------------------ quasiparticles --
+
+struct cplx {
+  double r, i;
+};
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.r - b.r, a.i - b.i}; }
+__device__ __forceinline__ cplx cmulc(cplx a, cplx b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ cplx cdivc(cplx a, cplx b) {
+  const double d = b.r * b.r + b.i * b.i;
+  return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
+}
+
+// Thiele continued fraction through (z_p, a_p), p < m, at z (the convergent
+// recurrence A_p = A_{p-1} + (z - z_{p-1}) a_p A_{p-2}, B likewise).
+__device__ cplx pade_at(const cplx* a, const double* om, int m, cplx z) {
+  cplx am2 = {0.0, 0.0}, am1 = a[0], bm2 = {1.0, 0.0}, bm1 = {1.0, 0.0};
+  for (int p = 1; p < m; ++p) {
+    const cplx t = cmulc(cplx{z.r, z.i - om[p - 1]}, a[p]);
+    const cplx an = cadd(am1, cmulc(t, am2)), bn = cadd(bm1, cmulc(t, bm2));
+    am2 = am1;
+    am1 = an;
+    bm2 = bm1;
+    bm1 = bn;
+  }
+  return cdivc(am1, bm1);
+}
+
+// One thread per orbital k: s_k(i w_f) = sum_t ph[t][f] Sigma~_kk(tau_t) for
+// f < m, the Pade coefficients through (i w_f, s_k), and the fixed point of
+// E = eps_k + Re C(E - mu + i eta) from E = eps_k, stopped at |dE| <= 1e-13.
+// work: [n][2 m] complex.
+__global__ void k_qp(const double* __restrict__ sig, int64_t ntau, int64_t np, int64_t n,
+                     const double* __restrict__ ph, int32_t m, int32_t ncp, const double* __restrict__ om,
+                     const double* __restrict__ eps, double mu, double eta, int32_t iters, cplx* work,
+                     double* e_out, int32_t* conv) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  cplx* g = work + k * 2 * m;
+  cplx* a = g + m;
+  const int64_t np2 = np * np;
+  for (int f = 0; f < m; ++f) g[f] = {0.0, 0.0};
+  for (int64_t t = 0; t < ntau; ++t) {
+    const double x = sig[t * np2 + k * np + k];
+    for (int f = 0; f < m; ++f) {
+      g[f].r = fma(ph[(t * ncp + f) * 2], x, g[f].r);
+      g[f].i = fma(ph[(t * ncp + f) * 2 + 1], x, g[f].i);
+    }
+  }
+  for (int p = 0; p < m; ++p) a[p] = {0.0, 0.0};
+  a[0] = g[0];
+  for (int p = 1; p < m; ++p) {
+    if (a[p - 1].r == 0.0 && a[p - 1].i == 0.0) break;     // the fraction ends
+    const cplx prev = g[p - 1];
+    for (int f = p; f < m; ++f) g[f] = cdivc(csub(prev, g[f]), cmulc(cplx{0.0, om[f] - om[p - 1]}, g[f]));
+    a[p] = g[p];
+  }
+  const double e0 = eps[k];
+  double e = e0;
+  int ok = 0;
+  for (int it = 0; it < iters; ++it) {
+    const double en = e0 + pade_at(a, om, m, cplx{e - mu, eta}).r;
+    const bool done = fabs(en - e) <= 1e-13;
+    e = en;
+    if (done) {
+      ok = 1;
+      break;
+    }
+  }
+  e_out[k] = e;
+  conv[k] = ok;
+}
+
 // ----------------------------------------------------------------- Fock --
 
 // Padded FP64 copies of B^Q for Q in [q0, q0 + qc) (zero for Q >= naux).
@@ -519,6 +592,13 @@ void launch_bq_dot(const void* b, bool f64, int64_t n, int64_t naux, const doubl
 void launch_fock_final(const void* b, bool f64, int64_t n, int64_t naux, const double* c, const double* h,
                        const double* kp, int64_t ng, int64_t np, double* f, hipStream_t st) {
   hipLaunchKernelGGL(k_fock_final, dim3(nblk(n * n)), dim3(256), 0, st, b, (int)f64, n, naux, c, h, kp, ng, np, f);
+}
+
+void launch_qp(const double* sig, int64_t ntau, int64_t np, int64_t n, const double* ph, int32_t m, int32_t ncp,
+               const double* om, const double* eps, double mu, double eta, int32_t iters, void* work, double* e_out,
+               int32_t* conv, hipStream_t st) {
+  hipLaunchKernelGGL(k_qp, dim3(nblk(n, 64)), dim3(64), 0, st, sig, ntau, np, n, ph, m, ncp, om, eps, mu, eta, iters,
+                     (cplx*)work, e_out, conv);
 }
 
 void launch_density(const double* gbeta, int64_t nn, double* p, hipStream_t st) {

@@ -125,6 +125,9 @@ _SIGS = {
                                  C.POINTER(C.c_int64)]),
     "gf2_split_large": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_double,
                                   C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "gf2_qp_energies": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double, C.c_double, C.c_int64, C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double), C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_double),
+                                  C.POINTER(C.c_int32)]),
     "gf2_dyson": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double, C.c_double, C.c_int64, C.POINTER(C.c_double),
                             C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gf2_electron_count": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double, C.c_double, C.c_int64,
@@ -382,6 +385,18 @@ class Context:
                                          tau.shape[0], _dp(tau), _dp(w), Sigma.data_ptr(), int(nw),
                                          float(n_elec), float(lo), float(hi), C.byref(mu), C.byref(ne)))
         return mu.value, ne.value
+
+    def qp_energies(self, F, S, mu, beta, tau, w, Sigma, n_pade, eta=1e-9, max_iter=200):
+        """Quasiparticle energies (gf2_qp_energies): (E [n], converged [n])."""
+        F, S, tau, w = self._f64(F), self._f64(S), self._f64(tau), self._f64(w)
+        n = F.shape[0]
+        e = np.empty(n)
+        ok = np.zeros(n, dtype=np.int32)
+        self._check(self.lib.gf2_qp_energies(self.h, n, _dp(F), None if S is None else _dp(S), float(mu),
+                                             float(beta), tau.shape[0], _dp(tau), _dp(w), Sigma.data_ptr(),
+                                             int(n_pade), float(eta), int(max_iter), _dp(e),
+                                             ok.ctypes.data_as(C.POINTER(C.c_int32))))
+        return e, ok.astype(bool)
 
     def fock(self, B, h, Gbeta):
         """eq:F on the RI factors, P = -2 G(beta-) (gf2_fock); host [n][n]."""
