@@ -2013,7 +2013,7 @@ struct ScfGrid {
   std::vector<double> eps, c, tau;
   double* sig = nullptr;     // Sigma~(tau) [ntau][np][np]
   double* ph = nullptr;      // [nchunk][ntau][ncp][2]: w_t (cos, sin)(w_f tau_t)
-  double* cs = nullptr;      // [nchunk][ntop][ncp][2]: (cos, sin)(w_f tau_o), tau_ntau = beta
+  double* cs = nullptr;      // [nchunk][ncp][ntop][2]: (cos, sin)(w_f tau_o), tau_ntau = beta
   double* om = nullptr;      // [nchunk][ncp]
   double* a = nullptr;       // [nc][2][np][np]
   double* colbuf = nullptr;  // [nc][2][np][32]
@@ -2113,7 +2113,7 @@ void scf_prepare(gf2_ctx* ctx, ScfGrid& g, int64_t n, const double* F, const dou
       if (need_back)
         for (int64_t o = 0; o < g.nto; ++o) {
           const double x = wf * (o < ntau ? tau[o] : beta);
-          double* p = &cs[((ch * g.ntop + o) * g.ncp + f) * 2];
+          double* p = &cs[((ch * g.ncp + f) * g.ntop + o) * 2];
           p[0] = std::cos(x);
           p[1] = std::sin(x);
         }

@@ -208,6 +208,24 @@ __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_
   const double* cbi = cbr + np * kNB;
   const double* pr_ = pbuf + mat * 2 * kNB * kNB;
   const double* pi_ = pr_ + kNB * kNB;
+  const int lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+  const int lr = lane & 15, lg = lane >> 4;
+  // the tile's old values, loaded first so that their latency overlaps the
+  // staging and the MFMAs (accumulator r of a lane: row lane / 16 + 4 r,
+  // column lane % 16)
+  double oldr[2][2][4], oldi[2][2][4];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = i0 + 32 * wr + 16 * bi + lg + 4 * r;
+        const int64_t gj = j0 + 32 * wc + 16 * bj + lr;
+        const bool live = gi < np && gj < np && !(gi >= k0 && gi < k0 + kNB) && !(gj >= k0 && gj < k0 + kNB);
+        oldr[bi][bj][r] = live ? ar[gi * np + gj] : 0.0;
+        oldi[bi][bj][r] = live ? ai[gi * np + gj] : 0.0;
+      }
   for (int x = tid; x < kTW * kNB; x += 256) {
     const int r = x / kNB, c = x % kNB;
     const int64_t i = i0 + r;
@@ -231,8 +249,6 @@ __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_
     rs[1][r][c] = vi;
   }
   __syncthreads();
-  const int lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
-  const int lr = lane & 15, lg = lane >> 4;
   f64x4_t accr[2][2], acci[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -264,7 +280,6 @@ __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_
         acci[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi[bi], yr[bj], acci[bi][bj], 0, 0, 0);
       }
   }
-  // accumulator r of a lane holds row (lane / 16) + 4 r, column lane % 16
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -283,15 +298,16 @@ __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_
           }
           continue;
         }
-        const double br = kj ? 0.0 : ar[o], bim = kj ? 0.0 : ai[o];
-        ar[o] = br - accr[bi][bj][r];
-        ai[o] = bim - acci[bi][bj][r];
+        ar[o] = oldr[bi][bj][r] - accr[bi][bj][r];
+        ai[o] = oldi[bi][bj][r] - acci[bi][bj][r];
       }
 }
 
 // D(i w_f) = A^{-1} - G0~(i w_f) (G0~ = diag 1 / (mu - eps_i + i w_f), zero
 // on the padding) accumulated into the back-transform sums
-//   pc[o] += sum_f cs[o][f].cos Re D_f,  ps[o] += sum_f cs[o][f].sin Im D_f.
+//   pc[o] += sum_f cs[f][o].cos Re D_f,  ps[o] += sum_f cs[f][o].sin Im D_f
+// (cs [nc][ntop][2]: one frequency's phases are contiguous, read as
+// wave-uniform wide scalar loads).
 __global__ __launch_bounds__(256) void k_iw_back(const double* __restrict__ a, int32_t nc, int64_t np, int64_t n,
                                                   const double* __restrict__ shift, const double* __restrict__ om,
                                                   const double* __restrict__ cs, int32_t nto, int32_t ncp,
@@ -306,9 +322,11 @@ __global__ __launch_bounds__(256) void k_iw_back(const double* __restrict__ a, i
   const bool dg = i == j && i < n, pad = i == j && i >= n;
   const double s = dg ? shift[i] : 0.0;
   const int o0 = g * kOG;
+  const int64_t ntop = (int64_t)((nto + kOG - 1) / kOG) * kOG;
   double qc[kOG], qs[kOG];
 #pragma unroll
   for (int o = 0; o < kOG; ++o) qc[o] = qs[o] = 0.0;
+#pragma unroll 2
   for (int f = 0; f < nc; ++f) {
     double dr = a[(int64_t)(2 * f) * np2 + e], di = a[(int64_t)(2 * f + 1) * np2 + e];
     if (dg) {
@@ -318,11 +336,11 @@ __global__ __launch_bounds__(256) void k_iw_back(const double* __restrict__ a, i
     } else if (pad) {
       dr -= 1.0;
     }
-    const double* p = cs + ((int64_t)o0 * ncp + f) * 2;
+    const double* p = cs + ((int64_t)f * ntop + o0) * 2;
 #pragma unroll
     for (int o = 0; o < kOG; ++o) {
-      qc[o] = fma(p[(int64_t)o * ncp * 2], dr, qc[o]);
-      qs[o] = fma(p[(int64_t)o * ncp * 2 + 1], di, qs[o]);
+      qc[o] = fma(p[2 * o], dr, qc[o]);
+      qs[o] = fma(p[2 * o + 1], di, qs[o]);
     }
   }
 #pragma unroll
