@@ -158,41 +158,25 @@ class Problem:
 
 
 PROPOSAL_ALPHA = 0.05     # floor: every Q keeps at least alpha / N_aux of the weight
-PROPOSAL_CLASSES = 12     # stratified classes Q mod K
 
 
 def train_proposal(ctx, eps, beta, steps=2000, ntau=16):
-    """Train the network on the per-Q targets of the small training chains
-    (10..48 dimers) with the library's training kernels.  Returns
-    (mlp, seconds, first loss, last loss)."""
+    """Train the proposal on the small training chains (10..48 dimers) with
+    the library's kernels: the network on the per-Q targets, then the class
+    count of the stratified vectors on the measured per-pair spread.
+    Returns (mlp, K, seconds, first loss, last loss, {K: variance ratio})."""
     import torch
     import chain_inputs as ci
-    from paper_2005_12338_amd import gf2
+    from paper_2005_12338_amd import training
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    phis, ts, off = [], [], [0]
-    for nd in ci.training_dimer_counts():
-        geo = ci.chain_geometry(nd)
-        f = ci.fock_tight_binding(geo.x)
-        B = ctx.build_B(geo.n, geo.naux, geom=geo, dtype=torch.float32)
-        spl = ctx.split(B, eps)
-        tau, w = gf2.gf2_tau_grid(beta, ntau)
-        G, Gb, _ = ctx.green_tau(f, tau, beta, n_occ=geo.n // 2)
-        _, Gb0, _ = ctx.green_tau(f, np.array([0.0]), beta, n_occ=geo.n // 2)
-        phi = torch.empty((geo.naux, 4), dtype=torch.float64, device="cuda")
-        ctx.proposal_features(spl, B, geo.x, geo.xq, Gb0[0].contiguous(), phi)
-        t = torch.empty(geo.naux, dtype=torch.float64, device="cuda")
-        ctx.proposal_targets(spl, B, G, Gb, w, 1e-10, t)
-        phis.append(phi)
-        ts.append(t / t.sum())
-        off.append(off[-1] + geo.naux)
-        spl.free()
-    m = ctx.mlp()
-    phi_all, t_all = torch.cat(phis).contiguous(), torch.cat(ts).contiguous()
-    ctx.proposal_init(m, phi_all, seed=0)
-    hist = ctx.proposal_train(m, np.array(off), phi_all, t_all, steps=steps, lr=1e-2)
+    chains = [training.training_chain(ctx, nd, eps, beta, ntau) for nd in ci.training_dimer_counts()]
+    m, hist = training.train_network(ctx, chains, steps=steps)
+    k, ratio = training.select_classes(ctx, chains, m)
+    for c in chains:
+        c["spl"].free()
     torch.cuda.synchronize()
-    return m, time.perf_counter() - t0, float(hist[0]), float(hist[-1])
+    return m, k, time.perf_counter() - t0, float(hist[0]), float(hist[-1]), ratio
 
 
 def gemm_reference(args):
@@ -250,11 +234,11 @@ def learned_bench(args):
     ctx = gf2.Context(0)
     pb = Problem(ctx, wl)
     log(f"[bench] workload {wl.name}: N={wl.n} Naux={wl.naux} ntau={wl.ntau} eps={wl.eps}")
-    mlp, t_train, l0, l1 = train_proposal(ctx, wl.eps, wl.beta)
-    log(f"[bench] proposal network trained in {t_train:.2f} s (loss {l0:.4f} -> {l1:.4f})")
+    mlp, k_cls, t_train, l0, l1, _ = train_proposal(ctx, wl.eps, wl.beta)
+    log(f"[bench] proposal trained in {t_train:.2f} s (loss {l0:.4f} -> {l1:.4f}; {k_cls} classes)")
     rows = {}
     target = args.target_meh * 1e-3
-    learned = dict(mlp=mlp, classes=PROPOSAL_CLASSES)
+    learned = dict(mlp=mlp, classes=k_cls)
     for name, prec, kw in (("fp32_pm1", "fp32", {}), ("bf16_pm1", "bf16", {}), ("auto_pm1", "auto", {}),
                            ("auto_learned_stratified", "auto", learned),
                            ("bf16_learned_stratified", "bf16", learned)):
@@ -698,12 +682,14 @@ def main():
         # network trained on the small chains (training is a one-off cost,
         # reported on its own), against +-1 vectors, at this target and at
         # a tight one where the number of pairs matters
-        mlp, t_train, l0, l1 = train_proposal(ctx, wl.eps, wl.beta)
-        log(f"[bench] proposal network trained in {t_train:.2f} s (loss {l0:.4f} -> {l1:.4f})")
-        learned = {"train_s": t_train, "loss_first": l0, "loss_last": l1, "classes": PROPOSAL_CLASSES}
+        mlp, k_cls, t_train, l0, l1, k_ratio = train_proposal(ctx, wl.eps, wl.beta)
+        log(f"[bench] proposal trained in {t_train:.2f} s (loss {l0:.4f} -> {l1:.4f}); class count {k_cls} "
+            f"(training-chain variance ratio to +-1: {k_ratio[k_cls]:.3f})")
+        learned = {"train_s": t_train, "loss_first": l0, "loss_last": l1, "classes": k_cls,
+                   "class_variance_ratios": {str(k): v for k, v in k_ratio.items()}}
         for tgt in (target, args.tight_target_ueh * 1e-6):
             row = {}
-            for name, kw in (("uniform_pm1", {}), ("learned_stratified", dict(mlp=mlp, classes=PROPOSAL_CLASSES))):
+            for name, kw in (("uniform_pm1", {}), ("learned_stratified", dict(mlp=mlp, classes=k_cls))):
                 if tgt == target:
                     pb.time_to_target("auto", tgt, **kw)           # warm (the tight runs reuse it)
                 t_s, info = pb.time_to_target("auto", tgt, **kw)
