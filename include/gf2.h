@@ -463,17 +463,20 @@ gf2_status gf2_sigma_batch(gf2_ctx* ctx, int32_t nitem, const gf2_batch_item* it
  * pairs - 1 degrees of freedom; 1.80x the estimate at 8 pairs, 1.26x at 32),
  * so a small first batch cannot stop on a lucky low estimate.
  *
- * prec GF2_PREC_AUTO: the two-level estimator.  Pairs 0 .. k-1
- * (k = min(8, max_pairs)) run in BF16 and in BF16X3, then the batches in
- * BF16; at the end Sigma and the per-pair traces are moved by the mean
- * BF16X3 - BF16 difference d of the k probe pairs (scaled to all pairs),
- * which removes the BF16 rounding bias in expectation.  If twice the
- * standard error of that mean, std(d_E)/sqrt(k), is >= 0.1 x the standard
- * error reached, or, for some tau, twice the standard error of the mean
- * trace difference is >= the larger of 0.1 x the standard error of that
- * tau's mean trace and 1e-5 x the trace Tr(Sigma(tau) Gbar(tau)), every
- * pair is recomputed in BF16X3 (same theta) and sampling continues in
- * BF16X3.  res->precision reports BF16C or BF16X3; res->bias_probe the
+ * prec GF2_PREC_AUTO: the two-level estimator.  Pairs 0 .. k-1 (the
+ * probe, first k = min(2, max_pairs)) run in BF16 and in BF16X3, the rest
+ * in BF16 (the first batch filled up to sampling->ns pairs); at the end
+ * Sigma and the per-pair traces are moved by the mean BF16X3 - BF16
+ * difference d of the k probe pairs (scaled to all pairs), which removes
+ * the BF16 rounding bias in expectation.  The correction is accepted when
+ * twice the standard error of that mean, std(d_E)/sqrt(k), is below 0.1 x
+ * the standard error reached and, for every tau, twice the standard error
+ * of the mean trace difference is below the larger of 0.1 x the standard
+ * error of that tau's mean trace and 1e-5 x the trace Tr(Sigma(tau)
+ * Gbar(tau)).  If it is not, the probe grows to min(8, pairs) pairs (their
+ * BF16X3 runs added); if it still is not, every pair is taken in BF16X3
+ * (same theta: the probe pairs from the probe, the others recomputed) and
+ * sampling continues in BF16X3.  res->precision reports BF16C or BF16X3; res->bias_probe the
  * |mean d_E| removed.  batch must be >= 2.
  *
  * Inputs as gf2_sigma_stoch; w host [ntau] quadrature weights; Sigma_det

@@ -25,6 +25,7 @@ namespace {
 
 constexpr double kGM = 0.5;   // E = -1/2 int Tr(Sigma Gbar): the MP2 limit fixes it
 constexpr int64_t kLevelProbe = 8;   // pairs run at both levels (BF16 and BF16X3) by BF16C and AUTO
+constexpr int64_t kAutoProbe0 = 2;   // AUTO's first probe; it grows to kLevelProbe where needed
 
 // ------------------------------------------------------------ scratch ----
 // Named device buffers owned by the context (grown on demand, never shrunk,
@@ -750,13 +751,30 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
   c.tcnt = force_tcnt > 0 ? std::min(force_tcnt, ntau) : std::max<int64_t>(1, std::min<int64_t>(ntau, slots / c.sc));
   c.slots = slots = c.sc * c.tcnt;
 
-  // The products run over the zero padding of every np x np matrix, so a
-  // change of layout clears all chain buffers (new allocations are zeroed).
+  // The products run over the zero padding of every np x np matrix, and the
+  // kernels write only the n x n part: every byte a chain buffer is used
+  // with under the current layout (n, np, precision) must have been cleared
+  // under that layout.  A change of layout forgets what was cleared; a later
+  // call that uses more of a buffer (more slots or vectors) clears the rest.
   const std::string key = std::to_string(n) + ":" + std::to_string(np) + ":" + std::to_string((int)prec);
   std::string& prev = ctx->chain_keys[pfx];
-  const bool reset = prev != key;
+  std::map<std::string, size_t>& cleared = ctx->chain_cleared[pfx];
+  if (prev != key) cleared.clear();
   prev = key;
-  auto CB = [&](const char* tag, size_t bytes) { return (char*)ctx_buf(ctx, pfx + tag, bytes, reset); };
+  auto zbuf = [&](const std::string& tag, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    const bool grows = ctx->bufs[tag].bytes < bytes;       // a new allocation comes back zeroed
+    char* p = (char*)ctx_buf(ctx, tag, bytes);
+    size_t& z = cleared[tag];
+    if (grows) {
+      z = bytes;
+    } else if (bytes > z) {
+      GF2_HIP(hipMemsetAsync(p + z, 0, bytes - z, ctx->stream));
+      z = bytes;
+    }
+    return p;
+  };
+  auto CB = [&](const char* tag, size_t bytes) { return zbuf(pfx + tag, bytes); };
 
   // ---- G, Gbar in padded storage format and FP64
   char* gst = CB("c_gst", sb * ntau);
@@ -821,7 +839,7 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
   GF2_HIP(hipGetLastError());
 
   // per-slot scratch
-  auto S = [&](const char* tag, size_t bytes) { return (char*)ctx_buf(ctx, pfx + tag, bytes * slots, reset); };
+  auto S = [&](const char* tag, size_t bytes) { return zbuf(pfx + tag, bytes * slots); };
   char *ul_n = S("c_uln", sb), *ul_t = S("c_ult", sb), *us_n = S("c_usn", sb), *us_t = S("c_ust", sb);
   char *vl_n = S("c_vln", sb), *vs_n = S("c_vsn", sb), *vs_t = S("c_vst", sb), *vsum_t = S("c_vsumt", sb);
   char* mst = S("c_mst", 4 * sb);
@@ -1695,35 +1713,45 @@ void adaptive_core(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const 
     // pairs also run in BF16X3.  Their differences d_q = BF16X3 - BF16 (per
     // pair energy and per-tau trace) estimate the BF16 rounding bias, which
     // is removed from the final mean; the correction's own uncertainty is
-    // std(d)/sqrt(kp).
-    const int64_t kp = autop ? std::min<int64_t>(kLevelProbe, max_pairs) : 0;
+    // std(d)/sqrt(kp).  The probe starts with kAutoProbe0 pairs and grows to
+    // kLevelProbe only when the correction is not precise enough at the
+    // error reached (loose targets stop after the small probe).
+    const int64_t kmax = autop ? std::min<int64_t>(kLevelProbe, max_pairs) : 0;
+    int64_t kp = autop ? std::min<int64_t>(kAutoProbe0, kmax) : 0;
     double* psum16 = nullptr;
     double* psum3 = nullptr;
     double* eprobe = nullptr;
+    double* psum16x = nullptr;                // BF16 sums of probe pairs that also sit in `sum`
     std::vector<double> dE, de;              // per probe pair: energy, and [kp][ntau] traces
     double bias = 0.0;
     int64_t pairs = 0;
+    // BF16 into `lo` and BF16X3 into psum3 for probe pairs [k0, k1); their
+    // trace differences appended to dE / de
+    auto probe = [&](int64_t k0, int64_t k1, double* lo) {
+      smp.s0 = k0;
+      smp.ns = k1 - k0;
+      run_stoch(ctx, split, B, G, Gbar, ntau, &smp, Prec::BF16, lo, e_samples + k0 * ntau);
+      run_stoch(ctx, split, B, G, Gbar, ntau, &smp, Prec::BF16X3, psum3, eprobe + k0 * ntau);
+      const int64_t cnt = k1 - k0;
+      std::vector<double> lv((size_t)(cnt * ntau)), hv((size_t)(cnt * ntau));
+      d2h(ctx, lv.data(), e_samples + k0 * ntau, lv.size());
+      d2h(ctx, hv.data(), eprobe + k0 * ntau, hv.size());
+      dE.resize((size_t)k1, 0.0);
+      de.resize((size_t)(k1 * ntau), 0.0);
+      for (int64_t q = 0; q < cnt; ++q)
+        for (int64_t t = 0; t < ntau; ++t) {
+          de[(k0 + q) * ntau + t] = hv[q * ntau + t] - lv[q * ntau + t];
+          dE[k0 + q] += -kGM * w[t] * de[(k0 + q) * ntau + t];
+        }
+      double m = 0.0;
+      for (int64_t q = 0; q < k1; ++q) m += dE[q];
+      bias = std::fabs(m / (double)k1);
+    };
     if (autop) {
       psum16 = (double*)ctx_buf(ctx, "a_probe_lo", mat * 8, true);
       psum3 = (double*)ctx_buf(ctx, "a_probe_hi", mat * 8, true);
-      eprobe = (double*)ctx_buf(ctx, "a_probe_e", (size_t)(kp * ntau) * 8);
-      smp.s0 = 0;
-      smp.ns = kp;
-      run_stoch(ctx, split, B, G, Gbar, ntau, &smp, Prec::BF16, psum16, e_samples);
-      run_stoch(ctx, split, B, G, Gbar, ntau, &smp, Prec::BF16X3, psum3, eprobe);
-      std::vector<double> lo((size_t)(kp * ntau)), hi((size_t)(kp * ntau));
-      d2h(ctx, lo.data(), e_samples, lo.size());
-      d2h(ctx, hi.data(), eprobe, hi.size());
-      dE.assign((size_t)kp, 0.0);
-      de.assign((size_t)(kp * ntau), 0.0);
-      for (int64_t q = 0; q < kp; ++q)
-        for (int64_t t = 0; t < ntau; ++t) {
-          de[q * ntau + t] = hi[q * ntau + t] - lo[q * ntau + t];
-          dE[q] += -kGM * w[t] * de[q * ntau + t];
-        }
-      double m = 0.0;
-      for (int64_t q = 0; q < kp; ++q) m += dE[q];
-      bias = std::fabs(m / (double)kp);
+      eprobe = (double*)ctx_buf(ctx, "a_probe_e", (size_t)(kmax * ntau) * 8);
+      probe(0, kp, psum16);
       pairs = kp;
     }
     // sample mean and standard error of the mean of x[0..k)
@@ -1754,29 +1782,49 @@ void adaptive_core(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const 
       return true;
     };
     double h[4] = {0, 0, 0, 0};
+    const int64_t first = std::max<int64_t>(2, std::min(batch, max_pairs));   // the first test, as without AUTO
     while (true) {
-      if (pairs >= 2) {
+      if (pairs >= first) {
         stat(pairs, h);
         bool done = stderr_upper(h[2], pairs) < target || pairs >= max_pairs;
+        if (done && autop && wp == Prec::BF16 && !bf16_ok(pairs, h[2]) && kp < std::min(kmax, pairs)) {
+          // a larger probe: pairs [kp, k1) ran in BF16 inside `sum`; their
+          // BF16 sums go to psum16x and are taken out again by the correction
+          const int64_t k1 = std::min(kmax, pairs);
+          psum16x = (double*)ctx_buf(ctx, "a_probe_lox", mat * 8, true);
+          probe(kp, k1, psum16x);
+          kp = k1;
+        }
         if (done && autop && wp == Prec::BF16 && !bf16_ok(pairs, h[2])) {
-          // the correction is not precise enough at this error: redo every
-          // pair in BF16X3 (same theta) and go on sampling in BF16X3
+          // the correction is not precise enough at this error: every pair
+          // in BF16X3 (same theta) -- the probe pairs have their BF16X3 sums
+          // and traces already, the others are redone -- and go on sampling
+          // in BF16X3
           wp = Prec::BF16X3;
-          GF2_HIP(hipMemsetAsync(sum, 0, mat * 8, ctx->stream));
-          for (int64_t s0 = 0; s0 < pairs; s0 += batch) run(s0, std::min(batch, pairs - s0), wp);
+          GF2_HIP(hipMemcpyAsync(sum, psum3, mat * 8, hipMemcpyDeviceToDevice, ctx->stream));
+          GF2_HIP(hipMemcpyAsync(e_samples, eprobe, (size_t)(kp * ntau) * 8, hipMemcpyDeviceToDevice, ctx->stream));
+          for (int64_t s0 = kp; s0 < pairs; s0 += batch) run(s0, std::min(batch, pairs - s0), wp);
           stat(pairs, h);
           done = stderr_upper(h[2], pairs) < target || pairs >= max_pairs;
         }
         if (done) break;
       }
-      const int64_t cnt = std::min(batch, max_pairs - pairs);
+      // batches of `batch` pairs; the first one is filled up after the probe
+      const int64_t cnt = std::min(pairs < batch ? batch - pairs : batch, max_pairs - pairs);
       if (cnt <= 0) break;
       run(pairs, cnt, wp);
       pairs += cnt;
     }
     if (autop && wp == Prec::BF16) {
-      // Sigma_sum and the samples to the BF16X3 level: sum += lo + (pairs/kp)(hi - lo)
-      launch_level_correct(sum, psum3, psum16, (int64_t)mat, (double)pairs / (double)kp, ctx->stream);
+      // Sigma_sum and the samples to the BF16X3 level: with lo the BF16 sums
+      // of all kp probe pairs, sum += psum16 + (pairs/kp)(hi - lo); the
+      // pairs of psum16x are already in `sum`, so they enter only through lo
+      const double c = (double)pairs / (double)kp;
+      launch_level_correct(sum, psum3, psum16, (int64_t)mat, c, ctx->stream);
+      if (psum16x) {
+        auto* zero = (double*)ctx_buf(ctx, "a_zero", mat * 8, true);
+        launch_level_correct(sum, zero, psum16x, (int64_t)mat, 1.0 + c, ctx->stream);   // sum -= c psum16x
+      }
       launch_level_shift(e_samples, eprobe, kp, pairs, ntau, ctx->stream);
       GF2_HIP(hipGetLastError());
       stat(pairs, h);

@@ -167,6 +167,8 @@ struct gf2_ctx {
   int32_t gemm_wide = 2;          // BF16 tiles where 160 pads less than 128: 2 all stages, 1 s4 only, 0 none
   // (n, np, precision) of the last chain layout per buffer-tag prefix
   std::map<std::string, std::string> chain_keys;
+  // per prefix and buffer: bytes cleared under that prefix's current layout
+  std::map<std::string, std::map<std::string, size_t>> chain_cleared;
   // launch shapes chosen by the batch autotuner, per batch signature
   std::map<std::string, std::pair<int32_t, int32_t>> tuned;
   // optional per-kernel-class timing with HIP events on ctx->stream

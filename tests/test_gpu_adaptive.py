@@ -91,3 +91,33 @@ def test_adaptive_with_the_deterministic_block_inside_equals_the_two_calls(ctx, 
     assert torch.equal(det, det_b)
     assert torch.equal(S_a, S_b) and torch.equal(es_a, es_b)
     assert info_a == info_b
+
+
+def test_more_units_after_a_layout_change_reuse_cleared_padding(ctx):
+    """A context's chain buffers outlive a call: after a run in another
+    precision, a small run and then a larger one in BF16 (more slots of the
+    same buffers) must give the results of a fresh context, bit for bit."""
+    from paper_2005_12338_amd import gf2
+    pb, geo, B64, spl64, G, Gb, w, det = _setup(ctx, torch.float64)
+    acc = torch.zeros_like(det)
+    ctx.sigma_stoch(spl64, B64, G, Gb, acc, ns=4, seed=0, prec="fp64")
+    pb, geo, B, spl, G, Gb, w, det = _setup(ctx, torch.float32)
+
+    def runs(c, s):
+        out = []
+        for s0, ns in ((0, 2), (2, 6)):
+            a = torch.zeros_like(det)
+            es = torch.zeros((ns, pb["ntau"]), dtype=torch.float64, device="cuda")
+            c.sigma_stoch(s, B, G, Gb, a, ns=ns, seed=0, prec="bf16", s0=s0, e_samples=es)
+            out.append((a, es))
+        return out
+
+    got = runs(ctx, spl)
+    fresh = gf2.Context(0)
+    spl_f = fresh.split(B, pb["eps"])
+    ref = runs(fresh, spl_f)
+    for (a, e), (ar, er) in zip(got, ref):
+        assert torch.isfinite(e).all()
+        assert torch.equal(a, ar) and torch.equal(e, er)
+    spl_f.free()
+    fresh.close()

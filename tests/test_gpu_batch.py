@@ -107,3 +107,28 @@ def test_batch_with_importance_and_stratified_items_equals_single_calls(ctx):
     for (S, es), (Sr, esr) in zip(got, ref):
         assert torch.equal(S, Sr)
         assert torch.equal(es, esr)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("fp64", 1e-10)])
+def test_batch_largest_instance_matches_oracle_pair_by_pair(ctx, prec, tol):
+    """The largest instance of an uneven multi-instance batch (FP32 and FP64
+    launches) against the oracle, every (tau, pair) trace and Sigma."""
+    dims, ntau, ns = [9, 31, 16, 48], 3, 4
+    inst = _instances(ctx, dims, ntau, 1e-2, torch.float64 if prec == "fp64" else torch.float32, ns)
+    got = ctx.sigma_batch(inst, prec=prec)
+    k = int(np.argmax(dims))
+    pb = inst[k]["pb"]
+    o = oracle_setup(pb)
+    per = oracle_pairs(o, k, ns, range(ntau), range(ns))
+    e_ref = np.array([[energy.trace_product(per[(t, s)], o["gb"][t]) for t in range(ntau)] for s in range(ns)])
+    es = got[k][1].cpu().numpy()
+    # traces: the bar is relative to the largest per-pair trace (the traces
+    # of single pairs scatter around zero)
+    assert np.abs(es - e_ref).max() < tol * np.abs(e_ref).max()
+    from oracle import selfenergy as se
+    acc = np.zeros((ntau, pb["n"], pb["n"]))
+    for t in range(ntau):
+        acc[t] = sum(per[(t, s)] for s in range(ns))
+    sig_ref = np.array([se.sigma_dd(o["split"], o["g"][t], o["gb"][t]) + (acc[t] + acc[t].T) / (2.0 * ns)
+                        for t in range(ntau)])
+    assert rel(got[k][0].cpu().numpy(), sig_ref) < tol
