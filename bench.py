@@ -92,8 +92,10 @@ class Problem:
 
     eps_override = None      # a threshold above 1 empties the large part: pure SRI
 
-    def setup(self, with_det=True):
-        """B, split, G(tau) and (with_det) the deterministic block."""
+    def setup(self, with_det=True, tau0=False):
+        """B, split, G(tau) and (with_det) the deterministic block.  With tau0
+        the same eigensolve also gives Gbar(0) for the proposal's features
+        (kept in self.gb0)."""
         import torch
         ctx, wl, geo = self.ctx, self.wl, self.geo
         t = self._mark("start", time.perf_counter()) if self.phase_log else 0.0
@@ -101,7 +103,12 @@ class Problem:
         t = self._mark("B", t)
         spl = ctx.split(B, wl.eps if self.eps_override is None else self.eps_override)
         t = self._mark("split", t)
-        G, Gb, mu = ctx.green_tau(self.F, self.tau, wl.beta, n_occ=wl.n_occ)
+        if tau0:
+            nt = self.tau.shape[0]
+            Ga, Gba, mu = ctx.green_tau(self.F, np.append(self.tau, 0.0), wl.beta, n_occ=wl.n_occ)
+            G, Gb, self.gb0 = Ga[:nt], Gba[:nt], Gba[nt]
+        else:
+            G, Gb, mu = ctx.green_tau(self.F, self.tau, wl.beta, n_occ=wl.n_occ)
         t = self._mark("G(tau)", t)
         if not with_det:
             return B, spl, G, Gb
@@ -130,12 +137,12 @@ class Problem:
         import torch
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        B, spl, G, Gb = self.setup(with_det=False)
+        B, spl, G, Gb = self.setup(with_det=False, tau0=mlp is not None)
         ctx, wl = self.ctx, self.wl
         p = None
         if mlp is not None:
             p = torch.empty(wl.naux, dtype=torch.float64, device="cuda")
-            ctx.proposal_infer(mlp, self.features(spl, B), PROPOSAL_ALPHA, p, bf16=True)
+            ctx.proposal_infer(mlp, self.features(spl, B, self.gb0), PROPOSAL_ALPHA, p, bf16=True)
             p = p.cpu().numpy()
         # the deterministic block runs inside, overlapped with the first pairs
         _, _, _, info = ctx.energy_adaptive_det(spl, B, G, Gb, self.w, wl.n_elec, target, batch=batch,
@@ -146,14 +153,15 @@ class Problem:
         spl.free()
         return t1 - t0, info
 
-    def features(self, spl, B):
-        """Per-Q features of this chain (centre, ||B^Q||, local density)."""
+    def features(self, spl, B, gb0=None):
+        """Per-Q features of this chain (centre, ||B^Q||, local density);
+        gb0 = Gbar(0) if the caller has it already."""
         import torch
-        from paper_2005_12338_amd import gf2
         ctx, wl, geo = self.ctx, self.wl, self.geo
-        _, Gb0, _ = ctx.green_tau(self.F, np.array([0.0]), wl.beta, n_occ=wl.n_occ)
+        if gb0 is None:
+            gb0 = ctx.green_tau(self.F, np.array([0.0]), wl.beta, n_occ=wl.n_occ)[1][0]
         phi = torch.empty((wl.naux, 4), dtype=torch.float64, device="cuda")
-        ctx.proposal_features(spl, B, geo.x, geo.xq, Gb0[0].contiguous(), phi)
+        ctx.proposal_features(spl, B, geo.x, geo.xq, gb0.contiguous(), phi)
         return phi
 
 
@@ -306,6 +314,11 @@ def batch_bench(args):
     bat = timed("batched", lambda: ctx.sigma_batch(items, prec=prec))
     timed("graph", lambda: ctx.sigma_batch(items, prec=prec, graph=True))
     tun = timed("tuned", lambda: ctx.sigma_batch(items, prec=prec, graph=True, autotune=True))
+    tiles = {}
+    if prec == "bf16":
+        tiles = {str(n): ctx.tuned_tiles(prec, n) for n in sorted({it["n"] for it in items})}
+        tiles = {n: m for n, m in tiles.items() if m >= 0}
+        log(f"[bench]   tile modes chosen per N (0: 128 tiles, 1: 160 on the deep-K stage, 2: 160 on all): {tiles}")
     dev = max(float((a[0] - b[0]).abs().max() / b[0].abs().max()) for a, b in zip(tun, seq))
     log(f"[bench]   max relative difference batched vs per-chain Sigma: {dev:.2e}")
     best = min(("batched", "graph", "tuned"), key=lambda k: res[k]["s"])
@@ -316,7 +329,7 @@ def batch_bench(args):
                                   f"default_rng(12345).integers(20, 201, {len(wls)}), beta=100, ntau=64, "
                                   f"Ns=128, eps=1e-3"},
            "setup_s": t_setup, "sigma_s": res, "best": best, "speedup_vs_per_chain": res["per_chain"]["s"] /
-           res[best]["s"], "max_rel_diff_vs_per_chain": dev}
+           res[best]["s"], "max_rel_diff_vs_per_chain": dev, "tuned_tile_modes": tiles}
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -419,8 +419,19 @@ gf2_status gf2_profile_read(gf2_ctx* ctx, int32_t cap, char* names, int64_t* lau
  * mode 1: only the deep-K stage on the 160 tile (and gf2_debug_gemm);
  * mode 0: the 128 x 128 tile everywhere.
  * All modes give the same results up to the FP32 rounding of the
- * accumulation order.  GF2_E_ARG for other modes. */
+ * accumulation order.  Setting a mode discards the tile modes the batch
+ * autotuner chose (below), so the setting applies to every size again.
+ * GF2_E_ARG for other modes. */
 gf2_status gf2_set_gemm_tiles(gf2_ctx* ctx, int32_t mode);
+
+/* Tile mode (0, 1 or 2, as gf2_set_gemm_tiles) that GF2_BATCH_AUTOTUNE chose
+ * for chains of size n at precision prec (FP64, FP32, BF16 or BF16X3), or
+ * -1 in *mode if it chose none (it tunes BF16 sizes where the 160-wide tile
+ * pads less than 128, i.e. where the mode changes the launch).  A chosen
+ * mode applies to every later call of the context on chains of that size,
+ * single-chain calls included.  GF2_E_ARG for a null mode, n <= 0 or an
+ * adaptive-only precision. */
+gf2_status gf2_tuned_tiles(gf2_ctx* ctx, gf2_precision prec, int64_t n, int32_t* mode);
 
 /* ------------------------------------------------------------ batch -------
  * Many chains of uneven size in one schedule: every instance's (tau, pair)
@@ -430,9 +441,12 @@ gf2_status gf2_set_gemm_tiles(gf2_ctx* ctx, int32_t mode);
  *   Sigma = Sigma[D,D] + (1/N_s) sum_s (Sigma_s + Sigma_s^T)/2  (eq:sigma_2)
  * and e_samples [ns][ntau] (may be NULL).
  * flags: GF2_BATCH_GRAPH records the chunk loop of the call into one HIP
- * graph and launches it; GF2_BATCH_AUTOTUNE times candidate launch shapes
- * (pairs x tau points per chunk, persistent grid or not) on the first chunks
- * and keeps the fastest for this batch signature (cached in ctx).
+ * graph and launches it; GF2_BATCH_AUTOTUNE first picks the tile mode of
+ * every chain size where it matters (each mode timed on one chain of that
+ * size; the fastest kept per (precision, N) in ctx, see gf2_tuned_tiles),
+ * then times candidate launch shapes (pairs x tau points per chunk,
+ * persistent grid or not) on the first chunks of the whole batch and keeps
+ * the fastest for this batch signature (cached in ctx).
  * The library allocates per-instance workspace (freed by gf2_destroy).
  * Errors: as gf2_sigma_tau for any item; GF2_E_ARG for nitem < 1. */
 typedef struct {

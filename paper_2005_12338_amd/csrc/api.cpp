@@ -146,12 +146,25 @@ int tiles_of(const Prob& p, Prec prec, int64_t m, int64_t nc, int wide = 0) {
 }
 int tiles_of(const Prob& p, Prec prec, int64_t n, int wide = 0) { return tiles_of(p, prec, n, n, wide); }
 
-// The wide BF16 tile for the chain's single-product stage when it pads an
-// n x n product less than the standard tile (n = 400, 800, ...).
-int wide_for(const gf2_ctx* ctx, Prec prec, int64_t n) {
-  if (prec != Prec::BF16 || !ctx->gemm_wide) return 0;
+// Tile mode for chains of size n: the autotuner's choice for (prec, n) if
+// it made one, else the context's setting.
+int32_t tile_mode(const gf2_ctx* ctx, Prec prec, int64_t n) {
+  const auto it = ctx->tiles_tuned.find({(int32_t)prec, n});
+  return it != ctx->tiles_tuned.end() ? it->second : ctx->gemm_wide;
+}
+
+// Whether a 160-wide BF16 tile pads an n x n product less than the standard
+// tile (n = 150, 300, 400, 800, ...): the sizes where the tile mode matters.
+bool wide_pads_less(Prec prec, int64_t n) {
+  if (prec != Prec::BF16) return false;
   const int64_t w = gemm_tile_m(prec, 1), s = gemm_tile_m(prec, 0);
-  return ((n + w - 1) / w) * w < ((n + s - 1) / s) * s ? 1 : 0;
+  return ((n + w - 1) / w) * w < ((n + s - 1) / s) * s;
+}
+
+// The wide BF16 tile for the chain's single-product stage when it pads an
+// n x n product less than the standard tile and the tile mode allows it.
+int wide_for(const gf2_ctx* ctx, Prec prec, int64_t n) {
+  return tile_mode(ctx, prec, n) && wide_pads_less(prec, n) ? 1 : 0;
 }
 
 // Orthonormal eigenbasis of (F, S) on the host in FP64: F C = S C diag(eps)
@@ -244,7 +257,16 @@ void gf2_destroy(gf2_ctx* ctx) {
 gf2_status gf2_set_gemm_tiles(gf2_ctx* ctx, int32_t mode) {
   if (!ctx || mode < 0 || mode > 2) return GF2_E_ARG;
   ctx->gemm_wide = mode;
+  ctx->tiles_tuned.clear();       // an explicit choice replaces the autotuner's
   return GF2_OK;
+}
+
+gf2_status gf2_tuned_tiles(gf2_ctx* ctx, gf2_precision prec, int64_t n, int32_t* mode) {
+  return guarded(ctx, [&] {
+    GF2_REQUIRE(mode && n > 0, GF2_E_ARG, "bad arguments");
+    const auto it = ctx->tiles_tuned.find({(int32_t)to_prec(prec), n});
+    *mode = it != ctx->tiles_tuned.end() ? it->second : -1;
+  });
 }
 
 gf2_status gf2_set_stream(gf2_ctx* ctx, void* stream) {
@@ -878,7 +900,7 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
     c.wideg[0] = c.wideg[1] = c.wideg[2] = c.wideg[3] = 0;
     if (wide_for(ctx, prec, n)) {
       c.wideg[3] = 1;
-      if (ctx->gemm_wide >= 2) c.wideg[0] = c.wideg[2] = 3;
+      if (tile_mode(ctx, prec, n) >= 2) c.wideg[0] = c.wideg[2] = 3;
     }
     Prob dual = prob0();
     dual.nA = 2;
@@ -983,7 +1005,7 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
       // 160-wide tiles where they pad n less: the deep-K stage s4 always, the
       // dual-A launches (s1, s2, s3) in the default mode 2
       c.wideg[3] = 1;
-      if (ctx->gemm_wide >= 2) c.wideg[0] = c.wideg[1] = c.wideg[2] = 3;
+      if (tile_mode(ctx, prec, n) >= 2) c.wideg[0] = c.wideg[1] = c.wideg[2] = 3;
     }
     Prob dual = prob0();
     dual.nA = 2;
@@ -1516,14 +1538,13 @@ gf2_status gf2_sigma_batch(gf2_ctx* ctx, int32_t nitem, const gf2_batch_item* it
       int dev_cus = 256;
       hipDeviceProp_t prop;
       if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) dev_cus = prop.multiProcessorCount;
-      const BatchShape cand[] = {{8, 0}, {4, 0}, {2, 0}, {8, 2 * dev_cus}, {4, 2 * dev_cus}};
-      double best = 1e300;
       const bool prof = ctx->prof;
       ctx->prof = false;
-      for (const BatchShape& cs : cand) {
+      // time per unit of a plan: warm with step 0, time steps [t0, t1)
+      // (step 0 again if it is the only one)
+      auto per_unit = [&](int32_t cnt, const gf2_batch_item* its, const std::vector<double*>& sm, BatchShape cs) {
         BatchRun R;
-        batch_plan(ctx, R, nitem, items, p, sums, cs);
-        // warm with step 0, time steps [t0, t1) (step 0 again if it is the only one)
+        batch_plan(ctx, R, cnt, its, p, sm, cs);
         const int64_t t0 = R.nsteps >= 2 ? 1 : 0;
         const int64_t t1 = R.nsteps >= 2 ? std::min<int64_t>(R.nsteps, 4) : 1;
         batch_steps(ctx, R, p, 0, 1);
@@ -1540,9 +1561,36 @@ gf2_status gf2_sigma_batch(gf2_ctx* ctx, int32_t nitem, const gf2_batch_item* it
         (void)hipEventDestroy(b);
         int64_t units = 0;
         for (int64_t st = t0; st < t1; ++st) units += R.steps[st].second;
-        const double per_unit = units > 0 ? ms / (double)units : 1e300;
-        if (per_unit < best) {
-          best = per_unit;
+        return units > 0 ? ms / (double)units : 1e300;
+      };
+      // 1. tile mode per chain size where it matters (BF16 sizes a 160-wide
+      // tile pads less): each mode timed on the first chain of that size
+      // alone, the fastest kept for the size
+      std::map<int64_t, int32_t> first_of;
+      for (int32_t i = 0; i < nitem; ++i)
+        if (wide_pads_less(p, items[i].split->n)) first_of.emplace(items[i].split->n, i);
+      for (const auto& fo : first_of) {
+        const std::pair<int32_t, int64_t> key{(int32_t)p, fo.first};
+        if (ctx->tiles_tuned.count(key)) continue;
+        int32_t pick = ctx->gemm_wide;
+        double tbest = 1e300;
+        for (int32_t m = 0; m <= 2; ++m) {
+          ctx->tiles_tuned[key] = m;
+          const double t = per_unit(1, items + fo.second, {sums[fo.second]}, BatchShape{8, 0});
+          if (t < tbest) {
+            tbest = t;
+            pick = m;
+          }
+        }
+        ctx->tiles_tuned[key] = pick;
+      }
+      // 2. launch shape of the whole batch with those tiles
+      const BatchShape cand[] = {{8, 0}, {4, 0}, {2, 0}, {8, 2 * dev_cus}, {4, 2 * dev_cus}};
+      double best = 1e300;
+      for (const BatchShape& cs : cand) {
+        const double t = per_unit(nitem, items, sums, cs);
+        if (t < best) {
+          best = t;
           shape = cs;
         }
       }

@@ -171,6 +171,9 @@ struct gf2_ctx {
   std::map<std::string, std::map<std::string, size_t>> chain_cleared;
   // launch shapes chosen by the batch autotuner, per batch signature
   std::map<std::string, std::pair<int32_t, int32_t>> tuned;
+  // tile mode (as gemm_wide) chosen by the batch autotuner per (precision, N);
+  // it takes precedence over gemm_wide for chains of that size
+  std::map<std::pair<int32_t, int64_t>, int32_t> tiles_tuned;
   // optional per-kernel-class timing with HIP events on ctx->stream
   bool prof = false;
   struct Ev { std::string name; hipEvent_t a, b; double flops, bytes; };

@@ -108,6 +108,7 @@ _SIGS = {
                                 C.POINTER(C.c_uint64)]),
     "gf2_set_profiling": (C.c_int, [C.c_void_p, C.c_int]),
     "gf2_set_gemm_tiles": (C.c_int, [C.c_void_p, C.c_int32]),
+    "gf2_tuned_tiles": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.POINTER(C.c_int32)]),
     "gf2_debug_gemm": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
                                  C.c_void_p]),
     "gf2_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -599,6 +600,12 @@ class Context:
         0 (or False) the 128-wide tile everywhere."""
         m = (2 if mode else 0) if isinstance(mode, bool) else int(mode)
         self._check(self.lib.gf2_set_gemm_tiles(self.h, m))
+
+    def tuned_tiles(self, prec: str, n: int) -> int:
+        """Tile mode the batch autotuner chose for chains of size n (-1: none)."""
+        m = C.c_int32(0)
+        self._check(self.lib.gf2_tuned_tiles(self.h, PREC[prec], int(n), C.byref(m)))
+        return m.value
 
     def set_profiling(self, on: bool):
         self._check(self.lib.gf2_set_profiling(self.h, 1 if on else 0))

@@ -3,7 +3,8 @@ instance and against the oracle.
 
 With the same chunk shape the batch runs the same per-unit arithmetic in the
 same order as single-instance calls, so results agree bitwise; a tuned shape
-regroups the accumulation of pairs (1e-12 relative).
+regroups the accumulation of pairs (1e-12 relative), and a tuned tile mode
+applies to single calls of that size too.
 """
 import numpy as np
 import pytest
@@ -73,8 +74,10 @@ def test_batch_ragged_tiles_autotuned(ctx, prec):
     """Instances spanning one to several 128-wide tiles with ragged tails,
     with the launch shape chosen by the autotuner (persistent or not)."""
     inst = _instances(ctx, [20, 33, 64, 70, 100, 41], 5, 1e-3, torch.float32, 4)
-    ref = _singles(ctx, inst, prec)
     got = ctx.sigma_batch(inst, prec=prec, autotune=True, graph=True)
+    # after the call: in BF16 the tuner may have changed the tile of N = 140,
+    # and single calls use its choice too
+    ref = _singles(ctx, inst, prec)
     for (S, es), (Sr, esr) in zip(got, ref):
         assert rel(S.cpu().numpy(), Sr.cpu().numpy()) < 1e-12
         assert rel(es.cpu().numpy(), esr.cpu().numpy()) < 1e-12
@@ -82,6 +85,37 @@ def test_batch_ragged_tiles_autotuned(ctx, prec):
     again = ctx.sigma_batch(inst, prec=prec, autotune=True)
     for (S, es), (S2, es2) in zip(got, again):
         assert torch.equal(S, S2) and torch.equal(es, es2)
+
+
+def test_tile_autotuner_picks_a_mode_per_size():
+    """GF2_BATCH_AUTOTUNE times the tile modes on one chain of each BF16 size
+    where the 160-wide tile pads less than 128 (N = 150, 160; not N = 80) and
+    keeps the fastest per size.  Single calls afterwards use the same tiles
+    (the batch equals them up to the regrouping of pairs); each tuned result
+    stays at the BF16 level against FP32, as the default tiles do; an
+    explicit gf2_set_gemm_tiles discards the choices."""
+    from paper_2005_12338_amd import gf2
+    c = gf2.Context(0)
+    try:
+        inst = _instances(c, [75, 40, 80], 3, 1e-3, torch.float32, 3)
+        base = c.sigma_batch(inst, prec="bf16")
+        s32 = _singles(c, inst, "fp32")
+        got = c.sigma_batch(inst, prec="bf16", autotune=True)
+        modes = {n: c.tuned_tiles("bf16", n) for n in (150, 80, 160)}
+        print("tuned tile modes:", modes)
+        assert modes[80] == -1 and modes[150] in (0, 1, 2) and modes[160] in (0, 1, 2)
+        assert c.tuned_tiles("fp32", 150) == -1
+        ref = _singles(c, inst, "bf16")
+        for (S, es), (Sr, esr) in zip(got, ref):
+            assert rel(S.cpu().numpy(), Sr.cpu().numpy()) < 1e-12
+            assert rel(es.cpu().numpy(), esr.cpu().numpy()) < 1e-12
+        for (S, _), (Sb, _), (S3, _) in zip(got, base, s32):
+            e_t, e_b = rel(S.cpu().numpy(), S3.cpu().numpy()), rel(Sb.cpu().numpy(), S3.cpu().numpy())
+            assert e_t < 2.0 * e_b + 1e-7, (e_t, e_b)
+        c.set_gemm_tiles(2)
+        assert c.tuned_tiles("bf16", 150) == -1
+    finally:
+        c.close()
 
 
 def test_batch_rejects_foreign_split(ctx):
