@@ -879,8 +879,7 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
   c.jz_st = jk + 2 * sb * slots;
   c.jz_sum_t = jk + 3 * sb * slots;
   char *jw_l = c.jw_l, *jw_s = c.jw_s, *jz_st = c.jz_st, *jz_sum_t = c.jz_sum_t;
-  const size_t jbytes = (size_t)slots * 4 * naux * kWMax * kWMax * (c.accf64 ? 8 : 4);
-  c.jblk = (char*)ctx_buf(ctx, pfx + "c_jblk", jbytes);
+  c.jblk = (char*)ctx_buf(ctx, pfx + "c_jblk", jk_block_bytes(c.accf64, slots, naux, sp->wmax));
   c.st_sl = (int64_t)(sb / st_elem(prec));        // elements per storage slot
   c.ac_sl = (int64_t)np2;
   const int64_t st_sl = c.st_sl, ac_sl = c.ac_sl;
@@ -1164,7 +1163,7 @@ void chain_jk(gf2_ctx* ctx, const ChainPlan& c, int64_t ci) {
                      c.accf64 ? (const void*)sp->blk : (const void*)sp->blk32, c.jblk, ctx->stream);
   }
   ProfScope ps(ctx, "jk_scatter");
-  launch_jk_scatter(c.accf64, c.jblk, c.naux, nu, sp->npat, sp->pat_ij, sp->pat_off, sp->pat_q, c.np, c.prec,
+  launch_jk_scatter(c.accf64, c.jblk, c.naux, nu, sp->wmax, sp->npat, sp->pat_ij, sp->pat_off, sp->pat_q, c.np, c.prec,
                     c.plane, c.jw_l, c.jw_s, c.jz_st, c.jz_sum_t, c.st_sl, ctx->stream);
 }
 

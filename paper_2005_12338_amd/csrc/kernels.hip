@@ -290,67 +290,93 @@ __global__ void k_pad_convert(const double* g, int64_t n, int64_t np, int64_t nt
 }
 
 // ------------------------------------------------------------- JK ---------
-// For every (slot, m in 0..3, Q): J = 2 Tr(k W_SS) k - k W_SS k with W the
-// m-th matrix of the slot (accumulator format, row-major padded).  One wave
-// per (slot, m, Q); lanes walk the w x w block elements (w <= WB).  Waves
-// share nothing: each keeps its blocks in its own LDS slice, ordered by a
-// wave-level fence (LDS operations of one wave complete in order).
-template <typename T, int WB>
-__global__ __launch_bounds__(256) void k_jk_blocks(const void* wbase, int64_t w_st_slot,
-                                                    int64_t w_st_m, int64_t np, int64_t naux,
-                                                    int32_t nslot, const int32_t* wq,
-                                                    const int32_t* idx, const T* blk, T* jout) {
-  __shared__ T sk[4][WB * WB];
-  __shared__ T sw[4][WB * WB];
-  __shared__ T st[4][WB * WB];
+// Block pitch of the J blocks: the split's widest block rounded up to 8, 16
+// or kWMax.
+__host__ __device__ __forceinline__ int jk_pitch(int32_t wmax) { return wmax <= 8 ? 8 : wmax <= 16 ? 16 : kWMax; }
+
+// For every (slot, Q) and m in 0..3: J = 2 Tr(k W) k - k W k with k the
+// w x w block of K^L_Q on its support and W the m-th matrix of the slot
+// (accumulator format, row-major padded) restricted to that support.  One
+// wave per (slot, Q) computes all four m, so k and the support are read
+// once; lane e holds block element (e / w, e % w) of every m (w <= WB).
+// Output jout[((slot naux + Q) JP^2 + a JP + c) 4 + m], JP = WB: the four m
+// of an element side by side for the scatter.  Waves share nothing: each
+// keeps its blocks in its own LDS slice, ordered by a wave-level fence (LDS
+// operations of one wave complete in order).
+template <typename T, int WB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_jk_blocks(const void* wbase, int64_t w_st_slot,
+                                                       int64_t w_st_m, int64_t np, int64_t naux,
+                                                       int32_t nslot, const int32_t* wq,
+                                                       const int32_t* idx, const T* blk, T* jout) {
+  constexpr int E = WB * WB;
+  __shared__ T sk[NW][E];
+  __shared__ T sw[NW][4][E];
+  __shared__ T st[NW][4][E];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t task = (int64_t)blockIdx.x * 4 + wv;
-  const int64_t total = (int64_t)nslot * 4 * naux;
-  if (task >= total) return;                      // whole wave leaves together
+  const int64_t task = (int64_t)blockIdx.x * NW + wv;
+  if (task >= (int64_t)nslot * naux) return;       // whole wave leaves together
   const int64_t q = task % naux;
-  const int64_t m = (task / naux) % 4;
-  const int64_t slot = task / (naux * 4);
+  const int64_t slot = task / naux;
   const int w = wq[q];
-  T* out = jout + task * kWMax * kWMax;
-  const T* W = (const T*)wbase + slot * w_st_slot + m * w_st_m;
+  const T* W = (const T*)wbase + slot * w_st_slot;
   const int32_t* s = idx + q * kWMax;
   const int ww = w * w;
   for (int e = lane; e < ww; e += 64) {
-    int a = e / w, c = e % w;
+    const int a = e / w, c = e % w;
     sk[wv][e] = blk[q * kWMax * kWMax + a * kWMax + c];
-    sw[wv][e] = W[(int64_t)s[a] * np + s[c]];
+    const int64_t o = (int64_t)s[a] * np + s[c];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) sw[wv][m][e] = W[m * w_st_m + o];
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  // t = Tr(k W) = sum_ab k_ab W_ba
-  T tr = 0;
+  // t_m = Tr(k W_m) = sum_ac k_ac (W_m)_ca
+  T tr[4] = {0, 0, 0, 0};
   for (int e = lane; e < ww; e += 64) {
-    int a = e / w, c = e % w;
-    tr += sk[wv][e] * sw[wv][c * w + a];
+    const int a = e / w, c = e % w;
+    const T kv = sk[wv][e];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) tr[m] += kv * sw[wv][m][c * w + a];
   }
-  for (int d = 32; d > 0; d >>= 1) tr += __shfl_xor(tr, d, 64);
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+    for (int d = 32; d > 0; d >>= 1) tr[m] += __shfl_xor(tr[m], d, 64);
   for (int e = lane; e < ww; e += 64) {
-    int a = e / w, c = e % w;
-    T acc = 0;
-    for (int x = 0; x < w; ++x) acc += sk[wv][a * w + x] * sw[wv][x * w + c];
-    st[wv][e] = acc;
+    const int a = e / w, c = e % w;
+    T acc[4] = {0, 0, 0, 0};
+    for (int x = 0; x < w; ++x) {
+      const T kv = sk[wv][a * w + x];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc[m] += kv * sw[wv][m][x * w + c];
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) st[wv][m][e] = acc[m];
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
+  T* out = jout + task * E * 4;
   for (int e = lane; e < ww; e += 64) {
-    int a = e / w, c = e % w;
-    T acc = 0;
-    for (int x = 0; x < w; ++x) acc += st[wv][a * w + x] * sk[wv][x * w + c];
-    out[a * kWMax + c] = 2 * tr * sk[wv][e] - acc;
+    const int a = e / w, c = e % w;
+    T acc[4] = {0, 0, 0, 0};
+    for (int x = 0; x < w; ++x) {
+      const T kv = sk[wv][x * w + c];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc[m] += st[wv][m][a * w + x] * kv;
+    }
+    const T kv = sk[wv][e];
+    T* o = out + (a * WB + c) * 4;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) o[m] = 2 * tr[m] * kv - acc[m];
   }
 }
 
 // Scatter the J blocks onto the union pattern: for every pattern entry (i,j)
-// sum the contributions in their fixed order.  m = 0, 1 (W_L, W_S) go to
-// row-major outputs; m = 2, 3 (Z_L, Z_S) to transposed outputs, with the
-// second transposed output holding J(Z_L) + J(Z_S).
+// sum the contributions in their fixed order (the four m of a contribution
+// are adjacent).  m = 0, 1 (W_L, W_S) go to row-major outputs; m = 2, 3
+// (Z_L, Z_S) to transposed outputs, with the second transposed output
+// holding J(Z_L) + J(Z_S).
 template <typename T>
-__global__ void k_jk_scatter(const T* jblk, int64_t naux, int32_t nslot, int64_t npat,
+__global__ void k_jk_scatter(const T* jblk, int64_t naux, int32_t nslot, int64_t npat, int jp,
                              const int32_t* pat_ij, const int32_t* pat_off, const int32_t* pat_q,
                              int64_t np, Prec prec, int64_t plane, void* jw_l, void* jw_s,
                              void* jz_st, void* jz_sum_t, int64_t out_st_slot) {
@@ -358,17 +384,15 @@ __global__ void k_jk_scatter(const T* jblk, int64_t naux, int32_t nslot, int64_t
   if (e >= (int64_t)nslot * npat) return;
   int64_t slot = e / npat, p = e % npat;
   int64_t ij = pat_ij[p], i = ij / np, j = ij % np;
+  const T* jb = jblk + slot * naux * jp * jp * 4;
   double v[4] = {0, 0, 0, 0};
-  for (int m = 0; m < 4; ++m) {
-    const T* jb = jblk + ((slot * 4 + m) * naux) * kWMax * kWMax;
-    double acc = 0.0;
-    for (int c = pat_off[p]; c < pat_off[p + 1]; ++c) {
-      int32_t code = pat_q[c];
-      int64_t q = code >> 10;
-      int a = (code >> 5) & 31, b = code & 31;
-      acc += (double)jb[q * kWMax * kWMax + a * kWMax + b];
-    }
-    v[m] = acc;
+  for (int c = pat_off[p]; c < pat_off[p + 1]; ++c) {
+    const int32_t code = pat_q[c];
+    const int64_t q = code >> 10;
+    const int a = (code >> 5) & 31, b = code & 31;
+    const T* x = jb + ((q * jp + a) * jp + b) * 4;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] += (double)x[m];
   }
   int64_t o = slot * out_st_slot;
   put_st(jw_l, o + i * np + j, plane, prec, v[0]);
@@ -734,44 +758,51 @@ void launch_pad_convert(const double* g, int64_t n, int64_t np, int64_t ntau, Pr
                      prec, stbuf, plane, mstride, f64pad);
 }
 template <typename T>
-void jk_blocks_launch(int32_t wmax, dim3 grid, hipStream_t st, const void* wbase, int64_t w_st_slot, int64_t w_st_m,
-                      int64_t np, int64_t naux, int32_t nslot, const int32_t* wq, const int32_t* idx, const T* blk,
-                      T* jout) {
+void jk_blocks_launch(int32_t wmax, int64_t tasks, hipStream_t st, const void* wbase, int64_t w_st_slot,
+                      int64_t w_st_m, int64_t np, int64_t naux, int32_t nslot, const int32_t* wq, const int32_t* idx,
+                      const T* blk, T* jout) {
+  // four waves per workgroup up to 16-wide blocks; one for the widest, whose
+  // LDS slices (9 x 1024 elements) would not fit four times
+  auto grid = [&](int nw) { return dim3((unsigned)((tasks + nw - 1) / nw)); };
   if (wmax <= 8)
-    hipLaunchKernelGGL((k_jk_blocks<T, 8>), grid, dim3(256), 0, st, wbase, w_st_slot, w_st_m, np, naux, nslot, wq,
-                       idx, blk, jout);
-  else if (wmax <= 16)
-    hipLaunchKernelGGL((k_jk_blocks<T, 16>), grid, dim3(256), 0, st, wbase, w_st_slot, w_st_m, np, naux, nslot, wq,
-                       idx, blk, jout);
-  else
-    hipLaunchKernelGGL((k_jk_blocks<T, kWMax>), grid, dim3(256), 0, st, wbase, w_st_slot, w_st_m, np, naux, nslot,
+    hipLaunchKernelGGL((k_jk_blocks<T, 8, 4>), grid(4), dim3(256), 0, st, wbase, w_st_slot, w_st_m, np, naux, nslot,
                        wq, idx, blk, jout);
+  else if (wmax <= 16)
+    hipLaunchKernelGGL((k_jk_blocks<T, 16, 4>), grid(4), dim3(256), 0, st, wbase, w_st_slot, w_st_m, np, naux, nslot,
+                       wq, idx, blk, jout);
+  else
+    hipLaunchKernelGGL((k_jk_blocks<T, kWMax, 1>), grid(1), dim3(64), 0, st, wbase, w_st_slot, w_st_m, np, naux,
+                       nslot, wq, idx, blk, jout);
 }
 void launch_jk_blocks(bool f64, const void* wbase, int64_t w_st_slot, int64_t w_st_m, int64_t np,
                       int64_t naux, int32_t nslot, int32_t wmax, const int32_t* wq, const int32_t* idx,
                       const void* blk, void* jout, hipStream_t st) {
-  int64_t tasks = (int64_t)nslot * 4 * naux;
-  dim3 grid((unsigned)((tasks + 3) / 4));
+  const int64_t tasks = (int64_t)nslot * naux;
   if (f64)
-    jk_blocks_launch<double>(wmax, grid, st, wbase, w_st_slot, w_st_m, np, naux, nslot, wq, idx, (const double*)blk,
+    jk_blocks_launch<double>(wmax, tasks, st, wbase, w_st_slot, w_st_m, np, naux, nslot, wq, idx, (const double*)blk,
                              (double*)jout);
   else
-    jk_blocks_launch<float>(wmax, grid, st, wbase, w_st_slot, w_st_m, np, naux, nslot, wq, idx, (const float*)blk,
+    jk_blocks_launch<float>(wmax, tasks, st, wbase, w_st_slot, w_st_m, np, naux, nslot, wq, idx, (const float*)blk,
                             (float*)jout);
 }
-void launch_jk_scatter(bool f64, const void* jblk, int64_t naux, int32_t nslot, int64_t npat,
+size_t jk_block_bytes(bool f64, int64_t nslot, int64_t naux, int32_t wmax) {
+  const int64_t jp = jk_pitch(wmax);
+  return (size_t)(nslot * naux * jp * jp * 4) * (f64 ? 8 : 4);
+}
+void launch_jk_scatter(bool f64, const void* jblk, int64_t naux, int32_t nslot, int32_t wmax, int64_t npat,
                        const int32_t* pat_ij, const int32_t* pat_off, const int32_t* pat_q, int64_t np,
                        Prec prec, int64_t plane, void* jw_l, void* jw_s, void* jz_st, void* jz_sum_t,
                        int64_t out_st_slot, hipStream_t st) {
   if ((int64_t)nslot * npat == 0) return;     // no large part: J and K vanish
   dim3 grid(blocks((int64_t)nslot * npat));
+  const int jp = jk_pitch(wmax);
   if (f64)
     hipLaunchKernelGGL((k_jk_scatter<double>), grid, dim3(256), 0, st, (const double*)jblk, naux, nslot,
-                       npat, pat_ij, pat_off, pat_q, np, prec, plane, jw_l, jw_s, jz_st, jz_sum_t,
+                       npat, jp, pat_ij, pat_off, pat_q, np, prec, plane, jw_l, jw_s, jz_st, jz_sum_t,
                        out_st_slot);
   else
     hipLaunchKernelGGL((k_jk_scatter<float>), grid, dim3(256), 0, st, (const float*)jblk, naux, nslot,
-                       npat, pat_ij, pat_off, pat_q, np, prec, plane, jw_l, jw_s, jz_st, jz_sum_t,
+                       npat, jp, pat_ij, pat_off, pat_q, np, prec, plane, jw_l, jw_s, jz_st, jz_sum_t,
                        out_st_slot);
 }
 void launch_trace_coef(const double* part, int64_t ntiles, int32_t nslot, double* coef, int mode,

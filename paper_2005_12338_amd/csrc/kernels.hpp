@@ -35,7 +35,9 @@ void launch_pad_convert(const double* g, int64_t n, int64_t np, int64_t ntau, Pr
 void launch_jk_blocks(bool f64, const void* wbase, int64_t w_st_slot, int64_t w_st_m, int64_t np,
                       int64_t naux, int32_t nslot, int32_t wmax, const int32_t* wq, const int32_t* idx,
                       const void* blk, void* jout, hipStream_t st);
-void launch_jk_scatter(bool f64, const void* jblk, int64_t naux, int32_t nslot, int64_t npat,
+// bytes of the J blocks of nslot slots (block pitch from the widest block)
+size_t jk_block_bytes(bool f64, int64_t nslot, int64_t naux, int32_t wmax);
+void launch_jk_scatter(bool f64, const void* jblk, int64_t naux, int32_t nslot, int32_t wmax, int64_t npat,
                        const int32_t* pat_ij, const int32_t* pat_off, const int32_t* pat_q, int64_t np,
                        Prec prec, int64_t plane, void* jw_l, void* jw_s, void* jz_st, void* jz_sum_t,
                        int64_t out_st_slot, hipStream_t st);
