@@ -2329,7 +2329,7 @@ void scf_dyson(gf2_ctx* ctx, const ScfGrid& g, double mu, double* G, double* Gba
     const int64_t cnt = scf_chunk(ctx, g, ch);
     ProfScope pr(ctx, "scf_back", 4.0 * (double)cnt * (double)g.nto * (double)np2);
     launch_iw_back(g.a, (int32_t)cnt, np, g.n, g.shift, g.om + ch * g.ncp, g.cs + ch * g.ntop * g.ncp * 2,
-                   (int32_t)g.nto, (int32_t)g.ncp, pc, ps, ctx->stream);
+                   (int32_t)g.nto, (int32_t)g.ntop, pc, ps, ctx->stream);
   }
   GF2_HIP(hipGetLastError());
   scf_check(ctx, g);

@@ -102,7 +102,7 @@ void launch_sig_iw(const double* sig, int64_t ntau, int64_t np, int64_t n, const
                    const double* shift, const double* om, double* a, hipStream_t st);
 void launch_gj_invert(double* a, int32_t nmat, int64_t np, double* colbuf, double* pbuf, int* err, hipStream_t st);
 void launch_iw_back(const double* a, int32_t nc, int64_t np, int64_t n, const double* shift, const double* om,
-                    const double* cs, int32_t nto, int32_t ncp, double* pc, double* ps, hipStream_t st);
+                    const double* cs, int32_t nto, int32_t ntop, double* pc, double* ps, hipStream_t st);
 void launch_iw_diag(const double* a, int32_t nc, int64_t np, int64_t n, const double* shift, const double* om,
                     double* tr, hipStream_t st);
 void launch_g_mo(const double* pc, const double* ps, int64_t np, int64_t n, int64_t ntau, const double* tau,

@@ -26,7 +26,7 @@ typedef double f64x4_t __attribute__((ext_vector_type(4)));
 constexpr int kNB = 32;    // Gauss-Jordan panel width
 constexpr int kTW = 64;    // output tile width of the panel kernels
 constexpr int kFG = 16;    // frequencies per thread in the forward transform
-constexpr int kOG = 16;    // output times per thread in the back-transform
+constexpr int kOG = 16;    // output times are padded to a multiple of this (the back-transform's MFMA rows)
 
 // Blocks that share an element tile land on one XCD (blockIdx % 8 picks
 // the XCD), one after the other: the tile's input stays in that XCD's L2.
@@ -87,44 +87,25 @@ __device__ __forceinline__ void cmul(double ar, double ai, double br, double bi,
   ci = ar * bi + ai * br;
 }
 
-// Gauss-Jordan, panel k0 (columns K = [k0, k0 + 32)), first half: every
-// block inverts the diagonal block P = A_KK^{-1} in LDS, copies rows
-// [64 ct, 64 ct + 64) of the column panel A_{:,K} to colbuf, and replaces
-// its 64 columns j (outside K) of the row panel by P A_Kj.  Block ct = 0
-// also stores P.  Grid (column tiles, matrices).
-__global__ __launch_bounds__(256) void k_gj_panel(double* a, int64_t np, int64_t k0, double* colbuf,
-                                                  double* pbuf, int* err) {
+// Gauss-Jordan, panel k0 (columns K = [k0, k0 + 32)), first step: one block
+// per matrix inverts the diagonal block P = A_KK^{-1} in LDS (without
+// pivoting: the Dyson matrices are complex symmetric with a positive
+// definite imaginary part, so every leading block is invertible) and stores
+// it in pbuf.  A vanishing or non-finite pivot sets *err.  Grid (matrices).
+__global__ __launch_bounds__(256) void k_gj_pivot(const double* a, int64_t np, int64_t k0, double* pbuf,
+                                                  int* err) {
   __shared__ double dr[kNB][kNB + 1], di[kNB][kNB + 1];
-  __shared__ double rr[kNB][kTW + 1], ri[kNB][kTW + 1];
   __shared__ double fr[kNB], fi[kNB];
-  const int tid = threadIdx.x, ct = blockIdx.x;
-  const int64_t mat = blockIdx.y, np2 = np * np;
-  double* ar = a + mat * 2 * np2;
-  double* ai = ar + np2;
-  const int64_t j0 = (int64_t)ct * kTW;
+  const int tid = threadIdx.x;
+  const int64_t mat = blockIdx.x, np2 = np * np;
+  const double* ar = a + mat * 2 * np2;
+  const double* ai = ar + np2;
   for (int x = tid; x < kNB * kNB; x += 256) {
     const int r = x / kNB, c = x % kNB;
     dr[r][c] = ar[(k0 + r) * np + k0 + c];
     di[r][c] = ai[(k0 + r) * np + k0 + c];
   }
-  for (int x = tid; x < kNB * kTW; x += 256) {
-    const int r = x / kTW, c = x % kTW;
-    const int64_t j = j0 + c;
-    rr[r][c] = j < np ? ar[(k0 + r) * np + j] : 0.0;
-    ri[r][c] = j < np ? ai[(k0 + r) * np + j] : 0.0;
-  }
-  double* cbr = colbuf + mat * 2 * np * kNB;
-  double* cbi = cbr + np * kNB;
-  for (int x = tid; x < kTW * kNB; x += 256) {
-    const int r = x / kNB, c = x % kNB;
-    const int64_t i = j0 + r;
-    if (i < np) {
-      cbr[i * kNB + c] = ar[i * np + k0 + c];
-      cbi[i * kNB + c] = ai[i * np + k0 + c];
-    }
-  }
   __syncthreads();
-  // in-place Gauss-Jordan inverse of the 32 x 32 diagonal block
   for (int p = 0; p < kNB; ++p) {
     if (tid < kNB) {
       fr[tid] = dr[tid][p];
@@ -133,7 +114,7 @@ __global__ __launch_bounds__(256) void k_gj_panel(double* a, int64_t np, int64_t
     __syncthreads();
     const double pr = fr[p], pi = fi[p];
     const double den = pr * pr + pi * pi;
-    if (tid == 0 && ct == 0 && !(den >= 1e-280 && den <= 1e280)) atomicOr(err, 1);
+    if (tid == 0 && !(den >= 1e-280 && den <= 1e280)) atomicOr(err, 1);
     const double vr = pr / den, vi = -pi / den;   // 1 / pivot
     if (tid < kNB) {
       if (tid == p) {
@@ -163,14 +144,49 @@ __global__ __launch_bounds__(256) void k_gj_panel(double* a, int64_t np, int64_t
     }
     __syncthreads();
   }
-  if (ct == 0) {
-    double* pr_ = pbuf + mat * 2 * kNB * kNB;
-    for (int x = tid; x < kNB * kNB; x += 256) {
-      const int r = x / kNB, c = x % kNB;
-      pr_[x] = dr[r][c];
-      pr_[kNB * kNB + x] = di[r][c];
+  double* pr_ = pbuf + mat * 2 * kNB * kNB;
+  for (int x = tid; x < kNB * kNB; x += 256) {
+    const int r = x / kNB, c = x % kNB;
+    pr_[x] = dr[r][c];
+    pr_[kNB * kNB + x] = di[r][c];
+  }
+}
+
+// Second step: every block copies rows [64 ct, 64 ct + 64) of the column
+// panel A_{:,K} to colbuf and replaces its 64 columns j (outside K) of the
+// row panel by P A_Kj, with P from pbuf.  Grid (column tiles, matrices).
+__global__ __launch_bounds__(256) void k_gj_panel(double* a, int64_t np, int64_t k0, double* colbuf,
+                                                  const double* pbuf) {
+  __shared__ double dr[kNB][kNB + 1], di[kNB][kNB + 1];
+  __shared__ double rr[kNB][kTW + 1], ri[kNB][kTW + 1];
+  const int tid = threadIdx.x, ct = blockIdx.x;
+  const int64_t mat = blockIdx.y, np2 = np * np;
+  double* ar = a + mat * 2 * np2;
+  double* ai = ar + np2;
+  const int64_t j0 = (int64_t)ct * kTW;
+  const double* pr_ = pbuf + mat * 2 * kNB * kNB;
+  for (int x = tid; x < kNB * kNB; x += 256) {
+    const int r = x / kNB, c = x % kNB;
+    dr[r][c] = pr_[x];
+    di[r][c] = pr_[kNB * kNB + x];
+  }
+  for (int x = tid; x < kNB * kTW; x += 256) {
+    const int r = x / kTW, c = x % kTW;
+    const int64_t j = j0 + c;
+    rr[r][c] = j < np ? ar[(k0 + r) * np + j] : 0.0;
+    ri[r][c] = j < np ? ai[(k0 + r) * np + j] : 0.0;
+  }
+  double* cbr = colbuf + mat * 2 * np * kNB;
+  double* cbi = cbr + np * kNB;
+  for (int x = tid; x < kTW * kNB; x += 256) {
+    const int r = x / kNB, c = x % kNB;
+    const int64_t i = j0 + r;
+    if (i < np) {
+      cbr[i * kNB + c] = ar[i * np + k0 + c];
+      cbi[i * kNB + c] = ai[i * np + k0 + c];
     }
   }
+  __syncthreads();
   // row panel: R_Kj = P A_Kj for the tile's columns outside K
   const int c = tid % kTW, rg = tid / kTW;   // 4 groups of 8 rows
   const int64_t j = j0 + c;
@@ -195,10 +211,12 @@ __global__ __launch_bounds__(256) void k_gj_panel(double* a, int64_t np, int64_t
 // with C the column panel saved by the first half and R' the new row panel
 // (P on the K columns), on FP64 MFMAs (complex product as four real ones);
 // the (K, K) block takes P.  Grid (column tiles, row tiles, matrices).
+// Each lane loads its MFMA operands straight from the panels (which stay in
+// L2: every tile of a matrix reads the same ones), so the kernel needs no
+// LDS and enough workgroups stay resident to keep many tiles' loads in
+// flight; the update is a stream over the matrices (8 flop per byte).
 __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_t k0, const double* colbuf,
                                                    const double* pbuf) {
-  __shared__ double cs[2][kTW][kNB + 1];
-  __shared__ double rs[2][kNB][kTW + 1];
   const int tid = threadIdx.x;
   const int64_t j0 = (int64_t)blockIdx.x * kTW, i0 = (int64_t)blockIdx.y * kTW, mat = blockIdx.z;
   const int64_t np2 = np * np;
@@ -211,7 +229,7 @@ __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_
   const int lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
   const int lr = lane & 15, lg = lane >> 4;
   // the tile's old values, loaded first so that their latency overlaps the
-  // staging and the MFMAs (accumulator r of a lane: row lane / 16 + 4 r,
+  // operand loads and the MFMAs (accumulator r of a lane: row lane / 16 + 4 r,
   // column lane % 16)
   double oldr[2][2][4], oldi[2][2][4];
 #pragma unroll
@@ -226,29 +244,20 @@ __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_
         oldr[bi][bj][r] = live ? ar[gi * np + gj] : 0.0;
         oldi[bi][bj][r] = live ? ai[gi * np + gj] : 0.0;
       }
-  for (int x = tid; x < kTW * kNB; x += 256) {
-    const int r = x / kNB, c = x % kNB;
-    const int64_t i = i0 + r;
-    cs[0][r][c] = i < np ? cbr[i * kNB + c] : 0.0;
-    cs[1][r][c] = i < np ? cbi[i * kNB + c] : 0.0;
+  // operand rows (column panel) and columns (row panel) of this lane
+  int64_t crow[2], rcol[2];
+  bool cok[2], rin[2], rok[2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi) {
+    crow[bi] = i0 + 32 * wr + 16 * bi + lr;
+    cok[bi] = crow[bi] < np;
   }
-  for (int x = tid; x < kNB * kTW; x += 256) {
-    const int r = x / kTW, c = x % kTW;
-    const int64_t j = j0 + c;
-    double vr = 0.0, vi = 0.0;
-    if (j < np) {
-      if (j >= k0 && j < k0 + kNB) {
-        vr = pr_[r * kNB + (j - k0)];
-        vi = pi_[r * kNB + (j - k0)];
-      } else {
-        vr = ar[(k0 + r) * np + j];
-        vi = ai[(k0 + r) * np + j];
-      }
-    }
-    rs[0][r][c] = vr;
-    rs[1][r][c] = vi;
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj) {
+    rcol[bj] = j0 + 32 * wc + 16 * bj + lr;
+    rok[bj] = rcol[bj] < np;
+    rin[bj] = rcol[bj] >= k0 && rcol[bj] < k0 + kNB;
   }
-  __syncthreads();
   f64x4_t accr[2][2], acci[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -258,17 +267,28 @@ __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_
       for (int r = 0; r < 4; ++r) accr[bi][bj][r] = acci[bi][bj][r] = 0.0;
 #pragma unroll
   for (int ks = 0; ks < kNB / 4; ++ks) {
+    const int k = 4 * ks + lg;                  // panel index of this lane's operands
     double xr[2], xi[2], yr[2], yi[2], yn[2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
-      xr[bi] = cs[0][32 * wr + 16 * bi + lr][4 * ks + lg];
-      xi[bi] = cs[1][32 * wr + 16 * bi + lr][4 * ks + lg];
+      xr[bi] = cok[bi] ? cbr[crow[bi] * kNB + k] : 0.0;
+      xi[bi] = cok[bi] ? cbi[crow[bi] * kNB + k] : 0.0;
     }
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
-      yr[bj] = rs[0][4 * ks + lg][32 * wc + 16 * bj + lr];
-      yi[bj] = rs[1][4 * ks + lg][32 * wc + 16 * bj + lr];
-      yn[bj] = -yi[bj];
+      double vr = 0.0, vi = 0.0;
+      if (rok[bj]) {
+        if (rin[bj]) {
+          vr = pr_[k * kNB + (rcol[bj] - k0)];
+          vi = pi_[k * kNB + (rcol[bj] - k0)];
+        } else {
+          vr = ar[(k0 + k) * np + rcol[bj]];
+          vi = ai[(k0 + k) * np + rcol[bj]];
+        }
+      }
+      yr[bj] = vr;
+      yi[bj] = vi;
+      yn[bj] = -vi;
     }
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -304,51 +324,85 @@ __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_
 }
 
 // D(i w_f) = A^{-1} - G0~(i w_f) (G0~ = diag 1 / (mu - eps_i + i w_f), zero
-// on the padding) accumulated into the back-transform sums
-//   pc[o] += sum_f cs[f][o].cos Re D_f,  ps[o] += sum_f cs[f][o].sin Im D_f
-// (cs [nc][ntop][2]: one frequency's phases are contiguous, read as
-// wave-uniform wide scalar loads).
-__global__ __launch_bounds__(256) void k_iw_back(const double* __restrict__ a, int32_t nc, int64_t np, int64_t n,
+// on the padding, where A^{-1} holds 1) accumulated into the back-transform
+// sums
+//   pc[o][e] += sum_f cs[f][o].cos Re D_f[e],  ps[o][e] += sum_f cs[f][o].sin Im D_f[e]
+// (cs [nc][ntop][2]) as two products (output times x frequencies) x
+// (frequencies x matrix elements) on FP64 MFMAs.  A block of 8 waves covers
+// kBR output rows and 64 elements: waves 0-3 the cosine sums of 16 elements
+// each, waves 4-7 the sine sums.  The phases of kBK frequencies at a time
+// are staged in LDS and shared by the waves; every wave streams its
+// elements of D once per row block, with the G0 correction applied to the
+// diagonal as it is loaded.  Grid (element tiles, row blocks).
+constexpr int kBRT = 10;             // 16-row MFMA tiles per row block
+constexpr int kBR = 16 * kBRT;       // output rows per block
+constexpr int kBK = 16;              // frequencies per LDS stage
+__global__ __launch_bounds__(512) void k_iw_back(const double* __restrict__ a, int32_t nc, int64_t np, int64_t n,
                                                   const double* __restrict__ shift, const double* __restrict__ om,
-                                                  const double* __restrict__ cs, int32_t nto, int32_t ncp,
+                                                  const double* __restrict__ cs, int32_t nto, int32_t ntop,
                                                   double* __restrict__ pc, double* __restrict__ ps) {
-  int64_t tile;
-  int g;
-  xcd_split(blockIdx.x, (nto + kOG - 1) / kOG, tile, g);
+  __shared__ double ph[2][kBK][kBR];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int part = w >> 2, cb = w & 3;               // part 0: cosine / Re, 1: sine / Im
+  const int lr = lane & 15, lg = lane >> 4;
   const int64_t np2 = np * np;
-  const int64_t e = tile * 256 + threadIdx.x;
-  if (e >= np2) return;
-  const int64_t i = e / np, j = e - i * np;
-  const bool dg = i == j && i < n, pad = i == j && i >= n;
-  const double s = dg ? shift[i] : 0.0;
-  const int o0 = g * kOG;
-  const int64_t ntop = (int64_t)((nto + kOG - 1) / kOG) * kOG;
-  double qc[kOG], qs[kOG];
-#pragma unroll
-  for (int o = 0; o < kOG; ++o) qc[o] = qs[o] = 0.0;
-#pragma unroll 2
-  for (int f = 0; f < nc; ++f) {
-    double dr = a[(int64_t)(2 * f) * np2 + e], di = a[(int64_t)(2 * f + 1) * np2 + e];
+  const int64_t e = (int64_t)blockIdx.x * 64 + 16 * cb + lr;   // this lane's element (B operand column)
+  const int o0 = blockIdx.y * kBR;
+  const bool live = e < np2;
+  const int64_t i = live ? e / np : 0, j = live ? e - i * np : 1;
+  const bool dg = live && i == j && i < n, pad = live && i == j && i >= n;
+  const double sh = dg ? shift[i] : 0.0;
+  const double* src = a + (int64_t)part * np2 + (live ? e : 0);
+  // operand of k step ks of the stage starting at frequency f0: D_f[e], f = f0 + 4 ks + lg
+  auto bval = [&](int f) -> double {
+    if (!live || f >= nc) return 0.0;
+    double v = src[(int64_t)(2 * f) * np2];
     if (dg) {
-      const double wf = om[f], den = s * s + wf * wf;
-      dr -= s / den;
-      di += wf / den;
-    } else if (pad) {
-      dr -= 1.0;
+      const double wf = om[f], den = sh * sh + wf * wf;
+      v += part == 0 ? -sh / den : wf / den;
+    } else if (pad && part == 0) {
+      v -= 1.0;
     }
-    const double* p = cs + ((int64_t)f * ntop + o0) * 2;
+    return v;
+  };
+  f64x4_t acc[kBRT];
 #pragma unroll
-    for (int o = 0; o < kOG; ++o) {
-      qc[o] = fma(p[2 * o], dr, qc[o]);
-      qs[o] = fma(p[2 * o + 1], di, qs[o]);
+  for (int t = 0; t < kBRT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[t][r] = 0.0;
+  double bn[kBK / 4];
+#pragma unroll
+  for (int ks = 0; ks < kBK / 4; ++ks) bn[ks] = bval(4 * ks + lg);
+  for (int f0 = 0; f0 < nc; f0 += kBK) {
+    __syncthreads();                                 // the previous stage's phases are consumed
+    for (int x = tid; x < 2 * kBK * kBR; x += 512) {
+      const int pp = x / (kBK * kBR), kk = (x / kBR) % kBK, o = x % kBR;
+      const int f = f0 + kk, oo = o0 + o;
+      ph[pp][kk][o] = f < nc && oo < ntop ? cs[((int64_t)f * ntop + oo) * 2 + pp] : 0.0;
     }
-  }
+    double bc[kBK / 4];
 #pragma unroll
-  for (int o = 0; o < kOG; ++o) {
-    if (o0 + o >= nto) break;
-    pc[(int64_t)(o0 + o) * np2 + e] += qc[o];
-    ps[(int64_t)(o0 + o) * np2 + e] += qs[o];
+    for (int ks = 0; ks < kBK / 4; ++ks) bc[ks] = bn[ks];
+    if (f0 + kBK < nc) {
+#pragma unroll
+      for (int ks = 0; ks < kBK / 4; ++ks) bn[ks] = bval(f0 + kBK + 4 * ks + lg);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kBK / 4; ++ks)
+#pragma unroll
+      for (int t = 0; t < kBRT; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ph[part][4 * ks + lg][16 * t + lr], bc[ks], acc[t], 0, 0, 0);
   }
+  if (!live) return;
+  double* out = part == 0 ? pc : ps;
+#pragma unroll
+  for (int t = 0; t < kBRT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = o0 + 16 * t + lg + 4 * r;        // accumulator r: row lane / 16 + 4 r, column lane % 16
+      if (o < nto) out[(int64_t)o * np2 + e] += acc[t][r];
+    }
 }
 
 // Per matrix f of a chunk: tr[2f] = sum_{i<n} Re D_ii(i w_f) and tr[2f + 1] =
@@ -574,17 +628,18 @@ void launch_sig_iw(const double* sig, int64_t ntau, int64_t np, int64_t n, const
 void launch_gj_invert(double* a, int32_t nmat, int64_t np, double* colbuf, double* pbuf, int* err, hipStream_t st) {
   const unsigned tiles = (unsigned)((np + kTW - 1) / kTW);
   for (int64_t k0 = 0; k0 < np; k0 += kNB) {
-    hipLaunchKernelGGL(k_gj_panel, dim3(tiles, (unsigned)nmat), dim3(256), 0, st, a, np, k0, colbuf, pbuf, err);
+    hipLaunchKernelGGL(k_gj_pivot, dim3((unsigned)nmat), dim3(256), 0, st, (const double*)a, np, k0, pbuf, err);
+    hipLaunchKernelGGL(k_gj_panel, dim3(tiles, (unsigned)nmat), dim3(256), 0, st, a, np, k0, colbuf,
+                       (const double*)pbuf);
     hipLaunchKernelGGL(k_gj_update, dim3(tiles, tiles, (unsigned)nmat), dim3(256), 0, st, a, np, k0,
                        (const double*)colbuf, (const double*)pbuf);
   }
 }
 
 void launch_iw_back(const double* a, int32_t nc, int64_t np, int64_t n, const double* shift, const double* om,
-                    const double* cs, int32_t nto, int32_t ncp, double* pc, double* ps, hipStream_t st) {
-  const int64_t tiles = (np * np + 255) / 256;
-  const unsigned grid = (unsigned)(((tiles + 7) / 8) * 8 * ((nto + kOG - 1) / kOG));
-  hipLaunchKernelGGL(k_iw_back, dim3(grid), dim3(256), 0, st, a, nc, np, n, shift, om, cs, nto, ncp, pc, ps);
+                    const double* cs, int32_t nto, int32_t ntop, double* pc, double* ps, hipStream_t st) {
+  const dim3 grid((unsigned)((np * np + 63) / 64), (unsigned)((ntop + kBR - 1) / kBR));
+  hipLaunchKernelGGL(k_iw_back, grid, dim3(512), 0, st, a, nc, np, n, shift, om, cs, nto, ntop, pc, ps);
 }
 
 void launch_iw_diag(const double* a, int32_t nc, int64_t np, int64_t n, const double* shift, const double* om,
