@@ -23,7 +23,7 @@ namespace {
 
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kNB = 32;    // Gauss-Jordan panel width
+constexpr int kNB = 32;    // Gauss-Jordan panel width (a narrower last panel is handled too)
 constexpr int kTW = 64;    // output tile width of the panel kernels
 constexpr int kFG = 16;    // frequencies per thread in the forward transform
 constexpr int kOG = 16;    // output times are padded to a multiple of this (the back-transform's MFMA rows)
@@ -34,6 +34,16 @@ __device__ __forceinline__ void xcd_split(unsigned b, int ng, int64_t& tile, int
   const unsigned xcd = b & 7u, r = b >> 3;
   g = (int)(r % (unsigned)ng);
   tile = (int64_t)(r / (unsigned)ng) * 8 + xcd;
+}
+
+// Workgroup b of a 1-D grid of `total` -> logical index, so that each XCD
+// (workgroups are dispatched round-robin over the 8) runs one contiguous
+// range of logical indices: with index = matrix * tiles + tile, whole
+// matrices stay on one XCD and the panels a kernel writes for a matrix are
+// read by the next kernel from the same L2.
+__device__ __forceinline__ int64_t xcd_range(int64_t b, int64_t total) {
+  const int64_t per = total / 8, rem = total % 8, xcd = b % 8, idx = b / 8;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
 // A(i w_f) for the frequencies of one chunk from Sigma~(tau_t) (padded,
@@ -87,7 +97,7 @@ __device__ __forceinline__ void cmul(double ar, double ai, double br, double bi,
   ci = ar * bi + ai * br;
 }
 
-// Gauss-Jordan, panel k0 (columns K = [k0, k0 + 32)), first step: one block
+// Gauss-Jordan, panel k0 (columns K = [k0, k0 + 32), or fewer at the end), first step: one block
 // per matrix inverts the diagonal block P = A_KK^{-1} in LDS (without
 // pivoting: the Dyson matrices are complex symmetric with a positive
 // definite imaginary part, so every leading block is invertible) and stores
@@ -97,13 +107,16 @@ __global__ __launch_bounds__(256) void k_gj_pivot(const double* a, int64_t np, i
   __shared__ double dr[kNB][kNB + 1], di[kNB][kNB + 1];
   __shared__ double fr[kNB], fi[kNB];
   const int tid = threadIdx.x;
-  const int64_t mat = blockIdx.x, np2 = np * np;
+  const int64_t mat = xcd_range(blockIdx.x, gridDim.x), np2 = np * np;
   const double* ar = a + mat * 2 * np2;
   const double* ai = ar + np2;
+  const int kb = (int)(np - k0 < kNB ? np - k0 : kNB);     // width of this panel
+  // a narrower last panel is completed by the identity, so P = diag(A_KK^{-1}, I)
   for (int x = tid; x < kNB * kNB; x += 256) {
     const int r = x / kNB, c = x % kNB;
-    dr[r][c] = ar[(k0 + r) * np + k0 + c];
-    di[r][c] = ai[(k0 + r) * np + k0 + c];
+    const bool in = r < kb && c < kb;
+    dr[r][c] = in ? ar[(k0 + r) * np + k0 + c] : (r == c ? 1.0 : 0.0);
+    di[r][c] = in ? ai[(k0 + r) * np + k0 + c] : 0.0;
   }
   __syncthreads();
   for (int p = 0; p < kNB; ++p) {
@@ -154,16 +167,18 @@ __global__ __launch_bounds__(256) void k_gj_pivot(const double* a, int64_t np, i
 
 // Second step: every block copies rows [64 ct, 64 ct + 64) of the column
 // panel A_{:,K} to colbuf and replaces its 64 columns j (outside K) of the
-// row panel by P A_Kj, with P from pbuf.  Grid (column tiles, matrices).
+// row panel by P A_Kj, with P from pbuf.  1-D grid of (matrix, column tile).
 __global__ __launch_bounds__(256) void k_gj_panel(double* a, int64_t np, int64_t k0, double* colbuf,
                                                   const double* pbuf) {
   __shared__ double dr[kNB][kNB + 1], di[kNB][kNB + 1];
   __shared__ double rr[kNB][kTW + 1], ri[kNB][kTW + 1];
-  const int tid = threadIdx.x, ct = blockIdx.x;
-  const int64_t mat = blockIdx.y, np2 = np * np;
+  const int tid = threadIdx.x;
+  const int64_t tiles = (np + kTW - 1) / kTW, q = xcd_range(blockIdx.x, gridDim.x);
+  const int64_t ct = q % tiles, mat = q / tiles, np2 = np * np;
   double* ar = a + mat * 2 * np2;
   double* ai = ar + np2;
   const int64_t j0 = (int64_t)ct * kTW;
+  const int kb = (int)(np - k0 < kNB ? np - k0 : kNB);     // width of this panel
   const double* pr_ = pbuf + mat * 2 * kNB * kNB;
   for (int x = tid; x < kNB * kNB; x += 256) {
     const int r = x / kNB, c = x % kNB;
@@ -173,8 +188,8 @@ __global__ __launch_bounds__(256) void k_gj_panel(double* a, int64_t np, int64_t
   for (int x = tid; x < kNB * kTW; x += 256) {
     const int r = x / kTW, c = x % kTW;
     const int64_t j = j0 + c;
-    rr[r][c] = j < np ? ar[(k0 + r) * np + j] : 0.0;
-    ri[r][c] = j < np ? ai[(k0 + r) * np + j] : 0.0;
+    rr[r][c] = j < np && r < kb ? ar[(k0 + r) * np + j] : 0.0;
+    ri[r][c] = j < np && r < kb ? ai[(k0 + r) * np + j] : 0.0;
   }
   double* cbr = colbuf + mat * 2 * np * kNB;
   double* cbi = cbr + np * kNB;
@@ -182,18 +197,19 @@ __global__ __launch_bounds__(256) void k_gj_panel(double* a, int64_t np, int64_t
     const int r = x / kNB, c = x % kNB;
     const int64_t i = j0 + r;
     if (i < np) {
-      cbr[i * kNB + c] = ar[i * np + k0 + c];
-      cbi[i * kNB + c] = ai[i * np + k0 + c];
+      cbr[i * kNB + c] = c < kb ? ar[i * np + k0 + c] : 0.0;
+      cbi[i * kNB + c] = c < kb ? ai[i * np + k0 + c] : 0.0;
     }
   }
   __syncthreads();
   // row panel: R_Kj = P A_Kj for the tile's columns outside K
-  const int c = tid % kTW, rg = tid / kTW;   // 4 groups of 8 rows
+  const int c = tid % kTW, rg = tid / kTW;   // 4 groups of kNB / 4 rows
   const int64_t j = j0 + c;
-  if (j >= np || (j >= k0 && j < k0 + kNB)) return;
-#pragma unroll
+  if (j >= np || (j >= k0 && j < k0 + kb)) return;
+#pragma unroll 4
   for (int q = 0; q < kNB / 4; ++q) {
     const int r = rg * (kNB / 4) + q;
+    if (r >= kb) break;
     double sr = 0.0, si = 0.0;
 #pragma unroll 8
     for (int l = 0; l < kNB; ++l) {
@@ -210,7 +226,7 @@ __global__ __launch_bounds__(256) void k_gj_panel(double* a, int64_t np, int64_t
 //   A_ij <- (j in K ? 0 : A_ij) - sum_k C_ik R'_kj
 // with C the column panel saved by the first half and R' the new row panel
 // (P on the K columns), on FP64 MFMAs (complex product as four real ones);
-// the (K, K) block takes P.  Grid (column tiles, row tiles, matrices).
+// the (K, K) block takes P.  1-D grid of (matrix, row tile, column tile).
 // Each lane loads its MFMA operands straight from the panels (which stay in
 // L2: every tile of a matrix reads the same ones), so the kernel needs no
 // LDS and enough workgroups stay resident to keep many tiles' loads in
@@ -218,7 +234,9 @@ __global__ __launch_bounds__(256) void k_gj_panel(double* a, int64_t np, int64_t
 __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_t k0, const double* colbuf,
                                                    const double* pbuf) {
   const int tid = threadIdx.x;
-  const int64_t j0 = (int64_t)blockIdx.x * kTW, i0 = (int64_t)blockIdx.y * kTW, mat = blockIdx.z;
+  const int64_t tiles = (np + kTW - 1) / kTW, q = xcd_range(blockIdx.x, gridDim.x);
+  const int64_t mat = q / (tiles * tiles), t2 = q % (tiles * tiles);
+  const int64_t j0 = (t2 % tiles) * kTW, i0 = (t2 / tiles) * kTW;
   const int64_t np2 = np * np;
   double* ar = a + mat * 2 * np2;
   double* ai = ar + np2;
@@ -228,6 +246,7 @@ __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_
   const double* pi_ = pr_ + kNB * kNB;
   const int lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
   const int lr = lane & 15, lg = lane >> 4;
+  const int64_t k1 = np - k0 < kNB ? np : k0 + kNB;       // K = [k0, k1)
   // the tile's old values, loaded first so that their latency overlaps the
   // operand loads and the MFMAs (accumulator r of a lane: row lane / 16 + 4 r,
   // column lane % 16)
@@ -240,7 +259,7 @@ __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_
       for (int r = 0; r < 4; ++r) {
         const int64_t gi = i0 + 32 * wr + 16 * bi + lg + 4 * r;
         const int64_t gj = j0 + 32 * wc + 16 * bj + lr;
-        const bool live = gi < np && gj < np && !(gi >= k0 && gi < k0 + kNB) && !(gj >= k0 && gj < k0 + kNB);
+        const bool live = gi < np && gj < np && !(gi >= k0 && gi < k1) && !(gj >= k0 && gj < k1);
         oldr[bi][bj][r] = live ? ar[gi * np + gj] : 0.0;
         oldi[bi][bj][r] = live ? ai[gi * np + gj] : 0.0;
       }
@@ -256,7 +275,7 @@ __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_
   for (int bj = 0; bj < 2; ++bj) {
     rcol[bj] = j0 + 32 * wc + 16 * bj + lr;
     rok[bj] = rcol[bj] < np;
-    rin[bj] = rcol[bj] >= k0 && rcol[bj] < k0 + kNB;
+    rin[bj] = rcol[bj] >= k0 && rcol[bj] < k1;
   }
   f64x4_t accr[2][2], acci[2][2];
 #pragma unroll
@@ -277,7 +296,7 @@ __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
       double vr = 0.0, vi = 0.0;
-      if (rok[bj]) {
+      if (rok[bj] && k0 + k < k1) {
         if (rin[bj]) {
           vr = pr_[k * kNB + (rcol[bj] - k0)];
           vi = pi_[k * kNB + (rcol[bj] - k0)];
@@ -309,7 +328,7 @@ __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_
         const int64_t gi = i0 + 32 * wr + 16 * bi + lg + 4 * r;
         const int64_t gj = j0 + 32 * wc + 16 * bj + lr;
         if (gi >= np || gj >= np) continue;
-        const bool ki = gi >= k0 && gi < k0 + kNB, kj = gj >= k0 && gj < k0 + kNB;
+        const bool ki = gi >= k0 && gi < k1, kj = gj >= k0 && gj < k1;
         const int64_t o = gi * np + gj;
         if (ki) {
           if (kj) {
@@ -629,9 +648,9 @@ void launch_gj_invert(double* a, int32_t nmat, int64_t np, double* colbuf, doubl
   const unsigned tiles = (unsigned)((np + kTW - 1) / kTW);
   for (int64_t k0 = 0; k0 < np; k0 += kNB) {
     hipLaunchKernelGGL(k_gj_pivot, dim3((unsigned)nmat), dim3(256), 0, st, (const double*)a, np, k0, pbuf, err);
-    hipLaunchKernelGGL(k_gj_panel, dim3(tiles, (unsigned)nmat), dim3(256), 0, st, a, np, k0, colbuf,
+    hipLaunchKernelGGL(k_gj_panel, dim3(tiles * (unsigned)nmat), dim3(256), 0, st, a, np, k0, colbuf,
                        (const double*)pbuf);
-    hipLaunchKernelGGL(k_gj_update, dim3(tiles, tiles, (unsigned)nmat), dim3(256), 0, st, a, np, k0,
+    hipLaunchKernelGGL(k_gj_update, dim3(tiles * tiles * (unsigned)nmat), dim3(256), 0, st, a, np, k0,
                        (const double*)colbuf, (const double*)pbuf);
   }
 }
