@@ -1772,12 +1772,13 @@ void adaptive_core(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const 
     std::vector<double> dE, de;              // per probe pair: energy, and [kp][ntau] traces
     double bias = 0.0;
     int64_t pairs = 0;
-    // BF16 into `lo` and BF16X3 into psum3 for probe pairs [k0, k1); their
-    // trace differences appended to dE / de
+    // BF16X3 into psum3 for probe pairs [k0, k1) (and, with lo, BF16 into
+    // lo; without, their BF16 traces are those the sampling already left in
+    // e_samples); their trace differences appended to dE / de
     auto probe = [&](int64_t k0, int64_t k1, double* lo) {
       smp.s0 = k0;
       smp.ns = k1 - k0;
-      run_stoch(ctx, split, B, G, Gbar, ntau, &smp, Prec::BF16, lo, e_samples + k0 * ntau);
+      if (lo) run_stoch(ctx, split, B, G, Gbar, ntau, &smp, Prec::BF16, lo, e_samples + k0 * ntau);
       run_stoch(ctx, split, B, G, Gbar, ntau, &smp, Prec::BF16X3, psum3, eprobe + k0 * ntau);
       const int64_t cnt = k1 - k0;
       std::vector<double> lv((size_t)(cnt * ntau)), hv((size_t)(cnt * ntau));
@@ -1835,11 +1836,11 @@ void adaptive_core(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const 
         stat(pairs, h);
         bool done = stderr_upper(h[2], pairs) < target || pairs >= max_pairs;
         if (done && autop && wp == Prec::BF16 && !bf16_ok(pairs, h[2]) && kp < std::min(kmax, pairs)) {
-          // a larger probe: pairs [kp, k1) ran in BF16 inside `sum`; their
-          // BF16 sums go to psum16x and are taken out again by the correction
+          // a larger probe: pairs [kp, k1) ran in BF16 inside `sum` (their
+          // traces are in e_samples), so only their BF16X3 level runs now;
+          // their separate BF16 sums are made only if the correction is used
           const int64_t k1 = std::min(kmax, pairs);
-          psum16x = (double*)ctx_buf(ctx, "a_probe_lox", mat * 8, true);
-          probe(kp, k1, psum16x);
+          probe(kp, k1, nullptr);
           kp = k1;
         }
         if (done && autop && wp == Prec::BF16 && !bf16_ok(pairs, h[2])) {
@@ -1865,7 +1866,15 @@ void adaptive_core(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const 
     if (autop && wp == Prec::BF16) {
       // Sigma_sum and the samples to the BF16X3 level: with lo the BF16 sums
       // of all kp probe pairs, sum += psum16 + (pairs/kp)(hi - lo); the
-      // pairs of psum16x are already in `sum`, so they enter only through lo
+      // pairs the probe grew by (psum16x, their BF16 sums, made here) are
+      // already in `sum`, so they enter only through lo
+      const int64_t kp0 = std::min<int64_t>(kAutoProbe0, kmax);
+      if (kp > kp0) {
+        psum16x = (double*)ctx_buf(ctx, "a_probe_lox", mat * 8, true);
+        smp.s0 = kp0;
+        smp.ns = kp - kp0;
+        run_stoch(ctx, split, B, G, Gbar, ntau, &smp, Prec::BF16, psum16x, e_samples + kp0 * ntau);
+      }
       const double c = (double)pairs / (double)kp;
       launch_level_correct(sum, psum3, psum16, (int64_t)mat, c, ctx->stream);
       if (psum16x) {
