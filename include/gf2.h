@@ -490,8 +490,12 @@ gf2_status gf2_sigma_batch(gf2_ctx* ctx, int32_t nitem, const gf2_batch_item* it
  * Gbar(tau)).  If it is not, the probe grows to min(8, pairs) pairs (their
  * BF16X3 runs added); if it still is not, every pair is taken in BF16X3
  * (same theta: the probe pairs from the probe, the others recomputed) and
- * sampling continues in BF16X3.  res->precision reports BF16C or BF16X3; res->bias_probe the
- * |mean d_E| removed.  batch must be >= 2.
+ * sampling continues in BF16X3.  When the first probe already puts twice
+ * std(d_E) above 3 x 0.1 x the spread std(E) of its own BF16X3 pair
+ * energies (the two standard errors fall together while the probe holds
+ * every pair, so a larger probe would not help), sampling goes on in BF16X3
+ * from there without the BF16 batch.  res->precision reports BF16C or
+ * BF16X3; res->bias_probe the |mean d_E| removed.  batch must be >= 2.
  *
  * Inputs as gf2_sigma_stoch; w host [ntau] quadrature weights; Sigma_det
  * device [ntau][n][n] (gf2_sigma_det).  Outputs: Sigma device [ntau][n][n]

@@ -26,6 +26,9 @@ namespace {
 constexpr double kGM = 0.5;   // E = -1/2 int Tr(Sigma Gbar): the MP2 limit fixes it
 constexpr int64_t kLevelProbe = 8;   // pairs run at both levels (BF16 and BF16X3) by BF16C and AUTO
 constexpr int64_t kAutoProbe0 = 2;   // AUTO's first probe; it grows to kLevelProbe where needed
+// AUTO goes to BF16X3 at once when its first probe already puts the BF16
+// correction this many times above what the error bar allows
+constexpr double kAutoEarly = 3.0;
 
 // ------------------------------------------------------------ scratch ----
 // Named device buffers owned by the context (grown on demand, never shrunk,
@@ -1770,6 +1773,7 @@ void adaptive_core(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const 
     double* eprobe = nullptr;
     double* psum16x = nullptr;                // BF16 sums of probe pairs that also sit in `sum`
     std::vector<double> dE, de;              // per probe pair: energy, and [kp][ntau] traces
+    std::vector<double> eh;                  // per probe pair: its BF16X3 energy
     double bias = 0.0;
     int64_t pairs = 0;
     // BF16X3 into psum3 for probe pairs [k0, k1) (and, with lo, BF16 into
@@ -1785,11 +1789,13 @@ void adaptive_core(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const 
       d2h(ctx, lv.data(), e_samples + k0 * ntau, lv.size());
       d2h(ctx, hv.data(), eprobe + k0 * ntau, hv.size());
       dE.resize((size_t)k1, 0.0);
+      eh.resize((size_t)k1, 0.0);
       de.resize((size_t)(k1 * ntau), 0.0);
       for (int64_t q = 0; q < cnt; ++q)
         for (int64_t t = 0; t < ntau; ++t) {
           de[(k0 + q) * ntau + t] = hv[q * ntau + t] - lv[q * ntau + t];
           dE[k0 + q] += -kGM * w[t] * de[(k0 + q) * ntau + t];
+          eh[k0 + q] += -kGM * w[t] * hv[q * ntau + t];
         }
       double m = 0.0;
       for (int64_t q = 0; q < k1; ++q) m += dE[q];
@@ -1801,6 +1807,29 @@ void adaptive_core(gf2_ctx* ctx, const gf2_split_h* split, const void* B, const 
       eprobe = (double*)ctx_buf(ctx, "a_probe_e", (size_t)(kmax * ntau) * 8);
       probe(0, kp, psum16);
       pairs = kp;
+      // Early decision.  While the probe holds every pair, the correction's
+      // uncertainty std(d)/sqrt(kp) and the standard error std(E)/sqrt(pairs)
+      // fall together, so their ratio on the first probe (the spread of its
+      // BF16X3 energies standing in for the error the batch will reach) is
+      // what a larger probe would see too.  Far above the bar, BF16 would be
+      // rejected after the batch anyway: the probe pairs' BF16X3 sums and
+      // traces become the samples and the sampling goes on in BF16X3.
+      if (kp >= 2) {
+        auto sd = [&](const std::vector<double>& x) {
+          double m = 0.0, v = 0.0;
+          for (int64_t q = 0; q < kp; ++q) m += x[q];
+          m /= (double)kp;
+          for (int64_t q = 0; q < kp; ++q) v += (x[q] - m) * (x[q] - m);
+          return std::sqrt(v / (double)(kp - 1));
+        };
+        const double unc2 = 2.0 * sd(dE);
+        if (unc2 > 0.0 && unc2 > kAutoEarly * 0.1 * sd(eh)) {
+          wp = Prec::BF16X3;
+          GF2_HIP(hipMemcpyAsync(sum, psum3, mat * 8, hipMemcpyDeviceToDevice, ctx->stream));
+          GF2_HIP(hipMemcpyAsync(e_samples, eprobe, (size_t)(kp * ntau) * 8, hipMemcpyDeviceToDevice,
+                                 ctx->stream));
+        }
+      }
     }
     // sample mean and standard error of the mean of x[0..k)
     auto mean_se = [](const double* x, int64_t k, int64_t stride) {
