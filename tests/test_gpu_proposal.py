@@ -236,4 +236,31 @@ def test_learned_proposal_gains_over_pm1(ctx):
     assert (s_lrn / s_rad) ** 2 < 0.8
     for mm, ss in ((m_uni, s_uni), (m_lrn, s_lrn)):
         assert abs(mm - m_rad) < 4.0 * np.hypot(ss, s_rad) / np.sqrt(ns)
+    _auto_early_decision(ctx, held, pl, k)
     held["spl"].free()
+
+
+def _auto_early_decision(ctx, held, p, k, seed=5):
+    """AUTO's decision on its first probe (2 pairs), recomputed here from
+    the two pairs in BF16 and BF16X3: with r = 2 std(dE) / (0.1 std(E)), r
+    above 3 must send the whole run to BF16X3 at once, with the results of a
+    plain BF16X3 run of the same pairs.  The learned vectors' spread is so
+    small that r is well above 3 on this chain."""
+    e = {}
+    for prec in ("bf16", "bf16x3"):
+        _, es = ctx.sigma_tau(held["spl"], held["B"], held["G"], held["Gb"], 2, seed=seed, prec=prec, p=p, classes=k)
+        e[prec] = -0.5 * (es.cpu().numpy() @ held["w"])
+    r = 2.0 * np.std(e["bf16x3"] - e["bf16"], ddof=1) / (0.1 * np.std(e["bf16x3"], ddof=1))
+    kw = dict(batch=8, max_pairs=8, seed=seed, p=p, classes=k)
+    n_e = float(held["geo"].n)
+    _, _, es_a, info = ctx.energy_adaptive_det(held["spl"], held["B"], held["G"], held["Gb"], held["w"], n_e, 1e-3,
+                                               prec="auto", **kw)
+    _, _, es_x, ref = ctx.energy_adaptive_det(held["spl"], held["B"], held["G"], held["Gb"], held["w"], n_e, 1e-3,
+                                              prec="bf16x3", **kw)
+    print(f"AUTO first-probe ratio r = {r:.2f}: {info['precision']}, E {info['E']:.12f} "
+          f"(BF16X3 run {ref['E']:.12f})")
+    assert r > 3.0
+    assert info["precision"] == "bf16x3" and info["pairs"] == ref["pairs"] == 8
+    assert abs(info["E"] - ref["E"]) < 1e-12 * abs(ref["E"])
+    assert abs(info["stderr"] - ref["stderr"]) < 1e-9 * ref["stderr"]
+    assert np.allclose(es_a.cpu().numpy(), es_x.cpu().numpy(), rtol=1e-12, atol=0.0)
