@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void k_rbuild(const void* b, const void* lsrc,
                                                  int64_t np, int64_t plane, int64_t mstride,
                                                  const double* vscale) {
   constexpr int QC = 64;
-  __shared__ T th[RV][QC];
+  __shared__ __attribute__((aligned(16))) T th[QC][RV];   // the RV signs of one Q side by side
   const int64_t ij = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t vb = v0 + (int64_t)blockIdx.y * RV;
   const bool ok = ij < n * n;
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void k_rbuild(const void* b, const void* lsrc,
     for (int e = threadIdx.x; e < RV * QC; e += blockDim.x) {
       int r = e / QC, qq = e % QC;
       int64_t v = vb + r, q = q0 + qq;
-      th[r][qq] = (v < nvec && q < naux) ? (T)theta[v * naux + q] : (T)0;
+      th[qq][r] = (v < nvec && q < naux) ? (T)theta[v * naux + q] : (T)0;
     }
     __syncthreads();
     if (ok) {
@@ -214,8 +214,8 @@ __global__ __launch_bounds__(256) void k_rbuild(const void* b, const void* lsrc,
         T sx = x - lx;
 #pragma unroll
         for (int r = 0; r < RV; ++r) {
-          al[r] += th[r][qq] * lx;
-          as[r] += th[r][qq] * sx;
+          al[r] += th[qq][r] * lx;
+          as[r] += th[qq][r] * sx;
         }
       }
     }
@@ -723,14 +723,21 @@ void launch_extract_blocks(const void* b, bool f64, int64_t n, int64_t naux, dou
 void launch_rbuild(const void* b, bool f64, int64_t n, int64_t naux, double thr, const int8_t* theta,
                    int64_t nvec, Prec prec, void* xl, void* xs, int64_t np, int64_t plane,
                    int64_t mstride, hipStream_t st, const double* vscale, const void* lsrc) {
-  constexpr int RV = 8;
-  dim3 grid(blocks(n * n), (unsigned)((nvec + RV - 1) / RV));
-  if (prec == Prec::F64)
-    hipLaunchKernelGGL((k_rbuild<RV, double>), grid, dim3(256), 0, st, b, lsrc, (int)f64, n, naux, thr,
-                       theta, nvec, (int64_t)0, prec, xl, xs, np, plane, mstride, vscale);
-  else
-    hipLaunchKernelGGL((k_rbuild<RV, float>), grid, dim3(256), 0, st, b, lsrc, (int)f64, n, naux, thr,
-                       theta, nvec, (int64_t)0, prec, xl, xs, np, plane, mstride, vscale);
+  // vectors per thread: B is streamed once per RV vectors, so RV is as large
+  // as the batch allows (up to 32) without idle vector slots
+  auto go = [&](auto rv) {
+    constexpr int RV = decltype(rv)::value;
+    dim3 grid(blocks(n * n), (unsigned)((nvec + RV - 1) / RV));
+    if (prec == Prec::F64)
+      hipLaunchKernelGGL((k_rbuild<RV, double>), grid, dim3(256), 0, st, b, lsrc, (int)f64, n, naux, thr,
+                         theta, nvec, (int64_t)0, prec, xl, xs, np, plane, mstride, vscale);
+    else
+      hipLaunchKernelGGL((k_rbuild<RV, float>), grid, dim3(256), 0, st, b, lsrc, (int)f64, n, naux, thr,
+                         theta, nvec, (int64_t)0, prec, xl, xs, np, plane, mstride, vscale);
+  };
+  if (nvec <= 8) go(std::integral_constant<int, 8>{});
+  else if (nvec <= 16) go(std::integral_constant<int, 16>{});
+  else go(std::integral_constant<int, 32>{});
 }
 void launch_theta_strat(uint64_t seed, int64_t ns, int64_t s0, int64_t naux, int32_t nclass, const double* cdf,
                         const double* pi, int8_t* theta, double* vscale, hipStream_t st) {
