@@ -275,7 +275,9 @@ def batch_bench(args):
     from paper_2005_12338_amd import gf2
     wls = ci.batch_workloads(args.batch_count)
     ctx = gf2.Context(0)
-    prec = args.prec if args.prec != "bf16" or args.batch_prec_bf16 else "fp32"
+    # the batch path takes one plain precision: BF16 on request, else FP32
+    # for the reduced-precision defaults (BF16C is a single-chain estimator)
+    prec = "bf16" if args.batch_prec_bf16 else "fp32" if args.prec in ("bf16", "bf16c") else args.prec
 
     def setup():
         items = []
