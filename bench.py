@@ -273,7 +273,8 @@ def batch_bench(args):
     import torch
     import chain_inputs as ci
     from paper_2005_12338_amd import gf2
-    wls = ci.batch_workloads(args.batch_count)
+    lo, hi = (int(x) for x in args.batch_dimers.split(","))
+    wls = ci.batch_workloads(args.batch_count, lo, hi)
     ctx = gf2.Context(0)
     # the batch path takes one plain precision: BF16 on request, else FP32
     # for the reduced-precision defaults (BF16C is a single-chain estimator)
@@ -324,11 +325,11 @@ def batch_bench(args):
     dev = max(float((a[0] - b[0]).abs().max() / b[0].abs().max()) for a, b in zip(tun, seq))
     log(f"[bench]   max relative difference batched vs per-chain Sigma: {dev:.2e}")
     best = min(("batched", "graph", "tuned"), key=lambda k: res[k]["s"])
-    out = {"metric": "batch pass time, 96 uneven chains (N=40..400, 64 tau, 128 pairs)", "value":
+    out = {"metric": f"batch pass time, {len(wls)} uneven chains (N={2 * lo}..{2 * hi}, 64 tau, 128 pairs)", "value":
            t_setup + res[best]["s"], "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": prec,
            "data": "synthetic", "vs_baseline": None,
            "config": {"workload": f"batch: {len(wls)} H2-dimer chains, dimer counts from "
-                                  f"default_rng(12345).integers(20, 201, {len(wls)}), beta=100, ntau=64, "
+                                  f"default_rng(12345).integers({lo}, {hi + 1}, {len(wls)}), beta=100, ntau=64, "
                                   f"Ns=128, eps=1e-3"},
            "setup_s": t_setup, "sigma_s": res, "best": best, "speedup_vs_per_chain": res["per_chain"]["s"] /
            res[best]["s"], "max_rel_diff_vs_per_chain": dev, "tuned_tile_modes": tiles}
@@ -575,6 +576,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n800", choices=["n800", "n200", "tiny", "batch", "n1600", "scf", "scf-bias"])
     ap.add_argument("--batch-count", type=int, default=96, help="chains in the batch workload")
+    ap.add_argument("--batch-dimers", default="20,200", help="range of dimer counts of the batch's chains")
     ap.add_argument("--batch-prec-bf16", action="store_true", help="run the batch in BF16 (default FP32)")
     ap.add_argument("--prec", default="bf16c", choices=["bf16c", "bf16", "bf16x3", "fp32", "fp64"])
     ap.add_argument("--ns", type=int, default=0, help="pairs per step (default: the workload's)")

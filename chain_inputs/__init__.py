@@ -125,15 +125,16 @@ N1600 = Workload("chain_n1600_learned", 800, 100.0, 128, 0, 1e-4, "bf16", 0)
 BATCH_BETA, BATCH_NTAU, BATCH_NS, BATCH_EPS = 100.0, 64, 128, 1e-3
 
 
-def batch_dimer_counts(count: int = 96) -> np.ndarray:
-    """Dimer counts of the uneven-size batch (uniform in 20..200)."""
-    return np.random.default_rng(12345).integers(20, 201, count)
+def batch_dimer_counts(count: int = 96, lo: int = 20, hi: int = 200) -> np.ndarray:
+    """Dimer counts of the uneven-size batch (uniform in lo..hi, 20..200 by
+    default)."""
+    return np.random.default_rng(12345).integers(lo, hi + 1, count)
 
 
-def batch_workloads(count: int = 96) -> List[Workload]:
+def batch_workloads(count: int = 96, lo: int = 20, hi: int = 200) -> List[Workload]:
     return [Workload(f"batch_{k}", int(nd), BATCH_BETA, BATCH_NTAU, BATCH_NS,
                      BATCH_EPS, "fp32", seed=k)
-            for k, nd in enumerate(batch_dimer_counts(count))]
+            for k, nd in enumerate(batch_dimer_counts(count, lo, hi))]
 
 
 def training_dimer_counts() -> List[int]:
