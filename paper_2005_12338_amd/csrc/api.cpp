@@ -692,6 +692,9 @@ struct ChainPlan {
   int64_t slots = 0, sc = 0, tcnt = 0;
   int mtiles = 0, ftiles = 0;
   int wideg[4] = {0, 0, 0, 0};    // per launch group: 0 the standard tile, else a 160-wide BF16 tile
+  // a BF16X3 chain's deep-K stage as BF16 products on the 160-wide tile:
+  // every segment A B^T becomes A_hi B_hi + A_hi B_lo + A_lo B_hi
+  bool s4split = false;
   double *mpart = nullptr, *epart = nullptr, *coef = nullptr, *gb64 = nullptr;
   char *wz = nullptr, *jw_l = nullptr, *jw_s = nullptr, *jz_st = nullptr, *jz_sum_t = nullptr, *jblk = nullptr;
   char* sig = nullptr;
@@ -746,6 +749,7 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
   c.sp = sp;
   c.prec = prec;
   c.variant = variant;
+  c.s4split = false;
   c.n = sp->n;
   c.np = sp->np;
   c.np2 = c.np * c.np;
@@ -903,12 +907,15 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
     if (wide_for(ctx, prec, n)) {
       c.wideg[3] = 1;
       if (tile_mode(ctx, prec, n) >= 2) c.wideg[0] = c.wideg[2] = 3;
+    } else if (prec == Prec::BF16X3 && tile_mode(ctx, prec, n) >= 1 && wide_pads_less(Prec::BF16, n)) {
+      c.wideg[3] = 1;
+      c.s4split = true;
     }
     Prob dual = prob0();
     dual.nA = 2;
     c.mtiles = tiles_of(dual, prec, n, c.wideg[2]);
     Prob single = prob0();
-    c.ftiles = tiles_of(single, prec, n, c.wideg[3]);
+    c.ftiles = tiles_of(single, c.s4split ? Prec::BF16 : prec, n, c.wideg[3]);
     c.mpart = (double*)S("c_mpart", 4 * c.mtiles * 8);
     c.epart = (double*)S("c_epart", c.ftiles * 8);
     c.coef = (double*)S("c_coef", kCoefStride * 8);
@@ -1008,12 +1015,15 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
       // dual-A launches (s1, s2, s3) in the default mode 2
       c.wideg[3] = 1;
       if (tile_mode(ctx, prec, n) >= 2) c.wideg[0] = c.wideg[1] = c.wideg[2] = 3;
+    } else if (prec == Prec::BF16X3 && tile_mode(ctx, prec, n) >= 1 && wide_pads_less(Prec::BF16, n)) {
+      c.wideg[3] = 1;
+      c.s4split = true;
     }
     Prob dual = prob0();
     dual.nA = 2;
     c.mtiles = tiles_of(dual, prec, n, c.wideg[2]);
     Prob single = prob0();
-    c.ftiles = tiles_of(single, prec, n, c.wideg[3]);
+    c.ftiles = tiles_of(single, c.s4split ? Prec::BF16 : prec, n, c.wideg[3]);
     c.mpart = (double*)S("c_mpart", 4 * c.mtiles * 8);
     c.epart = (double*)S("c_epart", c.ftiles * 8);
     c.coef = (double*)S("c_coef", kCoefStride * 8);
@@ -1116,6 +1126,27 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
     c.ngroups = kGroups;
     for (int g = 0; g < kGroups; ++g) { c.goff[g] = kStageOff[g]; c.gcnt[g] = kStageCnt[g]; c.gprod[g] = kStageProducts[g]; }
   }
+  if (c.s4split) {
+    // BF16X3 deep-K stage on the 160-wide BF16 tile: each segment A B^T
+    // becomes three BF16 segments A_hi B_hi, A_hi B_lo, A_lo B_hi (a storage
+    // matrix's lo plane follows its hi plane at `plane` elements); the FP32
+    // accumulator sums them as the BF16X3 tile does, in another order
+    Prob& q = P[c.goff[3]];
+    GF2_REQUIRE(c.gcnt[3] == 1 && 3 * q.nseg <= kMaxSeg, GF2_E_STATE, "deep-K stage too long to split");
+    const int ns0 = q.nseg;
+    OpRef a0[kMaxSeg], b0[kMaxSeg];
+    for (int x = 0; x < ns0; ++x) { a0[x] = q.a[x]; b0[x] = q.b[x]; }
+    auto lo = [&](OpRef r) {
+      r.base = (const char*)r.base + plane * (int64_t)sizeof(uint16_t);
+      return r;
+    };
+    for (int x = 0; x < ns0; ++x) {
+      q.a[3 * x] = a0[x];         q.b[3 * x] = b0[x];
+      q.a[3 * x + 1] = a0[x];     q.b[3 * x + 1] = lo(b0[x]);
+      q.a[3 * x + 2] = lo(a0[x]); q.b[3 * x + 2] = b0[x];
+    }
+    q.nseg = 3 * ns0;
+  }
   for (int g = 0; g < c.ngroups; ++g)
     for (int j = 0; j < c.gcnt[g]; ++j)
       GF2_REQUIRE(gemm_wide_supports(c.wideg[g], P[c.goff[g] + j]), GF2_E_STATE, "product problem not supported by its tile");
@@ -1147,14 +1178,16 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
 void chain_stage(gf2_ctx* ctx, const ChainPlan& c, int stage, int64_t ci) {
   const int off = c.goff[stage], cnt = c.gcnt[stage];
   const int wide = c.wideg[stage];
+  // a split BF16X3 deep-K stage launches BF16 products (named as the chain's precision)
+  const Prec lp = stage == 3 && c.s4split ? Prec::BF16 : c.prec;
   int mt = 0;
-  for (int i = 0; i < cnt; ++i) mt = std::max(mt, tiles_of(c.P[off + i], c.prec, c.n, wide));
+  for (int i = 0; i < cnt; ++i) mt = std::max(mt, tiles_of(c.P[off + i], lp, c.n, wide));
   const int nu = (int)c.chunks[ci].second;
   GemmLaunch L = chain_launch(c.dprobs + off, cnt, c.dunits + c.chunks[ci].first, nu, c.n, c.np, c.plane);
   L.wide = wide;
   const std::string nm = std::string(gemm_name(c.prec)) + kGroupTag[stage] + (wide ? "@160" : "");
   ProfScope ps(ctx, nm.c_str(), 2.0 * (double)c.n * c.n * c.n * c.gprod[stage] * nu);
-  launch_gemm(c.prec, L, mt, ctx->stream);
+  launch_gemm(lp, L, mt, ctx->stream);
 }
 
 void chain_jk(gf2_ctx* ctx, const ChainPlan& c, int64_t ci) {
@@ -2434,7 +2467,7 @@ void scf_fock(gf2_ctx* ctx, int64_t n, int64_t naux, const void* B, gf2_dtype dt
   launch_pad_convert(p, n, np, 1, Prec::F64, ppad, 0, np2, nullptr, ctx->stream);
   launch_bq_dot(B, f64, n, naux, p, cq, ctx->stream);
   GF2_HIP(hipGetLastError());
-  constexpr int64_t kSeg = kMaxSeg;
+  constexpr int64_t kSeg = 8;                 // B^Q of one group, K-concatenated
   const int64_t qc = std::min<int64_t>((naux + kSeg - 1) / kSeg * kSeg,
                                        std::max<int64_t>(kSeg, ((int64_t)1 << 30) / (16 * np2) / kSeg * kSeg));
   const int64_t nchunk = (naux + qc - 1) / qc, ngc = qc / kSeg, ng = nchunk * ngc;

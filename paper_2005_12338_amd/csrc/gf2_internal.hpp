@@ -58,7 +58,7 @@ struct OutSpec {
   int32_t type;
 };
 
-constexpr int kMaxSeg = 8;
+constexpr int kMaxSeg = 24;   // 8 segments, or 24 when each runs as three BF16 products (BF16X3)
 constexpr int kMaxOut = 8;
 constexpr int kMaxHad = 4;
 constexpr int kMaxAdd = 4;

@@ -339,3 +339,34 @@ def test_wide_tile_chain_matches_standard_tiles(ctx, n_dimer):
     print(f"n_dimer {n_dimer}: BF16 vs FP32: Sigma rel {err0:.2e} (128 tiles) {err2:.2e} (wide); "
           f"e_s rel {ee0:.2e} {ee2:.2e}")
     assert err2 < 2.0 * err0 + 1e-7 and ee2 < 2.0 * ee0 + 1e-6
+
+
+@pytest.mark.parametrize("n_dimer", [75, 400])
+def test_split_bf16x3_deep_k_stage_matches_the_bf16x3_tile(ctx, n_dimer):
+    """Where the 160-wide tile pads less (N = 150, 800), a BF16X3 chain runs
+    its deep-K stage as BF16 products on that tile (each segment A B^T as
+    A_hi B_hi + A_hi B_lo + A_lo B_hi, K-concatenated); mode 0 keeps the
+    BF16X3 tile.  The stage writes FP32, so the two differ by the order of
+    the FP32 accumulation alone; both stay at the BF16X3 level against FP32."""
+    pb = chain(n_dimer, 100.0, 2, 1e-3)
+    B, G, Gb, mu, tau, w = _gpu_inputs(ctx, pb, torch.float32)
+    spl = ctx.split(B, pb["eps"])
+    out, ran = {}, {}
+    try:
+        for mode in (0, 1):
+            ctx.set_gemm_tiles(mode)
+            ctx.set_profiling(True)
+            ctx.profile_read()
+            out[mode] = ctx.sigma_tau(spl, B, G, Gb, ns=2, seed=6, prec="bf16x3")
+            ran[mode] = sorted(k for k in ctx.profile_read() if k.startswith("gemm"))
+    finally:
+        ctx.set_profiling(False)
+        ctx.set_gemm_tiles(2)
+    assert "gemm_bf16x3.s4@160" in ran[1] and not any(k.endswith("@160") for k in ran[0])
+    S32, e32 = ctx.sigma_tau(spl, B, G, Gb, ns=2, seed=6, prec="fp32")
+    (S0, e0), (S1, e1) = out[0], out[1]
+    assert rel(S1.cpu().numpy(), S0.cpu().numpy()) < 1e-6
+    assert rel(e1.cpu().numpy(), e0.cpu().numpy()) < 1e-5
+    print(f"n_dimer {n_dimer}: BF16X3 vs FP32 Sigma rel {rel(S0.cpu().numpy(), S32.cpu().numpy()):.2e} (tile), "
+          f"{rel(S1.cpu().numpy(), S32.cpu().numpy()):.2e} (split)")
+    assert rel(S1.cpu().numpy(), S32.cpu().numpy()) < 3e-5
