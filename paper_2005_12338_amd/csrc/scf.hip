@@ -23,7 +23,7 @@ namespace {
 
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kNB = 32;    // Gauss-Jordan panel width (a narrower last panel is handled too)
+constexpr int kNB = 64;    // Gauss-Jordan panel width (a narrower last panel is handled too)
 constexpr int kTW = 64;    // output tile width of the panel kernels
 constexpr int kFG = 16;    // frequencies per thread in the forward transform
 constexpr int kOG = 16;    // output times are padded to a multiple of this (the back-transform's MFMA rows)
@@ -102,8 +102,9 @@ __device__ __forceinline__ void cmul(double ar, double ai, double br, double bi,
 // pivoting: the Dyson matrices are complex symmetric with a positive
 // definite imaginary part, so every leading block is invertible) and stores
 // it in pbuf.  A vanishing or non-finite pivot sets *err.  Grid (matrices).
-__global__ __launch_bounds__(256) void k_gj_pivot(const double* a, int64_t np, int64_t k0, double* pbuf,
-                                                  int* err) {
+constexpr int kPivT = kNB == 64 ? 1024 : 256;   // threads of the pivot-block kernel
+__global__ __launch_bounds__(kPivT) void k_gj_pivot(const double* a, int64_t np, int64_t k0, double* pbuf,
+                                                    int* err) {
   __shared__ double dr[kNB][kNB + 1], di[kNB][kNB + 1];
   __shared__ double fr[kNB], fi[kNB];
   const int tid = threadIdx.x;
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(256) void k_gj_pivot(const double* a, int64_t np, i
   const double* ai = ar + np2;
   const int kb = (int)(np - k0 < kNB ? np - k0 : kNB);     // width of this panel
   // a narrower last panel is completed by the identity, so P = diag(A_KK^{-1}, I)
-  for (int x = tid; x < kNB * kNB; x += 256) {
+  for (int x = tid; x < kNB * kNB; x += kPivT) {
     const int r = x / kNB, c = x % kNB;
     const bool in = r < kb && c < kb;
     dr[r][c] = in ? ar[(k0 + r) * np + k0 + c] : (r == c ? 1.0 : 0.0);
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(256) void k_gj_pivot(const double* a, int64_t np, i
       }
     }
     __syncthreads();
-    for (int x = tid; x < kNB * kNB; x += 256) {
+    for (int x = tid; x < kNB * kNB; x += kPivT) {
       const int r = x / kNB, c = x % kNB;
       if (r == p) continue;
       double xr, xi;
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(256) void k_gj_pivot(const double* a, int64_t np, i
     __syncthreads();
   }
   double* pr_ = pbuf + mat * 2 * kNB * kNB;
-  for (int x = tid; x < kNB * kNB; x += 256) {
+  for (int x = tid; x < kNB * kNB; x += kPivT) {
     const int r = x / kNB, c = x % kNB;
     pr_[x] = dr[r][c];
     pr_[kNB * kNB + x] = di[r][c];
@@ -167,11 +168,14 @@ __global__ __launch_bounds__(256) void k_gj_pivot(const double* a, int64_t np, i
 
 // Second step: every block copies rows [64 ct, 64 ct + 64) of the column
 // panel A_{:,K} to colbuf and replaces its 64 columns j (outside K) of the
-// row panel by P A_Kj, with P from pbuf.  1-D grid of (matrix, column tile).
+// row panel by P A_Kj, with P from pbuf, on FP64 MFMAs (complex product as
+// four real ones; each lane loads its operands from P and A_K directly).
+// Every wave reads all of A_K's rows for its columns before any wave
+// overwrites them: the new row panel is written after a barrier.
+// 1-D grid of (matrix, column tile).
 __global__ __launch_bounds__(256) void k_gj_panel(double* a, int64_t np, int64_t k0, double* colbuf,
                                                   const double* pbuf) {
-  __shared__ double dr[kNB][kNB + 1], di[kNB][kNB + 1];
-  __shared__ double rr[kNB][kTW + 1], ri[kNB][kTW + 1];
+  constexpr int BI = kNB / 32;                  // 16-row MFMA blocks per wave (rows of P)
   const int tid = threadIdx.x;
   const int64_t tiles = (np + kTW - 1) / kTW, q = xcd_range(blockIdx.x, gridDim.x);
   const int64_t ct = q % tiles, mat = q / tiles, np2 = np * np;
@@ -180,17 +184,7 @@ __global__ __launch_bounds__(256) void k_gj_panel(double* a, int64_t np, int64_t
   const int64_t j0 = (int64_t)ct * kTW;
   const int kb = (int)(np - k0 < kNB ? np - k0 : kNB);     // width of this panel
   const double* pr_ = pbuf + mat * 2 * kNB * kNB;
-  for (int x = tid; x < kNB * kNB; x += 256) {
-    const int r = x / kNB, c = x % kNB;
-    dr[r][c] = pr_[x];
-    di[r][c] = pr_[kNB * kNB + x];
-  }
-  for (int x = tid; x < kNB * kTW; x += 256) {
-    const int r = x / kTW, c = x % kTW;
-    const int64_t j = j0 + c;
-    rr[r][c] = j < np && r < kb ? ar[(k0 + r) * np + j] : 0.0;
-    ri[r][c] = j < np && r < kb ? ai[(k0 + r) * np + j] : 0.0;
-  }
+  const double* pi_ = pr_ + kNB * kNB;
   double* cbr = colbuf + mat * 2 * np * kNB;
   double* cbi = cbr + np * kNB;
   for (int x = tid; x < kTW * kNB; x += 256) {
@@ -201,25 +195,63 @@ __global__ __launch_bounds__(256) void k_gj_panel(double* a, int64_t np, int64_t
       cbi[i * kNB + c] = c < kb ? ai[i * np + k0 + c] : 0.0;
     }
   }
-  __syncthreads();
-  // row panel: R_Kj = P A_Kj for the tile's columns outside K
-  const int c = tid % kTW, rg = tid / kTW;   // 4 groups of kNB / 4 rows
-  const int64_t j = j0 + c;
-  if (j >= np || (j >= k0 && j < k0 + kb)) return;
-#pragma unroll 4
-  for (int q = 0; q < kNB / 4; ++q) {
-    const int r = rg * (kNB / 4) + q;
-    if (r >= kb) break;
-    double sr = 0.0, si = 0.0;
-#pragma unroll 8
-    for (int l = 0; l < kNB; ++l) {
-      const double xr = dr[r][l], xi = di[r][l], yr = rr[l][c], yi = ri[l][c];
-      sr = fma(xr, yr, fma(-xi, yi, sr));
-      si = fma(xr, yi, fma(xi, yr, si));
-    }
-    ar[(k0 + r) * np + j] = sr;
-    ai[(k0 + r) * np + j] = si;
+  const int lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+  const int lr = lane & 15, lg = lane >> 4;
+  int64_t col[2];
+  bool cok[2];
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj) {
+    col[bj] = j0 + 32 * wc + 16 * bj + lr;
+    cok[bj] = col[bj] < np && !(col[bj] >= k0 && col[bj] < k0 + kb);
   }
+  f64x4_t accr[BI][2], acci[BI][2];
+#pragma unroll
+  for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) accr[bi][bj][r] = acci[bi][bj][r] = 0.0;
+#pragma unroll 4
+  for (int ks = 0; ks < kNB / 4; ++ks) {
+    const int l = 4 * ks + lg;                 // panel index of this lane's operands
+    double xr[BI], xi[BI], yr[2], yi[2], yn[2];
+#pragma unroll
+    for (int bi = 0; bi < BI; ++bi) {
+      const int r = (kNB / 2) * wr + 16 * bi + lr;
+      xr[bi] = pr_[r * kNB + l];
+      xi[bi] = pi_[r * kNB + l];
+    }
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const bool ok = cok[bj] && l < kb;
+      yr[bj] = ok ? ar[(k0 + l) * np + col[bj]] : 0.0;
+      yi[bj] = ok ? ai[(k0 + l) * np + col[bj]] : 0.0;
+      yn[bj] = -yi[bj];
+    }
+#pragma unroll
+    for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        accr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[bi], yr[bj], accr[bi][bj], 0, 0, 0);
+        accr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi[bi], yn[bj], accr[bi][bj], 0, 0, 0);
+        acci[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[bi], yi[bj], acci[bi][bj], 0, 0, 0);
+        acci[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi[bi], yr[bj], acci[bi][bj], 0, 0, 0);
+      }
+  }
+  __syncthreads();                              // every wave has read A_K before it is overwritten
+#pragma unroll
+  for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      if (!cok[bj]) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = (kNB / 2) * wr + 16 * bi + lg + 4 * r;   // accumulator r: row lane / 16 + 4 r
+        if (row >= kb) continue;
+        ar[(k0 + row) * np + col[bj]] = accr[bi][bj][r];
+        ai[(k0 + row) * np + col[bj]] = acci[bi][bj][r];
+      }
+    }
 }
 
 // Second half: every 64 x 64 tile outside the panel rows takes
@@ -647,7 +679,7 @@ void launch_sig_iw(const double* sig, int64_t ntau, int64_t np, int64_t n, const
 void launch_gj_invert(double* a, int32_t nmat, int64_t np, double* colbuf, double* pbuf, int* err, hipStream_t st) {
   const unsigned tiles = (unsigned)((np + kTW - 1) / kTW);
   for (int64_t k0 = 0; k0 < np; k0 += kNB) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3((unsigned)nmat), dim3(256), 0, st, (const double*)a, np, k0, pbuf, err);
+    hipLaunchKernelGGL(k_gj_pivot, dim3((unsigned)nmat), dim3(kPivT), 0, st, (const double*)a, np, k0, pbuf, err);
     hipLaunchKernelGGL(k_gj_panel, dim3(tiles * (unsigned)nmat), dim3(256), 0, st, a, np, k0, colbuf,
                        (const double*)pbuf);
     hipLaunchKernelGGL(k_gj_update, dim3(tiles * tiles * (unsigned)nmat), dim3(256), 0, st, a, np, k0,
