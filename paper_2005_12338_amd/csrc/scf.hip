@@ -279,22 +279,6 @@ __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_
   const int lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
   const int lr = lane & 15, lg = lane >> 4;
   const int64_t k1 = np - k0 < kNB ? np : k0 + kNB;       // K = [k0, k1)
-  // the tile's old values, loaded first so that their latency overlaps the
-  // operand loads and the MFMAs (accumulator r of a lane: row lane / 16 + 4 r,
-  // column lane % 16)
-  double oldr[2][2][4], oldi[2][2][4];
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t gi = i0 + 32 * wr + 16 * bi + lg + 4 * r;
-        const int64_t gj = j0 + 32 * wc + 16 * bj + lr;
-        const bool live = gi < np && gj < np && !(gi >= k0 && gi < k1) && !(gj >= k0 && gj < k1);
-        oldr[bi][bj][r] = live ? ar[gi * np + gj] : 0.0;
-        oldi[bi][bj][r] = live ? ai[gi * np + gj] : 0.0;
-      }
   // operand rows (column panel) and columns (row panel) of this lane
   int64_t crow[2], rcol[2];
   bool cok[2], rin[2], rok[2];
@@ -369,8 +353,13 @@ __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_
           }
           continue;
         }
-        ar[o] = oldr[bi][bj][r] - accr[bi][bj][r];
-        ai[o] = oldi[bi][bj][r] - acci[bi][bj][r];
+        // the old value (zero on the K columns) is read only now, so that it
+        // holds no registers during the MFMAs (more waves per SIMD hide the
+        // load latency); accumulator r of a lane: row lane / 16 + 4 r,
+        // column lane % 16
+        const double ovr = kj ? 0.0 : ar[o], ovi = kj ? 0.0 : ai[o];
+        ar[o] = ovr - accr[bi][bj][r];
+        ai[o] = ovi - acci[bi][bj][r];
       }
 }
 
