@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kPivT) void k_gj_pivot(const double* a, int64_t np,
 // Every wave reads all of A_K's rows for its columns before any wave
 // overwrites them: the new row panel is written after a barrier.
 // 1-D grid of (matrix, column tile).
-__global__ __launch_bounds__(256) void k_gj_panel(double* a, int64_t np, int64_t k0, double* colbuf,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_gj_panel(double* a, int64_t np, int64_t k0, double* colbuf,
                                                   const double* pbuf) {
   constexpr int BI = kNB / 32;                  // 16-row MFMA blocks per wave (rows of P)
   const int tid = threadIdx.x;
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(256) void k_gj_update(double* a, int64_t np, int64_
 constexpr int kBRT = 10;             // 16-row MFMA tiles per row block
 constexpr int kBR = 16 * kBRT;       // output rows per block
 constexpr int kBK = 16;              // frequencies per LDS stage
-__global__ __launch_bounds__(512) void k_iw_back(const double* __restrict__ a, int32_t nc, int64_t np, int64_t n,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_iw_back(const double* __restrict__ a, int32_t nc, int64_t np, int64_t n,
                                                   const double* __restrict__ shift, const double* __restrict__ om,
                                                   const double* __restrict__ cs, int32_t nto, int32_t ntop,
                                                   double* __restrict__ pc, double* __restrict__ ps) {
