@@ -692,9 +692,10 @@ struct ChainPlan {
   int64_t slots = 0, sc = 0, tcnt = 0;
   int mtiles = 0, ftiles = 0;
   int wideg[4] = {0, 0, 0, 0};    // per launch group: 0 the standard tile, else a 160-wide BF16 tile
-  // a BF16X3 chain's deep-K stage as BF16 products on the 160-wide tile:
-  // every segment A B^T becomes A_hi B_hi + A_hi B_lo + A_lo B_hi
-  bool s4split = false;
+  // launch groups of a BF16X3 chain that run as BF16 products on the
+  // 160-wide tiles: every K segment A B^T becomes A_hi B_hi + A_hi B_lo +
+  // A_lo B_hi, and storage outputs are written as hi and lo planes
+  bool xsplit[4] = {false, false, false, false};
   double *mpart = nullptr, *epart = nullptr, *coef = nullptr, *gb64 = nullptr;
   char *wz = nullptr, *jw_l = nullptr, *jw_s = nullptr, *jz_st = nullptr, *jz_sum_t = nullptr, *jblk = nullptr;
   char* sig = nullptr;
@@ -749,7 +750,7 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
   c.sp = sp;
   c.prec = prec;
   c.variant = variant;
-  c.s4split = false;
+  for (bool& x : c.xsplit) x = false;
   c.n = sp->n;
   c.np = sp->np;
   c.np2 = c.np * c.np;
@@ -909,13 +910,17 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
       if (tile_mode(ctx, prec, n) >= 2) c.wideg[0] = c.wideg[2] = 3;
     } else if (prec == Prec::BF16X3 && tile_mode(ctx, prec, n) >= 1 && wide_pads_less(Prec::BF16, n)) {
       c.wideg[3] = 1;
-      c.s4split = true;
+      c.xsplit[3] = true;
+      if (tile_mode(ctx, prec, n) >= 2) {
+        c.wideg[0] = c.wideg[2] = 3;
+        c.xsplit[0] = c.xsplit[2] = true;
+      }
     }
     Prob dual = prob0();
     dual.nA = 2;
-    c.mtiles = tiles_of(dual, prec, n, c.wideg[2]);
+    c.mtiles = tiles_of(dual, c.xsplit[2] ? Prec::BF16 : prec, n, c.wideg[2]);
     Prob single = prob0();
-    c.ftiles = tiles_of(single, c.s4split ? Prec::BF16 : prec, n, c.wideg[3]);
+    c.ftiles = tiles_of(single, c.xsplit[3] ? Prec::BF16 : prec, n, c.wideg[3]);
     c.mpart = (double*)S("c_mpart", 4 * c.mtiles * 8);
     c.epart = (double*)S("c_epart", c.ftiles * 8);
     c.coef = (double*)S("c_coef", kCoefStride * 8);
@@ -1017,13 +1022,17 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
       if (tile_mode(ctx, prec, n) >= 2) c.wideg[0] = c.wideg[1] = c.wideg[2] = 3;
     } else if (prec == Prec::BF16X3 && tile_mode(ctx, prec, n) >= 1 && wide_pads_less(Prec::BF16, n)) {
       c.wideg[3] = 1;
-      c.s4split = true;
+      c.xsplit[3] = true;
+      if (tile_mode(ctx, prec, n) >= 2) {
+        c.wideg[0] = c.wideg[1] = c.wideg[2] = 3;
+        c.xsplit[0] = c.xsplit[1] = c.xsplit[2] = true;
+      }
     }
     Prob dual = prob0();
     dual.nA = 2;
-    c.mtiles = tiles_of(dual, prec, n, c.wideg[2]);
+    c.mtiles = tiles_of(dual, c.xsplit[2] ? Prec::BF16 : prec, n, c.wideg[2]);
     Prob single = prob0();
-    c.ftiles = tiles_of(single, c.s4split ? Prec::BF16 : prec, n, c.wideg[3]);
+    c.ftiles = tiles_of(single, c.xsplit[3] ? Prec::BF16 : prec, n, c.wideg[3]);
     c.mpart = (double*)S("c_mpart", 4 * c.mtiles * 8);
     c.epart = (double*)S("c_epart", c.ftiles * 8);
     c.coef = (double*)S("c_coef", kCoefStride * 8);
@@ -1126,26 +1135,41 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
     c.ngroups = kGroups;
     for (int g = 0; g < kGroups; ++g) { c.goff[g] = kStageOff[g]; c.gcnt[g] = kStageCnt[g]; c.gprod[g] = kStageProducts[g]; }
   }
-  if (c.s4split) {
-    // BF16X3 deep-K stage on the 160-wide BF16 tile: each segment A B^T
-    // becomes three BF16 segments A_hi B_hi, A_hi B_lo, A_lo B_hi (a storage
-    // matrix's lo plane follows its hi plane at `plane` elements); the FP32
-    // accumulator sums them as the BF16X3 tile does, in another order
-    Prob& q = P[c.goff[3]];
-    GF2_REQUIRE(c.gcnt[3] == 1 && 3 * q.nseg <= kMaxSeg, GF2_E_STATE, "deep-K stage too long to split");
-    const int ns0 = q.nseg;
-    OpRef a0[kMaxSeg], b0[kMaxSeg];
-    for (int x = 0; x < ns0; ++x) { a0[x] = q.a[x]; b0[x] = q.b[x]; }
-    auto lo = [&](OpRef r) {
-      r.base = (const char*)r.base + plane * (int64_t)sizeof(uint16_t);
-      return r;
-    };
-    for (int x = 0; x < ns0; ++x) {
-      q.a[3 * x] = a0[x];         q.b[3 * x] = b0[x];
-      q.a[3 * x + 1] = a0[x];     q.b[3 * x + 1] = lo(b0[x]);
-      q.a[3 * x + 2] = lo(a0[x]); q.b[3 * x + 2] = b0[x];
+  // Launch groups of a BF16X3 chain on the 160-wide BF16 tiles: each K
+  // segment A B^T becomes three BF16 segments A_hi B_hi, A_hi B_lo, A_lo B_hi
+  // (a storage matrix's lo plane follows its hi plane at `plane` elements),
+  // summed by the FP32 accumulator as the BF16X3 tile sums its products, in
+  // another order; storage outputs are written as hi and lo planes (type 2)
+  auto lo = [&](OpRef r) {
+    r.base = (const char*)r.base + plane * (int64_t)sizeof(uint16_t);
+    return r;
+  };
+  for (int g = 0; g < c.ngroups; ++g) {
+    if (!c.xsplit[g]) continue;
+    for (int j = 0; j < c.gcnt[g]; ++j) {
+      Prob& q = P[c.goff[g] + j];
+      const int ns0 = q.nseg;
+      OpRef a0[kMaxSeg], b0[kMaxSeg];
+      for (int x = 0; x < kMaxSeg; ++x) { a0[x] = q.a[x]; b0[x] = q.b[x]; }
+      if (c.wideg[g] == 3) {
+        // dual-A: segment x holds a[2x], a[2x + 1] against b[x]
+        GF2_REQUIRE(q.nA == 2 && q.nB == 1 && ns0 == 1 && 6 <= kMaxSeg, GF2_E_STATE, "dual-A product to split");
+        q.a[0] = a0[0];     q.a[1] = a0[1];     q.b[0] = b0[0];
+        q.a[2] = a0[0];     q.a[3] = a0[1];     q.b[1] = lo(b0[0]);
+        q.a[4] = lo(a0[0]); q.a[5] = lo(a0[1]); q.b[2] = b0[0];
+        q.nseg = 3;
+      } else {
+        GF2_REQUIRE(q.nA == 1 && q.nB == 1 && 3 * ns0 <= kMaxSeg, GF2_E_STATE, "deep-K stage too long to split");
+        for (int x = 0; x < ns0; ++x) {
+          q.a[3 * x] = a0[x];         q.b[3 * x] = b0[x];
+          q.a[3 * x + 1] = a0[x];     q.b[3 * x + 1] = lo(b0[x]);
+          q.a[3 * x + 2] = lo(a0[x]); q.b[3 * x + 2] = b0[x];
+        }
+        q.nseg = 3 * ns0;
+      }
+      for (int o = 0; o < q.nout; ++o)
+        if (q.out[o].type == 1) q.out[o].type = 2;
     }
-    q.nseg = 3 * ns0;
   }
   for (int g = 0; g < c.ngroups; ++g)
     for (int j = 0; j < c.gcnt[g]; ++j)
@@ -1178,8 +1202,8 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
 void chain_stage(gf2_ctx* ctx, const ChainPlan& c, int stage, int64_t ci) {
   const int off = c.goff[stage], cnt = c.gcnt[stage];
   const int wide = c.wideg[stage];
-  // a split BF16X3 deep-K stage launches BF16 products (named as the chain's precision)
-  const Prec lp = stage == 3 && c.s4split ? Prec::BF16 : c.prec;
+  // a split BF16X3 launch group runs BF16 products (named as the chain's precision)
+  const Prec lp = c.xsplit[stage] ? Prec::BF16 : c.prec;
   int mt = 0;
   for (int i = 0; i < cnt; ++i) mt = std::max(mt, tiles_of(c.P[off + i], lp, c.n, wide));
   const int nu = (int)c.chunks[ci].second;

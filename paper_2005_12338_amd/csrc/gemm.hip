@@ -377,11 +377,16 @@ __device__ __forceinline__ void wide_epilogue(const InstGeo& L, const Prob& pb, 
 
   // 2. outputs, staged
   constexpr int CAP = Smem<P, W>::BYTES;
-  for (int o = 0; o < pb.nout; ++o) {
-    const OutSpec& os = pb.out[o];
+  for (int o = 0; o < pb.nout * 2; ++o) {
+    // type 2 (the BF16X3 storage of a split product): the output is written
+    // twice, the hi plane bf16(x) and then, L.plane elements further, the lo
+    // plane bf16(x - hi); other types once
+    const OutSpec& os = pb.out[o >> 1];
+    const int pl = o & 1;
+    if (pl && os.type != 2) continue;
     const int es = os.type == 0 ? 4 : 2;              // bytes per element
     const int vl = 16 / es;                            // elements per 16-byte vector
-    char* dst = (char*)os.base + off(os, u) * (int64_t)es;
+    char* dst = (char*)os.base + (off(os, u) + (int64_t)pl * L.plane) * (int64_t)es;
     float cf[NA];
 #pragma unroll
     for (int a = 0; a < NA; ++a) cf[a] = os.coef[a];
@@ -405,6 +410,11 @@ __device__ __forceinline__ void wide_epilogue(const InstGeo& L, const Prob& pb, 
           for (int a = 0; a < NA; ++a) x += cf[a] * acc[a * FR + gi][gj][r];
           return x;
         };
+        // BF16 bits of an output element: x, or on a lo plane x - bf16(x)
+        auto b16 = [&](float x) {
+          const uint16_t h = bf16_bits(x);
+          return pl ? bf16_bits(x - __uint_as_float((uint32_t)h << 16)) : h;
+        };
         const int hr = h * rs;
         if (NA == 2 && kind == 0) {  // row-major BF16
 #pragma unroll
@@ -413,7 +423,7 @@ __device__ __forceinline__ void wide_epilogue(const InstGeo& L, const Prob& pb, 
             for (int gj = 0; gj < FC; ++gj)
 #pragma unroll
               for (int r = 0; r < 4; ++r)
-                ((uint16_t*)smem)[(lrow(gi, r) - hr) * pr + lcol(gj)] = bf16_bits(val(gi, gj, r));
+                ((uint16_t*)smem)[(lrow(gi, r) - hr) * pr + lcol(gj)] = b16(val(gi, gj, r));
         } else if (kind == 1) {      // row-major FP32
 #pragma unroll
           for (int gi = 0; gi < FR; ++gi)
@@ -426,8 +436,8 @@ __device__ __forceinline__ void wide_epilogue(const InstGeo& L, const Prob& pb, 
           for (int gi = 0; gi < FR; ++gi)
 #pragma unroll
             for (int gj = 0; gj < FC; ++gj) {
-              const uint32_t lo = (uint32_t)bf16_bits(val(gi, gj, 0)) | ((uint32_t)bf16_bits(val(gi, gj, 1)) << 16);
-              const uint32_t hi = (uint32_t)bf16_bits(val(gi, gj, 2)) | ((uint32_t)bf16_bits(val(gi, gj, 3)) << 16);
+              const uint32_t lo = (uint32_t)b16(val(gi, gj, 0)) | ((uint32_t)b16(val(gi, gj, 1)) << 16);
+              const uint32_t hi = (uint32_t)b16(val(gi, gj, 2)) | ((uint32_t)b16(val(gi, gj, 3)) << 16);
               *(uint2*)((uint16_t*)smem + lcol(gj) * pt + lrow(gi, 0) - hr) = make_uint2(lo, hi);
             }
         } else if (NA == 2) {        // transposed FP32
@@ -732,7 +742,7 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
     constexpr int RPI = direct_rows<BK>(), CPR = BK / 8;
     constexpr int NLA = Smem<P, W>::ROWS_A / (4 * RPI), NLB = Smem<P, W>::ROWS_B / (4 * RPI);
     static_assert(C::SWZ && PL == 1 && NB == 1 && (NA == 1 || W == 3),
-                  "direct loads: swizzled single-plane tiles, single products or dual-A (one K segment)");
+                  "direct loads: swizzled single-plane tiles, single products or dual-A");
     static_assert(SM % RPI == 0 && STG >= 2 && (STG - 2) * (NLA + NLB) < 64, "direct-load geometry");
     const int lrow = lane / CPR, pch = lane % CPR;
     const E* dab[NLA];
@@ -742,7 +752,7 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
 #pragma unroll
       for (int i = 0; i < NLA; ++i) {
         const int r = RPI * (4 * i + wave) + lrow;
-        const int sel = NA == 2 ? (r < SM ? 0 : 1) : seg;
+        const int sel = NA == 2 ? 2 * seg + (r < SM ? 0 : 1) : seg;   // dual-A: a[2 seg], a[2 seg + 1]
         const OpRef& ar = pb.a[sel];
         const int rr = NA == 2 ? r % SM : r;
         dab[i] = (const E*)ar.base + off(ar, u) + (row0 + rr) * ld;
@@ -1109,7 +1119,9 @@ int gemm_tile_n(Prec p, int wide) {
 }
 
 bool gemm_wide_supports(int wide, const Prob& pb) {
-  if (wide == 3) return pb.nA == 2 && pb.nB == 1 && pb.nseg == 1 && pb.nadd == 0 && (pb.nhad == 0 || pb.had_diag);
+  if (wide == 3)
+    return pb.nA == 2 && pb.nB == 1 && pb.nseg >= 1 && 2 * pb.nseg <= kMaxSeg && pb.nadd == 0 &&
+           (pb.nhad == 0 || pb.had_diag);
   if (wide == 1 || wide == 2) {
     if (pb.nA != 1 || pb.nB != 1 || pb.nadd != 0) return false;
     for (int o = 0; o < pb.nout; ++o)

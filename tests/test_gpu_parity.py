@@ -342,18 +342,21 @@ def test_wide_tile_chain_matches_standard_tiles(ctx, n_dimer):
 
 
 @pytest.mark.parametrize("n_dimer", [75, 400])
-def test_split_bf16x3_deep_k_stage_matches_the_bf16x3_tile(ctx, n_dimer):
+def test_split_bf16x3_stages_match_the_bf16x3_tile(ctx, n_dimer):
     """Where the 160-wide tile pads less (N = 150, 800), a BF16X3 chain runs
-    its deep-K stage as BF16 products on that tile (each segment A B^T as
-    A_hi B_hi + A_hi B_lo + A_lo B_hi, K-concatenated); mode 0 keeps the
-    BF16X3 tile.  The stage writes FP32, so the two differ by the order of
-    the FP32 accumulation alone; both stay at the BF16X3 level against FP32."""
+    its launch groups as BF16 products on the 160-wide tiles, each K segment
+    A B^T as A_hi B_hi + A_hi B_lo + A_lo B_hi: mode 1 the deep-K stage, mode
+    2 (default) also the dual-A stages, whose storage outputs are written as
+    hi and lo planes; mode 0 keeps the BF16X3 tile.  The deep-K stage writes
+    FP32, so mode 1 differs from mode 0 by the order of the FP32 accumulation
+    alone; in mode 2 the hi/lo split of the stored intermediates can round
+    differently, at the BF16X3 level.  All stay at that level against FP32."""
     pb = chain(n_dimer, 100.0, 2, 1e-3)
     B, G, Gb, mu, tau, w = _gpu_inputs(ctx, pb, torch.float32)
     spl = ctx.split(B, pb["eps"])
     out, ran = {}, {}
     try:
-        for mode in (0, 1):
+        for mode in (0, 1, 2):
             ctx.set_gemm_tiles(mode)
             ctx.set_profiling(True)
             ctx.profile_read()
@@ -362,11 +365,18 @@ def test_split_bf16x3_deep_k_stage_matches_the_bf16x3_tile(ctx, n_dimer):
     finally:
         ctx.set_profiling(False)
         ctx.set_gemm_tiles(2)
-    assert "gemm_bf16x3.s4@160" in ran[1] and not any(k.endswith("@160") for k in ran[0])
+    assert not any(k.endswith("@160") for k in ran[0])
+    assert [k for k in ran[1] if k.endswith("@160")] == ["gemm_bf16x3.s4@160"]
+    assert [k for k in ran[2] if k.endswith("@160")] == ["gemm_bf16x3.s1@160", "gemm_bf16x3.s2@160",
+                                                          "gemm_bf16x3.s3@160", "gemm_bf16x3.s4@160"]
     S32, e32 = ctx.sigma_tau(spl, B, G, Gb, ns=2, seed=6, prec="fp32")
-    (S0, e0), (S1, e1) = out[0], out[1]
-    assert rel(S1.cpu().numpy(), S0.cpu().numpy()) < 1e-6
-    assert rel(e1.cpu().numpy(), e0.cpu().numpy()) < 1e-5
-    print(f"n_dimer {n_dimer}: BF16X3 vs FP32 Sigma rel {rel(S0.cpu().numpy(), S32.cpu().numpy()):.2e} (tile), "
-          f"{rel(S1.cpu().numpy(), S32.cpu().numpy()):.2e} (split)")
-    assert rel(S1.cpu().numpy(), S32.cpu().numpy()) < 3e-5
+    S = {m: out[m][0].cpu().numpy() for m in out}
+    e = {m: out[m][1].cpu().numpy() for m in out}
+    assert rel(S[1], S[0]) < 1e-6
+    assert rel(e[1], e[0]) < 1e-5
+    assert rel(S[2], S[0]) < 3e-5
+    print(f"n_dimer {n_dimer}: BF16X3 vs FP32 Sigma rel {rel(S[0], S32.cpu().numpy()):.2e} (tile), "
+          f"{rel(S[1], S32.cpu().numpy()):.2e} (deep-K split), {rel(S[2], S32.cpu().numpy()):.2e} (all split); "
+          f"mode 2 vs 0 {rel(S[2], S[0]):.2e}")
+    for m in (0, 1, 2):
+        assert rel(S[m], S32.cpu().numpy()) < 3e-5
