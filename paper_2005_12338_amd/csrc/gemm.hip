@@ -375,102 +375,108 @@ __device__ __forceinline__ void wide_epilogue(const InstGeo& L, const Prob& pb, 
     }
   }
 
-  // 2. outputs, staged
+  // 2. outputs, staged. A first pass writes every output (FP32, BF16, or the
+  // hi plane bf16(x) of type 2, the BF16X3 storage of a split product); a
+  // second pass writes the lo planes bf16(x - hi) of type 2 outputs, L.plane
+  // elements further. The plane is a compile-time flag so that the first
+  // pass carries no per-element work for the second.
   constexpr int CAP = Smem<P, W>::BYTES;
-  for (int o = 0; o < pb.nout * 2; ++o) {
-    // type 2 (the BF16X3 storage of a split product): the output is written
-    // twice, the hi plane bf16(x) and then, L.plane elements further, the lo
-    // plane bf16(x - hi); other types once
-    const OutSpec& os = pb.out[o >> 1];
-    const int pl = o & 1;
-    if (pl && os.type != 2) continue;
-    const int es = os.type == 0 ? 4 : 2;              // bytes per element
-    const int vl = 16 / es;                            // elements per 16-byte vector
-    char* dst = (char*)os.base + (off(os, u) + (int64_t)pl * L.plane) * (int64_t)es;
-    float cf[NA];
+  auto pass = [&](auto lo_plane) {
+    constexpr bool LO = decltype(lo_plane)::value;
+    for (int o = 0; o < pb.nout; ++o) {
+      const OutSpec& os = pb.out[o];
+      if (LO && os.type != 2) continue;
+      const int es = os.type == 0 ? 4 : 2;              // bytes per element
+      const int vl = 16 / es;                            // elements per 16-byte vector
+      char* dst = (char*)os.base + (off(os, u) + (LO ? L.plane : 0)) * (int64_t)es;
+      float cf[NA];
 #pragma unroll
-    for (int a = 0; a < NA; ++a) cf[a] = os.coef[a];
-    const bool tr = os.layout != 0;
-    // staged region: tile rows [h RS, (h+1) RS); pitch padded by 16 bytes
-    const int pr = SN + vl, pt_full = SM + vl, pt_half = HALF_R + vl;
-    const bool halves = (tr ? SN * pt_full : SM * pr) * es > CAP;
-    const int rs = halves ? HALF_R : SM;
-    const int pt = halves ? pt_half : pt_full;
-    // single-product wide tiles write row-major FP32 outputs only (the
-    // deep-K stage's; the host checks), which keeps their epilogue within
-    // two workgroups' registers
-    const int kind = (tr ? 2 : 0) + (es == 4 ? 1 : 0);
-    if (NA == 1 && kind != 1) continue;
-    for (int h = 0; h < (halves ? 2 : 1); ++h) {
-      __syncthreads();                               // LDS free (main loop, traces, last copy-out)
-      if (!halves || wm == h) {
-        auto val = [&](int gi, int gj, int r) {
-          float x = 0.0f;
+      for (int a = 0; a < NA; ++a) cf[a] = os.coef[a];
+      const bool tr = os.layout != 0;
+      // staged region: tile rows [h RS, (h+1) RS); pitch padded by 16 bytes
+      const int pr = SN + vl, pt_full = SM + vl, pt_half = HALF_R + vl;
+      const bool halves = (tr ? SN * pt_full : SM * pr) * es > CAP;
+      const int rs = halves ? HALF_R : SM;
+      const int pt = halves ? pt_half : pt_full;
+      // single-product wide tiles write row-major FP32 outputs only (the
+      // deep-K stage's; the host checks), which keeps their epilogue within
+      // two workgroups' registers
+      const int kind = (tr ? 2 : 0) + (es == 4 ? 1 : 0);
+      if (NA == 1 && kind != 1) continue;
+      if (LO && (es != 2 || NA != 2)) continue;          // lo planes: dual-A BF16 outputs only
+      for (int h = 0; h < (halves ? 2 : 1); ++h) {
+        __syncthreads();                               // LDS free (main loop, traces, last copy-out)
+        if (!halves || wm == h) {
+          auto val = [&](int gi, int gj, int r) {
+            float x = 0.0f;
 #pragma unroll
-          for (int a = 0; a < NA; ++a) x += cf[a] * acc[a * FR + gi][gj][r];
-          return x;
-        };
-        // BF16 bits of an output element: x, or on a lo plane x - bf16(x)
-        auto b16 = [&](float x) {
-          const uint16_t h = bf16_bits(x);
-          return pl ? bf16_bits(x - __uint_as_float((uint32_t)h << 16)) : h;
-        };
-        const int hr = h * rs;
-        if (NA == 2 && kind == 0) {  // row-major BF16
+            for (int a = 0; a < NA; ++a) x += cf[a] * acc[a * FR + gi][gj][r];
+            return x;
+          };
+          // BF16 bits of an output element: x, or on a lo plane x - bf16(x)
+          auto b16 = [&](float x) {
+            if constexpr (LO) return bf16_bits(x - __uint_as_float((uint32_t)bf16_bits(x) << 16));
+            else return bf16_bits(x);
+          };
+          const int hr = h * rs;
+          if (NA == 2 && kind == 0) {  // row-major BF16
 #pragma unroll
-          for (int gi = 0; gi < FR; ++gi)
+            for (int gi = 0; gi < FR; ++gi)
 #pragma unroll
-            for (int gj = 0; gj < FC; ++gj)
+              for (int gj = 0; gj < FC; ++gj)
 #pragma unroll
-              for (int r = 0; r < 4; ++r)
-                ((uint16_t*)smem)[(lrow(gi, r) - hr) * pr + lcol(gj)] = b16(val(gi, gj, r));
-        } else if (kind == 1) {      // row-major FP32
+                for (int r = 0; r < 4; ++r)
+                  ((uint16_t*)smem)[(lrow(gi, r) - hr) * pr + lcol(gj)] = b16(val(gi, gj, r));
+          } else if (!LO && kind == 1) {      // row-major FP32
 #pragma unroll
-          for (int gi = 0; gi < FR; ++gi)
+            for (int gi = 0; gi < FR; ++gi)
 #pragma unroll
-            for (int gj = 0; gj < FC; ++gj)
+              for (int gj = 0; gj < FC; ++gj)
 #pragma unroll
-              for (int r = 0; r < 4; ++r) ((float*)smem)[(lrow(gi, r) - hr) * pr + lcol(gj)] = val(gi, gj, r);
-        } else if (NA == 2 && kind == 2) {   // transposed BF16: four consecutive tile rows = four elements of an output row
+                for (int r = 0; r < 4; ++r) ((float*)smem)[(lrow(gi, r) - hr) * pr + lcol(gj)] = val(gi, gj, r);
+          } else if (NA == 2 && kind == 2) {   // transposed BF16: four consecutive tile rows = four elements of an output row
 #pragma unroll
-          for (int gi = 0; gi < FR; ++gi)
+            for (int gi = 0; gi < FR; ++gi)
 #pragma unroll
-            for (int gj = 0; gj < FC; ++gj) {
-              const uint32_t lo = (uint32_t)b16(val(gi, gj, 0)) | ((uint32_t)b16(val(gi, gj, 1)) << 16);
-              const uint32_t hi = (uint32_t)b16(val(gi, gj, 2)) | ((uint32_t)b16(val(gi, gj, 3)) << 16);
-              *(uint2*)((uint16_t*)smem + lcol(gj) * pt + lrow(gi, 0) - hr) = make_uint2(lo, hi);
-            }
-        } else if (NA == 2) {        // transposed FP32
+              for (int gj = 0; gj < FC; ++gj) {
+                const uint32_t lo = (uint32_t)b16(val(gi, gj, 0)) | ((uint32_t)b16(val(gi, gj, 1)) << 16);
+                const uint32_t hi = (uint32_t)b16(val(gi, gj, 2)) | ((uint32_t)b16(val(gi, gj, 3)) << 16);
+                *(uint2*)((uint16_t*)smem + lcol(gj) * pt + lrow(gi, 0) - hr) = make_uint2(lo, hi);
+              }
+          } else if (!LO && NA == 2) {        // transposed FP32
 #pragma unroll
-          for (int gi = 0; gi < FR; ++gi)
+            for (int gi = 0; gi < FR; ++gi)
 #pragma unroll
-            for (int gj = 0; gj < FC; ++gj)
-              *(float4*)((float*)smem + lcol(gj) * pt + lrow(gi, 0) - hr) =
-                  make_float4(val(gi, gj, 0), val(gi, gj, 1), val(gi, gj, 2), val(gi, gj, 3));
+              for (int gj = 0; gj < FC; ++gj)
+                *(float4*)((float*)smem + lcol(gj) * pt + lrow(gi, 0) - hr) =
+                    make_float4(val(gi, gj, 0), val(gi, gj, 1), val(gi, gj, 2), val(gi, gj, 3));
+          }
         }
-      }
-      __syncthreads();
-      // copy-out: output rows of the staged region as 16-byte vectors
-      const int orows = tr ? SN : rs, ocols = tr ? rs : SN;
-      const int64_t grow0 = tr ? col0 : row0 + h * rs, gcol0 = tr ? row0 + h * rs : col0;
-      const int64_t grows = tr ? ncols : mrows, gcols = tr ? mrows : ncols;
-      const int opitch = tr ? pt : pr;
-      const int vpr = ocols / vl;
-      for (int idx = tid; idx < orows * vpr; idx += kThreads) {
-        const int rr = idx / vpr, cc = (idx % vpr) * vl;
-        const int64_t gr = grow0 + rr, gc = gcol0 + cc;
-        if (gr >= grows || gc >= gcols) continue;
-        const unsigned char* src = smem + ((int64_t)rr * opitch + cc) * es;
-        char* d = dst + (gr * ld + gc) * es;
-        if (gc + vl <= gcols) {
-          *(u32x4_t*)d = *(const u32x4_t*)src;
-        } else {
-          for (int e = 0; e < vl && gc + e < gcols; ++e)
-            for (int bq = 0; bq < es; ++bq) d[e * es + bq] = (char)src[e * es + bq];
+        __syncthreads();
+        // copy-out: output rows of the staged region as 16-byte vectors
+        const int orows = tr ? SN : rs, ocols = tr ? rs : SN;
+        const int64_t grow0 = tr ? col0 : row0 + h * rs, gcol0 = tr ? row0 + h * rs : col0;
+        const int64_t grows = tr ? ncols : mrows, gcols = tr ? mrows : ncols;
+        const int opitch = tr ? pt : pr;
+        const int vpr = ocols / vl;
+        for (int idx = tid; idx < orows * vpr; idx += kThreads) {
+          const int rr = idx / vpr, cc = (idx % vpr) * vl;
+          const int64_t gr = grow0 + rr, gc = gcol0 + cc;
+          if (gr >= grows || gc >= gcols) continue;
+          const unsigned char* src = smem + ((int64_t)rr * opitch + cc) * es;
+          char* d = dst + (gr * ld + gc) * es;
+          if (gc + vl <= gcols) {
+            *(u32x4_t*)d = *(const u32x4_t*)src;
+          } else {
+            for (int e = 0; e < vl && gc + e < gcols; ++e)
+              for (int bq = 0; bq < es; ++bq) d[e * es + bq] = (char)src[e * es + bq];
+          }
         }
       }
     }
-  }
+  };
+  pass(std::false_type{});
+  pass(std::true_type{});
 }
 
 template <Prec P, int W, int NA, int NB>
