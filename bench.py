@@ -39,14 +39,14 @@ MFMA_PEAK = {"bf16": 2.5e15, "bf16c": 2.5e15, "bf16x3": 2.5e15, "fp32": 157.3e12
 # 256 MiB copy in the same runs), recorded with the hash of the kernel source
 # they were taken on: reported only while that source is unchanged.
 GEMM_TRAFFIC = {
-    # launch-weighted mean of the two BF16 chain GEMM kernels at N=800
-    # (dual-A 320x160 tile: 132 launches of stages s1-s3, FETCH 270502.2 /
-    # WRITE 544790.3 KiB; 160x160 tile: 44 launches of stage s4, FETCH
-    # 737054.7 / WRITE 116377.9 KiB), FETCH scaled by 1.9987 and WRITE by
-    # 0.9997 from a plain copy
-    ("bf16c", "n800"): {"bytes_per_launch": ((270502.2 * 1.9987 + 544790.3 * 0.9997) * 132
-                                          + (737054.7 * 1.9987 + 116377.9 * 0.9997) * 44) / 176 * 1024.0,
-                        "gemm_src_sha256_16": "3673d727129be642",
+    # launch-weighted mean over the BF16 launches of the two BF16 chain GEMM
+    # kernels at N=800 (dual-A 320x160 tile: 132 launches of stages s1-s3,
+    # FETCH 269348.3 / WRITE 544984.7 KiB; 160x160 tile: 44 launches of stage
+    # s4, FETCH 731507.1 / WRITE 116377.8 KiB), FETCH scaled by 1.9997 and
+    # WRITE by 1.0000 from a plain 256 MiB copy
+    ("bf16c", "n800"): {"bytes_per_launch": ((269348.3 * 1.9997 + 544984.7 * 1.0) * 132
+                                          + (731507.1 * 1.9997 + 116377.8 * 1.0) * 44) / 176 * 1024.0,
+                        "gemm_src_sha256_16": "b9ead5a556ed4671",
                         "profile": "profiles/chain_n800_bf16.md"},
 }
 
