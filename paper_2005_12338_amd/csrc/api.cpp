@@ -522,6 +522,12 @@ gf2_status split_impl(gf2_ctx* ctx, const void* B, const void* L, gf2_dtype dtyp
     if (!tq.empty()) h2d(ctx, h->row_q, tq.data(), tq.size());
     launch_extract_blocks(L, f64, n, naux, thr, h->w, h->idx, h->blk, h->blk32, ctx->stream);
     GF2_HIP(hipGetLastError());
+    if (h->wmax <= kDdW) {
+      alloc((void**)&h->idx_t, naux * kDdW * 4);
+      alloc((void**)&h->blk_t, naux * kDdW * kDdW * 8);
+      launch_dd_tables(h->idx, h->blk, naux, h->idx_t, h->blk_t, ctx->stream);
+      GF2_HIP(hipGetLastError());
+    }
     GF2_HIP(hipStreamSynchronize(ctx->stream));
     *out = h;
     if (nnzL) *nnzL = h->nnz;
@@ -552,7 +558,7 @@ gf2_status gf2_split_large(gf2_ctx* ctx, const void* B, const void* KL, gf2_dtyp
 
 void gf2_split_free(gf2_split_h* h) {
   if (!h) return;
-  void* ps[] = {h->w, h->idx, h->blk, h->blk32, h->pat_ij, h->pat_off, h->pat_q, h->row_off, h->row_q,
+  void* ps[] = {h->w, h->idx, h->blk, h->blk32, h->idx_t, h->blk_t, h->pat_ij, h->pat_off, h->pat_q, h->row_off, h->row_q,
                 h->orb_off, h->orb_q, h->orb_cs};
   for (void* p : ps)
     if (p) (void)hipFree(p);
@@ -665,8 +671,8 @@ void run_dd(gf2_ctx* ctx, const gf2_split_h* sp, const double* G, const double* 
     const int64_t per = dd_strip_bytes(sp->n, sp->naux, sp->wmax, 1);
     const int64_t tb = std::max<int64_t>(1, std::min<int64_t>(ntau, (int64_t)2e9 / std::max<int64_t>(per, 1)));
     auto* strip = (double*)ctx_buf(ctx, "dd_strip", (size_t)(per * tb));
-    launch_dd_strips(G, Gb, sp->n, sp->naux, ntau, sp->wmax, sp->span128, sp->w, sp->idx, sp->blk, sp->orb_off, sp->orb_q,
-                     sp->orb_cs, sp->orb_ncs, strip, tb, out, ctx->stream);
+    launch_dd_strips(G, Gb, sp->n, sp->naux, ntau, sp->wmax, sp->span128, sp->w, sp->idx, sp->blk, sp->idx_t,
+                     sp->blk_t, sp->orb_off, sp->orb_q, sp->orb_cs, sp->orb_ncs, strip, tb, out, ctx->stream);
   } else {
     launch_dblock(G, Gb, sp->n, ntau, sp->wmax, sp->w, sp->idx, sp->blk, sp->row_off, sp->row_q, out,
                   ctx->stream);

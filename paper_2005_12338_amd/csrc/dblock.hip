@@ -285,9 +285,13 @@ __global__ __launch_bounds__(256) void k_dd_strip(const double* G, const double*
 template <int W, int CH>
 __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* Gb, int64_t n, int64_t naux,
                                                 int32_t tau0, const int32_t* wq, const int32_t* idx,
-                                                const double* blk, const int32_t* col_q,
-                                                const int32_t* col_cs, int32_t ncs, double* strip) {
-  __shared__ double cbuf[CH * W * W];
+                                                const double* blk, const int32_t* idx_t, const double* blk_t,
+                                                const int32_t* col_q, const int32_t* col_cs, int32_t ncs,
+                                                double* strip) {
+  // one lane's C block in LDS: W x W, padded to an odd number of doubles so
+  // that the lanes' writes spread over the banks
+  constexpr int CS = W * W + 1;
+  __shared__ double cbuf[CH * CS];
   __shared__ double uq[W * kDdSpan];
   __shared__ double gq[W * kDdSpan];
   __shared__ double kq[W * W];
@@ -318,15 +322,18 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
   // accumulation before the pair products.
   int w2n;
   int srn[W];
+  // the chunk's supports and blocks are read from the by-column tables
+  // (element c of S_Q' at idx_t[c naux + Q'], block element (c, d) at
+  // blk_t[(c kDdW + d) naux + Q']), so that a wave's loads are contiguous
   auto load_meta = [&](int64_t cc) {
     const int64_t rr = cc + tid;
     w2n = rr < naux ? wq[rr] : 0;
 #pragma unroll
-    for (int c = 0; c < W; ++c) srn[c] = rr < naux ? idx[rr * kWMax + c] : -1;
+    for (int c = 0; c < W; ++c) srn[c] = rr < naux ? idx_t[c * naux + rr] : -1;
   };
   load_meta(0);
   constexpr int NJ = kDdSpan / CH;          // strip columns per lane and chunk
-  constexpr int NPRE = 8;                   // column entries fetched ahead
+  constexpr int NPRE = 24;                  // column entries fetched ahead
   for (int64_t c0 = 0; c0 < naux; c0 += CH) {
     const int64_t r = c0 + tid;
     const int w2r = w2n;
@@ -369,13 +376,28 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
       }
     }
     const int width = jhi - jlo + 1;          // <= kDdSpan (checked on the host)
-    for (int e = tid; e < W * width; e += CH) {
-      const int a = e / width, jj = e % width;
+    // each lane stages whole window columns: the rows S_Q of G and Gb are
+    // read once per column, all loads issued before the sums
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      const int jj = tid + u * CH;
+      if (jj >= width) break;
       const int64_t j = jlo + jj;
-      double s = 0.0;
-      for (int b = 0; b < w1; ++b) s += kq[a * W + b] * g[(int64_t)sq[b] * n + j];
-      uq[a * kDdSpan + jj] = s;
-      gq[a * kDdSpan + jj] = a < w1 ? gb[(int64_t)sq[a] * n + j] : 0.0;
+      double gv[W], gbv[W];
+#pragma unroll
+      for (int b = 0; b < W; ++b) {
+        gv[b] = b < w1 ? g[(int64_t)sq[b] * n + j] : 0.0;
+        gbv[b] = b < w1 ? gb[(int64_t)sq[b] * n + j] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < W; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < W; ++b)
+          if (b < w1) s += kq[a * W + b] * gv[b];
+        uq[a * kDdSpan + jj] = s;
+        gq[a * kDdSpan + jj] = gbv[a];
+      }
     }
     __syncthreads();
     if (act) {
@@ -385,19 +407,22 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
       for (int a = 0; a < W; ++a)
 #pragma unroll
         for (int d = 0; d < W; ++d) m[a][d] = 0.0;
-      const double* kr = blk + r * kWMax * kWMax;
+      // the lane's k_Q' block, every load issued at once (zero padded beyond w2)
+      const double* kr = blk_t + r;
+      double kv[W][W];
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+#pragma unroll
+        for (int d = 0; d < W; ++d) kv[c][d] = c < w2 ? kr[(c * kDdW + d) * naux] : 0.0;
 #pragma unroll
       for (int c = 0; c < W; ++c) {
         if (c >= w2) break;
-        double row[W];
-#pragma unroll
-        for (int d = 0; d < W; ++d) row[d] = kr[c * kWMax + d];   // zero padded beyond w2
         const int col = sr[c] - jlo;            // c < w2: inside the window
 #pragma unroll
         for (int a = 0; a < W; ++a) {
           const double uv = uq[a * kDdSpan + col];
 #pragma unroll
-          for (int d = 0; d < W; ++d) m[a][d] += uv * row[d];
+          for (int d = 0; d < W; ++d) m[a][d] += uv * kv[c][d];
         }
       }
       // T = M Gb[S_Q', S_Q]
@@ -420,7 +445,7 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
       double tr = 0.0;
 #pragma unroll
       for (int a = 0; a < W; ++a) tr += tt[a][a];
-      double* cb = cbuf + tid * W * W;
+      double* cb = cbuf + tid * CS;
 #pragma unroll
       for (int a = 0; a < W; ++a)
 #pragma unroll
@@ -447,14 +472,14 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
 #pragma unroll
       for (int x = 0; x < NPRE; ++x) {
         if (klo[u] + x >= khi[u]) break;
-        const double* cb = cbuf + ((cq[x] >> 5) - c0) * W * W + (cq[x] & 31);
+        const double* cb = cbuf + ((cq[x] >> 5) - c0) * CS + (cq[x] & 31);
 #pragma unroll
         for (int a = 0; a < W; ++a)
           if (a < w1) acc[a] += cb[a * W];
       }
       for (int k = klo[u] + NPRE; k < khi[u]; ++k) {
         const int32_t c = col_q[k];
-        const double* cb = cbuf + ((c >> 5) - c0) * W * W + (c & 31);
+        const double* cb = cbuf + ((c >> 5) - c0) * CS + (c & 31);
 #pragma unroll
         for (int a = 0; a < W; ++a)
           if (a < w1) acc[a] += cb[a * W];
@@ -517,6 +542,25 @@ __global__ __launch_bounds__(256) void k_dd_gather(const double* strip, int64_t 
 
 int dblock_tile() { return TD; }
 
+// By-column copies of the supports and blocks of width at most kDdW:
+// idx_t[c naux + Q] = S_Q(c) (-1 beyond w_Q), blk_t[(c kDdW + d) naux + Q] =
+// k_Q[c][d] (0 beyond w_Q).
+__global__ void k_dd_tables(const int32_t* idx, const double* blk, int64_t naux, int32_t* idx_t, double* blk_t) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= naux * kDdW * kDdW) return;
+  const int64_t q = e % naux;
+  const int cd = (int)(e / naux), c = cd / kDdW, d = cd % kDdW;
+  blk_t[e] = blk[q * kWMax * kWMax + c * kWMax + d];
+  if (cd < kDdW) idx_t[e] = idx[q * kWMax + cd];
+}
+
+void launch_dd_tables(const int32_t* idx, const double* blk, int64_t naux, int32_t* idx_t, double* blk_t,
+                      hipStream_t st) {
+  const int64_t tot = naux * kDdW * kDdW;
+  hipLaunchKernelGGL(k_dd_tables, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, idx, blk, naux, idx_t,
+                     blk_t);
+}
+
 int64_t dd_strip_bytes(int64_t n, int64_t naux, int32_t wmax, int64_t ntau_batch) {
   const int W = wmax <= 4 ? 4 : wmax <= 6 ? 6 : 8;
   return ntau_batch * naux * W * n * (int64_t)sizeof(double);
@@ -524,7 +568,7 @@ int64_t dd_strip_bytes(int64_t n, int64_t naux, int32_t wmax, int64_t ntau_batch
 
 bool launch_dd_strips(const double* G, const double* Gb, int64_t n, int64_t naux, int64_t ntau, int32_t wmax,
                       int32_t span128, const int32_t* wq, const int32_t* idx, const double* blk,
-                      const int32_t* col_off, const int32_t* col_q, const int32_t* col_cs, int32_t ncs,
+                      const int32_t* idx_t, const double* blk_t, const int32_t* col_off, const int32_t* col_q, const int32_t* col_cs, int32_t ncs,
                       double* strip, int64_t ntau_batch, double* out, hipStream_t st) {
   if (wmax > 8) return false;
   const bool rows = span128 <= kDdSpan;
@@ -536,13 +580,13 @@ bool launch_dd_strips(const double* G, const double* Gb, int64_t n, int64_t naux
     if (rows) {
       if (wmax <= 4)
         hipLaunchKernelGGL((k_dd_rows<4, 128>), grid, dim3(128), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
-                           col_q, col_cs, ncs, strip);
+                           idx_t, blk_t, col_q, col_cs, ncs, strip);
       else if (wmax <= 6)
         hipLaunchKernelGGL((k_dd_rows<6, 128>), grid, dim3(128), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
-                           col_q, col_cs, ncs, strip);
+                           idx_t, blk_t, col_q, col_cs, ncs, strip);
       else
         hipLaunchKernelGGL((k_dd_rows<8, 64>), grid, dim3(64), 0, st, G, Gb, n, naux, (int32_t)t0, wq, idx, blk,
-                           col_q, col_cs, ncs, strip);
+                           idx_t, blk_t, col_q, col_cs, ncs, strip);
       GF2_HIP(hipGetLastError());
       const int W = wmax <= 4 ? 4 : wmax <= 6 ? 6 : 8;
       if (W == 4)

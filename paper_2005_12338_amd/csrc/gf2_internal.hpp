@@ -214,6 +214,10 @@ struct gf2_split_h {
   int32_t* idx = nullptr;      // [naux][32], -1 padded
   double* blk = nullptr;       // [naux][32][32]
   float* blk32 = nullptr;      // same in FP32
+  // by-column copies for supports of at most kDdW orbitals (else null):
+  // idx_t[c * naux + Q] = idx[Q][c], blk_t[(c * kDdW + d) * naux + Q] = blk[Q][c][d]
+  int32_t* idx_t = nullptr;    // [kDdW][naux]
+  double* blk_t = nullptr;     // [kDdW * kDdW][naux]
   // union pattern of the blocks: for every nonzero (i, j) of
   // U_Q S_Q x S_Q (sorted row-major) the list of contributing (Q, a, b).
   int64_t npat = 0;
@@ -236,3 +240,5 @@ struct gf2_split_h {
 constexpr int kWMax = 32;
 // Widest column window the row-staged deterministic block stages in LDS.
 constexpr int kDdSpan = 128;
+// Widest support the register form of the deterministic block takes.
+constexpr int kDdW = 8;

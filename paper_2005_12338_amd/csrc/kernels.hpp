@@ -85,9 +85,14 @@ int64_t dd_strip_bytes(int64_t n, int64_t naux, int32_t wmax, int64_t ntau_batch
 // orbitals (returns false, launching nothing, for wider supports).
 bool launch_dd_strips(const double* G, const double* Gb, int64_t n, int64_t naux, int64_t ntau, int32_t wmax,
                       int32_t span128,
-                      const int32_t* wq, const int32_t* idx, const double* blk, const int32_t* col_off,
+                      const int32_t* wq, const int32_t* idx, const double* blk, const int32_t* idx_t,
+                      const double* blk_t, const int32_t* col_off,
                       const int32_t* col_q, const int32_t* col_cs, int32_t ncs, double* strip,
                       int64_t ntau_batch, double* out, hipStream_t st);
+// By-column tables of the supports and blocks for the register form:
+// idx_t [kDdW][naux], blk_t [kDdW * kDdW][naux].
+void launch_dd_tables(const int32_t* idx, const double* blk, int64_t naux, int32_t* idx_t, double* blk_t,
+                      hipStream_t st);
 
 // eq:V_ijA screening (front.hip); mbits [n] and kept must be zeroed.
 void launch_screen_ija(const void* x, bool f64, int64_t n, int64_t naux, double eps_over_n,
