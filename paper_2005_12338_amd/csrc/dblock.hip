@@ -333,7 +333,7 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
   };
   load_meta(0);
   constexpr int NJ = kDdSpan / CH;          // strip columns per lane and chunk
-  constexpr int NPRE = 24;                  // column entries fetched ahead
+  constexpr int NPRE = NJ == 1 ? 24 : 8;    // column entries fetched ahead
   for (int64_t c0 = 0; c0 < naux; c0 += CH) {
     const int64_t r = c0 + tid;
     const int w2r = w2n;
@@ -375,6 +375,25 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
         khi[u] = cs[min(c64 + CH / 64, ncs - 1)];
       }
     }
+    // Loads whose addresses are known now go out with the staging loads, so
+    // that the chunk waits on memory once before its products: the lane's
+    // k_Q' block (zero padded beyond w2), and (one strip column per lane)
+    // the strip values the chunk adds to.
+    double kv[W][W];
+    {
+      const double* kr = blk_t + r;
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+#pragma unroll
+        for (int d = 0; d < W; ++d) kv[c][d] = (act && c < w2) ? kr[(c * kDdW + d) * naux] : 0.0;
+    }
+    constexpr bool kEarlySt = NJ == 1;
+    double sv[W];
+    if constexpr (kEarlySt) {
+      const int j = jl + tid;
+#pragma unroll
+      for (int a = 0; a < W; ++a) sv[a] = (j <= jhi && a < w1) ? st[(int64_t)a * n + j] : 0.0;
+    }
     const int width = jhi - jlo + 1;          // <= kDdSpan (checked on the host)
     // each lane stages whole window columns: the rows S_Q of G and Gb are
     // read once per column, all loads issued before the sums
@@ -407,13 +426,6 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
       for (int a = 0; a < W; ++a)
 #pragma unroll
         for (int d = 0; d < W; ++d) m[a][d] = 0.0;
-      // the lane's k_Q' block, every load issued at once (zero padded beyond w2)
-      const double* kr = blk_t + r;
-      double kv[W][W];
-#pragma unroll
-      for (int c = 0; c < W; ++c)
-#pragma unroll
-        for (int d = 0; d < W; ++d) kv[c][d] = c < w2 ? kr[(c * kDdW + d) * naux] : 0.0;
 #pragma unroll
       for (int c = 0; c < W; ++c) {
         if (c >= w2) break;
@@ -456,6 +468,12 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
           cb[a * W + d] = 2.0 * tr * m[a][d] - s;
         }
     }
+    // the first column entries, fetched before the barrier
+    int cqa[NJ][NPRE];
+#pragma unroll
+    for (int u = 0; u < NJ; ++u)
+#pragma unroll
+      for (int x = 0; x < NPRE; ++x) cqa[u][x] = klo[u] + x < khi[u] ? col_q[klo[u] + x] : 0;
     __syncthreads();
     // add the chunk to the strip: output (a, j), contributions from the
     // chunk's Q' with S_Q'(d) = j in increasing Q'
@@ -463,9 +481,7 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
     for (int u = 0; u < NJ; ++u) {
       const int j = jl + tid + u * CH;
       if (j > jhi) continue;
-      int cq[NPRE];
-#pragma unroll
-      for (int x = 0; x < NPRE; ++x) cq[x] = klo[u] + x < khi[u] ? col_q[klo[u] + x] : 0;
+      const int* cq = cqa[u];
       double acc[W];
 #pragma unroll
       for (int a = 0; a < W; ++a) acc[a] = 0.0;
@@ -485,8 +501,11 @@ __global__ __launch_bounds__(CH) void k_dd_rows(const double* G, const double* G
           if (a < w1) acc[a] += cb[a * W];
       }
 #pragma unroll
-      for (int a = 0; a < W; ++a)
-        if (a < w1) st[(int64_t)a * n + j] += acc[a];
+      for (int a = 0; a < W; ++a) {
+        if (a >= w1) continue;
+        if constexpr (kEarlySt) st[(int64_t)a * n + j] = sv[a] + acc[a];
+        else st[(int64_t)a * n + j] += acc[a];
+      }
     }
     __syncthreads();
   }
