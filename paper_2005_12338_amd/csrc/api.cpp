@@ -747,6 +747,43 @@ int64_t auto_slots(int64_t n, Prec prec) {
   return (int64_t)std::max(1.0, std::min(64.0, 4.0e9 / per_slot));
 }
 
+// Chunk length along tau (at most tmax) for chains on the 160-wide BF16
+// tiles (BF16, and BF16X3 split into BF16 products).  A launch spreads its
+// tiles evenly over the 8 XCDs and runs them on each XCD's CUs in rounds
+// (one dual-A workgroup per CU for stages s1-s3, two single-tile workgroups
+// for the deep-K stage s4); a round that is only partly filled takes about
+// as long as a full one.  The length with the fewest estimated rounds over
+// all chunks of the tau axis is taken (rounds of s4, about twice as long,
+// counted twice; a small cost per chunk for its other launches); ties go to
+// the longer chunk.  Other tiles keep tmax.
+int64_t chunk_tau(const gf2_ctx* ctx, Prec prec, int64_t n, int64_t ntau, int64_t sc, int64_t tmax) {
+  if (!((prec == Prec::BF16 || prec == Prec::BF16X3) && tile_mode(ctx, prec, n) >= 2 &&
+        wide_pads_less(Prec::BF16, n)))
+    return tmax;
+  const int64_t tw = gemm_tile_n(Prec::BF16, 1);
+  const int64_t tpu = ((n + tw - 1) / tw) * ((n + tw - 1) / tw);     // tiles per unit and stage
+  int cus = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess && prop.multiProcessorCount > 0)
+    cus = prop.multiProcessorCount;
+  const int64_t per_xcd = std::max(1, cus / 8);
+  auto rounds = [&](int64_t units) {
+    const int64_t tx = (units * tpu + 7) / 8;                         // tiles on one XCD
+    return 3.0 * (double)((tx + per_xcd - 1) / per_xcd) + 2.0 * (double)((tx + 2 * per_xcd - 1) / (2 * per_xcd)) + 0.2;
+  };
+  int64_t best = tmax;
+  double best_cost = 0.0;
+  for (int64_t t = tmax; t >= 1; --t) {
+    const int64_t full = ntau / t, tail = ntau % t;
+    const double cost = (double)full * rounds(sc * t) + (tail ? rounds(sc * tail) : 0.0);
+    if (t == tmax || cost < best_cost * (1.0 - 1e-9)) {
+      best = t;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
 // Buffers (tags prefixed by pfx), G conversions, stochastic vectors, problem
 // tables and unit lists of one instance.  sc / tcnt > 0 force the chunk shape.
 void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_split_h* sp, const void* B,
@@ -785,6 +822,7 @@ void plan_chain(gf2_ctx* ctx, ChainPlan& c, const std::string& pfx, const gf2_sp
   slots = std::min<int64_t>(slots, ntau * npairs);
   c.sc = force_sc > 0 ? std::min(force_sc, npairs) : std::min<int64_t>(npairs, std::min<int64_t>(8, slots));
   c.tcnt = force_tcnt > 0 ? std::min(force_tcnt, ntau) : std::max<int64_t>(1, std::min<int64_t>(ntau, slots / c.sc));
+  if (force_tcnt <= 0 && ctx->max_units <= 0) c.tcnt = chunk_tau(ctx, prec, n, ntau, c.sc, c.tcnt);
   c.slots = slots = c.sc * c.tcnt;
 
   // The products run over the zero padding of every np x np matrix, and the
