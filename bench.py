@@ -37,28 +37,35 @@ MFMA_PEAK = {"bf16": 2.5e15, "bf16c": 2.5e15, "bf16x3": 2.5e15, "fp32": 157.3e12
 # HBM bytes per launch of the chain GEMM from two rocprofv3 PMC passes
 # (FETCH_SIZE x 2.0 + WRITE_SIZE, KiB x 1024; the factors come from a plain
 # 256 MiB copy in the same runs), recorded with the hash of the kernel source
-# they were taken on: reported only while that source is unchanged.
+# and the launch shape they were taken on: reported only while both are
+# unchanged.
 GEMM_TRAFFIC = {
     # launch-weighted mean over the BF16 launches of the two BF16 chain GEMM
-    # kernels at N=800 (dual-A 320x160 tile: 132 launches of stages s1-s3,
-    # FETCH 269348.3 / WRITE 544984.7 KiB; 160x160 tile: 44 launches of stage
-    # s4, FETCH 731507.1 / WRITE 116377.8 KiB), FETCH scaled by 1.9997 and
+    # kernels at N=800 (dual-A 320x160 tile: 156 launches of stages s1-s3,
+    # FETCH 229803.4 / WRITE 461416.4 KiB; 160x160 tile: 52 launches of stage
+    # s4, FETCH 611034.0 / WRITE 98472.2 KiB), FETCH scaled by 1.9997 and
     # WRITE by 1.0000 from a plain 256 MiB copy
-    ("bf16c", "n800"): {"bytes_per_launch": ((269348.3 * 1.9997 + 544984.7 * 1.0) * 132
-                                          + (731507.1 * 1.9997 + 116377.8 * 1.0) * 44) / 176 * 1024.0,
+    ("bf16c", "n800"): {"bytes_per_launch": ((229803.4 * 1.9997 + 461416.4 * 1.0) * 156
+                                          + (611034.0 * 1.9997 + 98472.2 * 1.0) * 52) / 208 * 1024.0,
                         "gemm_src_sha256_16": "b9ead5a556ed4671",
+                        # 8 pairs x 5 tau per launch: 26 chunks per 128 tau, 4 launches each
+                        "units_per_launch": 4 * 128 * 8 / (26 * 4),
                         "profile": "profiles/chain_n800_bf16.md"},
 }
 
 
-def gemm_traffic(prec, wl_key):
+def gemm_traffic(prec, wl_key, units_per_launch):
+    """The recorded HBM bytes per launch, or None when the GEMM source or the
+    launch shape (units per launch) differs from the run the counters came from."""
     import hashlib
     rec = GEMM_TRAFFIC.get((prec, wl_key))
     if rec is None:
         return None
     src = os.path.join(ROOT, "paper_2005_12338_amd", "csrc", "gemm.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    return rec["bytes_per_launch"] if sha == rec["gemm_src_sha256_16"] else None
+    if sha != rec["gemm_src_sha256_16"] or abs(units_per_launch - rec["units_per_launch"]) > 1e-6:
+        return None
+    return rec["bytes_per_launch"]
 
 
 def log(msg):
@@ -667,6 +674,9 @@ def main():
                 f"avg={v['ms'] / max(1, v['launches']):8.4f} ms  {rate:8.1f} TFLOP/s")
         log(f"[bench]   kernel time {tot_ms:.1f} ms of {ms_step * args.steps:.1f} ms wall")
     achieved = gk["flops"] / (gk["ms"] * 1e-3) if gk["ms"] > 0 else 0.0
+    # chain units (tau, pair) per GEMM launch: each unit's chain has 4 stage
+    # launches, each the same units
+    units_per_launch = (4.0 * args.steps * wl.ntau * ns / gk["launches"]) if gk["launches"] else 0.0
     peak = MFMA_PEAK[args.prec]
 
     out = {
@@ -680,9 +690,11 @@ def main():
         "E_corr_total": e, "stderr_total": se_,
         "chain_mfma_tflops": achieved / 1e12,
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": gemm_traffic(args.prec, args.workload),
+                     "frac": achieved / peak, "traffic": gemm_traffic(args.prec, args.workload,
+                                                                       units_per_launch),
                      "traffic_unit": "bytes per launch", "kernel": gname,
-                     "launches": gk["launches"], "avg_launch_ms": gk["ms"] / max(1, gk["launches"])},
+                     "launches": gk["launches"], "avg_launch_ms": gk["ms"] / max(1, gk["launches"]),
+                     "units_per_launch": units_per_launch},
     }
     if not args.no_target:
         target = args.target_meh * 1e-3
