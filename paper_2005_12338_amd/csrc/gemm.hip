@@ -523,10 +523,13 @@ __device__ __forceinline__ void gemm_body(const InstGeo& L, const Prob& pb, cons
   auto frag_row_out = [&](int i) { return wm * (FR * MT) + i * MT; };   // i < FR
   auto frag_col_out = [&](int j) { return wn * (FC * MT) + j * MT; };   // j < FC
   // element (row, k) of a tile plane in LDS; k a multiple of 8 with SWZ
-  // 16-byte chunk c of row r sits at chunk c ^ swz(r): 128-byte rows (BK 64)
-  // rotate by r mod 8, 64-byte rows (BK 32) by (r / 4) mod 4, so that the 16
-  // rows one MFMA fragment read touches fall in distinct banks
-  auto swz = [&](int row) { return BK == 64 ? (row & 7) : ((row >> 2) & 3); };
+  // 16-byte chunk c of row r sits at chunk c ^ swz(r).  A 16-byte fragment
+  // read is served 8 lanes (8 consecutive rows, one logical chunk) at a time
+  // from 32 banks of 4 bytes, so those 8 rows must hit 8 distinct 16-byte
+  // bank groups: 128-byte rows (BK 64) rotate by r mod 8; 64-byte rows (BK
+  // 32, two rows per 32 banks) by (r / 2) mod 4, which gives each of the
+  // two row parities 4 distinct chunks
+  auto swz = [&](int row) { return BK == 64 ? (row & 7) : ((row >> 1) & 3); };
   auto lds_at = [&](int row, int k) {
     if constexpr (C::SWZ) return row * PITCH + ((((k >> 3) ^ swz(row))) << 3);
     else return row * PITCH + k;
