@@ -42,12 +42,12 @@ MFMA_PEAK = {"bf16": 2.5e15, "bf16c": 2.5e15, "bf16x3": 2.5e15, "fp32": 157.3e12
 GEMM_TRAFFIC = {
     # launch-weighted mean over the BF16 launches of the two BF16 chain GEMM
     # kernels at N=800 (dual-A 320x160 tile: 156 launches of stages s1-s3,
-    # FETCH 229803.4 / WRITE 461416.4 KiB; 160x160 tile: 52 launches of stage
-    # s4, FETCH 611034.0 / WRITE 98472.2 KiB), FETCH scaled by 1.9997 and
+    # FETCH 230771.1 / WRITE 461424.0 KiB; 160x160 tile: 52 launches of stage
+    # s4, FETCH 614129.5 / WRITE 98472.3 KiB), FETCH scaled by 1.9997 and
     # WRITE by 1.0000 from a plain 256 MiB copy
-    ("bf16c", "n800"): {"bytes_per_launch": ((229803.4 * 1.9997 + 461416.4 * 1.0) * 156
-                                          + (611034.0 * 1.9997 + 98472.2 * 1.0) * 52) / 208 * 1024.0,
-                        "gemm_src_sha256_16": "b9ead5a556ed4671",
+    ("bf16c", "n800"): {"bytes_per_launch": ((230771.1 * 1.9997 + 461424.0 * 1.0) * 156
+                                          + (614129.5 * 1.9997 + 98472.3 * 1.0) * 52) / 208 * 1024.0,
+                        "gemm_src_sha256_16": "eedf36376ebdfd7e",
                         # 8 pairs x 5 tau per launch: 26 chunks per 128 tau, 4 launches each
                         "units_per_launch": 4 * 128 * 8 / (26 * 4),
                         "profile": "profiles/chain_n800_bf16.md"},
