@@ -602,7 +602,7 @@ def main():
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU (the hot path of one instance); --gpus must be 1"}))
         sys.exit(2)
 
     if args.gemm_reference:
