@@ -279,14 +279,19 @@ __global__ void k_unpad_sym(const double* p, int64_t n, int64_t np, int64_t ntau
 }
 
 // Padded copies of G(tau) in storage format and FP64.
-__global__ void k_pad_convert(const double* g, int64_t n, int64_t np, int64_t ntau, Prec prec,
-                              void* st, int64_t plane, int64_t mstride, double* f64pad) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ntau * np * np) return;
-  int64_t t = e / (np * np), ij = e % (np * np), i = ij / np, j = ij % np;
-  double v = (i < n && j < n) ? g[(t * n + i) * n + j] : 0.0;
-  put_st(st, t * mstride + ij, plane, prec, v);
-  if (f64pad) f64pad[e] = v;
+// One workgroup per (padded row i, tau t0 + blockIdx.y), its threads along
+// the row: contiguous reads and writes, no index divisions per element.
+__global__ __launch_bounds__(256) void k_pad_convert(const double* g, int64_t n, int64_t np, int64_t t0,
+                                                     Prec prec, void* st, int64_t plane, int64_t mstride,
+                                                     double* f64pad) {
+  const int64_t i = blockIdx.x, t = t0 + blockIdx.y;
+  const double* grow = g + (t * n + i) * n;
+  for (int64_t j = threadIdx.x; j < np; j += blockDim.x) {
+    const int64_t ij = i * np + j;
+    const double v = (i < n && j < n) ? grow[j] : 0.0;
+    put_st(st, t * mstride + ij, plane, prec, v);
+    if (f64pad) f64pad[t * np * np + ij] = v;
+  }
 }
 
 // ------------------------------------------------------------- JK ---------
@@ -761,8 +766,11 @@ void launch_unpad_sym(const double* p, int64_t n, int64_t np, int64_t ntau, doub
 }
 void launch_pad_convert(const double* g, int64_t n, int64_t np, int64_t ntau, Prec prec, void* stbuf,
                         int64_t plane, int64_t mstride, double* f64pad, hipStream_t st) {
-  hipLaunchKernelGGL(k_pad_convert, dim3(blocks(ntau * np * np)), dim3(256), 0, st, g, n, np, ntau,
-                     prec, stbuf, plane, mstride, f64pad);
+  for (int64_t t0 = 0; t0 < ntau; t0 += 65535) {
+    const unsigned nt = (unsigned)std::min<int64_t>(65535, ntau - t0);
+    hipLaunchKernelGGL(k_pad_convert, dim3((unsigned)np, nt), dim3(256), 0, st, g, n, np, t0, prec, stbuf, plane,
+                       mstride, f64pad);
+  }
 }
 template <typename T>
 void jk_blocks_launch(int32_t wmax, int64_t tasks, hipStream_t st, const void* wbase, int64_t w_st_slot,
