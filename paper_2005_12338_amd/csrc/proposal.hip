@@ -47,11 +47,25 @@ __global__ __launch_bounds__(256) void k_features(const void* b, int f64, int64_
   const int64_t q = blockIdx.x;
   const int64_t nn = n * n;
   double bb = 0.0, bs = 0.0, bp = 0.0;
-  for (int64_t e = threadIdx.x; e < nn; e += blockDim.x) {
-    const double v = getb(b, q * nn + e, f64);
+  auto take = [&](double v, double g) {
     bb += v * v;
     if (fabs(v) < thr) bs += v * v;
-    bp += v * gbeta[e];
+    bp += v * g;
+  };
+  if (!f64 && nn % 4 == 0 && ((uintptr_t)b & 15) == 0) {
+    // FP32 B: four elements per 16-byte load (B_Q starts 16-byte aligned)
+    const float4* b4 = (const float4*)((const float*)b + q * nn);
+    const int64_t n4 = nn / 4;
+    for (int64_t e = threadIdx.x; e < n4; e += blockDim.x) {
+      const float4 v = b4[e];
+      const double* g = gbeta + 4 * e;
+      take(v.x, g[0]);
+      take(v.y, g[1]);
+      take(v.z, g[2]);
+      take(v.w, g[3]);
+    }
+  } else {
+    for (int64_t e = threadIdx.x; e < nn; e += blockDim.x) take(getb(b, q * nn + e, f64), gbeta[e]);
   }
   bb = block_sum256(bb, sm);
   bs = block_sum256(bs, sm);
