@@ -131,9 +131,20 @@ __global__ void k_synth_b(int64_t n, int64_t naux, const double* x, const double
 __global__ void k_maxabs(const void* b, int f64, int64_t total, double* part) {
   __shared__ double sm[256];
   double m = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x)
-    m = fmax(m, fabs(get_acc(b, e, f64)));
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+  if (!f64 && total % 4 == 0 && ((uintptr_t)b & 15) == 0) {
+    // FP32: four elements per 16-byte load (the maximum does not depend on
+    // the order it is taken in)
+    const float4* b4 = (const float4*)b;
+    float m4 = 0.0f;
+    for (int64_t e = t0; e < total / 4; e += stride) {
+      const float4 v = b4[e];
+      m4 = fmaxf(m4, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+    m = (double)m4;
+  } else {
+    for (int64_t e = t0; e < total; e += stride) m = fmax(m, fabs(get_acc(b, e, f64)));
+  }
   sm[threadIdx.x] = m;
   __syncthreads();
   for (int d = 128; d > 0; d >>= 1) {
@@ -151,7 +162,17 @@ __global__ void k_rowflags(const void* b, int f64, int64_t n, int64_t naux, doub
   if (wid >= naux * n) return;
   const int64_t base = wid * n;
   int cnt = 0;
-  for (int64_t j = lane; j < n; j += 64) cnt += fabs(get_acc(b, base + j, f64)) >= thr ? 1 : 0;
+  if (!f64 && n % 4 == 0 && ((uintptr_t)b & 15) == 0) {
+    // FP32 rows: four elements per 16-byte load
+    const float4* r4 = (const float4*)((const float*)b + base);
+    for (int64_t j = lane; j < n / 4; j += 64) {
+      const float4 v = r4[j];
+      cnt += (fabs((double)v.x) >= thr) + (fabs((double)v.y) >= thr) + (fabs((double)v.z) >= thr) +
+             (fabs((double)v.w) >= thr);
+    }
+  } else {
+    for (int64_t j = lane; j < n; j += 64) cnt += fabs(get_acc(b, base + j, f64)) >= thr ? 1 : 0;
+  }
   for (int d = 32; d > 0; d >>= 1) cnt += __shfl_down(cnt, d, 64);
   if (lane == 0) {
     flags[wid] = cnt > 0;
