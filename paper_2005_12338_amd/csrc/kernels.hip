@@ -114,16 +114,25 @@ __global__ void k_theta_strat(uint64_t seed, int64_t ns, int64_t s0, int64_t nau
 }
 
 // ------------------------------------------------------------- B build ----
-__global__ void k_synth_b(int64_t n, int64_t naux, const double* x, const double* xq,
-                          double amp, double a, double c, void* out, int f64) {
-  int64_t total = naux * n * n;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int64_t q = e / (n * n), ij = e % (n * n), i = ij / n, j = ij % n;
-    double d = x[i] - x[j];
-    double m = xq[q] - 0.5 * (x[i] + x[j]);
-    double v = amp * exp(-a * d * d) * exp(-c * m * m);
-    if (f64) ((double*)out)[e] = v; else ((float*)out)[e] = (float)v;
+// One workgroup per (row i, kSynthQ consecutive Q), its threads along the
+// row: the (i, j) factor amp exp(-a d^2) is evaluated once for those Q, and
+// every element is the same product as B's definition evaluated directly.
+constexpr int kSynthQ = 8;
+__global__ __launch_bounds__(256) void k_synth_b(int64_t n, int64_t naux, const double* x, const double* xq,
+                                                 double amp, double a, double c, void* out, int f64) {
+  const int64_t i = blockIdx.x, q0 = (int64_t)blockIdx.y * kSynthQ;
+  const double xi = x[i];
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    const double xj = x[j];
+    const double d = xi - xj;
+    const double f = amp * exp(-a * d * d);
+    const double mid = 0.5 * (xi + xj);
+    for (int64_t q = q0; q < q0 + kSynthQ && q < naux; ++q) {
+      const double m = xq[q] - mid;
+      const double v = f * exp(-c * m * m);
+      const int64_t e = (q * n + i) * n + j;
+      if (f64) ((double*)out)[e] = v; else ((float*)out)[e] = (float)v;
+    }
   }
 }
 
@@ -728,9 +737,14 @@ void launch_draws(uint64_t seed, int64_t ns, int64_t s0, int32_t k, const double
 }
 void launch_synth_b(int64_t n, int64_t naux, const double* x, const double* xq, double amp, double a,
                     double c, void* out, bool f64, hipStream_t st) {
-  int64_t total = naux * n * n;
-  unsigned g = (unsigned)std::min<int64_t>(blocks(total), 65536 * 4);
-  hipLaunchKernelGGL(k_synth_b, dim3(g), dim3(256), 0, st, n, naux, x, xq, amp, a, c, out, (int)f64);
+  const int64_t nqb = (naux + kSynthQ - 1) / kSynthQ;
+  for (int64_t b0 = 0; b0 < nqb; b0 += 65535) {
+    const unsigned nb = (unsigned)std::min<int64_t>(65535, nqb - b0);
+    const int64_t off = b0 * kSynthQ * n * n;           // elements before this group of Q
+    char* o = (char*)out + off * (f64 ? 8 : 4);
+    hipLaunchKernelGGL(k_synth_b, dim3((unsigned)n, nb), dim3(256), 0, st, n, naux - b0 * kSynthQ, x,
+                       xq + b0 * kSynthQ, amp, a, c, (void*)o, (int)f64);
+  }
 }
 void launch_maxabs(const void* b, bool f64, int64_t total, double* part, int nblk, hipStream_t st) {
   hipLaunchKernelGGL(k_maxabs, dim3(nblk), dim3(256), 0, st, b, (int)f64, total, part);
