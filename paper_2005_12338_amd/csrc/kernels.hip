@@ -299,13 +299,26 @@ __global__ void k_scale_cols(const double* c, const double* lw, int64_t n, int64
 }
 
 // out[t] (n x n) = (P[t] + P[t]^T) / 2 * sign from padded P.
-__global__ void k_unpad_sym(const double* p, int64_t n, int64_t np, int64_t ntau, double sign,
-                            double* out) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ntau * n * n) return;
-  int64_t t = e / (n * n), ij = e % (n * n), i = ij / n, j = ij % n;
+// out[t][i][j] = sign (p[t][i][j] + p[t][j][i]) / 2 on 32 x 32 tiles: one
+// workgroup per (output tile, tau t0 + blockIdx.y); the mirror tile is read
+// row by row and transposed through LDS, so every global access is
+// contiguous.
+__global__ __launch_bounds__(256) void k_unpad_sym(const double* p, int64_t n, int64_t np, int64_t t0,
+                                                   int64_t ntile, double sign, double* out) {
+  __shared__ double tb[32][33];
+  const int64_t t = t0 + blockIdx.y;
+  const int64_t bi = blockIdx.x / ntile, bj = blockIdx.x % ntile;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const double* pt = p + t * np * np;
-  out[e] = sign * 0.5 * (pt[i * np + j] + pt[j * np + i]);
+  for (int r = ty; r < 32; r += 8) {           // tb[r][c] = p[32 bj + r][32 bi + c]
+    const int64_t gi = bj * 32 + r, gj = bi * 32 + tx;
+    tb[r][tx] = (gi < n && gj < n) ? pt[gi * np + gj] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi * 32 + r, j = bj * 32 + tx;
+    if (i < n && j < n) out[(t * n + i) * n + j] = sign * 0.5 * (pt[i * np + j] + tb[tx][r]);
+  }
 }
 
 // Padded copies of G(tau) in storage format and FP64.
@@ -797,7 +810,12 @@ void launch_scale_cols(const double* c, const double* lw, int64_t n, int64_t np,
 }
 void launch_unpad_sym(const double* p, int64_t n, int64_t np, int64_t ntau, double sign, double* out,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_unpad_sym, dim3(blocks(ntau * n * n)), dim3(256), 0, st, p, n, np, ntau, sign, out);
+  const int64_t ntile = (n + 31) / 32;
+  for (int64_t t0 = 0; t0 < ntau; t0 += 65535) {
+    const unsigned nt = (unsigned)std::min<int64_t>(65535, ntau - t0);
+    hipLaunchKernelGGL(k_unpad_sym, dim3((unsigned)(ntile * ntile), nt), dim3(256), 0, st, p, n, np, t0, ntile,
+                       sign, out);
+  }
 }
 void launch_pad_convert(const double* g, int64_t n, int64_t np, int64_t ntau, Prec prec, void* stbuf,
                         int64_t plane, int64_t mstride, double* f64pad, hipStream_t st) {
